@@ -1,0 +1,369 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: printed
+values (eq. (1), the barrel-shift example of sec. 2.2), textbook field tables,
+closed forms (Table 1 loop counts), brute-force enumeration and ML decoding on
+tiny codes, and exact symmetries of the decoders.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2508_03567_amd import synth as S
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    rows = []
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            rows.append([int(v) for v in line.split()])
+    return np.array(rows)
+
+
+# ------------------------------------------------------------------ GF pins
+def test_gf4_matches_textbook_table():
+    T = _golden("gf4_mul.txt")
+    for a in range(4):
+        for b in range(4):
+            assert O.gf_mul(4, 0x7, a, b) == T[a, b]
+
+
+@pytest.mark.parametrize("g", [4, 8, 16, 32, 64, 128, 256])
+def test_gf_alpha_is_primitive(g):
+    poly = S.PRIM_POLY[g]
+    seen, v = set(), 1
+    for _ in range(g - 1):
+        seen.add(v)
+        v = O.gf_mul(g, poly, v, 2)
+    assert v == 1 and len(seen) == g - 1 and 0 not in seen
+
+
+def test_gf64_reduction_rule():
+    # x^6 = x + 1 modulo x^6 + x + 1
+    assert O.gf_mul(64, 0x43, 32, 2) == 3
+    # x^7 = x^2 + x
+    assert O.gf_mul(64, 0x43, 32, 4) == 6
+
+
+@pytest.mark.parametrize("g", [4, 8, 16, 64])
+def test_gf_field_axioms(g):
+    poly = S.PRIM_POLY[g]
+    M = np.array([[O.gf_mul(g, poly, a, b) for b in range(g)] for a in range(g)])
+    assert (M == M.T).all()
+    assert (M[1] == np.arange(g)).all() and (M[0] == 0).all()
+    for a in range(1, g):
+        assert sorted(M[a, 1:]) == list(range(1, g))  # no zero divisors, a bijection
+        assert M[a, O.gf_inv(g, poly, a)] == 1
+    rng = np.random.default_rng(0)
+    for a, b, c in rng.integers(0, g, size=(300, 3)):
+        assert M[M[a, b], c] == M[a, M[b, c]]
+        assert M[a, b ^ c] == M[a, b] ^ M[a, c]
+
+
+def test_gf_matches_independent_log_tables():
+    for g in [4, 8, 64, 256]:
+        gf = S._GFEnc(g, S.PRIM_POLY[g])
+        rng = np.random.default_rng(g)
+        for a, b in rng.integers(0, g, size=(200, 2)):
+            assert O.gf_mul(g, S.PRIM_POLY[g], a, b) == int(gf.mul(a, b))
+
+
+@pytest.mark.parametrize("g", [4, 8, 64])
+def test_barrel_shift_example(g):
+    """Sec. 2.2: in the order [0, 1, a, a^2, ...], multiplying a message by a is a
+    right barrel shift of the nonzero entries with entry 0 fixed; by a^2 a shift
+    by two; by a^-1 a left shift."""
+    poly = S.PRIM_POLY[g]
+    order = [0]
+    v = 1
+    for _ in range(g - 1):
+        order.append(v)
+        v = O.gf_mul(g, poly, v, 2)
+    order = np.array(order)
+    msg = np.arange(100, 100 + g, dtype=np.int32)  # v(x) = 100 + x
+    log_vec = msg[order]
+    a2 = O.gf_mul(g, poly, 2, 2)
+    ainv = O.gf_inv(g, poly, 2)
+    for h, shift in [(2, 1), (a2, 2), (ainv, -1)]:
+        out = O.gf_permute(g, poly, h, msg)[order]
+        assert out[0] == log_vec[0]
+        assert (out[1:] == np.roll(log_vec[1:], shift)).all()
+
+
+# ------------------------------------------------------------ eq. (1) code
+def test_eq1_code_has_64_codewords_and_degrees():
+    code = S.eq1_code()
+    H = _golden("eq1_H.txt")
+    assert (code.dense() == H).all()
+    assert (code.row_degrees() == 4).all() and (code.col_degrees() == 2).all()
+    assert H[0, 0] != 0 and H[0, 1] == 0  # CN0 - VN0 connected, CN0 - VN1 not
+    words = np.array(list(itertools.product(range(4), repeat=6)), dtype=np.uint8)
+    n_ok = sum(O.syndrome_ok(code, w) for w in words)
+    assert n_ok == 64  # dimension N - M = 3 over GF(4)
+
+
+# ----------------------------------------------------------- check nodes
+def _brute_cn(g, poly, h, alpha):
+    """beta_j(x): min over other-edge symbols c_k with sum h_k c_k = h_j x of max alpha_k(c_k)."""
+    gf = S._GFEnc(g, poly)
+    dc = len(h)
+    beta = np.full((dc, g), np.iinfo(np.int64).max, dtype=np.int64)
+    for j in range(dc):
+        others = [k for k in range(dc) if k != j]
+        for combo in itertools.product(range(g), repeat=len(others)):
+            s = 0
+            cost = 0
+            for k, c in zip(others, combo):
+                s ^= int(gf.mul(h[k], c))
+                cost = max(cost, alpha[k][c])
+            # h_j x = s  ->  x = h_j^-1 s
+            x = int(gf.mul(gf.inv(h[j]), s))
+            beta[j, x] = min(beta[j, x], cost)
+    return beta
+
+
+@pytest.mark.parametrize("g,dc", [(2, 2), (2, 4), (4, 2), (4, 3), (4, 4), (8, 3), (8, 4)])
+def test_minmax_cn_equals_brute_force(g, dc):
+    rng = np.random.default_rng(g * 10 + dc)
+    poly = S.PRIM_POLY[g]
+    for _ in range(5):
+        h = rng.integers(1, g, size=dc)
+        alpha = rng.integers(0, 30, size=(dc, g))
+        alpha -= alpha.min(axis=1, keepdims=True)
+        beta, _, _ = O.minmax_cn(g, poly, h, alpha)
+        assert (beta == _brute_cn(g, poly, h, alpha)).all()
+
+
+def test_minmax_cn_gf64_dc3_brute_force():
+    g, poly = 64, 0x43
+    gf = S._GFEnc(g, poly)
+    rng = np.random.default_rng(7)
+    h = rng.integers(1, g, size=3)
+    alpha = rng.integers(0, 500, size=(3, g))
+    alpha[np.arange(3), rng.integers(0, g, 3)] = 0
+    beta, _, _ = O.minmax_cn(g, poly, h, alpha)
+    c = np.arange(g)
+    for j in range(3):
+        a, b = [k for k in range(3) if k != j]
+        for x in range(g):
+            # c_b solves h_b c_b = h_j x + h_a c_a
+            cb = gf.mul(gf.inv(h[b]), gf.mul(h[j], x) ^ gf.mul(h[a], c))
+            assert beta[j, x] == np.maximum(alpha[a][c], alpha[b][cb]).min()
+
+
+def test_minmax_cn_edge_order_invariance_and_value_origin():
+    g, poly, dc = 16, 0x13, 5
+    rng = np.random.default_rng(3)
+    h = rng.integers(1, g, size=dc)
+    alpha = rng.integers(0, 100, size=(dc, g))
+    alpha -= alpha.min(axis=1, keepdims=True)
+    beta, _, _ = O.minmax_cn(g, poly, h, alpha)
+    perm = rng.permutation(dc)
+    beta_p, _, _ = O.minmax_cn(g, poly, h[perm], alpha[perm])
+    assert (beta_p == beta[perm]).all()
+    for j in range(dc):
+        assert beta[j].min() == 0
+        others = set(alpha[[k for k in range(dc) if k != j]].ravel().tolist())
+        assert set(beta[j].tolist()) <= others
+
+
+def test_minmax_pair_counts_match_table1_loops():
+    """Table 1: the F&B loops over remaining edges run M(dc-1)g^2 times (each
+    evaluating one forward and one backward pair) and the middle-beta loop
+    M(dc-2)g^2 times per iteration."""
+    code = S.random_regular_nb_code(16, 8, 2, 4, 8, 0xB, seed=5)
+    gamma = np.random.default_rng(0).integers(0, 20, size=(1, 16, 8)).astype(np.int16)
+    out = O.decode_nb(code, O.params("minmax", max_iters=3, early_stop=False), gamma)
+    M, dc, g, I = 8, 4, 8, 3
+    assert out["pairs"][0] == I * 2 * M * (dc - 1) * g * g
+    assert out["pairs"][1] == I * M * (dc - 2) * g * g
+
+
+def test_binary_ms_special_cases():
+    prm_ms = O.params("ms")
+    q = np.array([5, -3, 7, 2, -9], dtype=np.int32)
+    r = O.binary_cn(q, prm_ms)
+    # r_j = (product of the others' signs) * (min of the others' magnitudes)
+    assert list(r) == [2, -2, 2, 3, -2]
+    # NMS with factor 4/4 and OMS with offset 0 reduce to plain MS
+    assert (O.binary_cn(q, O.params("nms", nms_num=4, nms_shift=2)) == r).all()
+    assert (O.binary_cn(q, O.params("oms", oms_offset=0)) == r).all()
+    # a zero input zeroes every other output
+    q0 = np.array([0, -4, 6], dtype=np.int32)
+    assert list(O.binary_cn(q0, prm_ms)) == [-4, 0, 0]
+
+
+def test_binary_cn_is_gf2_minmax():
+    rng = np.random.default_rng(11)
+    for dc in range(2, 9):
+        for _ in range(20):
+            q = rng.integers(-40, 41, size=dc).astype(np.int32)
+            r = O.binary_cn(q, O.params("ms"))
+            alpha = np.stack([np.maximum(0, -q), np.maximum(0, q)], axis=1)
+            beta, _, _ = O.minmax_cn(2, 0x3, np.ones(dc), alpha)
+            # cost form -> LLR form: r = beta(1) - beta(0)
+            assert (beta[:, 1] - beta[:, 0] == r).all()
+
+
+# ----------------------------------------------------- whole-decoder pins
+def _tree_code():
+    # chain of checks: a cycle-free Tanner graph
+    H = np.zeros((4, 9), dtype=np.int64)
+    H[0, [0, 1, 2]] = 1
+    H[1, [2, 3, 4]] = 1
+    H[2, [4, 5, 6]] = 1
+    H[3, [6, 7, 8]] = 1
+    return S.code_from_dense(H)
+
+
+def test_tree_code_min_sum_equals_ml():
+    """Max-product exactness on trees: plain min-sum without saturation equals
+    brute-force ML after at least diameter iterations (when ML is unique)."""
+    code = _tree_code()
+    H = code.dense()
+    words = np.array(list(itertools.product([0, 1], repeat=9)), dtype=np.int64)
+    cws = words[((words @ H.T) % 2 == 0).all(axis=1)]
+    rng = np.random.default_rng(1)
+    checked = 0
+    for _ in range(200):
+        L = rng.integers(-20, 21, size=9)
+        costs = (np.abs(L)[None, :] * (cws != (L < 0)[None, :])).sum(axis=1)
+        order = np.argsort(costs)
+        if costs[order[0]] == costs[order[1]] or (L == 0).any():
+            continue
+        ml = cws[order[0]]
+        for sched in ["flooding", "layered"]:
+            prm = O.params("ms", sched, max_iters=12, early_stop=False, msg_max=10 ** 6)
+            out = O.decode_binary(code, prm, L[None].astype(np.int8))
+            assert (out["hard"][0] == ml).all(), (L, sched)
+        checked += 1
+    assert checked > 50
+
+
+def test_gf2_minmax_decoder_equals_min_sum_decoder():
+    """Binary min-sum is the GF(2) case of Alg. 2: decisions, iteration counts
+    and every message agree (alpha(1)-alpha(0) = q, beta(1)-beta(0) = r)."""
+    w = S.workload(0, batch=40)
+    cw, llr = S.make_inputs(w)
+    code = w.code
+    L = llr.astype(np.int32)
+    gamma = np.stack([np.maximum(0, -L), np.maximum(0, L)], axis=2).astype(np.int16)
+    for iters in [1, 2, 5]:
+        prm_b = O.params("ms", "flooding", iters, True, msg_max=10 ** 6)
+        prm_n = O.params("minmax", "flooding", iters, True)
+        b = O.decode_binary(code, prm_b, llr, dump=True)
+        code_nb = S.Code("gf2", 2, 0x3, code.n, code.m, code.row_ptr, code.col_idx,
+                         np.ones(code.nnz, dtype=np.uint8))
+        nb = O.decode_nb(code_nb, prm_n, gamma, dump=True)
+        assert (b["iters"] == nb["iters"]).all()
+        assert (b["ok"] == nb["ok"]).all()
+        assert (b["hard"] == nb["hard"]).all()
+        assert (nb["alpha"][..., 1] - nb["alpha"][..., 0] == b["q"]).all()
+        assert (nb["beta"][..., 1] - nb["beta"][..., 0] == b["r"]).all()
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 3])
+def test_noiseless_codewords(cfg):
+    w = S.workload(cfg, batch=12)
+    cw, llr = S.make_inputs(w, noiseless=True)
+    for early in [True, False]:
+        prm = O.params(w.rule, w.schedule, 5, early)
+        out = (O.decode_binary if w.code.g == 2 else O.decode_nb)(w.code, prm, llr)
+        assert (out["hard"] == cw).all()
+        assert out["ok"].all()
+        assert (out["iters"] == (0 if early else 5)).all()
+
+
+def test_noiseless_long_code():
+    w = S.workload(2, batch=2)
+    cw, llr = S.make_inputs(w, noiseless=True)
+    out = O.decode_binary(w.code, O.params("nms", "flooding", 3, True), llr)
+    assert (out["hard"] == cw).all() and out["ok"].all() and (out["iters"] == 0).all()
+
+
+def test_binary_codeword_sign_flip_equivariance():
+    for cfg in [0, 1]:
+        w = S.workload(cfg, batch=8)
+        cw, llr = S.make_inputs(w)
+        c2 = S.random_codewords(w.code, 8, seed=99)
+        flip = (1 - 2 * c2.astype(np.int16))
+        llr2 = (llr.astype(np.int16) * flip).astype(np.int8)
+        prm = O.params(w.rule, w.schedule, 7, False)
+        a = O.decode_binary(w.code, prm, llr, dump=True)
+        b = O.decode_binary(w.code, prm, llr2, dump=True)
+        fe = flip[:, w.code.col_idx]
+        assert (b["r"] == a["r"] * fe).all()
+        assert (b["q"] == a["q"] * fe).all()
+        assert (b["lam"] == a["lam"] * flip).all()
+        nz = a["lam"] != 0
+        assert (b["hard"][nz] == (a["hard"] ^ c2)[nz]).all()
+
+
+def test_nb_codeword_shift_equivariance():
+    w = S.workload(3, batch=4)
+    cw, gamma = S.make_inputs(w)
+    c2 = S.random_codewords(w.code, 4, seed=77)
+    x = np.arange(64)
+    gamma2 = np.take_along_axis(gamma, (x[None, None, :] ^ c2[:, :, None].astype(np.int64)), axis=2)
+    prm = O.params("minmax", "flooding", 4, False)
+    a = O.decode_nb(w.code, prm, gamma, dump=True)
+    b = O.decode_nb(w.code, prm, gamma2, dump=True)
+    ce = c2[:, w.code.col_idx].astype(np.int64)
+    idx = x[None, None, :] ^ ce[:, :, None]
+    assert (b["beta"] == np.take_along_axis(a["beta"], idx, axis=2)).all()
+    assert (b["alpha"] == np.take_along_axis(a["alpha"], idx, axis=2)).all()
+    # decisions are equivariant wherever the a posteriori minimum is unique
+    app = gamma.astype(np.int64).copy()
+    for e, v in enumerate(w.code.col_idx):
+        app[:, v, :] += a["beta"][:, e, :]
+    srt = np.sort(app, axis=2)
+    unique = srt[..., 0] != srt[..., 1]
+    assert unique.mean() > 0.5
+    assert (b["hard"] == (a["hard"] ^ c2))[unique].all()
+
+
+def test_nb_message_invariants():
+    w = S.workload(3, batch=3)
+    cw, gamma = S.make_inputs(w)
+    for iters in [1, 3]:
+        out = O.decode_nb(w.code, O.params("minmax", "flooding", iters, False), gamma, dump=True)
+        assert (out["alpha"].min(axis=2) == 0).all()
+        assert (out["beta"].min(axis=2) == 0).all()
+
+
+def test_eq1_decoder_cost_not_below_ml():
+    code = S.eq1_code()
+    words = np.array(list(itertools.product(range(4), repeat=6)), dtype=np.uint8)
+    cws = words[[O.syndrome_ok(code, wd) for wd in words]]
+    rng = np.random.default_rng(5)
+    for ebn0, seed in [(0.0, 1), (1.0, 2), (3.0, 3), (8.0, 4)]:
+        c = cws[rng.integers(0, 64, size=64)]
+        gamma = S.nb_gamma_int16(c, 4, ebn0, seed)
+        out = O.decode_nb(code, O.params("minmax", "flooding", 10, True), gamma)
+        cost_all = gamma[:, np.arange(6)[None, :], cws].sum(axis=2)  # [B, 64]
+        ml = cost_all.min(axis=1)
+        dec_cost = np.take_along_axis(gamma, out["hard"][..., None].astype(np.int64), 2)[..., 0].sum(1)
+        valid = out["ok"].astype(bool)
+        assert (dec_cost[valid] >= ml[valid]).all()
+        if ebn0 >= 8.0:
+            assert (out["hard"] == c).all()
+
+
+def test_fer_falls_with_snr_layered_oms():
+    w = S.workload(1, batch=48)
+    fer = []
+    for eb in [1.0, 2.0, 3.0]:
+        w.ebn0_db = eb
+        cw, llr = S.make_inputs(w)
+        out = O.decode_binary(w.code, O.params("oms", "layered", 20, True), llr)
+        fer.append((out["hard"] != cw).any(axis=1).mean())
+        # coded bit error rate below uncoded BPSK hard decisions
+        if eb >= 2.0:
+            assert (out["hard"] != cw).mean() < ((llr < 0) != cw).mean()
+    assert fer[0] >= fer[1] >= fer[2]
