@@ -1,0 +1,243 @@
+/*
+ * ldpcx.h -- C-ABI of libldpcx, batched LDPC decoding on AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the paper's statement of the decoding problem (Algs. 1 and
+ * 2: input H, the iteration cap I_max and the channel observation y; output
+ * the decision c-hat, sought such that c-hat H^T = 0 or the cap is reached;
+ * sec. 2.1: H is a sparse M x N matrix over GF(2^p), code size (N, K) with
+ * K = N - M).  Binary codes (g = 2) are decoded with min-sum variants, codes
+ * over GF(g), g = 2^p <= 256, with the Min-Max algorithm (Alg. 2).
+ *
+ * Conventions for every call:
+ *   - Pointers documented as "device" must point to memory of the current HIP
+ *     device (e.g. a torch tensor's data_ptr()); "host" pointers are ordinary
+ *     CPU memory.  The caller owns every input/output buffer; the library owns
+ *     code handles, internal workspaces and servers.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the legacy default
+ *     stream).  Decode calls are stream-ordered and asynchronous: they return
+ *     once the work is enqueued; buffers must stay valid until it completes.
+ *   - Arguments are validated on the host before anything is enqueued.  Every
+ *     call returns an ldpcx_status; no C++ exception crosses the ABI.  The
+ *     last error message of the calling thread is available from
+ *     ldpcx_last_error().  A device fault surfaces as LDPCX_E_DEVICE at the
+ *     next call that synchronises.
+ *   - Code handles are immutable after creation and may be shared between
+ *     threads and streams.
+ *   - Integer semantics are fixed and identical on every code path: results
+ *     are bit-exact functions of the inputs (see ldpcx_decode_params).
+ */
+#ifndef LDPCX_H
+#define LDPCX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LDPCX_OK = 0,
+    LDPCX_E_INVAL = -1,       /* bad argument or malformed code description */
+    LDPCX_E_NOMEM = -2,       /* device or host allocation failed */
+    LDPCX_E_DEVICE = -3,      /* HIP runtime error (launch failure, device fault) */
+    LDPCX_E_UNSUPPORTED = -4, /* valid request outside what the kernels implement */
+    LDPCX_E_BUDGET = -5,      /* server: request cannot fit the memory budget */
+    LDPCX_E_CANCELLED = -6,   /* server: request was cancelled */
+    LDPCX_E_TIMEOUT = -7,     /* server: wait timed out (request still pending) */
+    LDPCX_E_NOTFOUND = -8     /* server: unknown ticket */
+} ldpcx_status;
+
+enum { LDPCX_SCHED_FLOODING = 0, LDPCX_SCHED_LAYERED = 1, LDPCX_SCHED_AUTO = 2 };
+enum { LDPCX_RULE_MS = 0, LDPCX_RULE_NMS = 1, LDPCX_RULE_OMS = 2, LDPCX_RULE_MINMAX = 3 };
+
+typedef struct ldpcx_code ldpcx_code;
+
+/* Description of a parity-check matrix H (host memory; copied by ldpcx_code_create).
+ *   g          field size: 2 for binary codes, else 2^p with 4 <= g <= 256.
+ *   prim_poly  primitive polynomial of GF(g), bit i = coefficient of x^i (e.g. 0x43 for
+ *              x^6 + x + 1); ignored when g == 2.  Field elements use the polynomial basis
+ *              of sec. 2.1 (element x encodes the polynomial whose coefficients are x's bits).
+ *   n, m       number of variable nodes (columns, symbols) and check nodes (rows).
+ *   row_ptr    [m + 1] CSR row offsets, row_ptr[0] = 0.
+ *   col_idx    [row_ptr[m]] column of each nonzero, strictly ascending inside a row.
+ *   h_val      [row_ptr[m]] nonzero GF(g) coefficient of each entry; NULL when g == 2.
+ *   z          layer size for the layered schedule: rows [l*z, (l+1)*z) form layer l and
+ *              must touch pairwise disjoint columns; m % z == 0.  0 = no layer structure.
+ *   k_info     information symbols per codeword used for throughput accounting (n - m).
+ * Limits: every check degree in [2, 14] for g == 2 (in [2, 16] for g > 2); n, m >= 1. */
+typedef struct {
+    int32_t g;
+    uint32_t prim_poly;
+    int32_t n, m;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const uint8_t *h_val;
+    int32_t z;
+    int32_t k_info;
+} ldpcx_code_desc;
+
+/* Decoding parameters.
+ *   max_iters   I_max >= 0.
+ *   early_stop  1: iteration k first tests the syndrome of the decision of iteration
+ *               k - 1 and stops the codeword when it is zero (Alg. 2); 0: always run
+ *               max_iters iterations (fixed-iteration throughput mode).
+ *   schedule    FLOODING (two-phase, Alg. 2), LAYERED (rows of one layer in parallel,
+ *               layers in ascending order; binary codes with z > 0 or z == 0 meaning
+ *               row by row), or AUTO (the autotuner picks; ldpcx_decode reports the
+ *               schedule used).
+ *   rule        MS / NMS / OMS for g == 2, MINMAX for g > 2.
+ *   nms_num, nms_shift   NMS magnitude f(m) = (nms_num * m) >> nms_shift (0.75 = 3, 2).
+ *   oms_offset  OMS magnitude f(m) = max(m - oms_offset, 0).
+ *   msg_max     binary variable-to-check message saturation, 1..127 (default 127).
+ * Binary arithmetic: channel LLRs L are int8, positive favours bit 0.  Check-to-
+ * variable message r_mn = prod_{n' != n} sgn(q_mn') * f(min_{n' != n} |q_mn'|),
+ * sgn(0) = +1; a posteriori Lambda_n = L_n + sum_m r_mn (exact, 16 bit); variable-
+ * to-check q_mn = clamp(Lambda_n - r_mn, +-msg_max); decision c_n = [Lambda_n < 0].
+ * Min-Max arithmetic (eqs. (7)-(15)): messages int16, sums in 32 bit, alpha clamped
+ * to 32767; decision = lowest x minimising gamma_n(x) + sum_m beta_mn(x). */
+typedef struct {
+    int32_t max_iters;
+    int32_t early_stop;
+    int32_t schedule;
+    int32_t rule;
+    int32_t nms_num;
+    int32_t nms_shift;
+    int32_t oms_offset;
+    int32_t msg_max;
+} ldpcx_decode_params;
+
+/* Validate `desc`, build the library's device structures (CSR/CSC, layer table, GF
+ * tables) on the current device and return an opaque handle in *out.
+ * Errors: LDPCX_E_INVAL (malformed H: unsorted or repeated columns, zero or out-of-range
+ * coefficient, bad layer size, check degree < 2), LDPCX_E_UNSUPPORTED (degrees above the
+ * limits), LDPCX_E_NOMEM, LDPCX_E_DEVICE. */
+ldpcx_status ldpcx_code_create(const ldpcx_code_desc *desc, ldpcx_code **out);
+
+/* Release a code handle (synchronises the device first).  NULL is accepted. */
+ldpcx_status ldpcx_code_destroy(ldpcx_code *code);
+
+/* Sizes of a code handle (host pointers, any may be NULL). */
+ldpcx_status ldpcx_code_info(const ldpcx_code *code, int32_t *n, int32_t *m, int32_t *nnz,
+                             int32_t *g, int32_t *max_dc, int32_t *max_dv);
+
+/* Decode `batch` independent codewords (Algs. 2 / min-sum; the multicodeword mapping of
+ * sec. 4: every codeword is an independent decoder).
+ *   llr          device, g == 2: int8 [batch][n] channel LLRs;
+ *                g > 2: int16 [batch][n][g] channel vectors gamma_n(x) = ln(p(eta)/p(x))
+ *                quantised (Alg. 2 initialisation), entries in [0, 32767].
+ *   hard         device, g == 2: uint8 [batch][ceil(n/8)], bit j of codeword b is bit
+ *                (j % 8) (LSB first) of byte j / 8; padding bits are 0.
+ *                g > 2: uint8 [batch][n] decided symbols.
+ *   syndrome_ok  device uint8 [batch]: 1 when the final decision satisfies every check.
+ *   iters        device int16 [batch]: iterations performed (0 when the channel decision
+ *                already satisfied H and early_stop is on).
+ *   schedule_used host int32*, may be NULL: the schedule actually run.
+ * batch == 0 is a no-op.  The library may allocate a workspace on `stream` (stream-ordered
+ * allocator). */
+ldpcx_status ldpcx_decode(const ldpcx_code *code, const ldpcx_decode_params *params, int32_t batch,
+                          const void *llr, void *hard, uint8_t *syndrome_ok, int16_t *iters,
+                          int32_t *schedule_used, void *stream);
+
+/* Same as ldpcx_decode, and additionally writes the final message state in canonical
+ * CSR edge order (edge e = position in col_idx), for bit-exact comparison of every message:
+ *   g == 2: msg_a = int8 q [batch][nnz] (q_e = clamp(Lambda - r_e)), msg_b = int8 r
+ *           [batch][nnz], msg_c = int16 Lambda [batch][n].
+ *   g > 2:  msg_a = int16 alpha [batch][nnz][g], msg_b = int16 beta [batch][nnz][g],
+ *           msg_c unused (may be NULL).
+ * All message pointers are device memory.  Before the first iteration beta = r = 0. */
+ldpcx_status ldpcx_debug_dump(const ldpcx_code *code, const ldpcx_decode_params *params,
+                              int32_t batch, const void *llr, void *hard, uint8_t *syndrome_ok,
+                              int16_t *iters, void *msg_a, void *msg_b, void *msg_c, void *stream);
+
+/* One job of a ragged batch: `batch` codewords of `code` with their own parameters and
+ * buffers (same layouts as ldpcx_decode). */
+typedef struct {
+    const ldpcx_code *code;
+    ldpcx_decode_params params;
+    int32_t batch;
+    const void *llr;
+    void *hard;
+    uint8_t *syndrome_ok;
+    int16_t *iters;
+} ldpcx_job;
+
+/* Decode a ragged batch of jobs over different codes and sizes with ONE persistent
+ * kernel launch on `stream` (per-codeword early termination inside).  Results are
+ * identical to calling ldpcx_decode on each job.  AUTO schedules are resolved per job
+ * as in ldpcx_decode. */
+ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs, void *stream);
+
+/* Autotune the launch configuration of (code, params, batch) by timing the candidate
+ * configurations on `stream` (synchronous).  The choice is cached per (code, params,
+ * batch class) and used by later decode calls; when params->schedule is AUTO the
+ * schedule is tuned too.  *chosen_schedule (may be NULL) receives the schedule and
+ * *best_us (may be NULL) the measured time of the winner in microseconds. */
+ldpcx_status ldpcx_tune(const ldpcx_code *code, const ldpcx_decode_params *params, int32_t batch,
+                        int32_t *chosen_schedule, float *best_us, void *stream);
+
+/* Launch configuration that the next decode of (code, params, batch) would use:
+ * kernel family (0 = LDS-resident binary, 1 = interleaved binary, 2 = interleaved
+ * min-max), codewords per workgroup, threads per workgroup. */
+ldpcx_status ldpcx_plan_info(const ldpcx_code *code, const ldpcx_decode_params *params,
+                             int32_t batch, int32_t *family, int32_t *cw_per_wg,
+                             int32_t *threads);
+
+/* Pin the launch configuration used for (code, params, batch class) instead of the
+ * default or tuned one.  family as in ldpcx_plan_info; cw_per_wg and threads are used by
+ * family 0 (threads a multiple of 64 in [64, 1024]).  The pinned plan must be able to
+ * run the requested schedule (LDPCX_E_UNSUPPORTED otherwise; family 1 and 2 are
+ * flooding only).  Results never depend on the plan. */
+ldpcx_status ldpcx_plan_set(ldpcx_code *code, const ldpcx_decode_params *params, int32_t batch,
+                            int32_t family, int32_t cw_per_wg, int32_t threads);
+
+/* ------------------------------------------------------------------ serving */
+typedef struct ldpcx_server ldpcx_server;
+
+/* Create a continuous-batching server on the current device.  Requests are admitted
+ * while their device memory (inputs, outputs and decoder state) fits `hbm_budget`
+ * bytes; admitted requests share persistent ragged launches that advance every
+ * in-flight codeword by up to `iters_per_step` iterations (0 = run to completion),
+ * and requests that arrive meanwhile are admitted as memory frees up.  A request
+ * larger than the budget is split into chunks that fit. */
+ldpcx_status ldpcx_server_create(size_t hbm_budget, int32_t iters_per_step, ldpcx_server **out);
+
+/* Submit a request (host buffers, layouts as ldpcx_decode; they must stay valid until
+ * the request completes).  Returns at once with a ticket.  LDPCX_E_BUDGET when even one
+ * codeword does not fit the budget. */
+ldpcx_status ldpcx_server_submit(ldpcx_server *srv, const ldpcx_code *code,
+                                 const ldpcx_decode_params *params, int32_t batch,
+                                 const void *llr_host, void *hard_host, uint8_t *syndrome_ok_host,
+                                 int16_t *iters_host, uint64_t *ticket);
+
+/* *done = 1 when the request finished (its host outputs are complete). */
+ldpcx_status ldpcx_server_poll(ldpcx_server *srv, uint64_t ticket, int32_t *done);
+
+/* Block until the request finishes or `timeout_ms` elapses (< 0: no limit).  Returns the
+ * request's final status (LDPCX_OK, LDPCX_E_CANCELLED, LDPCX_E_DEVICE ...) or
+ * LDPCX_E_TIMEOUT.  Timing of the request (submit, first admission, completion) is
+ * returned in microseconds since server creation when the pointers are not NULL. */
+ldpcx_status ldpcx_server_wait(ldpcx_server *srv, uint64_t ticket, int32_t timeout_ms,
+                               double *t_submit_us, double *t_admit_us, double *t_done_us);
+
+/* Cancel a request that has not completed; its chunks still queued are dropped. */
+ldpcx_status ldpcx_server_cancel(ldpcx_server *srv, uint64_t ticket);
+
+/* Counters: requests completed, codewords decoded, launches, peak bytes admitted. */
+ldpcx_status ldpcx_server_stats(ldpcx_server *srv, uint64_t *completed, uint64_t *codewords,
+                                uint64_t *launches, uint64_t *peak_bytes);
+
+/* Stop the scheduler thread (pending requests are cancelled) and free the server. */
+ldpcx_status ldpcx_server_destroy(ldpcx_server *srv);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *ldpcx_last_error(void);
+
+/* Library version string. */
+const char *ldpcx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LDPCX_H */

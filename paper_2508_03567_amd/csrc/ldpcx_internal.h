@@ -1,0 +1,109 @@
+// Internal declarations shared by the HIP kernels and the host runtime of libldpcx.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/ldpcx.h"
+
+namespace ldpcx {
+
+constexpr int kBinDcMax = 14;  // binary check state: 7b min1 | 7b min2 | 4b argmin | 14 sign bits
+constexpr int kNbDcMax = 16;
+constexpr int kWave = 64;
+
+// Read-only device image of a code handle.
+struct DevCode {
+    int n, m, E, g, p, z, nlayers, dc_max, dv_max;
+    const int *row_ptr;    // [m + 1]
+    const int *col_idx;    // [E]
+    const int *vn_ptr;     // [n + 1]  edges of each variable node (CSC)
+    const int *vn_ref;     // [E] binary: (check << 4) | position in row ; g > 2: edge id
+    const uint8_t *h;      // [E] GF coefficient (g > 2)
+    const uint8_t *hinv;   // [E] its inverse (g > 2)
+    const uint8_t *gfmul;  // [g * g] multiplication table (g > 2)
+};
+
+struct BinRule {
+    int rule, nms_num, nms_shift, oms_offset, msg_max;
+};
+
+// Outputs of one decode.  Dump pointers may be null.
+struct DecodeIO {
+    const void *llr;
+    void *hard;
+    uint8_t *ok;
+    int16_t *iters;
+    void *dump_a, *dump_b, *dump_c;
+};
+
+// Binary check-node state packed in 32 bits: |min1| (7b), |min2| (7b), argmin (4b),
+// sign bit of every incoming message (bit 18 + position).
+__host__ __device__ inline uint32_t st_pack(int m1, int m2, int idx, uint32_t signs) {
+    return (uint32_t)m1 | ((uint32_t)m2 << 7) | ((uint32_t)idx << 14) | (signs << 18);
+}
+
+// Magnitude normalisation f of the min-sum variants.
+__device__ __forceinline__ int bin_norm(const BinRule &R, int m) {
+    if (R.rule == LDPCX_RULE_NMS) return (R.nms_num * m) >> R.nms_shift;
+    if (R.rule == LDPCX_RULE_OMS) return m > R.oms_offset ? m - R.oms_offset : 0;
+    return m;
+}
+
+// Outgoing check-to-variable message of position j given an unpacked state.
+__device__ __forceinline__ int bin_r(int j, int fm1, int fm2, int idx, uint32_t signs, uint32_t parity) {
+    int mag = (j == idx) ? fm2 : fm1;
+    uint32_t neg = parity ^ ((signs >> j) & 1u);
+    return neg ? -mag : mag;
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// ---------------------------------------------------------------- launchers
+// Each returns a hipError_t from the launch (hipSuccess when enqueued).
+
+// LDS-resident binary decoder: one workgroup decodes `cpw` whole codewords.
+hipError_t launch_bin_lds(const DevCode &C, const BinRule &R, int max_iters, int early_stop,
+                          int layered, int batch, int cpw, int threads, const DecodeIO &io,
+                          hipStream_t s);
+size_t bin_lds_smem_bytes(const DevCode &C, int layered, int cpw);
+
+// Interleaved (codeword-per-lane) binary flooding decoder, state in device memory.
+struct BinIlWork {
+    int8_t *L;        // [n][Bp]
+    int16_t *lam;     // [n][Bp]
+    uint32_t *st;     // [m][Bp]
+    uint64_t *hb;     // [n][Bp/64] hard-decision bits
+    uint64_t *unsat;  // [(max_iters + 1)][Bp/64] unsatisfied-codeword masks per syndrome test
+    int16_t *it;      // [Bp]
+};
+size_t bin_il_work_bytes(const DevCode &C, int max_iters, int batch);
+void bin_il_carve(void *base, const DevCode &C, int max_iters, int batch, BinIlWork &w);
+hipError_t launch_bin_il(const DevCode &C, const BinRule &R, int max_iters, int early_stop,
+                         int batch, const BinIlWork &w, const DecodeIO &io, hipStream_t s);
+// Debug dump of the final messages; q_t and r_t are [nnz][Bp] int8 scratch buffers.
+hipError_t launch_bin_il_dump(const DevCode &C, const BinRule &R, int batch, const BinIlWork &w,
+                              int8_t *q_t, int8_t *r_t, void *dq, void *dr, void *dlam, hipStream_t s);
+
+// Interleaved Min-Max decoder over GF(g).
+struct NbWork {
+    int16_t *gam;     // [n][g][Bp]
+    int16_t *alpha;   // [E][g][Bp]
+    int16_t *beta;    // [E][g][Bp]
+    uint8_t *hard;    // [n][Bp]
+    uint64_t *unsat;  // [(max_iters + 1)][Bp/64]
+    int16_t *it;      // [Bp]
+};
+size_t nb_work_bytes(const DevCode &C, int max_iters, int batch);
+void nb_carve(void *base, const DevCode &C, int max_iters, int batch, NbWork &w);
+hipError_t launch_nb(const DevCode &C, int max_iters, int early_stop, int batch, const NbWork &w,
+                     const DecodeIO &io, hipStream_t s);
+// Field sizes with a compiled Min-Max kernel.
+bool nb_supported(int g);
+
+__host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+__host__ __device__ inline int pad64(int b) { return (b + 63) & ~63; }
+
+}  // namespace ldpcx

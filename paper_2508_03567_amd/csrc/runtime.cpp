@@ -1,0 +1,476 @@
+// Host runtime of libldpcx: code handles, validation, launch planning and the
+// plain per-code decode entry points of the C-ABI.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "runtime.h"
+
+namespace ldpcx {
+
+thread_local std::string g_err;
+
+ldpcx_status fail(ldpcx_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+ldpcx_status fail_hip(hipError_t e, const char *what) {
+    return fail(LDPCX_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+
+std::mutex g_dev_mu;
+std::map<int, DeviceInfo> g_dev;
+
+// GF(2^p) tables from powers of the primitive element (log/exp construction).
+bool build_gf(int g, uint32_t poly, std::vector<uint8_t> &mul, std::vector<uint8_t> &inv) {
+    int p = 0;
+    while ((1 << p) < g) ++p;
+    std::vector<int> ex(2 * g), lg(g, -1);
+    int v = 1;
+    for (int i = 0; i < g - 1; ++i) {
+        if (lg[v] >= 0) return false;  // alpha is not primitive
+        ex[i] = v;
+        lg[v] = i;
+        v <<= 1;
+        if (v >> p) v ^= (int)poly;
+        if (v >= g) return false;
+    }
+    if (v != 1) return false;
+    for (int i = g - 1; i < 2 * g; ++i) ex[i] = ex[i - (g - 1)];
+    mul.assign((size_t)g * g, 0);
+    inv.assign(g, 0);
+    for (int a = 1; a < g; ++a) {
+        for (int b = 1; b < g; ++b) mul[(size_t)a * g + b] = (uint8_t)ex[lg[a] + lg[b]];
+        inv[a] = (uint8_t)ex[(g - 1 - lg[a]) % (g - 1)];
+    }
+    return true;
+}
+
+}  // namespace
+
+const DeviceInfo &device_info(int dev) {
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_dev.find(dev);
+    if (it != g_dev.end()) return it->second;
+    DeviceInfo d;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        d.cus = prop.multiProcessorCount;
+        d.lds_per_block = (int)prop.sharedMemPerBlock;
+    }
+    // Keep freed stream-ordered workspaces cached in the default pool.
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    return g_dev.emplace(dev, d).first->second;
+}
+
+ldpcx_status check_params(const ldpcx_code *c, const ldpcx_decode_params *p) {
+    if (!p) return fail(LDPCX_E_INVAL, "params is NULL");
+    if (p->max_iters < 0 || p->max_iters > 100000) return fail(LDPCX_E_INVAL, "max_iters out of range");
+    if (p->schedule < 0 || p->schedule > 2) return fail(LDPCX_E_INVAL, "unknown schedule");
+    if (c->g == 2) {
+        if (p->rule < 0 || p->rule > 2) return fail(LDPCX_E_INVAL, "binary codes take rule MS, NMS or OMS");
+        if (p->msg_max < 1 || p->msg_max > 127) return fail(LDPCX_E_INVAL, "msg_max must be in [1, 127]");
+        if (p->rule == LDPCX_RULE_NMS && (p->nms_num < 0 || p->nms_num > 64 || p->nms_shift < 0 || p->nms_shift > 15))
+            return fail(LDPCX_E_INVAL, "NMS factor out of range");
+        if (p->rule == LDPCX_RULE_OMS && (p->oms_offset < 0 || p->oms_offset > 127))
+            return fail(LDPCX_E_INVAL, "OMS offset out of range");
+        if (p->schedule == LDPCX_SCHED_LAYERED && !c->layers_ok)
+            return fail(LDPCX_E_INVAL, "layered schedule needs a valid layer size");
+    } else {
+        if (p->rule != LDPCX_RULE_MINMAX) return fail(LDPCX_E_INVAL, "codes over GF(g > 2) take rule MINMAX");
+        if (p->schedule == LDPCX_SCHED_LAYERED)
+            return fail(LDPCX_E_UNSUPPORTED, "layered Min-Max is not implemented");
+    }
+    return LDPCX_OK;
+}
+
+BinRule bin_rule(const ldpcx_decode_params *p) {
+    BinRule R;
+    R.rule = p->rule;
+    R.nms_num = p->nms_num;
+    R.nms_shift = p->nms_shift;
+    R.oms_offset = p->oms_offset;
+    R.msg_max = p->msg_max;
+    return R;
+}
+
+// Default launch plan (overridden by the autotuner's cached choice).
+Plan default_plan(const ldpcx_code *c, const ldpcx_decode_params *p, int batch) {
+    Plan pl;
+    const DeviceInfo &di = device_info(c->device);
+    if (c->g > 2) {
+        pl.family = FAMILY_NB;
+        pl.schedule = LDPCX_SCHED_FLOODING;
+        pl.cpw = 64;
+        pl.threads = 256;
+        return pl;
+    }
+    int sched = p->schedule;
+    if (sched == LDPCX_SCHED_AUTO) sched = (c->desc.z > 0 && c->layers_ok) ? LDPCX_SCHED_LAYERED : LDPCX_SCHED_FLOODING;
+    pl.schedule = sched;
+    const size_t per_cw = bin_lds_smem_bytes(c->dev, sched == LDPCX_SCHED_LAYERED, 1);
+    if (per_cw <= (size_t)64 * 1024 || (sched == LDPCX_SCHED_LAYERED && per_cw <= (size_t)di.lds_per_block)) {
+        pl.family = FAMILY_BIN_LDS;
+        int cpw = (int)std::max<size_t>(1, (size_t)(40 * 1024) / per_cw);
+        cpw = std::min(cpw, 16);
+        // keep at least ~2 workgroups per compute unit when the batch allows it
+        const int per_cu = std::max(1, batch / std::max(1, 2 * di.cus));
+        cpw = std::max(1, std::min(cpw, per_cu));
+        while (cpw > 1 && bin_lds_smem_bytes(c->dev, sched == LDPCX_SCHED_LAYERED, cpw) > (size_t)di.lds_per_block) --cpw;
+        pl.cpw = cpw;
+        const int rows = sched == LDPCX_SCHED_LAYERED ? std::max(1, c->desc.z) : c->dev.m;
+        int thr = ((rows * cpw + 63) / 64) * 64;
+        pl.threads = std::min(thr, sched == LDPCX_SCHED_LAYERED ? 1024 : 256);
+    } else {
+        pl.family = FAMILY_BIN_IL;
+        pl.schedule = LDPCX_SCHED_FLOODING;
+        pl.cpw = 64;
+        pl.threads = 256;
+    }
+    return pl;
+}
+
+Plan plan_for(ldpcx_code *c, const ldpcx_decode_params *p, int batch) {
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        auto it = c->tuned.find(tune_key(p, batch));
+        if (it != c->tuned.end()) return it->second;
+    }
+    return default_plan(c, p, batch);
+}
+
+uint64_t tune_key(const ldpcx_decode_params *p, int batch) {
+    int cls = 0;
+    while ((1 << cls) < batch && cls < 40) ++cls;
+    return ((uint64_t)p->schedule << 48) | ((uint64_t)p->rule << 40) | ((uint64_t)(p->early_stop != 0) << 39) |
+           ((uint64_t)std::min(p->max_iters, 65535) << 16) | (uint64_t)cls;
+}
+
+// Enqueue one decode with an explicit plan.
+ldpcx_status run_plan(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &pl, int batch, const DecodeIO &io,
+                      hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (pl.family == FAMILY_BIN_LDS) {
+        const size_t smem = bin_lds_smem_bytes(c->dev, pl.schedule == LDPCX_SCHED_LAYERED, pl.cpw);
+        if (smem > (size_t)device_info(c->device).lds_per_block)
+            return fail(LDPCX_E_UNSUPPORTED, "code state does not fit the LDS of one workgroup");
+        e = launch_bin_lds(c->dev, bin_rule(p), p->max_iters, p->early_stop, pl.schedule == LDPCX_SCHED_LAYERED, batch,
+                           pl.cpw, pl.threads, io, s);
+        if (e != hipSuccess) return fail_hip(e, "binary LDS decoder launch");
+        return LDPCX_OK;
+    }
+    if (pl.family == FAMILY_BIN_IL && pl.schedule == LDPCX_SCHED_LAYERED)
+        return fail(LDPCX_E_UNSUPPORTED, "the interleaved binary decoder implements the flooding schedule only");
+    size_t bytes = pl.family == FAMILY_BIN_IL ? bin_il_work_bytes(c->dev, p->max_iters, batch)
+                                              : nb_work_bytes(c->dev, p->max_iters, batch);
+    const size_t Bp = pad64(batch);
+    size_t dump_bytes = 0;
+    if (io.dump_a && pl.family == FAMILY_BIN_IL) dump_bytes = align_up((size_t)c->dev.E * Bp, 256) * 2;
+    void *ws = nullptr;
+    e = hipMallocAsync(&ws, bytes + dump_bytes, s);
+    if (e != hipSuccess) return fail(LDPCX_E_NOMEM, std::string("workspace allocation: ") + hipGetErrorString(e));
+    if (pl.family == FAMILY_BIN_IL) {
+        BinIlWork w;
+        bin_il_carve(ws, c->dev, p->max_iters, batch, w);
+        e = launch_bin_il(c->dev, bin_rule(p), p->max_iters, p->early_stop, batch, w, io, s);
+        if (e == hipSuccess && io.dump_a) {
+            int8_t *q_t = (int8_t *)ws + bytes;
+            int8_t *r_t = q_t + align_up((size_t)c->dev.E * Bp, 256);
+            e = launch_bin_il_dump(c->dev, bin_rule(p), batch, w, q_t, r_t, io.dump_a, io.dump_b, io.dump_c, s);
+        }
+    } else {
+        NbWork w;
+        nb_carve(ws, c->dev, p->max_iters, batch, w);
+        e = launch_nb(c->dev, p->max_iters, p->early_stop, batch, w, io, s);
+    }
+    hipError_t e2 = hipFreeAsync(ws, s);
+    if (e != hipSuccess) return fail_hip(e, "decoder launch");
+    if (e2 != hipSuccess) return fail_hip(e2, "workspace release");
+    return LDPCX_OK;
+}
+
+ldpcx_status check_device(const ldpcx_code *c) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    if (dev != c->device) return fail(LDPCX_E_INVAL, "the current device is not the code handle's device");
+    return LDPCX_OK;
+}
+
+ldpcx_status decode_common(const ldpcx_code *code, const ldpcx_decode_params *params, int32_t batch, const void *llr,
+                           void *hard, uint8_t *ok, int16_t *iters, int32_t *sched_used, void *a, void *b, void *cc,
+                           void *stream) {
+    if (!code) return fail(LDPCX_E_INVAL, "code is NULL");
+    ldpcx_code *c = const_cast<ldpcx_code *>(code);
+    ldpcx_status st = check_params(c, params);
+    if (st != LDPCX_OK) return st;
+    if (batch < 0) return fail(LDPCX_E_INVAL, "batch < 0");
+    if (batch == 0) return LDPCX_OK;
+    if (!llr || !hard || !ok || !iters) return fail(LDPCX_E_INVAL, "null buffer");
+    if (a && (!b || (c->g == 2 && !cc))) return fail(LDPCX_E_INVAL, "dump needs every message buffer");
+    if ((st = check_device(c)) != LDPCX_OK) return st;
+    const Plan pl = plan_for(c, params, batch);
+    if (sched_used) *sched_used = pl.schedule;
+    DecodeIO io{llr, hard, ok, iters, a, b, cc};
+    return run_plan(c, params, pl, batch, io, (hipStream_t)stream);
+}
+
+}  // namespace ldpcx
+
+using namespace ldpcx;
+
+extern "C" {
+
+const char *ldpcx_last_error(void) { return g_err.c_str(); }
+
+const char *ldpcx_version(void) { return "ldpcx 0.1 (gfx950)"; }
+
+ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
+    try {
+        if (!d || !out) return fail(LDPCX_E_INVAL, "null argument");
+        *out = nullptr;
+        const int g = d->g;
+        if (g < 2 || g > 256 || (g & (g - 1))) return fail(LDPCX_E_INVAL, "g must be a power of two in [2, 256]");
+        if (d->n < 1 || d->m < 1) return fail(LDPCX_E_INVAL, "n and m must be positive");
+        if (!d->row_ptr || !d->col_idx) return fail(LDPCX_E_INVAL, "row_ptr/col_idx is NULL");
+        if (g > 2 && !d->h_val) return fail(LDPCX_E_INVAL, "h_val is required for g > 2");
+        const int n = d->n, m = d->m;
+        if (d->row_ptr[0] != 0) return fail(LDPCX_E_INVAL, "row_ptr[0] must be 0");
+        for (int i = 0; i < m; ++i)
+            if (d->row_ptr[i + 1] < d->row_ptr[i]) return fail(LDPCX_E_INVAL, "row_ptr must be non-decreasing");
+        const int E = d->row_ptr[m];
+        if (E < 2) return fail(LDPCX_E_INVAL, "too few nonzeros");
+        if ((long long)m >= (1LL << 27)) return fail(LDPCX_E_UNSUPPORTED, "too many checks");
+        const int dc_lim = g == 2 ? kBinDcMax : kNbDcMax;
+        int dc_max = 0;
+        for (int i = 0; i < m; ++i) {
+            const int dc = d->row_ptr[i + 1] - d->row_ptr[i];
+            if (dc < 2) return fail(LDPCX_E_INVAL, "every check needs degree >= 2");
+            if (dc > dc_lim) return fail(LDPCX_E_UNSUPPORTED, "check degree above the supported maximum");
+            dc_max = std::max(dc_max, dc);
+            for (int e = d->row_ptr[i]; e < d->row_ptr[i + 1]; ++e) {
+                const int col = d->col_idx[e];
+                if (col < 0 || col >= n) return fail(LDPCX_E_INVAL, "column index out of range");
+                if (e > d->row_ptr[i] && col <= d->col_idx[e - 1])
+                    return fail(LDPCX_E_INVAL, "columns must be strictly ascending within a row");
+                if (g > 2 && (d->h_val[e] == 0 || d->h_val[e] >= g))
+                    return fail(LDPCX_E_INVAL, "GF coefficient must be nonzero and < g");
+            }
+        }
+        ldpcx_code *c = new ldpcx_code();
+        c->desc = *d;
+        c->g = g;
+        c->row_ptr.assign(d->row_ptr, d->row_ptr + m + 1);
+        c->col_idx.assign(d->col_idx, d->col_idx + E);
+        if (g > 2) {
+            c->h.assign(d->h_val, d->h_val + E);
+            std::vector<uint8_t> inv;
+            if (!build_gf(g, d->prim_poly, c->gfmul, inv)) {
+                delete c;
+                return fail(LDPCX_E_INVAL, "prim_poly is not primitive for this field size");
+            }
+            c->hinv.resize(E);
+            for (int e = 0; e < E; ++e) c->hinv[e] = inv[c->h[e]];
+        }
+        // CSC: edges of each variable node, in ascending check order.
+        c->vn_ptr.assign(n + 1, 0);
+        for (int e = 0; e < E; ++e) c->vn_ptr[c->col_idx[e] + 1]++;
+        int dv_max = 0;
+        for (int v = 0; v < n; ++v) {
+            dv_max = std::max(dv_max, c->vn_ptr[v + 1]);
+            c->vn_ptr[v + 1] += c->vn_ptr[v];
+        }
+        if (g == 2 && dv_max > 250) {
+            delete c;
+            return fail(LDPCX_E_UNSUPPORTED, "variable degree above 250");
+        }
+        c->vn_ref.assign(E, 0);
+        {
+            std::vector<int> fill(n, 0);
+            for (int i = 0; i < m; ++i)
+                for (int e = c->row_ptr[i]; e < c->row_ptr[i + 1]; ++e) {
+                    const int v = c->col_idx[e];
+                    c->vn_ref[c->vn_ptr[v] + fill[v]++] = g == 2 ? ((i << 4) | (e - c->row_ptr[i])) : e;
+                }
+        }
+        // Layers: rows [l z, (l + 1) z) must touch disjoint columns.
+        c->layers_ok = false;
+        if (g == 2) {
+            const int z = d->z > 0 ? d->z : 1;
+            if (d->z < 0 || m % z != 0) {
+                delete c;
+                return fail(LDPCX_E_INVAL, "m must be a multiple of the layer size z");
+            }
+            std::vector<int> mark(n, -1);
+            bool ok = true;
+            for (int l = 0; l < m / z && ok; ++l)
+                for (int e = c->row_ptr[l * z]; e < c->row_ptr[(l + 1) * z] && ok; ++e) {
+                    if (mark[c->col_idx[e]] == l) ok = false;
+                    mark[c->col_idx[e]] = l;
+                }
+            if (!ok && d->z > 0) {
+                delete c;
+                return fail(LDPCX_E_INVAL, "rows of one layer share a column");
+            }
+            c->layers_ok = ok;
+        }
+        hipError_t e = hipGetDevice(&c->device);
+        if (e != hipSuccess) {
+            delete c;
+            return fail_hip(e, "hipGetDevice");
+        }
+        device_info(c->device);
+        // One device block for every array.
+        const size_t o_rp = 0;
+        const size_t o_ci = align_up(o_rp + 4 * (size_t)(m + 1), 256);
+        const size_t o_vp = align_up(o_ci + 4 * (size_t)E, 256);
+        const size_t o_vr = align_up(o_vp + 4 * (size_t)(n + 1), 256);
+        const size_t o_h = align_up(o_vr + 4 * (size_t)E, 256);
+        const size_t o_hi = align_up(o_h + (size_t)E, 256);
+        const size_t o_mul = align_up(o_hi + (size_t)E, 256);
+        const size_t total = align_up(o_mul + (size_t)g * g + 4, 256);
+        e = hipMalloc(&c->dmem, total);
+        if (e != hipSuccess) {
+            delete c;
+            return fail(LDPCX_E_NOMEM, "code upload");
+        }
+        std::vector<uint8_t> host(total, 0);
+        std::memcpy(host.data() + o_rp, c->row_ptr.data(), 4 * (size_t)(m + 1));
+        std::memcpy(host.data() + o_ci, c->col_idx.data(), 4 * (size_t)E);
+        std::memcpy(host.data() + o_vp, c->vn_ptr.data(), 4 * (size_t)(n + 1));
+        std::memcpy(host.data() + o_vr, c->vn_ref.data(), 4 * (size_t)E);
+        if (g > 2) {
+            std::memcpy(host.data() + o_h, c->h.data(), E);
+            std::memcpy(host.data() + o_hi, c->hinv.data(), E);
+            std::memcpy(host.data() + o_mul, c->gfmul.data(), (size_t)g * g);
+        }
+        e = hipMemcpy(c->dmem, host.data(), total, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(c->dmem);
+            delete c;
+            return fail_hip(e, "code upload");
+        }
+        char *b = (char *)c->dmem;
+        DevCode &D = c->dev;
+        D.n = n;
+        D.m = m;
+        D.E = E;
+        D.g = g;
+        D.p = 0;
+        while ((1 << D.p) < g) ++D.p;
+        D.z = g == 2 ? (d->z > 0 ? d->z : 1) : 0;
+        D.nlayers = g == 2 ? m / D.z : 0;
+        D.dc_max = dc_max;
+        D.dv_max = dv_max;
+        D.row_ptr = (const int *)(b + o_rp);
+        D.col_idx = (const int *)(b + o_ci);
+        D.vn_ptr = (const int *)(b + o_vp);
+        D.vn_ref = (const int *)(b + o_vr);
+        D.h = (const uint8_t *)(b + o_h);
+        D.hinv = (const uint8_t *)(b + o_hi);
+        D.gfmul = (const uint8_t *)(b + o_mul);
+        if (g > 2 && !nb_supported(g)) {
+            // Valid code, but no compiled Min-Max kernel for this field size.
+            c->nb_unsupported = true;
+        }
+        *out = c;
+        return LDPCX_OK;
+    } catch (const std::exception &ex) {
+        return fail(LDPCX_E_NOMEM, ex.what());
+    }
+}
+
+ldpcx_status ldpcx_code_destroy(ldpcx_code *c) {
+    if (!c) return LDPCX_OK;
+    (void)hipDeviceSynchronize();
+    if (c->dmem) (void)hipFree(c->dmem);
+    delete c;
+    return LDPCX_OK;
+}
+
+ldpcx_status ldpcx_code_info(const ldpcx_code *c, int32_t *n, int32_t *m, int32_t *nnz, int32_t *g, int32_t *max_dc,
+                             int32_t *max_dv) {
+    if (!c) return fail(LDPCX_E_INVAL, "code is NULL");
+    if (n) *n = c->dev.n;
+    if (m) *m = c->dev.m;
+    if (nnz) *nnz = c->dev.E;
+    if (g) *g = c->g;
+    if (max_dc) *max_dc = c->dev.dc_max;
+    if (max_dv) *max_dv = c->dev.dv_max;
+    return LDPCX_OK;
+}
+
+ldpcx_status ldpcx_decode(const ldpcx_code *code, const ldpcx_decode_params *params, int32_t batch, const void *llr,
+                          void *hard, uint8_t *syndrome_ok, int16_t *iters, int32_t *schedule_used, void *stream) {
+    try {
+        if (code && code->nb_unsupported) return fail(LDPCX_E_UNSUPPORTED, "no Min-Max kernel for this field size");
+        return decode_common(code, params, batch, llr, hard, syndrome_ok, iters, schedule_used, nullptr, nullptr,
+                             nullptr, stream);
+    } catch (const std::exception &ex) {
+        return fail(LDPCX_E_NOMEM, ex.what());
+    }
+}
+
+ldpcx_status ldpcx_debug_dump(const ldpcx_code *code, const ldpcx_decode_params *params, int32_t batch,
+                              const void *llr, void *hard, uint8_t *syndrome_ok, int16_t *iters, void *msg_a,
+                              void *msg_b, void *msg_c, void *stream) {
+    try {
+        if (!msg_a || !msg_b) return fail(LDPCX_E_INVAL, "dump buffers are NULL");
+        if (code && code->nb_unsupported) return fail(LDPCX_E_UNSUPPORTED, "no Min-Max kernel for this field size");
+        return decode_common(code, params, batch, llr, hard, syndrome_ok, iters, nullptr, msg_a, msg_b, msg_c, stream);
+    } catch (const std::exception &ex) {
+        return fail(LDPCX_E_NOMEM, ex.what());
+    }
+}
+
+ldpcx_status ldpcx_plan_info(const ldpcx_code *code, const ldpcx_decode_params *params, int32_t batch, int32_t *family,
+                             int32_t *cw_per_wg, int32_t *threads) {
+    if (!code) return fail(LDPCX_E_INVAL, "code is NULL");
+    ldpcx_code *c = const_cast<ldpcx_code *>(code);
+    ldpcx_status st = check_params(c, params);
+    if (st != LDPCX_OK) return st;
+    const Plan pl = plan_for(c, params, std::max(1, batch));
+    if (family) *family = pl.family;
+    if (cw_per_wg) *cw_per_wg = pl.cpw;
+    if (threads) *threads = pl.threads;
+    return LDPCX_OK;
+}
+
+ldpcx_status ldpcx_plan_set(ldpcx_code *c, const ldpcx_decode_params *params, int32_t batch, int32_t family,
+                            int32_t cw_per_wg, int32_t threads) {
+    if (!c) return fail(LDPCX_E_INVAL, "code is NULL");
+    ldpcx_status st = check_params(c, params);
+    if (st != LDPCX_OK) return st;
+    if (family < 0 || family > 2) return fail(LDPCX_E_INVAL, "unknown kernel family");
+    if ((c->g > 2) != (family == FAMILY_NB)) return fail(LDPCX_E_INVAL, "family does not match the field size");
+    Plan pl;
+    pl.family = family;
+    pl.schedule = params->schedule == LDPCX_SCHED_AUTO ? default_plan(c, params, std::max(1, batch)).schedule
+                                                        : params->schedule;
+    if (family != FAMILY_BIN_LDS && pl.schedule == LDPCX_SCHED_LAYERED)
+        return fail(LDPCX_E_UNSUPPORTED, "this kernel family runs the flooding schedule only");
+    if (family == FAMILY_BIN_LDS) {
+        if (cw_per_wg < 1 || cw_per_wg > 64) return fail(LDPCX_E_INVAL, "cw_per_wg out of range");
+        if (threads < 64 || threads > 1024 || threads % 64) return fail(LDPCX_E_INVAL, "threads out of range");
+        if (bin_lds_smem_bytes(c->dev, pl.schedule == LDPCX_SCHED_LAYERED, cw_per_wg) >
+            (size_t)device_info(c->device).lds_per_block)
+            return fail(LDPCX_E_UNSUPPORTED, "state of cw_per_wg codewords does not fit the LDS");
+        pl.cpw = cw_per_wg;
+        pl.threads = threads;
+    }
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->tuned[tune_key(params, std::max(1, batch))] = pl;
+    return LDPCX_OK;
+}
+
+}  // extern "C"

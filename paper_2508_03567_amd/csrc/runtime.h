@@ -1,0 +1,59 @@
+// Host-side structures shared by the runtime, the ragged engine, the autotuner
+// and the server.
+#pragma once
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ldpcx_internal.h"
+
+namespace ldpcx {
+
+enum { FAMILY_BIN_LDS = 0, FAMILY_BIN_IL = 1, FAMILY_NB = 2 };
+
+struct Plan {
+    int family = FAMILY_BIN_LDS;
+    int schedule = LDPCX_SCHED_FLOODING;
+    int cpw = 1;
+    int threads = 256;
+};
+
+struct DeviceInfo {
+    int cus = 256;
+    int lds_per_block = 64 * 1024;
+};
+
+}  // namespace ldpcx
+
+struct ldpcx_code {
+    ldpcx_code_desc desc{};
+    int g = 2;
+    int device = 0;
+    bool layers_ok = false;
+    bool nb_unsupported = false;
+    std::vector<int> row_ptr, col_idx, vn_ptr, vn_ref;
+    std::vector<uint8_t> h, hinv, gfmul;
+    void *dmem = nullptr;
+    ldpcx::DevCode dev{};
+    std::mutex mu;
+    std::map<uint64_t, ldpcx::Plan> tuned;
+};
+
+namespace ldpcx {
+
+extern thread_local std::string g_err;
+ldpcx_status fail(ldpcx_status st, const std::string &msg);
+ldpcx_status fail_hip(hipError_t e, const char *what);
+const DeviceInfo &device_info(int dev);
+ldpcx_status check_params(const ldpcx_code *c, const ldpcx_decode_params *p);
+ldpcx_status check_device(const ldpcx_code *c);
+BinRule bin_rule(const ldpcx_decode_params *p);
+Plan default_plan(const ldpcx_code *c, const ldpcx_decode_params *p, int batch);
+Plan plan_for(ldpcx_code *c, const ldpcx_decode_params *p, int batch);
+uint64_t tune_key(const ldpcx_decode_params *p, int batch);
+ldpcx_status run_plan(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &pl, int batch, const DecodeIO &io,
+                      hipStream_t s);
+
+}  // namespace ldpcx

@@ -1,0 +1,253 @@
+"""GPU parity: the HIP decoders against the CPU oracle, bit-exact.
+
+Decisions, syndrome flags, iteration counts and every message of the final
+state (q, r, Lambda for binary codes; alpha, beta for Min-Max) must equal the
+oracle's on the same seeded inputs.  Small batches span several workgroups and
+a ragged tail; the full-size workloads are checked on sampled codewords in the
+launch configuration the benchmark uses.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2508_03567_amd import ldpcx as L
+from paper_2508_03567_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def _prm(w, **kw):
+    d = dict(rule=w.rule, schedule=w.schedule, max_iters=w.max_iters, early_stop=True,
+             nms_num=w.nms_num, nms_shift=w.nms_shift, oms_offset=w.oms_offset, msg_max=w.msg_max)
+    d.update(kw)
+    return d
+
+
+def _gpu(code_h, d, llr, dump=False):
+    prm = L.params(**d)
+    x = torch.from_numpy(np.ascontiguousarray(llr)).to(DEV)
+    if dump:
+        out = L.debug_dump(code_h, prm, x)
+    else:
+        out = L.decode(code_h, prm, x)[:3]
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() if o is not None else None for o in out]
+
+
+def _check_decisions(code, g_out, ref, idx=None):
+    hard, ok, it = g_out[:3]
+    if code.g == 2:
+        hard = L.unpack_bits(hard, code.n)
+    sel = slice(None) if idx is None else idx
+    assert (hard[sel] == ref["hard"]).all(), "decisions differ"
+    assert (ok[sel] == ref["ok"]).all(), "syndrome flags differ"
+    assert (it[sel] == ref["iters"]).all(), "iteration counts differ"
+
+
+def _ref(code, d, llr, dump=False):
+    prm = O.params(**d)
+    return (O.decode_binary if code.g == 2 else O.decode_nb)(code, prm, llr, dump=dump)
+
+
+_CODES = {}
+
+
+def _handle(code):
+    key = id(code)
+    if key not in _CODES:
+        _CODES[key] = L.Code(code)
+    return _CODES[key]
+
+
+@pytest.mark.parametrize("cfg,batch", [(0, 1), (0, 130), (1, 7), (1, 70), (2, 3), (3, 1), (3, 67)])
+@pytest.mark.parametrize("early", [True, False])
+def test_decode_matches_oracle(cfg, batch, early):
+    w = S.workload(cfg, batch=batch)
+    cw, llr = S.make_inputs(w, seed_offset=17)
+    d = _prm(w, early_stop=early, max_iters=min(w.max_iters, 12))
+    h = _handle(w.code)
+    _check_decisions(w.code, _gpu(h, d, llr), _ref(w.code, d, llr))
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("iters", [0, 1, 2, 5])
+def test_every_message_matches_oracle(cfg, iters):
+    batch = {0: 66, 1: 9, 2: 2, 3: 65}[cfg]
+    w = S.workload(cfg, batch=batch)
+    cw, llr = S.make_inputs(w, seed_offset=3)
+    d = _prm(w, max_iters=iters, early_stop=False)
+    h = _handle(w.code)
+    g = _gpu(h, d, llr, dump=True)
+    ref = _ref(w.code, d, llr, dump=True)
+    _check_decisions(w.code, g, ref)
+    if w.code.g == 2:
+        assert (g[3].astype(np.int32) == ref["q"]).all(), "q messages differ"
+        assert (g[4].astype(np.int32) == ref["r"]).all(), "r messages differ"
+        assert (g[5].astype(np.int32) == ref["lam"]).all(), "Lambda differs"
+    else:
+        assert (g[3].astype(np.int32) == ref["alpha"]).all(), "alpha messages differ"
+        assert (g[4].astype(np.int32) == ref["beta"]).all(), "beta messages differ"
+
+
+@pytest.mark.parametrize("family,cpw,threads", [("bin_lds", 1, 64), ("bin_lds", 3, 192), ("bin_lds", 5, 320),
+                                                ("bin_interleaved", 64, 256)])
+@pytest.mark.parametrize("rule", ["nms", "oms", "ms"])
+def test_families_agree_on_flooding(family, cpw, threads, rule):
+    w = S.workload(0, batch=77)
+    cw, llr = S.make_inputs(w, seed_offset=5)
+    d = _prm(w, rule=rule, max_iters=6, early_stop=True)
+    code = L.Code(w.code)
+    L.plan_set(code, L.params(**d), 77, family, cpw, threads)
+    assert L.plan_info(code, L.params(**d), 77)["family"] == family
+    g = _gpu(code, d, llr, dump=True)
+    ref = _ref(w.code, d, llr, dump=True)
+    _check_decisions(w.code, g, ref)
+    assert (g[4].astype(np.int32) == ref["r"]).all()
+    assert (g[5].astype(np.int32) == ref["lam"]).all()
+
+
+@pytest.mark.parametrize("cpw,threads", [(1, 64), (1, 128), (2, 192), (4, 256), (8, 768)])
+def test_layered_launch_shapes(cpw, threads):
+    w = S.workload(1, batch=21)
+    cw, llr = S.make_inputs(w, seed_offset=9)
+    d = _prm(w, max_iters=4)
+    code = L.Code(w.code)
+    L.plan_set(code, L.params(**d), 21, "bin_lds", cpw, threads)
+    g = _gpu(code, d, llr, dump=True)
+    ref = _ref(w.code, d, llr, dump=True)
+    _check_decisions(w.code, g, ref)
+    assert (g[4].astype(np.int32) == ref["r"]).all()
+
+
+def _random_binary_code(n, m, dmin, dmax, seed, z=0):
+    rng = np.random.default_rng(seed)
+    rows, cols = [], []
+    for i in range(m):
+        d = int(rng.integers(dmin, dmax + 1))
+        c = rng.choice(n, size=d, replace=False)
+        rows += [i] * d
+        cols += list(c)
+    return S.code_from_pairs("rand", 2, 3, n, m, rows, cols, z=z)
+
+
+@pytest.mark.parametrize("seed,dmin,dmax", [(1, 2, 4), (2, 5, 14), (3, 2, 14)])
+@pytest.mark.parametrize("schedule", ["flooding", "layered"])
+def test_irregular_random_codes(seed, dmin, dmax, schedule):
+    code = _random_binary_code(150, 60, dmin, dmax, seed)
+    cws = np.zeros((45, 150), dtype=np.uint8)
+    llr = S.binary_llr_int8(cws, 1.0, seed=seed)
+    d = dict(rule="oms", schedule=schedule, max_iters=7, early_stop=True)
+    h = L.Code(code)
+    g = _gpu(h, d, llr, dump=True)
+    ref = _ref(code, d, llr, dump=True)
+    _check_decisions(code, g, ref)
+    assert (g[4].astype(np.int32) == ref["r"]).all()
+    assert (g[5].astype(np.int32) == ref["lam"]).all()
+
+
+@pytest.mark.parametrize("kind", ["zeros", "maxpos", "maxneg", "alternating", "ties"])
+def test_adversarial_binary_inputs(kind):
+    w = S.workload(0, batch=64)
+    n = w.code.n
+    if kind == "zeros":
+        llr = np.zeros((64, n), dtype=np.int8)
+    elif kind == "maxpos":
+        llr = np.full((64, n), 127, dtype=np.int8)
+    elif kind == "maxneg":
+        llr = np.full((64, n), -128, dtype=np.int8)
+    elif kind == "alternating":
+        llr = np.tile(np.array([127, -128], dtype=np.int8), (64, n // 2))
+    else:
+        llr = np.random.default_rng(0).choice(np.array([-1, 0, 1], dtype=np.int8), size=(64, n))
+    for rule, sched in [("nms", "flooding"), ("oms", "flooding"), ("ms", "layered")]:
+        code = w.code if sched == "flooding" else S.workload(0).code
+        d = dict(rule=rule, schedule=sched, max_iters=5, early_stop=True, msg_max=100)
+        g = _gpu(_handle(code), d, llr, dump=True)
+        ref = _ref(code, d, llr, dump=True)
+        _check_decisions(code, g, ref)
+        assert (g[3].astype(np.int32) == ref["q"]).all()
+
+
+@pytest.mark.parametrize("g_size", [4, 8, 16, 32, 64])
+def test_minmax_field_sizes(g_size):
+    code = S.random_regular_nb_code(24, 12, 2, 4, g_size, S.PRIM_POLY[g_size], seed=g_size)
+    cw = S.random_codewords(code, 70, seed=1)
+    gam = S.nb_gamma_int16(cw, g_size, 1.5, seed=2)
+    d = dict(rule="minmax", schedule="flooding", max_iters=6, early_stop=True)
+    g = _gpu(L.Code(code), d, gam, dump=True)
+    ref = _ref(code, d, gam, dump=True)
+    _check_decisions(code, g, ref)
+    assert (g[3].astype(np.int32) == ref["alpha"]).all()
+    assert (g[4].astype(np.int32) == ref["beta"]).all()
+
+
+@pytest.mark.parametrize("dc", [2, 3, 5, 8])
+def test_minmax_check_degrees(dc):
+    n, dv = 6 * dc, 2
+    m = n * dv // dc
+    code = S.random_regular_nb_code(n, m, dv, dc, 16, 0x13, seed=dc)
+    cw = S.random_codewords(code, 33, seed=3)
+    gam = S.nb_gamma_int16(cw, 16, 1.0, seed=4)
+    d = dict(rule="minmax", schedule="flooding", max_iters=4, early_stop=False)
+    g = _gpu(L.Code(code), d, gam, dump=True)
+    ref = _ref(code, d, gam, dump=True)
+    _check_decisions(code, g, ref)
+    assert (g[4].astype(np.int32) == ref["beta"]).all()
+
+
+def test_eq1_code_exhaustive_noise():
+    code = S.eq1_code()
+    rng = np.random.default_rng(8)
+    gam = rng.integers(0, 40, size=(200, 6, 4)).astype(np.int16)
+    gam -= gam.min(axis=2, keepdims=True)
+    d = dict(rule="minmax", schedule="flooding", max_iters=8, early_stop=True)
+    g = _gpu(L.Code(code), d, gam, dump=True)
+    ref = _ref(code, d, gam, dump=True)
+    _check_decisions(code, g, ref)
+    assert (g[4].astype(np.int32) == ref["beta"]).all()
+
+
+def test_minmax_large_and_tied_values():
+    w = S.workload(3, batch=64)
+    rng = np.random.default_rng(2)
+    gam = rng.choice(np.array([0, 5, 5000, 32767], dtype=np.int16), size=(64, 192, 64))
+    gam[:, :, 0] = 0
+    d = _prm(w, max_iters=3, early_stop=False)
+    g = _gpu(_handle(w.code), d, gam, dump=True)
+    ref = _ref(w.code, d, gam, dump=True)
+    _check_decisions(w.code, g, ref)
+    assert (g[3].astype(np.int32) == ref["alpha"]).all()
+    assert (g[4].astype(np.int32) == ref["beta"]).all()
+
+
+def test_zero_batch_is_noop_and_bad_args_rejected():
+    w = S.workload(0, batch=4)
+    h = _handle(w.code)
+    prm = L.params("nms")
+    L.ldpcx_decode(h.handle, prm, 0, 0, 0, 0, 0, 0)
+    with pytest.raises(L.LdpcxError):
+        L.ldpcx_decode(h.handle, L.params("minmax"), 4, 1, 1, 1, 1, 0)
+    with pytest.raises(L.LdpcxError):
+        L.ldpcx_decode(h.handle, L.params("nms", msg_max=200), 4, 1, 1, 1, 1, 0)
+
+
+# ------------------------------------------------------- full-size workloads
+@pytest.mark.parametrize("cfg,sample", [(0, 64), (1, 48), (2, 6), (3, 24)])
+def test_full_size_sampled(cfg, sample):
+    w = S.workload(cfg)
+    cw, llr = S.make_inputs(w)
+    d = _prm(w, early_stop=False)
+    h = _handle(w.code)
+    g = _gpu(h, d, llr)
+    rng = np.random.default_rng(cfg)
+    idx = np.sort(rng.choice(w.batch, size=sample, replace=False))
+    idx[-1] = w.batch - 1  # the ragged tail
+    ref = _ref(w.code, d, llr[idx])
+    _check_decisions(w.code, g, ref, idx)
+    # early-stop mode on the same sample
+    d2 = _prm(w, early_stop=True)
+    g2 = _gpu(h, d2, llr)
+    _check_decisions(w.code, g2, _ref(w.code, d2, llr[idx]), idx)
