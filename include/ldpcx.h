@@ -92,8 +92,9 @@ typedef struct {
  *   msg_max     binary variable-to-check message saturation, 1..127 (default 127).
  * Binary arithmetic: channel LLRs L are int8, positive favours bit 0.  Check-to-
  * variable message r_mn = prod_{n' != n} sgn(q_mn') * f(min_{n' != n} |q_mn'|),
- * sgn(0) = +1; a posteriori Lambda_n = L_n + sum_m r_mn (exact, 16 bit); variable-
- * to-check q_mn = clamp(Lambda_n - r_mn, +-msg_max); decision c_n = [Lambda_n < 0].
+ * sgn(0) = +1; a posteriori Lambda_n = L_n + sum_m r_mn (exact, 16 bit, in both
+ * schedules: the layered update is Lambda_n <- Lambda_n - r_old + r_new); the check
+ * node sees q_mn = clamp(Lambda_n - r_mn, +-msg_max); decision c_n = [Lambda_n < 0].
  * Min-Max arithmetic (eqs. (7)-(15)): messages int16, sums in 32 bit, alpha clamped
  * to 32767; decision = lowest x minimising gamma_n(x) + sum_m beta_mn(x). */
 typedef struct {

@@ -23,7 +23,10 @@
  *     magnitudes, found by a naive loop over the other edges (no min1/min2
  *     compression).  Normalisation: NMS (num * m) >> shift, OMS max(m - off, 0),
  *     MS m.  Flooding follows the two-phase schedule of Alg. 2; layered
- *     processes rows one at a time in ascending order.
+ *     processes rows one at a time in ascending order.  In both schedules the
+ *     check node sees the variable-to-check message saturated to +-msg_max,
+ *     while the a posteriori sum Lambda = L + sum_m r_mn is kept exact (a
+ *     reading: the paper does not define binary min-sum or its saturation).
  *   - Iteration semantics follow Alg. 2: iteration k first tests the syndrome
  *     of the decision of iteration k-1 and stops when it is zero (early stop),
  *     so a codeword whose channel decision already satisfies H is reported
@@ -161,11 +164,15 @@ static void bin_decode_one(const bin_code *C, const orc_params *P, const int8_t 
             for (int v = 0; v < n; v++) lam[v] = L[v];
             for (int e = 0; e < E; e++) lam[C->col_idx[e]] += r[e];
         } else {
+            /* Row-by-row: the check sees the saturated message clamp(Lambda - r_old); the
+             * a posteriori value is updated exactly, Lambda <- Lambda - r_old + r_new, so
+             * that Lambda = L + sum of the current check messages at every step. */
             for (int i = 0; i < m; i++) {
                 int b = C->row_ptr[i], dc = C->row_ptr[i + 1] - b;
                 for (int e = b; e < b + dc; e++) q[e] = clampi(lam[C->col_idx[e]] - r[e], -mm, mm);
+                for (int e = b; e < b + dc; e++) lam[C->col_idx[e]] -= r[e];
                 orc_binary_cn(dc, q + b, r + b, P);
-                for (int e = b; e < b + dc; e++) lam[C->col_idx[e]] = q[e] + r[e];
+                for (int e = b; e < b + dc; e++) lam[C->col_idx[e]] += r[e];
             }
         }
         bin_decide(n, lam, hard);

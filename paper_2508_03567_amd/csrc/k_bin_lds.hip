@@ -44,8 +44,10 @@ __device__ __forceinline__ Unpacked unpack(const BinRule &R, uint32_t s) {
 }
 
 // Process one check row: read Lambda of its variables and the row's previous
-// state, form q = clamp(Lambda - r_old), compute the new state; in layered mode
-// also write Lambda = q + r_new back.  Returns the new packed state.
+// state, form q = Lambda - r_old, compute the new state from the saturated
+// messages clamp(q, +-msg_max); in layered mode also write Lambda = q + r_new
+// back (exact, so Lambda stays L + sum of the current check messages).
+// Returns the new packed state.
 template <bool WRITE_LAM>
 __device__ __forceinline__ uint32_t row_update(const DevCode &C, const BinRule &R, int row,
                                                int16_t *__restrict__ lam, uint32_t st_old) {
@@ -63,8 +65,9 @@ __device__ __forceinline__ uint32_t row_update(const DevCode &C, const BinRule &
         if (j < dc) {
             const int vv = cols[j];
             v[j] = vv;
-            const int qq = clampi((int)lam[vv] - bin_r(j, o.fm1, o.fm2, o.idx, o.signs, o.parity), -mm, mm);
-            q[j] = qq;
+            const int qraw = (int)lam[vv] - bin_r(j, o.fm1, o.fm2, o.idx, o.signs, o.parity);
+            q[j] = qraw;
+            const int qq = clampi(qraw, -mm, mm);
             const int a = qq < 0 ? -qq : qq;
             sg |= (uint32_t)(qq < 0) << j;
             if (a < m1) {

@@ -367,3 +367,18 @@ def test_fer_falls_with_snr_layered_oms():
         if eb >= 2.0:
             assert (out["hard"] != cw).mean() < ((llr < 0) != cw).mean()
     assert fer[0] >= fer[1] >= fer[2]
+
+
+@pytest.mark.parametrize("cfg,sched", [(0, "flooding"), (0, "layered"), (1, "layered"), (1, "flooding")])
+def test_app_is_channel_plus_check_messages(cfg, sched):
+    """Lambda_n = L_n + sum_m r_mn holds exactly after any number of iterations in
+    both schedules (saturation applies to what the check node sees, not to Lambda)."""
+    w = S.workload(cfg, batch=16)
+    cw, llr = S.make_inputs(w)
+    for iters in [1, 3, 25]:
+        out = O.decode_binary(w.code, O.params(w.rule, sched, iters, False), llr, dump=True)
+        lam = llr.astype(np.int64).copy()
+        for e, v in enumerate(w.code.col_idx):
+            lam[:, v] += out["r"][:, e]
+        assert (lam == out["lam"]).all()
+        assert (out["q"] == np.clip(out["lam"][:, w.code.col_idx] - out["r"], -127, 127)).all()
