@@ -179,7 +179,9 @@ ldpcx_status ldpcx_tune(const ldpcx_code *code, const ldpcx_decode_params *param
 
 /* Launch configuration that the next decode of (code, params, batch) would use:
  * kernel family (0 = LDS-resident binary, 1 = interleaved binary, 2 = interleaved
- * min-max), codewords per workgroup, threads per workgroup. */
+ * min-max, 3 = packed two-codewords-per-lane binary for quasi-cyclic codes, available
+ * when every layer of z rows consists of z x z circulant blocks, at most 16 layers and
+ * 8 blocks per layer), codewords per workgroup, threads per workgroup. */
 ldpcx_status ldpcx_plan_info(const ldpcx_code *code, const ldpcx_decode_params *params,
                              int32_t batch, int32_t *family, int32_t *cw_per_wg,
                              int32_t *threads);

@@ -70,6 +70,22 @@ hipError_t launch_bin_lds(const DevCode &C, const BinRule &R, int max_iters, int
                           hipStream_t s);
 size_t bin_lds_smem_bytes(const DevCode &C, int layered, int cpw);
 
+// Quasi-cyclic description: layer l has dc[l] circulant blocks (column block col, shift sh).
+constexpr int kQcMaxL = 16, kQcMaxDc = 8;
+struct QcDesc {
+    int Z, nl;
+    int dc[kQcMaxL];
+    short col[kQcMaxL][kQcMaxDc];
+    short sh[kQcMaxL][kQcMaxDc];
+    const int2 *edges;  // device copy: edges[l * kQcMaxDc + j] = {col * Z, sh}
+};
+
+// Packed two-codewords-per-lane decoder for QC codes: a workgroup of Z * npairs threads
+// decodes 2 * npairs codewords, messages in registers, Lambda in LDS.
+hipError_t launch_bin_qc(const QcDesc &Q, const DevCode &C, const BinRule &R, int max_iters, int early_stop,
+                         int layered, int batch, int npairs, const DecodeIO &io, hipStream_t s);
+size_t bin_qc_smem_bytes(const QcDesc &Q, const DevCode &C, int layered, int npairs);
+
 // Interleaved (codeword-per-lane) binary flooding decoder, state in device memory.
 struct BinIlWork {
     int8_t *L;        // [n][Bp]

@@ -118,6 +118,17 @@ Plan default_plan(const ldpcx_code *c, const ldpcx_decode_params *p, int batch) 
     int sched = p->schedule;
     if (sched == LDPCX_SCHED_AUTO) sched = (c->desc.z > 0 && c->layers_ok) ? LDPCX_SCHED_LAYERED : LDPCX_SCHED_FLOODING;
     pl.schedule = sched;
+    if (c->qc_ok) {
+        pl.family = FAMILY_BIN_QC;
+        const int Z = c->qc.Z;
+        const int pairs = (batch + 1) / 2;
+        int np = std::max(1, std::min(512 / Z, 256 / Z));
+        while (np > 1 && (pairs + np - 1) / np < 2 * di.cus) --np;
+        while (np > 1 && bin_qc_smem_bytes(c->qc, c->dev, sched == LDPCX_SCHED_LAYERED, np) > (size_t)di.lds_per_block) --np;
+        pl.cpw = 2 * np;
+        pl.threads = Z * np;
+        return pl;
+    }
     const size_t per_cw = bin_lds_smem_bytes(c->dev, sched == LDPCX_SCHED_LAYERED, 1);
     if (per_cw <= (size_t)64 * 1024 || (sched == LDPCX_SCHED_LAYERED && per_cw <= (size_t)di.lds_per_block)) {
         pl.family = FAMILY_BIN_LDS;
@@ -160,6 +171,16 @@ uint64_t tune_key(const ldpcx_decode_params *p, int batch) {
 ldpcx_status run_plan(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &pl, int batch, const DecodeIO &io,
                       hipStream_t s) {
     hipError_t e = hipSuccess;
+    if (pl.family == FAMILY_BIN_QC) {
+        if (!c->qc_ok) return fail(LDPCX_E_UNSUPPORTED, "code has no quasi-cyclic description");
+        const int np = pl.cpw / 2;
+        if (bin_qc_smem_bytes(c->qc, c->dev, pl.schedule == LDPCX_SCHED_LAYERED, np) > (size_t)device_info(c->device).lds_per_block)
+            return fail(LDPCX_E_UNSUPPORTED, "pair state does not fit the LDS of one workgroup");
+        e = launch_bin_qc(c->qc, c->dev, bin_rule(p), p->max_iters, p->early_stop, pl.schedule == LDPCX_SCHED_LAYERED,
+                          batch, np, io, s);
+        if (e != hipSuccess) return fail_hip(e, "QC decoder launch");
+        return LDPCX_OK;
+    }
     if (pl.family == FAMILY_BIN_LDS) {
         const size_t smem = bin_lds_smem_bytes(c->dev, pl.schedule == LDPCX_SCHED_LAYERED, pl.cpw);
         if (smem > (size_t)device_info(c->device).lds_per_block)
@@ -323,6 +344,33 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
                 return fail(LDPCX_E_INVAL, "rows of one layer share a column");
             }
             c->layers_ok = ok;
+            // Quasi-cyclic structure: every layer of z rows made of z x z circulant blocks.
+            if (ok && d->z > 0 && n % d->z == 0 && m / d->z <= kQcMaxL) {
+                const int Z = d->z, nl = m / Z;
+                bool qc = true;
+                c->qc.Z = Z;
+                c->qc.nl = nl;
+                for (int l = 0; l < nl && qc; ++l) {
+                    const int r0 = l * Z;
+                    const int dcl = c->row_ptr[r0 + 1] - c->row_ptr[r0];
+                    if (dcl > kQcMaxDc) { qc = false; break; }
+                    c->qc.dc[l] = dcl;
+                    for (int j = 0; j < dcl; ++j) {
+                        const int col = c->col_idx[c->row_ptr[r0] + j];
+                        c->qc.col[l][j] = (short)(col / Z);
+                        c->qc.sh[l][j] = (short)(col % Z);
+                    }
+                    for (int i = 0; i < Z && qc; ++i) {
+                        const int r = r0 + i;
+                        if (c->row_ptr[r + 1] - c->row_ptr[r] != dcl) { qc = false; break; }
+                        for (int j = 0; j < dcl; ++j) {
+                            const int want = c->qc.col[l][j] * Z + (i + c->qc.sh[l][j]) % Z;
+                            if (c->col_idx[c->row_ptr[r] + j] != want) { qc = false; break; }
+                        }
+                    }
+                }
+                c->qc_ok = qc;
+            }
         }
         hipError_t e = hipGetDevice(&c->device);
         if (e != hipSuccess) {
@@ -338,7 +386,8 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
         const size_t o_h = align_up(o_vr + 4 * (size_t)E, 256);
         const size_t o_hi = align_up(o_h + (size_t)E, 256);
         const size_t o_mul = align_up(o_hi + (size_t)E, 256);
-        const size_t total = align_up(o_mul + (size_t)g * g + 4, 256);
+        const size_t o_qc = align_up(o_mul + (size_t)g * g + 4, 256);
+        const size_t total = align_up(o_qc + sizeof(int2) * kQcMaxL * kQcMaxDc, 256);
         e = hipMalloc(&c->dmem, total);
         if (e != hipSuccess) {
             delete c;
@@ -353,6 +402,12 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
             std::memcpy(host.data() + o_h, c->h.data(), E);
             std::memcpy(host.data() + o_hi, c->hinv.data(), E);
             std::memcpy(host.data() + o_mul, c->gfmul.data(), (size_t)g * g);
+        }
+        if (c->qc_ok) {
+            int2 *qe = (int2 *)(host.data() + o_qc);
+            for (int l = 0; l < c->qc.nl; ++l)
+                for (int j = 0; j < c->qc.dc[l]; ++j)
+                    qe[l * kQcMaxDc + j] = make_int2(c->qc.col[l][j] * c->qc.Z, c->qc.sh[l][j]);
         }
         e = hipMemcpy(c->dmem, host.data(), total, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
@@ -379,6 +434,7 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
         D.h = (const uint8_t *)(b + o_h);
         D.hinv = (const uint8_t *)(b + o_hi);
         D.gfmul = (const uint8_t *)(b + o_mul);
+        c->qc.edges = (const int2 *)(b + o_qc);
         if (g > 2 && !nb_supported(g)) {
             // Valid code, but no compiled Min-Max kernel for this field size.
             c->nb_unsupported = true;
@@ -451,14 +507,24 @@ ldpcx_status ldpcx_plan_set(ldpcx_code *c, const ldpcx_decode_params *params, in
     if (!c) return fail(LDPCX_E_INVAL, "code is NULL");
     ldpcx_status st = check_params(c, params);
     if (st != LDPCX_OK) return st;
-    if (family < 0 || family > 2) return fail(LDPCX_E_INVAL, "unknown kernel family");
+    if (family < 0 || family > 3) return fail(LDPCX_E_INVAL, "unknown kernel family");
+    if (family == FAMILY_BIN_QC && !c->qc_ok) return fail(LDPCX_E_UNSUPPORTED, "code has no quasi-cyclic description");
     if ((c->g > 2) != (family == FAMILY_NB)) return fail(LDPCX_E_INVAL, "family does not match the field size");
     Plan pl;
     pl.family = family;
     pl.schedule = params->schedule == LDPCX_SCHED_AUTO ? default_plan(c, params, std::max(1, batch)).schedule
                                                         : params->schedule;
-    if (family != FAMILY_BIN_LDS && pl.schedule == LDPCX_SCHED_LAYERED)
+    if (family != FAMILY_BIN_LDS && family != FAMILY_BIN_QC && pl.schedule == LDPCX_SCHED_LAYERED)
         return fail(LDPCX_E_UNSUPPORTED, "this kernel family runs the flooding schedule only");
+    if (family == FAMILY_BIN_QC) {
+        if (cw_per_wg < 2 || cw_per_wg % 2 || c->qc.Z * cw_per_wg / 2 > 512)
+            return fail(LDPCX_E_INVAL, "cw_per_wg must be even with Z * cw_per_wg / 2 <= 512");
+        if (bin_qc_smem_bytes(c->qc, c->dev, pl.schedule == LDPCX_SCHED_LAYERED, cw_per_wg / 2) >
+            (size_t)device_info(c->device).lds_per_block)
+            return fail(LDPCX_E_UNSUPPORTED, "state of cw_per_wg codewords does not fit the LDS");
+        pl.cpw = cw_per_wg;
+        pl.threads = c->qc.Z * cw_per_wg / 2;
+    }
     if (family == FAMILY_BIN_LDS) {
         if (cw_per_wg < 1 || cw_per_wg > 64) return fail(LDPCX_E_INVAL, "cw_per_wg out of range");
         if (threads < 64 || threads > 1024 || threads % 64) return fail(LDPCX_E_INVAL, "threads out of range");

@@ -11,7 +11,7 @@
 
 namespace ldpcx {
 
-enum { FAMILY_BIN_LDS = 0, FAMILY_BIN_IL = 1, FAMILY_NB = 2 };
+enum { FAMILY_BIN_LDS = 0, FAMILY_BIN_IL = 1, FAMILY_NB = 2, FAMILY_BIN_QC = 3 };
 
 struct Plan {
     int family = FAMILY_BIN_LDS;
@@ -33,6 +33,8 @@ struct ldpcx_code {
     int device = 0;
     bool layers_ok = false;
     bool nb_unsupported = false;
+    bool qc_ok = false;
+    ldpcx::QcDesc qc{};
     std::vector<int> row_ptr, col_idx, vn_ptr, vn_ref;
     std::vector<uint8_t> h, hinv, gfmul;
     void *dmem = nullptr;

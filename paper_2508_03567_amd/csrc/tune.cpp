@@ -28,6 +28,19 @@ std::vector<Plan> candidates(const ldpcx_code *c, const ldpcx_decode_params *p, 
     const DeviceInfo &di = device_info(c->device);
     for (int sched : scheds) {
         const bool lay = sched == LDPCX_SCHED_LAYERED;
+        if (c->qc_ok) {
+            for (int np : {1, 2, 3, 4, 6, 8, 12, 16}) {
+                if (c->qc.Z * np > 512) break;
+                if (bin_qc_smem_bytes(c->qc, c->dev, lay, np) > (size_t)di.lds_per_block) break;
+                if (np > 1 && ((batch + 1) / 2 + np - 1) / np < di.cus / 2) break;
+                Plan pl;
+                pl.family = FAMILY_BIN_QC;
+                pl.schedule = sched;
+                pl.cpw = 2 * np;
+                pl.threads = c->qc.Z * np;
+                out.push_back(pl);
+            }
+        }
         const size_t per_cw = bin_lds_smem_bytes(c->dev, lay, 1);
         if (per_cw <= (size_t)di.lds_per_block) {
             for (int cpw : {1, 2, 3, 4, 6, 8, 12, 16}) {

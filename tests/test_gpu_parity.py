@@ -251,3 +251,39 @@ def test_full_size_sampled(cfg, sample):
     d2 = _prm(w, early_stop=True)
     g2 = _gpu(h, d2, llr)
     _check_decisions(w.code, g2, _ref(w.code, d2, llr[idx]), idx)
+
+
+@pytest.mark.parametrize("cfg,schedule", [(0, "flooding"), (0, "layered"), (1, "layered"), (1, "flooding")])
+@pytest.mark.parametrize("cw_per_wg", [2, 4, 6])
+@pytest.mark.parametrize("early", [True, False])
+def test_qc_packed_family(cfg, schedule, cw_per_wg, early):
+    w = S.workload(cfg, batch=29)
+    cw, llr = S.make_inputs(w, seed_offset=11)
+    d = _prm(w, schedule=schedule, max_iters=7, early_stop=early)
+    code = L.Code(w.code)
+    if cfg == 1 and cw_per_wg == 6:
+        cw_per_wg = 4  # Z * pairs must stay <= 512
+    L.plan_set(code, L.params(**d), 29, "bin_qc_packed", cw_per_wg)
+    assert L.plan_info(code, L.params(**d), 29)["family"] == "bin_qc_packed"
+    g = _gpu(code, d, llr, dump=True)
+    ref = _ref(w.code, d, llr, dump=True)
+    _check_decisions(w.code, g, ref)
+    assert (g[3].astype(np.int32) == ref["q"]).all()
+    assert (g[4].astype(np.int32) == ref["r"]).all()
+    assert (g[5].astype(np.int32) == ref["lam"]).all()
+
+
+@pytest.mark.parametrize("rule", ["nms", "oms", "ms"])
+def test_qc_packed_rules_and_saturation(rule):
+    w = S.workload(1, batch=40)
+    cw, llr = S.make_inputs(w, seed_offset=2)
+    llr = (llr.astype(np.int16) * 4).clip(-128, 127).astype(np.int8)  # exercise saturation
+    for mm in [127, 40]:
+        d = _prm(w, rule=rule, max_iters=9, early_stop=False, msg_max=mm)
+        code = L.Code(w.code)
+        L.plan_set(code, L.params(**d), 40, "bin_qc_packed", 4)
+        g = _gpu(code, d, llr, dump=True)
+        ref = _ref(w.code, d, llr, dump=True)
+        _check_decisions(w.code, g, ref)
+        assert (g[4].astype(np.int32) == ref["r"]).all()
+        assert (g[5].astype(np.int32) == ref["lam"]).all()
