@@ -1,0 +1,302 @@
+// Packed two-codewords-per-lane min-sum decoder for quasi-cyclic codes, as a
+// workgroup-level device function (see k_bin_qc.hip for the design).
+#pragma once
+
+#include "dev_common.h"
+
+namespace ldpcx {
+namespace dev {
+
+struct PkNorm {
+    v2s num, shift, off;
+};
+
+__device__ __forceinline__ PkNorm pk_norm_params(const BinRule &R) {
+    PkNorm P;
+    const bool nms = R.rule == LDPCX_RULE_NMS, oms = R.rule == LDPCX_RULE_OMS;
+    P.num = splat(nms ? R.nms_num : 1);
+    P.shift = splat(nms ? R.nms_shift : 0);
+    P.off = splat(oms ? R.oms_offset : 0);
+    return P;
+}
+
+__device__ __forceinline__ v2s pk_norm(const PkNorm &P, v2s m) {
+    return pmax(((m * P.num) >> P.shift) - P.off, splat(0));
+}
+
+// Byte offset of the Lambda word of an edge {4 c Z, 4 s} for row i (given as 4 i):
+// 4 (c Z + (i + s) mod Z), with the wrap done as an unsigned minimum (i + s < 2Z
+// since s < Z).  Virtual edges carry {4 n, 0} and map row i to its dummy slot n + i.
+__device__ __forceinline__ uint32_t qc_off(int2 e, uint32_t i4, uint32_t Z4) {
+    const uint32_t x = i4 + (uint32_t)e.y;
+    return (uint32_t)e.x + min(x, x - Z4);
+}
+
+__device__ __forceinline__ uint32_t &lds_word(uint32_t *base, uint32_t off) {
+    return *(uint32_t *)((char *)base + off);
+}
+
+// (M & a) | (~M & b) in one v_bfi_b32.
+__device__ __forceinline__ uint32_t bfi(uint32_t M, uint32_t a, uint32_t b) {
+    uint32_t d;
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(d) : "v"(M), "v"(a), "v"(b));
+    return d;
+}
+
+// Dummy slot contents for virtual edges: +16383 in both halves.  Minus any check
+// message (|r| <= 127) it stays positive and above msg_max, so a virtual edge
+// always enters its check with magnitude msg_max and sign +, which never changes
+// the two smallest magnitudes (real ones are <= msg_max) or the sign parity, and
+// its decision bit is 0 for the parity test.
+constexpr uint32_t kDummy = 0x3FFF3FFFu;
+
+// Decode codewords [2 npairs blk, 2 npairs (blk + 1)) with the calling workgroup.
+// Threads beyond Z * npairs take part in the barriers only.  Ends with a barrier,
+// so the caller may reuse the LDS right after.
+template <int ML, int MD, bool LAYERED>
+__device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const BinRule &R, int max_iters, int early_stop, int batch,
+                        int npairs, const DecodeIO &io, int blk, uint32_t *lds) {
+    const int n = C.n, E = C.E, Z = Q.Z, nl = Q.nl;
+    const int ld = n + Z;  // per-pair Lambda row: n variables + Z dummy slots
+    const uint32_t Z4 = 4 * Z;
+    const int tid = threadIdx.x, T = blockDim.x;
+    const bool act = tid < Z * npairs;
+    const int p = act ? tid / Z : 0, i0 = act ? tid - p * Z : 0;
+    const int cw0 = blk * npairs * 2;
+    if (cw0 >= batch) return;
+    int2 *sdesc = (int2 *)lds;                     // [ML][MD] layer descriptors
+    uint32_t *lam = lds + 2 * ML * MD;             // [npairs][ld] packed Lambda
+    uint32_t *Lch = lam + (size_t)npairs * ld;     // [npairs][ld] packed channel LLRs (flooding)
+    int *unsat = (int *)(lam + (size_t)(LAYERED ? 1 : 2) * npairs * ld);
+    int *done = unsat + npairs;
+    int *itc = done + npairs;  // [2 * npairs]
+    const v2s mm = splat(R.msg_max), nmm = splat(-R.msg_max);
+    const PkNorm NP = pk_norm_params(R);
+
+    for (int idx = tid; idx < ML * MD; idx += T) {
+        const int l = idx / MD, j = idx - l * MD;
+        const int2 e = (l < nl && j < Q.dc[l]) ? Q.edges[l * kQcMaxDc + j] : make_int2(n, 0);
+        sdesc[idx] = make_int2(4 * e.x, 4 * e.y);
+    }
+    const int8_t *llr = (const int8_t *)io.llr;
+    for (int idx = tid; idx < npairs * ld; idx += T) {
+        const int pp = idx / ld, v = idx - pp * ld;
+        const int c0 = cw0 + 2 * pp;
+        short lo = 0x3FFF, hi = 0x3FFF;
+        if (v < n) {
+            lo = c0 < batch ? (short)llr[(size_t)c0 * n + v] : (short)0;
+            hi = c0 + 1 < batch ? (short)llr[(size_t)(c0 + 1) * n + v] : (short)0;
+        }
+        const uint32_t w = as_u32((v2s){lo, hi});
+        lam[idx] = w;
+        if (!LAYERED) Lch[idx] = w;
+    }
+    for (int idx = tid; idx < npairs; idx += T) {
+        const int c0 = cw0 + 2 * idx;
+        unsat[idx] = 0;
+        done[idx] = (c0 < batch ? 0 : 1) | (c0 + 1 < batch ? 0 : 2);
+        itc[2 * idx] = itc[2 * idx + 1] = 0;
+    }
+    __syncthreads();
+
+    v2s r[ML][MD];
+#pragma unroll
+    for (int l = 0; l < ML; ++l)
+#pragma unroll
+        for (int j = 0; j < MD; ++j) r[l][j] = splat(0);
+
+    uint32_t *lamp = lam + (size_t)p * ld;
+
+    // Parity of the current hard decisions of this thread's rows, as a 2-bit mask
+    // (one bit per codeword); virtual edges read a dummy slot whose sign bits are 0.
+    auto row_parities = [&]() -> int {
+        int any = 0;
+        if (!act) return 0;
+#pragma unroll
+        for (int l = 0; l < ML; ++l) {
+            if (l < nl) {
+                uint32_t i4 = 4 * i0;
+                asm volatile("" : "+v"(i4));
+                const int2 *wl = sdesc + l * MD;
+                uint32_t x = 0;
+#pragma unroll
+                for (int j = 0; j < MD; ++j) x ^= lds_word(lamp, qc_off(wl[j], i4, Z4));
+                any |= (int)((x >> 15) & 1u) | (int)((x >> 30) & 2u);
+            }
+        }
+        return any;
+    };
+
+    uint32_t M = 0xFFFFFFFFu;  // halves (codewords) still being decoded
+    for (int k = 1; k <= max_iters; ++k) {
+        if (early_stop) {
+            const int any = row_parities();
+            if (any) atomicOr(&unsat[p], any);
+            __syncthreads();
+            if (tid < npairs) {
+                done[tid] |= (~unsat[tid]) & 3;
+                unsat[tid] = 0;
+            }
+            __syncthreads();
+            int all = 1;
+            for (int q = 0; q < npairs; ++q) all &= done[q] == 3;
+            if (all) break;
+            const int d = done[p];
+            M = ((d & 1) ? 0u : 0x0000FFFFu) | ((d & 2) ? 0u : 0xFFFF0000u);
+        }
+#pragma unroll
+        for (int l = 0; l < ML; ++l) {
+            if (l < nl) {
+              if (act) {
+                // Column indices are recomputed every layer rather than kept live.
+                uint32_t i4 = 4 * i0;
+                asm volatile("" : "+v"(i4));
+                int dc = __builtin_amdgcn_readfirstlane(Q.dc[l]);  // uniform by construction
+                asm volatile("" : "+s"(dc));
+                const int2 *wl = sdesc + l * MD;
+                uint32_t vv[MD];
+                v2s lv[MD];
+#pragma unroll
+                for (int j = 0; j < MD; ++j) vv[j] = qc_off(wl[j], i4, Z4);
+#pragma unroll
+                for (int j = 0; j < MD; ++j) lv[j] = as_v2s(lds_word(lamp, vv[j]));
+                v2s m1 = splat(0x7FFF), m2 = splat(0x7FFF);
+                uint32_t stot = 0;
+                v2s qv[MD], av[MD];
+                uint32_t sv[MD];
+#pragma unroll
+                for (int j = 0; j < MD; ++j) {
+                    // |clamp(q, +-msg_max)| = min(|q|, msg_max); the sign of q is the sign of clamp(q)
+                    const v2s q = lv[j] - r[l][j];
+                    const uint32_t sg = as_u32(q >> splat(15));
+                    const v2s a = pmin(pmax(q, -q), mm);
+                    m2 = pmin(m2, pmax(m1, a));
+                    m1 = pmin(m1, a);
+                    stot ^= sg;
+                    qv[j] = q;
+                    av[j] = a;
+                    sv[j] = sg;
+                }
+                const v2s f1 = pk_norm(NP, m1), f2 = pk_norm(NP, m2);
+                const v2s df = f1 - f2;
+#pragma unroll
+                for (int j = 0; j < MD; ++j) {
+                    const v2s t = pmin(av[j] - m1, splat(1));  // 0 where this edge holds the minimum
+                    const v2s mag = f2 + t * df;
+                    const uint32_t sr = stot ^ sv[j];
+                    const v2s rn = as_v2s(as_u32(mag) ^ sr) - as_v2s(sr);
+                    const v2s rk = as_v2s(bfi(M, as_u32(rn), as_u32(r[l][j])));
+                    r[l][j] = rk;
+                    if (LAYERED) lds_word(lamp, vv[j]) = as_u32(qv[j] + rk);
+                }
+                // virtual edges wrote q + r into their dummy slot: restore it
+                if (LAYERED && dc < MD) lamp[n + i0] = kDummy;
+              }
+                if (LAYERED) __syncthreads();
+            }
+        }
+        if (!LAYERED) {
+            __syncthreads();
+            for (int idx = tid; idx < npairs * ld; idx += T) lam[idx] = Lch[idx];
+            __syncthreads();
+#pragma unroll
+            for (int l = 0; l < ML; ++l) {
+                if (l < nl) {
+                    uint32_t i4 = 4 * i0;
+                    asm volatile("" : "+v"(i4));
+                    const int dc = Q.dc[l];
+                    const int2 *wl = sdesc + l * MD;
+#pragma unroll
+                    for (int j = 0; j < MD; ++j) {
+                        if (act && j < dc) {
+                            uint32_t &w = lds_word(lamp, qc_off(wl[j], i4, Z4));
+                            w = as_u32(as_v2s(w) + r[l][j]);
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+        if (tid < 2 * npairs && !((done[tid >> 1] >> (tid & 1)) & 1)) itc[tid] = k;
+    }
+
+    // Syndrome of the final decision.
+    __syncthreads();
+    {
+        const int any = row_parities();
+        if (any) atomicOr(&unsat[p], any);
+    }
+    __syncthreads();
+    const int ncw = min(2 * npairs, batch - cw0);
+    if (tid < ncw) {
+        io.ok[cw0 + tid] = ((unsat[tid >> 1] >> (tid & 1)) & 1) ? 0 : 1;
+        io.iters[cw0 + tid] = (int16_t)itc[tid];
+    }
+    const int nbytes = (n + 7) >> 3;
+    uint8_t *hard = (uint8_t *)io.hard + (size_t)cw0 * nbytes;
+    for (int idx = tid; idx < ncw * nbytes; idx += T) {
+        const int c = idx / nbytes, jb = idx - c * nbytes;
+        const uint32_t *lp = lam + (size_t)(c >> 1) * ld;
+        const int sh = (c & 1) ? 31 : 15;
+        uint32_t byte = 0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int v = 8 * jb + b;
+            if (v < n) byte |= ((lp[v] >> sh) & 1u) << b;
+        }
+        hard[idx] = (uint8_t)byte;
+    }
+    if (io.dump_a) {
+        int8_t *dq = (int8_t *)io.dump_a;
+        int8_t *dr = (int8_t *)io.dump_b;
+        int16_t *dl = (int16_t *)io.dump_c;
+        const int i = i0;
+#pragma unroll
+        for (int l = 0; l < ML; ++l) {
+            if (act && l < nl) {
+                const int e0 = C.row_ptr[l * Z + i];
+#pragma unroll
+                for (int j = 0; j < MD; ++j)
+                    if (j < Q.dc[l]) {
+                        const v2s lv = as_v2s(lds_word(lamp, qc_off(sdesc[l * MD + j], 4 * i, 4 * Z)));
+                        const v2s qc = pmin(pmax(lv - r[l][j], nmm), mm);
+                        for (int h = 0; h < 2; ++h) {
+                            const int c = cw0 + 2 * p + h;
+                            if (c < batch) {
+                                dr[(size_t)c * E + e0 + j] = (int8_t)r[l][j][h];
+                                dq[(size_t)c * E + e0 + j] = (int8_t)qc[h];
+                            }
+                        }
+                    }
+            }
+        }
+        for (int idx = tid; idx < ncw * n; idx += T) {
+            const int c = idx / n, v = idx - c * n;
+            dl[(size_t)(cw0 + c) * n + v] = as_v2s(lam[(size_t)(c >> 1) * ld + v])[c & 1];
+        }
+    }
+    __syncthreads();
+}
+
+// Register arrays are sized by the number of layers (ML) and the largest layer degree (MD).
+#define LDPCX_QC_SHAPES(X) X(4, 6) X(4, 8) X(8, 6) X(8, 8) X(12, 7) X(12, 8) X(16, 6) X(16, 8)
+
+inline void qc_shape_of(const QcDesc &Q, int &ml, int &md) {
+    int d = 0;
+    for (int l = 0; l < Q.nl; ++l) d = Q.dc[l] > d ? Q.dc[l] : d;
+    ml = md = 0;
+#define LDPCX_PICK(L_, D_)              \
+    if (!ml && Q.nl <= L_ && d <= D_) { \
+        ml = L_;                        \
+        md = D_;                        \
+    }
+    LDPCX_QC_SHAPES(LDPCX_PICK)
+#undef LDPCX_PICK
+}
+
+inline size_t qc_smem_bytes(int ML, int MD, const DevCode &C, int Z, int layered, int npairs) {
+    return sizeof(int2) * ML * MD + (size_t)(layered ? 1 : 2) * npairs * (C.n + Z) * 4 + (size_t)npairs * 16;
+}
+
+}  // namespace dev
+}  // namespace ldpcx

@@ -1,0 +1,335 @@
+// Interleaved Min-Max decoder over GF(g), g = 2^p <= 64 (Alg. 2), as
+// block-level device functions (blocks of 256 threads, block index explicit).
+//
+// Mapping: lane = codeword.  A wavefront processes one check node for 64
+// codewords; each lane holds whole g-entry messages in registers as packed
+// 16-bit pairs.  The forward/backward recursions of eqs. (9)-(10) and the
+// middle outputs of eq. (13) become XOR (min,max)-convolutions
+//     (A (*) B)(s) = min_t max(A(s ^ t), B(t))
+// of messages that were first permuted by the edge coefficient
+// (a~(t) = alpha(h^-1 t), the "multiply by h" of sec. 2.2; with that
+// substitution x' + h x'' = x becomes x' ^ t = x).  Because every lane of a
+// wave works on the same check, the permutation index h^-1 t is uniform across
+// the wave and the permutation is done by the loads themselves: each load is a
+// contiguous 128-byte segment of [edge][x][codeword] memory.  The convolution
+// is fully unrolled over compile-time register indices (no cross-lane traffic,
+// no LDS), two entries per v_pk_max_i16 / v_pk_min_i16.  Only the forward
+// vectors needed by later middle outputs go through LDS.  Forward at the last
+// edge and backward at the first edge are never used by eqs. (11)-(13) and are
+// not computed (3(dc-2) convolutions per check instead of 4dc-6).
+#pragma once
+
+#include "dev_common.h"
+
+namespace ldpcx {
+namespace dev {
+namespace nb {
+
+struct Args {
+    DevCode C;
+    int max_iters, early_stop, batch, Bp, Gn, fslots;
+    NbWork w;
+    DecodeIO io;
+};
+
+template <int G>
+__device__ __forceinline__ void conv(const v2s (&A)[G / 2], const v2s (&B)[G / 2], v2s (&R)[G / 2]) {
+    constexpr int H = G / 2;
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+        const v2s bt = (t & 1) ? B[t >> 1].yy : B[t >> 1].xx;
+#pragma unroll
+        for (int p = 0; p < H; ++p) {
+            v2s a = A[p ^ (t >> 1)];
+            if (t & 1) a = a.yx;
+            const v2s v = __builtin_elementwise_max(a, bt);
+            R[p] = (t == 0) ? v : __builtin_elementwise_min(R[p], v);
+        }
+    }
+}
+
+// a~(t) = msg(hinv * t) for one edge, loaded straight from [edge][x][Bp] memory.
+template <int G>
+__device__ __forceinline__ void load_perm(const int16_t *__restrict__ msg, long Bp, int e,
+                                          const uint8_t *__restrict__ mrow, int b, v2s (&A)[G / 2]) {
+    const int16_t *base = msg + (long)e * G * Bp + b;
+#pragma unroll
+    for (int t = 0; t < G; t += 2) {
+        const int x0 = mrow[t], x1 = mrow[t + 1];
+        A[t >> 1] = (v2s){base[(long)x0 * Bp], base[(long)x1 * Bp]};
+    }
+}
+
+// msg(x) = v~(h x) stored for one edge: entry t goes to x = hinv * t.
+template <int G>
+__device__ __forceinline__ void store_deperm(int16_t *__restrict__ msg, long Bp, int e,
+                                             const uint8_t *__restrict__ mrow, int b, const v2s (&V)[G / 2], bool act) {
+    int16_t *base = msg + (long)e * G * Bp + b;
+    if (!act) return;
+#pragma unroll
+    for (int t = 0; t < G; t += 2) {
+        base[(long)mrow[t] * Bp] = V[t >> 1].x;
+        base[(long)mrow[t + 1] * Bp] = V[t >> 1].y;
+    }
+}
+
+template <int G>
+__device__ __forceinline__ void lds_put(uint32_t *slot, int lane, const v2s (&V)[G / 2]) {
+#pragma unroll
+    for (int p = 0; p < G / 2; ++p) slot[p * 64 + lane] = __builtin_bit_cast(uint32_t, V[p]);
+}
+
+template <int G>
+__device__ __forceinline__ void lds_get(const uint32_t *slot, int lane, v2s (&V)[G / 2]) {
+#pragma unroll
+    for (int p = 0; p < G / 2; ++p) V[p] = __builtin_bit_cast(v2s, slot[p * 64 + lane]);
+}
+
+// Waves per block of the check-node phase and its LDS need (forward vectors kept
+// for the middle outputs: fslots x (G/2) x 64 lanes x 4 bytes per wave).
+inline int cn_waves(const Args &A, size_t lds_budget) {
+    const size_t per_wave = (size_t)A.fslots * (A.C.g / 2) * 64 * 4;
+    const size_t w = lds_budget / per_wave;
+    return (int)(w >= 4 ? 4 : w);
+}
+inline size_t cn_lds_bytes(const Args &A, int waves) { return (size_t)waves * A.fslots * (A.C.g / 2) * 64 * 4; }
+
+// Check-node phase of iteration k: wave (threadIdx.x / 64) of virtual block (bx, by)
+// processes check bx * wpb + wave for codewords [64 by, 64 by + 64).
+template <int G>
+__device__ __forceinline__ void cn_block(const Args &A, int k, int wpb, int bx, int by, uint32_t *lds) {
+    constexpr int H = G / 2;
+    const DevCode &C = A.C;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    if (w >= wpb) return;
+    const int row = bx * wpb + w;
+    if (row >= C.m) return;
+    const int g = by;
+    const int b = g * 64 + lane;
+    const uint64_t *slot = A.w.unsat + (size_t)k * A.Gn;
+    const bool act = b < A.batch && (!A.early_stop || ((slot[g] >> lane) & 1ull));
+    if (__ballot(act) == 0) return;
+    const long Bp = A.Bp;
+    const int16_t *alpha = A.w.alpha;
+    int16_t *beta = A.w.beta;
+    uint32_t *fs = lds + (size_t)w * A.fslots * H * 64;
+    const int e0 = C.row_ptr[row];
+    const int dc = C.row_ptr[row + 1] - e0;
+    const uint8_t *mul = C.gfmul;
+    v2s X[H], Y[H], R[H];
+    load_perm<G>(alpha, Bp, e0, mul + C.hinv[e0] * G, b, X);
+    const int nf = dc - 2;
+    for (int s = 0; s < 3 * nf; ++s) {
+        int kind, j;
+        if (s < nf) {
+            kind = 0;
+            j = s + 1;
+            load_perm<G>(alpha, Bp, e0 + j, mul + C.hinv[e0 + j] * G, b, Y);
+        } else {
+            const int t = s - nf;
+            j = dc - 2 - (t >> 1);
+            if (t == 0) {
+                // X = F_{dc-2} is the output of the last edge (eq. (12)); start the backward pass.
+                store_deperm<G>(beta, Bp, e0 + dc - 1, mul + C.hinv[e0 + dc - 1] * G, b, X, act);
+                load_perm<G>(alpha, Bp, e0 + dc - 1, mul + C.hinv[e0 + dc - 1] * G, b, X);
+            }
+            if ((t & 1) == 0) {
+                kind = 1;  // middle output: F_{j-1} (*) B_{j+1}
+                if (j == 1) load_perm<G>(alpha, Bp, e0, mul + C.hinv[e0] * G, b, Y);
+                else lds_get<G>(fs + (size_t)(j - 2) * H * 64, lane, Y);
+            } else {
+                kind = 2;  // B_j = B_{j+1} (*) a~_j
+                load_perm<G>(alpha, Bp, e0 + j, mul + C.hinv[e0 + j] * G, b, Y);
+            }
+        }
+        conv<G>(X, Y, R);
+        if (kind == 1) {
+            store_deperm<G>(beta, Bp, e0 + j, mul + C.hinv[e0 + j] * G, b, R, act);
+        } else {
+#pragma unroll
+            for (int p = 0; p < H; ++p) X[p] = R[p];
+            if (kind == 0 && j <= dc - 3) lds_put<G>(fs + (size_t)(j - 1) * H * 64, lane, X);
+        }
+    }
+    if (nf == 0) {
+        store_deperm<G>(beta, Bp, e0 + 1, mul + C.hinv[e0 + 1] * G, b, X, act);
+        load_perm<G>(alpha, Bp, e0 + 1, mul + C.hinv[e0 + 1] * G, b, X);
+    }
+    store_deperm<G>(beta, Bp, e0, mul + C.hinv[e0] * G, b, X, act);
+}
+
+// Variable-node update (eqs. (14)-(15)) and decision: one wave per (variable, group).
+template <int G>
+__device__ __forceinline__ void vn_block(const Args &A, int k, int bx, int by) {
+    const DevCode &C = A.C;
+    const long Bp = A.Bp;
+    const int lane = threadIdx.x & 63;
+    const int v = bx * 4 + (threadIdx.x >> 6);
+    if (v >= C.n) return;
+    const int g = by;
+    const int b = g * 64 + lane;
+    const uint64_t *slot = A.w.unsat + (size_t)k * A.Gn;
+    const bool act = b < A.batch && (!A.early_stop || ((slot[g] >> lane) & 1ull));
+    if (__ballot(act) == 0) return;
+    int S[G];
+    const int16_t *gp = A.w.gam + (long)v * G * Bp + b;
+#pragma unroll
+    for (int x = 0; x < G; ++x) S[x] = gp[(long)x * Bp];
+    const int t0 = C.vn_ptr[v], t1 = C.vn_ptr[v + 1];
+    for (int t = t0; t < t1; ++t) {
+        const int16_t *bp = A.w.beta + (long)C.vn_ref[t] * G * Bp + b;
+#pragma unroll
+        for (int x = 0; x < G; ++x) S[x] += bp[(long)x * Bp];
+    }
+    int best = 0, bv = S[0];
+#pragma unroll
+    for (int x = 1; x < G; ++x)
+        if (S[x] < bv) {
+            bv = S[x];
+            best = x;
+        }
+    if (act) {
+        A.w.hard[(long)v * Bp + b] = (uint8_t)best;
+        if (v == 0) A.w.it[b] = (int16_t)k;
+    }
+    for (int t = t0; t < t1; ++t) {
+        const int e = C.vn_ref[t];
+        const int16_t *bp = A.w.beta + (long)e * G * Bp + b;
+        int a[G];
+        int mn = 0x7fffffff;
+#pragma unroll
+        for (int x = 0; x < G; ++x) {
+            a[x] = S[x] - bp[(long)x * Bp];
+            mn = min(mn, a[x]);
+        }
+        if (act) {
+            int16_t *ap = A.w.alpha + (long)e * G * Bp + b;
+#pragma unroll
+            for (int x = 0; x < G; ++x) ap[(long)x * Bp] = (int16_t)min(a[x] - mn, 32767);
+        }
+    }
+}
+
+// Syndrome sum_j h_j c_j over GF(g) for one check and 64 codewords (wave per (check, group)).
+__device__ __forceinline__ void syn_block(const Args &A, int slot_k, int bx, int by) {
+    const DevCode &C = A.C;
+    const int lane = threadIdx.x & 63;
+    const int row = bx * 4 + (threadIdx.x >> 6);
+    if (row >= C.m) return;
+    const int g = by;
+    const int b = g * 64 + lane;
+    int s = 0;
+    for (int e = C.row_ptr[row]; e < C.row_ptr[row + 1]; ++e)
+        s ^= C.gfmul[C.h[e] * C.g + A.w.hard[(long)C.col_idx[e] * A.Bp + b]];
+    const uint64_t bits = __ballot(s != 0 && b < A.batch);
+    if (lane == 0 && bits)
+        atomicOr((unsigned long long *)&A.w.unsat[(size_t)slot_k * A.Gn + g], (unsigned long long)bits);
+}
+
+// alpha^(0) = gamma of the edge's variable, beta = 0, decision of iteration 0 (wave per
+// (edge or variable, group)).
+template <int G>
+__device__ __forceinline__ void init_block(const Args &A, int bx, int by) {
+    const DevCode &C = A.C;
+    const long Bp = A.Bp;
+    const int lane = threadIdx.x & 63;
+    const int e = bx * 4 + (threadIdx.x >> 6);
+    const int b = by * 64 + lane;
+    if (e < C.E) {
+        const int16_t *gp = A.w.gam + (long)C.col_idx[e] * G * Bp + b;
+        int16_t *ap = A.w.alpha + (long)e * G * Bp + b;
+        int16_t *bp = A.w.beta + (long)e * G * Bp + b;
+#pragma unroll 8
+        for (int x = 0; x < G; ++x) {
+            ap[(long)x * Bp] = gp[(long)x * Bp];
+            bp[(long)x * Bp] = 0;
+        }
+    }
+    if (e < C.n) {
+        // most likely channel symbol, lowest x on ties
+        const int16_t *gp = A.w.gam + (long)e * G * Bp + b;
+        int best = 0, bv = gp[0];
+        for (int x = 1; x < G; ++x) {
+            const int val = gp[(long)x * Bp];
+            if (val < bv) {
+                bv = val;
+                best = x;
+            }
+        }
+        A.w.hard[(long)e * Bp + b] = (uint8_t)best;
+    }
+}
+
+__device__ __forceinline__ void fin_block(const Args &A, long bx) {
+    const int b = (int)(bx * 256 + threadIdx.x);
+    if (b >= A.batch) return;
+    A.io.ok[b] = ((A.w.unsat[b >> 6] >> (b & 63)) & 1ull) ? 0 : 1;
+    A.io.iters[b] = A.w.it[b];
+}
+
+__host__ __device__ inline long grid_init_x(const Args &A) { return ((A.C.E > A.C.n ? A.C.E : A.C.n) + 3) / 4; }
+__host__ __device__ inline long grid_rows_x(const Args &A) { return (A.C.m + 3) / 4; }
+__host__ __device__ inline long grid_vn_x(const Args &A) { return (A.C.n + 3) / 4; }
+__host__ __device__ inline long grid_fin(const Args &A) { return (A.batch + 255) / 256; }
+
+struct Carve {
+    size_t gam, alpha, beta, hard, unsat, it, total;
+};
+
+inline Carve carve(const DevCode &C, int max_iters, int batch) {
+    const size_t Bp = pad64(batch), Gn = Bp / 64;
+    Carve c;
+    size_t o = 0;
+    c.gam = o;
+    o = align_up(o + (size_t)C.n * C.g * Bp * 2, 256);
+    c.alpha = o;
+    o = align_up(o + (size_t)C.E * C.g * Bp * 2, 256);
+    c.beta = o;
+    o = align_up(o + (size_t)C.E * C.g * Bp * 2, 256);
+    c.hard = o;
+    o = align_up(o + (size_t)C.n * Bp, 256);
+    c.unsat = o;
+    o = align_up(o + (size_t)(max_iters + 1) * Gn * 8, 256);
+    c.it = o;
+    o = align_up(o + Bp * 2, 256);
+    c.total = o;
+    return c;
+}
+
+inline Args make_args(const DevCode &C, int max_iters, int early_stop, int batch, void *base, const DecodeIO &io) {
+    Args A;
+    A.C = C;
+    A.max_iters = max_iters;
+    A.early_stop = early_stop;
+    A.batch = batch;
+    A.Bp = pad64(batch);
+    A.Gn = A.Bp / 64;
+    A.fslots = C.dc_max > 3 ? C.dc_max - 3 : 1;
+    const Carve c = carve(C, max_iters, batch);
+    char *p = (char *)base;
+    A.w.gam = (int16_t *)(p + c.gam);
+    A.w.alpha = (int16_t *)(p + c.alpha);
+    A.w.beta = (int16_t *)(p + c.beta);
+    A.w.hard = (uint8_t *)(p + c.hard);
+    A.w.unsat = (uint64_t *)(p + c.unsat);
+    A.w.it = (int16_t *)(p + c.it);
+    A.io = io;
+    return A;
+}
+
+inline TransposeArgs tr_in(const Args &A) {
+    const long cols = (long)A.C.n * A.C.g;
+    return TransposeArgs{A.io.llr, A.w.gam, A.batch, cols, cols, A.Bp, A.Bp, 2};
+}
+inline TransposeArgs tr_out(const Args &A) {
+    return TransposeArgs{A.w.hard, A.io.hard, A.C.n, A.batch, A.Bp, A.C.n, A.C.n, 1};
+}
+inline FillArgs fill_unsat(const Args &A) {
+    return FillArgs{(uint32_t *)A.w.unsat, (size_t)(A.max_iters + 1) * A.Gn * 2, 0u};
+}
+inline FillArgs fill_it(const Args &A) { return FillArgs{(uint32_t *)A.w.it, (size_t)A.Bp / 2, 0u}; }
+
+}  // namespace nb
+}  // namespace dev
+}  // namespace ldpcx

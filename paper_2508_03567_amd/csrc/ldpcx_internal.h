@@ -96,12 +96,9 @@ struct BinIlWork {
     int16_t *it;      // [Bp]
 };
 size_t bin_il_work_bytes(const DevCode &C, int max_iters, int batch);
-void bin_il_carve(void *base, const DevCode &C, int max_iters, int batch, BinIlWork &w);
-hipError_t launch_bin_il(const DevCode &C, const BinRule &R, int max_iters, int early_stop,
-                         int batch, const BinIlWork &w, const DecodeIO &io, hipStream_t s);
-// Debug dump of the final messages; q_t and r_t are [nnz][Bp] int8 scratch buffers.
-hipError_t launch_bin_il_dump(const DevCode &C, const BinRule &R, int batch, const BinIlWork &w,
-                              int8_t *q_t, int8_t *r_t, void *dq, void *dr, void *dlam, hipStream_t s);
+// ws: workspace of bin_il_work_bytes; dump_scratch: 2 x align256(nnz * Bp) bytes when io dumps.
+hipError_t launch_bin_il(const DevCode &C, const BinRule &R, int max_iters, int early_stop, int batch, void *ws,
+                         const DecodeIO &io, int8_t *dump_scratch, hipStream_t s);
 
 // Interleaved Min-Max decoder over GF(g).
 struct NbWork {
@@ -113,9 +110,8 @@ struct NbWork {
     int16_t *it;      // [Bp]
 };
 size_t nb_work_bytes(const DevCode &C, int max_iters, int batch);
-void nb_carve(void *base, const DevCode &C, int max_iters, int batch, NbWork &w);
-hipError_t launch_nb(const DevCode &C, int max_iters, int early_stop, int batch, const NbWork &w,
-                     const DecodeIO &io, hipStream_t s);
+hipError_t launch_nb(const DevCode &C, int max_iters, int early_stop, int batch, void *ws, const DecodeIO &io,
+                     hipStream_t s);
 // Field sizes with a compiled Min-Max kernel.
 bool nb_supported(int g);
 

@@ -192,6 +192,10 @@ ldpcx_status run_plan(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &p
     }
     if (pl.family == FAMILY_BIN_IL && pl.schedule == LDPCX_SCHED_LAYERED)
         return fail(LDPCX_E_UNSUPPORTED, "the interleaved binary decoder implements the flooding schedule only");
+    if (!io.dump_a && graphs_enabled()) {
+        ldpcx_status st = run_graph(c, p, pl, batch, io, s);
+        if (st != LDPCX_E_UNSUPPORTED) return st;  // else: capture not possible, run eagerly
+    }
     size_t bytes = pl.family == FAMILY_BIN_IL ? bin_il_work_bytes(c->dev, p->max_iters, batch)
                                               : nb_work_bytes(c->dev, p->max_iters, batch);
     const size_t Bp = pad64(batch);
@@ -200,23 +204,158 @@ ldpcx_status run_plan(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &p
     void *ws = nullptr;
     e = hipMallocAsync(&ws, bytes + dump_bytes, s);
     if (e != hipSuccess) return fail(LDPCX_E_NOMEM, std::string("workspace allocation: ") + hipGetErrorString(e));
-    if (pl.family == FAMILY_BIN_IL) {
-        BinIlWork w;
-        bin_il_carve(ws, c->dev, p->max_iters, batch, w);
-        e = launch_bin_il(c->dev, bin_rule(p), p->max_iters, p->early_stop, batch, w, io, s);
-        if (e == hipSuccess && io.dump_a) {
-            int8_t *q_t = (int8_t *)ws + bytes;
-            int8_t *r_t = q_t + align_up((size_t)c->dev.E * Bp, 256);
-            e = launch_bin_il_dump(c->dev, bin_rule(p), batch, w, q_t, r_t, io.dump_a, io.dump_b, io.dump_c, s);
-        }
-    } else {
-        NbWork w;
-        nb_carve(ws, c->dev, p->max_iters, batch, w);
-        e = launch_nb(c->dev, p->max_iters, p->early_stop, batch, w, io, s);
-    }
+    e = enqueue_interleaved(c, p, pl, batch, ws, io, dump_bytes ? (int8_t *)ws + bytes : nullptr, s);
     hipError_t e2 = hipFreeAsync(ws, s);
     if (e != hipSuccess) return fail_hip(e, "decoder launch");
     if (e2 != hipSuccess) return fail_hip(e2, "workspace release");
+    return LDPCX_OK;
+}
+
+hipError_t enqueue_interleaved(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &pl, int batch, void *ws,
+                               const DecodeIO &io, int8_t *dump_scratch, hipStream_t s) {
+    if (pl.family == FAMILY_BIN_IL)
+        return launch_bin_il(c->dev, bin_rule(p), p->max_iters, p->early_stop, batch, ws, io, dump_scratch, s);
+    return launch_nb(c->dev, p->max_iters, p->early_stop, batch, ws, io, s);
+}
+
+bool graphs_enabled() {
+    static const bool on = [] {
+        const char *v = getenv("LDPCX_GRAPHS");
+        return !(v && v[0] == '0');
+    }();
+    return on;
+}
+
+// Replay a captured launch sequence of the interleaved decoders.  One cached entry per
+// (plan, params, batch, buffers) holds its own workspace; an event orders replays of
+// the same entry issued on different streams.
+ldpcx_status run_graph(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &pl, int batch, const DecodeIO &io,
+                       hipStream_t s) {
+    GraphKey key{};
+    key.family = pl.family;
+    key.batch = batch;
+    key.params = *p;
+    key.llr = io.llr;
+    key.hard = io.hard;
+    key.ok = io.ok;
+    key.iters = io.iters;
+    std::lock_guard<std::mutex> lk(c->graph_mu);
+    GraphEntry *ge = nullptr;
+    for (auto &g : c->graphs)
+        if (std::memcmp(&g.key, &key, sizeof key) == 0) ge = &g;
+    if (!ge) {
+        if (c->graphs.size() >= 8) {  // evict the least recently used entry
+            auto lru = c->graphs.begin();
+            for (auto it = c->graphs.begin(); it != c->graphs.end(); ++it)
+                if (it->last_use < lru->last_use) lru = it;
+            (void)hipEventSynchronize(lru->done);
+            release_graph(*lru);
+            c->graphs.erase(lru);
+        }
+        GraphEntry g{};
+        g.key = key;
+        const size_t bytes = pl.family == FAMILY_BIN_IL ? bin_il_work_bytes(c->dev, p->max_iters, batch)
+                                                        : nb_work_bytes(c->dev, p->max_iters, batch);
+        if (hipMalloc(&g.ws, bytes) != hipSuccess) return fail(LDPCX_E_NOMEM, "graph workspace allocation");
+        hipStream_t cs = nullptr;
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipFree(g.ws);
+            return fail(LDPCX_E_DEVICE, "capture stream");
+        }
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t el = enqueue_interleaved(c, p, pl, batch, g.ws, io, nullptr, cs);
+            e = hipStreamEndCapture(cs, &graph);
+            if (el != hipSuccess) e = el;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cs);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&g.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+            (void)hipFree(g.ws);
+            return fail(LDPCX_E_UNSUPPORTED, std::string("graph capture: ") + hipGetErrorString(e));
+        }
+        c->graphs.push_back(g);
+        ge = &c->graphs.back();
+    }
+    ge->last_use = ++c->graph_clock;
+    hipError_t e = hipStreamWaitEvent(s, ge->done, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(ge->exec, s);
+    if (e == hipSuccess) e = hipEventRecord(ge->done, s);
+    if (e != hipSuccess) return fail_hip(e, "graph launch");
+    return LDPCX_OK;
+}
+
+void release_graph(GraphEntry &g) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.done) (void)hipEventDestroy(g.done);
+    if (g.ws) (void)hipFree(g.ws);
+    g = GraphEntry{};
+}
+
+namespace {
+
+struct Stage {
+    char *p = nullptr;
+    size_t cap = 0;
+    int device = -1;
+    hipEvent_t ev = nullptr;
+    bool used = false;
+};
+std::mutex g_stage_mu;
+std::vector<Stage> g_stages;  // kept until the process ends
+constexpr size_t kMaxStages = 64;
+
+}  // namespace
+
+ldpcx_status upload_async(void *dst, const void *src, size_t bytes, int device, hipStream_t s) {
+    if (bytes == 0) return LDPCX_OK;
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    Stage *pick = nullptr;
+    for (Stage &st : g_stages)
+        if (st.device == device && st.cap >= bytes && (!st.used || hipEventQuery(st.ev) == hipSuccess)) {
+            pick = &st;
+            break;
+        }
+    if (!pick && g_stages.size() >= kMaxStages) {
+        // Every buffer is in flight: wait for the first one that is large enough.
+        for (Stage &st : g_stages)
+            if (st.device == device && st.cap >= bytes) {
+                hipError_t e = hipEventSynchronize(st.ev);
+                if (e != hipSuccess) return fail_hip(e, "staging buffer wait");
+                pick = &st;
+                break;
+            }
+    }
+    if (!pick) {
+        Stage st;
+        st.device = device;
+        st.cap = std::max<size_t>(bytes, 64 * 1024);
+        hipError_t e = hipHostMalloc((void **)&st.p, st.cap, hipHostMallocDefault);
+        if (e != hipSuccess) return fail_hip(e, "pinned staging buffer");
+        e = hipEventCreateWithFlags(&st.ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            (void)hipHostFree(st.p);
+            return fail_hip(e, "staging event");
+        }
+        g_stages.push_back(st);
+        pick = &g_stages.back();
+    }
+    std::memcpy(pick->p, src, bytes);
+    hipError_t e = hipMemcpyAsync(dst, pick->p, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return fail_hip(e, "upload");
+    e = hipEventRecord(pick->ev, s);
+    if (e != hipSuccess) {
+        // Without the event the buffer cannot be reused safely: wait for the copy.
+        (void)hipStreamSynchronize(s);
+        pick->used = false;
+        return fail_hip(e, "staging event record");
+    }
+    pick->used = true;
     return LDPCX_OK;
 }
 
@@ -449,6 +588,7 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
 ldpcx_status ldpcx_code_destroy(ldpcx_code *c) {
     if (!c) return LDPCX_OK;
     (void)hipDeviceSynchronize();
+    for (auto &g : c->graphs) release_graph(g);
     if (c->dmem) (void)hipFree(c->dmem);
     delete c;
     return LDPCX_OK;

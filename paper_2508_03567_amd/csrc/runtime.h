@@ -25,6 +25,25 @@ struct DeviceInfo {
     int lds_per_block = 64 * 1024;
 };
 
+// A captured launch sequence of the interleaved decoders, keyed by everything that is
+// baked into its kernel arguments.
+struct GraphKey {
+    int family, batch;
+    ldpcx_decode_params params;
+    const void *llr;
+    void *hard;
+    uint8_t *ok;
+    int16_t *iters;
+};
+
+struct GraphEntry {
+    GraphKey key;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    void *ws = nullptr;
+    uint64_t last_use = 0;
+};
+
 }  // namespace ldpcx
 
 struct ldpcx_code {
@@ -41,6 +60,9 @@ struct ldpcx_code {
     ldpcx::DevCode dev{};
     std::mutex mu;
     std::map<uint64_t, ldpcx::Plan> tuned;
+    std::mutex graph_mu;
+    std::vector<ldpcx::GraphEntry> graphs;
+    uint64_t graph_clock = 0;
 };
 
 namespace ldpcx {
@@ -57,5 +79,15 @@ Plan plan_for(ldpcx_code *c, const ldpcx_decode_params *p, int batch);
 uint64_t tune_key(const ldpcx_decode_params *p, int batch);
 ldpcx_status run_plan(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &pl, int batch, const DecodeIO &io,
                       hipStream_t s);
+hipError_t enqueue_interleaved(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &pl, int batch, void *ws,
+                               const DecodeIO &io, int8_t *dump_scratch, hipStream_t s);
+bool graphs_enabled();
+ldpcx_status run_graph(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &pl, int batch, const DecodeIO &io,
+                       hipStream_t s);
+void release_graph(GraphEntry &g);
+// Copy `bytes` of host memory to device memory `dst` in the order of stream `s` without
+// blocking the host: the data goes through a pinned staging buffer that is reused once
+// the copy has completed.
+ldpcx_status upload_async(void *dst, const void *src, size_t bytes, int device, hipStream_t s);
 
 }  // namespace ldpcx

@@ -1,0 +1,125 @@
+"""GPU tests of the ragged persistent engine and of the graph-replayed launch sequences.
+
+A ragged launch of jobs over different codes, sizes and decoder families must give
+exactly what one plain decode per job gives (and what the oracle gives), including
+per-codeword early termination; graph replays of the interleaved decoders must give
+the eager result on every replay.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2508_03567_amd import ldpcx as L
+from paper_2508_03567_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _prm(w, **kw):
+    d = dict(rule=w.rule, schedule=w.schedule, max_iters=w.max_iters, early_stop=True, nms_num=w.nms_num,
+             nms_shift=w.nms_shift, oms_offset=w.oms_offset, msg_max=w.msg_max)
+    d.update(kw)
+    return d
+
+
+_CODES = {}
+
+
+def _code(cfg):
+    if cfg not in _CODES:
+        _CODES[cfg] = L.Code(S.workload(cfg).code)
+    return _CODES[cfg]
+
+
+def _mk(cfg, batch, seed, **kw):
+    w = S.workload(cfg, batch=batch)
+    cw, llr = S.make_inputs(w, seed_offset=seed)
+    return w, _prm(w, **kw), llr
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("early", [True, False])
+def test_ragged_mix_equals_per_job_decodes_and_oracle(early):
+    specs = [(0, 37, 1), (1, 19, 2), (3, 11, 3), (0, 130, 4), (2, 2, 5), (1, 1, 6), (3, 70, 7), (0, 0, 8)]
+    items, refs = [], []
+    for cfg, batch, seed in specs:
+        w, d, llr = _mk(cfg, max(batch, 1), seed, early_stop=early, max_iters=min(12, S.workload(cfg).max_iters))
+        llr = llr[:batch]
+        items.append((_code(cfg), L.params(**d), torch.from_numpy(np.ascontiguousarray(llr)).to(DEV)))
+        refs.append((w, d, llr))
+    outs = L.decode_ragged(items)
+    torch.cuda.synchronize()
+    for (code, prm, x), (hard, ok, it), (w, d, llr) in zip(items, outs, refs):
+        if x.shape[0] == 0:
+            continue
+        h2, ok2, it2, _ = L.decode(code, prm, x)
+        torch.cuda.synchronize()
+        assert (_np(hard) == _np(h2)).all()
+        assert (_np(ok) == _np(ok2)).all()
+        assert (_np(it) == _np(it2)).all()
+        ref = (O.decode_binary if w.code.g == 2 else O.decode_nb)(w.code, O.params(**d), llr)
+        hh = _np(hard)
+        if w.code.g == 2:
+            hh = L.unpack_bits(hh, w.code.n)
+        assert (hh == ref["hard"]).all()
+        assert (_np(ok) == ref["ok"]).all()
+        assert (_np(it) == ref["iters"]).all()
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+def test_ragged_single_job(cfg):
+    batch = {0: 300, 1: 65, 2: 3, 3: 129}[cfg]
+    w, d, llr = _mk(cfg, batch, 21, max_iters=6)
+    x = torch.from_numpy(llr).to(DEV)
+    (hard, ok, it), = L.decode_ragged([(_code(cfg), L.params(**d), x)])
+    torch.cuda.synchronize()
+    ref = (O.decode_binary if w.code.g == 2 else O.decode_nb)(w.code, O.params(**d), llr)
+    hh = _np(hard)
+    if w.code.g == 2:
+        hh = L.unpack_bits(hh, w.code.n)
+    assert (hh == ref["hard"]).all() and (_np(ok) == ref["ok"]).all() and (_np(it) == ref["iters"]).all()
+
+
+def test_ragged_many_small_requests():
+    rng = np.random.default_rng(3)
+    items, refs = [], []
+    for r in range(40):
+        cfg = int(rng.choice([0, 1, 3], p=[0.5, 0.3, 0.2]))
+        batch = int(np.exp(rng.uniform(0, np.log(65))))
+        w, d, llr = _mk(cfg, batch, 100 + r, max_iters=8)
+        items.append((_code(cfg), L.params(**d), torch.from_numpy(llr).to(DEV)))
+        refs.append((w, d, llr))
+    outs = L.decode_ragged(items)
+    torch.cuda.synchronize()
+    for (hard, ok, it), (w, d, llr) in zip(outs, refs):
+        ref = (O.decode_binary if w.code.g == 2 else O.decode_nb)(w.code, O.params(**d), llr)
+        hh = _np(hard)
+        if w.code.g == 2:
+            hh = L.unpack_bits(hh, w.code.n)
+        assert (hh == ref["hard"]).all() and (_np(it) == ref["iters"]).all()
+
+
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_graph_replays_match_eager(cfg):
+    w, d, llr = _mk(cfg, {2: 5, 3: 70}[cfg], 31, max_iters=5)
+    code = _code(cfg)
+    prm = L.params(**d)
+    x = torch.from_numpy(llr).to(DEV)
+    out = L._outputs(code, x.shape[0], DEV)
+    ref = (O.decode_binary if w.code.g == 2 else O.decode_nb)(w.code, O.params(**d), llr)
+    eager = L.debug_dump(code, prm, x)  # the dump path never uses graphs
+    torch.cuda.synchronize()
+    for rep in range(4):
+        for t in out:
+            t.fill_(0x55 if t.dtype == torch.uint8 else 7)
+        y = torch.randn(1 << 20, device=DEV) * 2.0  # unrelated eager work between replays
+        L.decode(code, prm, x, out=out)
+        torch.cuda.synchronize()
+        assert float(y.abs().sum()) > 0
+        assert (_np(out[0]) == _np(eager[0])).all()
+        assert (_np(out[1]) == ref["ok"]).all() and (_np(out[2]) == ref["iters"]).all()
