@@ -197,17 +197,45 @@ ldpcx_status ldpcx_plan_set(ldpcx_code *code, const ldpcx_decode_params *params,
 /* ------------------------------------------------------------------ serving */
 typedef struct ldpcx_server ldpcx_server;
 
-/* Create a continuous-batching server on the current device.  Requests are admitted
- * while their device memory (inputs, outputs and decoder state) fits `hbm_budget`
- * bytes; admitted requests share persistent ragged launches that advance every
- * in-flight codeword by up to `iters_per_step` iterations (0 = run to completion),
- * and requests that arrive meanwhile are admitted as memory frees up.  A request
- * larger than the budget is split into chunks that fit. */
-ldpcx_status ldpcx_server_create(size_t hbm_budget, int32_t iters_per_step, ldpcx_server **out);
+/* Serving.  Sec. 4 lets every decoder start as soon as its codewords are available
+ * instead of waiting for a full batch; the server does that on one GPU by admitting
+ * requests into launches while earlier launches still run.
+ *
+ * Serving modes.
+ *   CONTINUOUS: whenever one of the `max_inflight` launch slots is free and requests
+ *     wait, the scheduler admits waiting codewords in arrival order while the free
+ *     budget allows (a request that only partly fits is split at a codeword boundary)
+ *     and launches them together on the slot's stream: codes whose decoder state fits
+ *     one workgroup as ONE ragged persistent launch (ldpcx_decode_ragged), long codes
+ *     (interleaved decoder) as their own launch sequence on the same stream.  Requests
+ *     that arrive while launches are in flight are admitted into the next free slot
+ *     without waiting for those launches to end, so their work overlaps on the device.
+ *   PER_REQUEST: the one-code-per-launch baseline: one request (or budget-sized
+ *     chunk of it) per launch through the plain decoder, one launch at a time, in
+ *     arrival order.
+ * Decoded results never depend on the mode, the mix or the chunking: every codeword
+ * gets exactly what ldpcx_decode gives it alone. */
+enum { LDPCX_SERVE_CONTINUOUS = 0, LDPCX_SERVE_PER_REQUEST = 1 };
 
-/* Submit a request (host buffers, layouts as ldpcx_decode; they must stay valid until
- * the request completes).  Returns at once with a ticket.  LDPCX_E_BUDGET when even one
- * codeword does not fit the budget. */
+typedef struct {
+    size_t hbm_budget;     /* device bytes admitted work may hold at once: inputs, outputs
+                            * and decoder workspaces of every chunk in flight */
+    int32_t max_inflight;  /* launch slots (streams) in flight at once, >= 1 (PER_REQUEST: 1) */
+    int32_t mode;          /* LDPCX_SERVE_* */
+    int32_t max_launch_cw; /* cap on codewords per launch, 0 = only the budget caps it */
+} ldpcx_server_config;
+
+/* Create a server on the current device with its scheduler thread.  The code handles
+ * of submitted requests stay resident on the device (they are the caller's handles;
+ * keep them alive while requests use them).  LDPCX_E_INVAL for a bad configuration,
+ * LDPCX_E_DEVICE when streams or events cannot be created. */
+ldpcx_status ldpcx_server_create(const ldpcx_server_config *cfg, ldpcx_server **out);
+
+/* Submit a request: `batch` codewords of `code` in HOST buffers with the layouts of
+ * ldpcx_decode (llr_host read when the request is admitted, outputs written when it
+ * completes; all must stay valid until then, or until a cancel returns).  Returns at
+ * once with a ticket (thread-safe).  LDPCX_E_BUDGET when one codeword alone does not
+ * fit the budget; parameter errors as ldpcx_decode.  batch = 0 completes at once. */
 ldpcx_status ldpcx_server_submit(ldpcx_server *srv, const ldpcx_code *code,
                                  const ldpcx_decode_params *params, int32_t batch,
                                  const void *llr_host, void *hard_host, uint8_t *syndrome_ok_host,
@@ -217,20 +245,27 @@ ldpcx_status ldpcx_server_submit(ldpcx_server *srv, const ldpcx_code *code,
 ldpcx_status ldpcx_server_poll(ldpcx_server *srv, uint64_t ticket, int32_t *done);
 
 /* Block until the request finishes or `timeout_ms` elapses (< 0: no limit).  Returns the
- * request's final status (LDPCX_OK, LDPCX_E_CANCELLED, LDPCX_E_DEVICE ...) or
- * LDPCX_E_TIMEOUT.  Timing of the request (submit, first admission, completion) is
- * returned in microseconds since server creation when the pointers are not NULL. */
+ * request's final status (LDPCX_OK, LDPCX_E_CANCELLED, LDPCX_E_DEVICE ...) and releases
+ * the ticket (a later poll or wait on it gives LDPCX_E_NOTFOUND), or LDPCX_E_TIMEOUT
+ * and keeps it.  Timing of the request (submit, first admission into a launch,
+ * completion with its outputs in host memory) is returned in microseconds since
+ * server creation when the pointers are not NULL. */
 ldpcx_status ldpcx_server_wait(ldpcx_server *srv, uint64_t ticket, int32_t timeout_ms,
                                double *t_submit_us, double *t_admit_us, double *t_done_us);
 
-/* Cancel a request that has not completed; its chunks still queued are dropped. */
+/* Cancel a request that has not completed: chunks still queued are dropped, chunks in
+ * flight finish on the device but their outputs are discarded; the request completes
+ * at once with LDPCX_E_CANCELLED and its host buffers are no longer touched.  Cancelling
+ * a completed request is a no-op. */
 ldpcx_status ldpcx_server_cancel(ldpcx_server *srv, uint64_t ticket);
 
-/* Counters: requests completed, codewords decoded, launches, peak bytes admitted. */
+/* Counters: requests completed, codewords decoded, launches, peak bytes admitted
+ * (any pointer may be NULL). */
 ldpcx_status ldpcx_server_stats(ldpcx_server *srv, uint64_t *completed, uint64_t *codewords,
                                 uint64_t *launches, uint64_t *peak_bytes);
 
-/* Stop the scheduler thread (pending requests are cancelled) and free the server. */
+/* Cancel pending requests, wait for launches in flight, stop the scheduler thread
+ * and free the server.  Tickets not yet waited on become invalid. */
 ldpcx_status ldpcx_server_destroy(ldpcx_server *srv);
 
 /* Message of the last failing call on this thread ("" if none). */

@@ -70,6 +70,7 @@ const DeviceInfo &device_info(int dev) {
         uint64_t thr = UINT64_MAX;
         (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
     }
+    (void)hipGetLastError();  // the pool setting is best effort; leave no sticky error behind
     return g_dev.emplace(dev, d).first->second;
 }
 
@@ -169,7 +170,7 @@ uint64_t tune_key(const ldpcx_decode_params *p, int batch) {
 
 // Enqueue one decode with an explicit plan.
 ldpcx_status run_plan(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &pl, int batch, const DecodeIO &io,
-                      hipStream_t s) {
+                      hipStream_t s, bool allow_graph) {
     hipError_t e = hipSuccess;
     if (pl.family == FAMILY_BIN_QC) {
         if (!c->qc_ok) return fail(LDPCX_E_UNSUPPORTED, "code has no quasi-cyclic description");
@@ -192,7 +193,7 @@ ldpcx_status run_plan(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &p
     }
     if (pl.family == FAMILY_BIN_IL && pl.schedule == LDPCX_SCHED_LAYERED)
         return fail(LDPCX_E_UNSUPPORTED, "the interleaved binary decoder implements the flooding schedule only");
-    if (!io.dump_a && graphs_enabled()) {
+    if (allow_graph && !io.dump_a && graphs_enabled()) {
         ldpcx_status st = run_graph(c, p, pl, batch, io, s);
         if (st != LDPCX_E_UNSUPPORTED) return st;  // else: capture not possible, run eagerly
     }
@@ -316,11 +317,18 @@ ldpcx_status upload_async(void *dst, const void *src, size_t bytes, int device, 
     if (bytes == 0) return LDPCX_OK;
     std::lock_guard<std::mutex> lk(g_stage_mu);
     Stage *pick = nullptr;
-    for (Stage &st : g_stages)
-        if (st.device == device && st.cap >= bytes && (!st.used || hipEventQuery(st.ev) == hipSuccess)) {
-            pick = &st;
-            break;
+    for (Stage &st : g_stages) {
+        if (st.device != device || st.cap < bytes) continue;
+        if (st.used) {
+            const hipError_t q = hipEventQuery(st.ev);
+            if (q != hipSuccess) {
+                (void)hipGetLastError();  // "not ready" is an answer, not an error to report later
+                continue;
+            }
         }
+        pick = &st;
+        break;
+    }
     if (!pick && g_stages.size() >= kMaxStages) {
         // Every buffer is in flight: wait for the first one that is large enough.
         for (Stage &st : g_stages)

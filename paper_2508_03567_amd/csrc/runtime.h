@@ -77,8 +77,10 @@ BinRule bin_rule(const ldpcx_decode_params *p);
 Plan default_plan(const ldpcx_code *c, const ldpcx_decode_params *p, int batch);
 Plan plan_for(ldpcx_code *c, const ldpcx_decode_params *p, int batch);
 uint64_t tune_key(const ldpcx_decode_params *p, int batch);
+// allow_graph = false always enqueues the launch sequence itself (no cached graph keyed
+// by the I/O buffers), for callers whose buffers change from call to call.
 ldpcx_status run_plan(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &pl, int batch, const DecodeIO &io,
-                      hipStream_t s);
+                      hipStream_t s, bool allow_graph = true);
 hipError_t enqueue_interleaved(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &pl, int batch, void *ws,
                                const DecodeIO &io, int8_t *dump_scratch, hipStream_t s);
 bool graphs_enabled();

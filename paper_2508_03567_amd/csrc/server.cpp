@@ -1,12 +1,529 @@
-// Continuous-batching server (placeholder).
+// Continuous-batching decode server.
+//
+// A scheduler thread owns a few launch slots (one stream each).  Whenever a slot
+// is free and requests wait, it admits waiting codewords in arrival order while
+// the device-memory budget allows, splitting a request that only partly fits at
+// a codeword boundary, and launches the admitted chunks together: one pinned
+// staging copy of the inputs, one ragged persistent launch for the codes whose
+// state fits a workgroup (long interleaved-layout codes and large Min-Max chunks
+// get their own launch sequence on the same stream), one copy of the outputs
+// back, and an event.  Launches on different slots overlap on the device, so a
+// request that arrives while others run starts without waiting for them.
+// Completed launches are retired by polling their events: outputs are copied to
+// the requests' host buffers and their budget is released.
+//
+// Locking: `mu` guards the request table, the queue and the counters.  `io_mu`
+// is held while a launch reads request inputs from host memory and by cancel, so
+// that a cancelled request's host buffers are never touched after cancel
+// returns.  Order: io_mu before mu.
+#include <chrono>
+#include <cstring>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <thread>
+
 #include "runtime.h"
-using namespace ldpcx;
-extern "C" {
-ldpcx_status ldpcx_server_create(size_t, int32_t, ldpcx_server **) { return fail(LDPCX_E_UNSUPPORTED, "server not built yet"); }
-ldpcx_status ldpcx_server_submit(ldpcx_server *, const ldpcx_code *, const ldpcx_decode_params *, int32_t, const void *, void *, uint8_t *, int16_t *, uint64_t *) { return LDPCX_E_UNSUPPORTED; }
-ldpcx_status ldpcx_server_poll(ldpcx_server *, uint64_t, int32_t *) { return LDPCX_E_UNSUPPORTED; }
-ldpcx_status ldpcx_server_wait(ldpcx_server *, uint64_t, int32_t, double *, double *, double *) { return LDPCX_E_UNSUPPORTED; }
-ldpcx_status ldpcx_server_cancel(ldpcx_server *, uint64_t) { return LDPCX_E_UNSUPPORTED; }
-ldpcx_status ldpcx_server_stats(ldpcx_server *, uint64_t *, uint64_t *, uint64_t *, uint64_t *) { return LDPCX_E_UNSUPPORTED; }
-ldpcx_status ldpcx_server_destroy(ldpcx_server *) { return LDPCX_E_UNSUPPORTED; }
+
+namespace ldpcx {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+// Interleaved-family chunks with at least this many groups of 64 codewords run as
+// their own launch sequence (parallel over checks), not as per-group ragged items.
+constexpr int kOwnLaunchGroups = 32;
+
+struct Request {
+    ldpcx_code *code = nullptr;
+    ldpcx_decode_params prm{};
+    int batch = 0;
+    const char *llr = nullptr;
+    char *hard = nullptr;
+    uint8_t *ok = nullptr;
+    int16_t *it = nullptr;
+    size_t in_cw = 0, out_cw = 0;  // bytes per codeword of llr / hard
+    int family = FAMILY_BIN_LDS;
+    int next_cw = 0;   // first codeword not yet admitted
+    int done_cw = 0;   // codewords whose outputs are in host memory
+    int inflight = 0;  // chunks on the device
+    bool done = false, released = false;
+    ldpcx_status status = LDPCX_OK;
+    double t_submit = 0, t_admit = -1, t_done = 0;
+};
+
+struct Chunk {
+    uint64_t id = 0;
+    int cw0 = 0, ncw = 0;
+    size_t charge = 0;                // budget bytes
+    size_t o_llr = 0, o_hard = 0;     // offsets in the launch's device buffer
+    size_t o_ok = 0, o_it = 0;
+    bool own_launch = false;
+};
+
+struct Slot {
+    hipStream_t s = nullptr;
+    hipEvent_t ev = nullptr;
+    bool busy = false;
+    std::vector<Chunk> chunks;
+    size_t charge = 0;
+    size_t in_bytes = 0, out_off = 0, out_bytes = 0, dev_bytes = 0;
+    char *pin_in = nullptr, *pin_out = nullptr;
+    size_t cap_in = 0, cap_out = 0;
+    ldpcx_status st = LDPCX_OK;
+};
+
+size_t io_bytes(const Request &r, int ncw) {
+    return align_up((size_t)ncw * r.in_cw, 256) + align_up((size_t)ncw * r.out_cw, 256) + align_up((size_t)ncw, 256) +
+           align_up((size_t)ncw * 2, 256);
 }
+
+// Device bytes one chunk of `ncw` codewords holds while in flight.
+size_t chunk_bytes(const Request &r, int ncw) {
+    size_t b = io_bytes(r, ncw);
+    if (r.family == FAMILY_BIN_IL) b += bin_il_work_bytes(r.code->dev, r.prm.max_iters, ncw);
+    else if (r.family == FAMILY_NB) b += nb_work_bytes(r.code->dev, r.prm.max_iters, ncw);
+    return b;
+}
+
+// Largest n in [0, cap] with chunk_bytes(r, n) <= avail (monotone in n).
+int max_fit(const Request &r, int cap, size_t avail) {
+    if (cap <= 0 || chunk_bytes(r, 1) > avail) return 0;
+    int lo = 1, hi = cap;
+    while (lo < hi) {
+        const int mid = lo + (hi - lo + 1) / 2;
+        if (chunk_bytes(r, mid) <= avail) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+bool grow_pinned(char *&p, size_t &cap, size_t need) {
+    if (need <= cap) return true;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    size_t c = std::max<size_t>(need, 1 << 20);
+    if (hipHostMalloc((void **)&p, c, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        return false;
+    }
+    cap = c;
+    return true;
+}
+
+}  // namespace
+}  // namespace ldpcx
+
+using namespace ldpcx;
+
+struct ldpcx_server {
+    ldpcx_server_config cfg{};
+    int device = 0;
+    Clock::time_point t0;
+    std::mutex mu, io_mu;
+    std::condition_variable cv_work, cv_done;
+    bool stop = false;
+    uint64_t next_id = 1;
+    std::map<uint64_t, Request> reqs;
+    std::deque<uint64_t> queue;
+    std::vector<Slot> slots;
+    size_t in_use = 0, peak = 0;
+    uint64_t completed = 0, codewords = 0, launches = 0;
+    std::thread th;
+
+    double now_us() const { return std::chrono::duration<double, std::micro>(Clock::now() - t0).count(); }
+
+    // Mark request `id` finished and drop what it still has queued (mu held).
+    void finish(uint64_t id, Request &r, ldpcx_status st) {
+        if (r.done) return;
+        r.done = true;
+        r.status = st;
+        r.t_done = now_us();
+        if (st == LDPCX_OK) ++completed;
+        for (auto it = queue.begin(); it != queue.end(); ++it)
+            if (*it == id) {
+                queue.erase(it);
+                break;
+            }
+        cv_done.notify_all();
+    }
+
+    void maybe_erase(uint64_t id) {
+        auto it = reqs.find(id);
+        if (it != reqs.end() && it->second.released && it->second.done && it->second.inflight == 0) reqs.erase(it);
+    }
+
+    // Take the chunks of the next launch (mu held).
+    std::vector<Chunk> form(bool others_in_flight) {
+        std::vector<Chunk> take;
+        size_t charge = 0;
+        int cw_total = 0;
+        while (!queue.empty()) {
+            const uint64_t id = queue.front();
+            Request &r = reqs.at(id);
+            const int rem = r.batch - r.next_cw;
+            int cap = rem;
+            if (cfg.max_launch_cw > 0) cap = std::min(cap, cfg.max_launch_cw - cw_total);
+            if (cap <= 0) break;
+            const size_t avail = cfg.hbm_budget - in_use - charge;
+            const int n = max_fit(r, cap, avail);
+            if (n == 0) break;
+            // Do not split off a small piece while memory is about to be released.
+            if (n < rem && n < 64 && n < cap && (others_in_flight || !take.empty())) break;
+            Chunk c;
+            c.id = id;
+            c.cw0 = r.next_cw;
+            c.ncw = n;
+            c.charge = chunk_bytes(r, n);
+            c.own_launch = cfg.mode == LDPCX_SERVE_PER_REQUEST || r.family == FAMILY_BIN_IL ||
+                           (r.family == FAMILY_NB && pad64(n) / 64 >= kOwnLaunchGroups);
+            take.push_back(c);
+            r.next_cw += n;
+            r.inflight += 1;
+            if (r.t_admit < 0) r.t_admit = now_us();
+            charge += c.charge;
+            cw_total += n;
+            if (r.next_cw < r.batch) break;  // arrival order: nothing passes a partly admitted request
+            queue.pop_front();
+            if (cfg.mode == LDPCX_SERVE_PER_REQUEST) break;
+        }
+        return take;
+    }
+
+    // Stage inputs and enqueue the launch of slot `sl` (mu not held).
+    void launch(Slot &sl) {
+        sl.st = LDPCX_OK;
+        // Device layout: all inputs, then all hard decisions, flags and counts, each
+        // chunk 256-byte aligned; the pinned buffers mirror the input and output parts.
+        size_t off = 0;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (Chunk &c : sl.chunks) {
+                const Request &r = reqs.at(c.id);
+                c.o_llr = off;
+                off += align_up((size_t)c.ncw * r.in_cw, 256);
+            }
+            sl.in_bytes = off;
+            sl.out_off = off;
+            for (Chunk &c : sl.chunks) {
+                const Request &r = reqs.at(c.id);
+                c.o_hard = off;
+                off += align_up((size_t)c.ncw * r.out_cw, 256);
+                c.o_ok = off;
+                off += align_up((size_t)c.ncw, 256);
+                c.o_it = off;
+                off += align_up((size_t)c.ncw * 2, 256);
+            }
+        }
+        sl.dev_bytes = off;
+        sl.out_bytes = off - sl.out_off;
+        char *dbuf = nullptr;
+        hipError_t e = hipSuccess;
+        {
+            std::lock_guard<std::mutex> io(io_mu);
+            if (!grow_pinned(sl.pin_in, sl.cap_in, sl.in_bytes) || !grow_pinned(sl.pin_out, sl.cap_out, sl.out_bytes)) {
+                sl.st = fail(LDPCX_E_NOMEM, "pinned staging buffers");
+            } else {
+                for (const Chunk &c : sl.chunks) {
+                    const char *src = nullptr;
+                    size_t len = 0;
+                    {
+                        std::lock_guard<std::mutex> lk(mu);
+                        const Request &r = reqs.at(c.id);
+                        if (!r.done) {
+                            src = r.llr + (size_t)c.cw0 * r.in_cw;
+                            len = (size_t)c.ncw * r.in_cw;
+                        }
+                    }
+                    if (src) std::memcpy(sl.pin_in + c.o_llr, src, len);
+                }
+            }
+        }
+        if (sl.st == LDPCX_OK) {
+            e = hipMallocAsync((void **)&dbuf, sl.dev_bytes, sl.s);
+            if (e != hipSuccess) sl.st = fail(LDPCX_E_NOMEM, "server device buffer");
+        }
+        if (sl.st == LDPCX_OK) {
+            e = hipMemcpyAsync(dbuf, sl.pin_in, sl.in_bytes, hipMemcpyHostToDevice, sl.s);
+            if (e != hipSuccess) sl.st = fail_hip(e, "input upload");
+        }
+        if (sl.st == LDPCX_OK) {
+            std::vector<ldpcx_job> jobs;
+            for (const Chunk &c : sl.chunks) {
+                Request r;
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    r = reqs.at(c.id);
+                }
+                ldpcx_job j{r.code, r.prm, c.ncw, dbuf + c.o_llr, dbuf + c.o_hard, (uint8_t *)(dbuf + c.o_ok),
+                            (int16_t *)(dbuf + c.o_it)};
+                if (!c.own_launch) {
+                    jobs.push_back(j);
+                    continue;
+                }
+                const Plan pl = plan_for(r.code, &r.prm, c.ncw);
+                const DecodeIO io{j.llr, j.hard, j.syndrome_ok, j.iters, nullptr, nullptr, nullptr};
+                const ldpcx_status st = run_plan(r.code, &r.prm, pl, c.ncw, io, sl.s, false);
+                if (st != LDPCX_OK) {
+                    sl.st = st;
+                    break;
+                }
+            }
+            if (sl.st == LDPCX_OK && !jobs.empty())
+                sl.st = ldpcx_decode_ragged(jobs.data(), (int32_t)jobs.size(), sl.s);
+        }
+        if (sl.st == LDPCX_OK) {
+            e = hipMemcpyAsync(sl.pin_out, dbuf + sl.out_off, sl.out_bytes, hipMemcpyDeviceToHost, sl.s);
+            if (e != hipSuccess) sl.st = fail_hip(e, "output download");
+        }
+        if (dbuf) (void)hipFreeAsync(dbuf, sl.s);
+        e = hipEventRecord(sl.ev, sl.s);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(sl.s);
+            (void)hipGetLastError();
+            (void)hipEventRecord(sl.ev, sl.s);
+        }
+    }
+
+    // Hand the outputs of a finished launch to its requests (mu held).
+    void retire(Slot &sl, bool device_ok) {
+        const bool ok = device_ok && sl.st == LDPCX_OK;
+        for (const Chunk &c : sl.chunks) {
+            auto it = reqs.find(c.id);
+            if (it == reqs.end()) continue;
+            Request &r = it->second;
+            r.inflight -= 1;
+            if (!r.done) {
+                if (ok) {
+                    std::memcpy(r.hard + (size_t)c.cw0 * r.out_cw, sl.pin_out + (c.o_hard - sl.out_off),
+                                (size_t)c.ncw * r.out_cw);
+                    std::memcpy(r.ok + c.cw0, sl.pin_out + (c.o_ok - sl.out_off), (size_t)c.ncw);
+                    std::memcpy(r.it + c.cw0, sl.pin_out + (c.o_it - sl.out_off), (size_t)c.ncw * 2);
+                    r.done_cw += c.ncw;
+                    codewords += (uint64_t)c.ncw;
+                    if (r.done_cw == r.batch) finish(c.id, r, LDPCX_OK);
+                } else {
+                    finish(c.id, r, sl.st != LDPCX_OK ? sl.st : LDPCX_E_DEVICE);
+                }
+            }
+            maybe_erase(c.id);
+        }
+        in_use -= sl.charge;
+        sl.charge = 0;
+        sl.chunks.clear();
+        sl.busy = false;
+    }
+
+    void run() {
+        (void)hipSetDevice(device);
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            bool did = false, busy_any = false;
+            for (Slot &sl : slots) {
+                if (!sl.busy) continue;
+                const hipError_t q = hipEventQuery(sl.ev);
+                if (q != hipSuccess) (void)hipGetLastError();
+                if (q == hipErrorNotReady) {
+                    busy_any = true;
+                    continue;
+                }
+                retire(sl, q == hipSuccess);
+                did = true;
+            }
+            if (stop && queue.empty() && !busy_any) break;
+            for (Slot &sl : slots) {
+                if (sl.busy || queue.empty()) continue;
+                std::vector<Chunk> take = form(busy_any);
+                if (take.empty()) break;
+                sl.busy = true;
+                sl.chunks = std::move(take);
+                sl.charge = 0;
+                for (const Chunk &c : sl.chunks) sl.charge += c.charge;
+                in_use += sl.charge;
+                peak = std::max(peak, in_use);
+                ++launches;
+                lk.unlock();
+                launch(sl);
+                lk.lock();
+                did = true;
+                busy_any = true;
+            }
+            if (!did) {
+                if (busy_any) cv_work.wait_for(lk, std::chrono::microseconds(20));
+                else cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+            }
+        }
+    }
+};
+
+extern "C" {
+
+ldpcx_status ldpcx_server_create(const ldpcx_server_config *cfg, ldpcx_server **out) {
+    try {
+        if (!cfg || !out) return fail(LDPCX_E_INVAL, "null argument");
+        *out = nullptr;
+        if (cfg->hbm_budget == 0) return fail(LDPCX_E_INVAL, "hbm_budget must be positive");
+        if (cfg->mode != LDPCX_SERVE_CONTINUOUS && cfg->mode != LDPCX_SERVE_PER_REQUEST)
+            return fail(LDPCX_E_INVAL, "unknown serving mode");
+        if (cfg->max_inflight < 1 || cfg->max_inflight > 64) return fail(LDPCX_E_INVAL, "max_inflight must be in [1, 64]");
+        if (cfg->max_launch_cw < 0) return fail(LDPCX_E_INVAL, "max_launch_cw < 0");
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+        device_info(dev);
+        ldpcx_server *S = new ldpcx_server();
+        S->cfg = *cfg;
+        if (S->cfg.mode == LDPCX_SERVE_PER_REQUEST) S->cfg.max_inflight = 1;
+        S->device = dev;
+        S->t0 = Clock::now();
+        S->slots.resize(S->cfg.max_inflight);
+        for (Slot &sl : S->slots) {
+            e = hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                for (Slot &t : S->slots) {
+                    if (t.ev) (void)hipEventDestroy(t.ev);
+                    if (t.s) (void)hipStreamDestroy(t.s);
+                }
+                delete S;
+                return fail_hip(e, "server streams");
+            }
+        }
+        S->th = std::thread([S] { S->run(); });
+        *out = S;
+        return LDPCX_OK;
+    } catch (const std::exception &ex) {
+        return fail(LDPCX_E_NOMEM, ex.what());
+    }
+}
+
+ldpcx_status ldpcx_server_submit(ldpcx_server *srv, const ldpcx_code *code, const ldpcx_decode_params *params,
+                                 int32_t batch, const void *llr_host, void *hard_host, uint8_t *syndrome_ok_host,
+                                 int16_t *iters_host, uint64_t *ticket) {
+    try {
+        if (!srv || !code || !ticket) return fail(LDPCX_E_INVAL, "null argument");
+        ldpcx_code *c = const_cast<ldpcx_code *>(code);
+        ldpcx_status st = check_params(c, params);
+        if (st != LDPCX_OK) return st;
+        if (batch < 0) return fail(LDPCX_E_INVAL, "batch < 0");
+        if (batch > 0 && (!llr_host || !hard_host || !syndrome_ok_host || !iters_host))
+            return fail(LDPCX_E_INVAL, "null buffer");
+        if (c->device != srv->device) return fail(LDPCX_E_INVAL, "code handle lives on another device");
+        if (c->nb_unsupported) return fail(LDPCX_E_UNSUPPORTED, "no Min-Max kernel for this field size");
+        Request r;
+        r.code = c;
+        r.prm = *params;
+        r.batch = batch;
+        r.llr = (const char *)llr_host;
+        r.hard = (char *)hard_host;
+        r.ok = syndrome_ok_host;
+        r.it = iters_host;
+        const int n = c->dev.n;
+        r.in_cw = c->g == 2 ? (size_t)n : (size_t)n * c->g * 2;
+        r.out_cw = c->g == 2 ? (size_t)(n + 7) / 8 : (size_t)n;
+        r.family = plan_for(c, params, std::max(1, batch)).family;
+        if (batch > 0 && chunk_bytes(r, 1) > srv->cfg.hbm_budget)
+            return fail(LDPCX_E_BUDGET, "one codeword does not fit the server's memory budget");
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->stop) return fail(LDPCX_E_CANCELLED, "server is shutting down");
+        r.t_submit = srv->now_us();
+        const uint64_t id = srv->next_id++;
+        Request &in = srv->reqs.emplace(id, r).first->second;
+        if (batch == 0) {
+            in.t_admit = in.t_submit;
+            srv->finish(id, in, LDPCX_OK);
+        } else {
+            srv->queue.push_back(id);
+            srv->cv_work.notify_one();
+        }
+        *ticket = id;
+        return LDPCX_OK;
+    } catch (const std::exception &ex) {
+        return fail(LDPCX_E_NOMEM, ex.what());
+    }
+}
+
+ldpcx_status ldpcx_server_poll(ldpcx_server *srv, uint64_t ticket, int32_t *done) {
+    if (!srv || !done) return fail(LDPCX_E_INVAL, "null argument");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end() || it->second.released) return fail(LDPCX_E_NOTFOUND, "unknown ticket");
+    *done = it->second.done ? 1 : 0;
+    return LDPCX_OK;
+}
+
+ldpcx_status ldpcx_server_wait(ldpcx_server *srv, uint64_t ticket, int32_t timeout_ms, double *t_submit_us,
+                               double *t_admit_us, double *t_done_us) {
+    if (!srv) return fail(LDPCX_E_INVAL, "null argument");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end() || it->second.released) return fail(LDPCX_E_NOTFOUND, "unknown ticket");
+    auto is_done = [&] {
+        auto j = srv->reqs.find(ticket);
+        return j == srv->reqs.end() || j->second.done;
+    };
+    if (timeout_ms < 0) srv->cv_done.wait(lk, is_done);
+    else if (!srv->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), is_done))
+        return fail(LDPCX_E_TIMEOUT, "request still pending");
+    it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) return fail(LDPCX_E_NOTFOUND, "unknown ticket");
+    Request &r = it->second;
+    if (t_submit_us) *t_submit_us = r.t_submit;
+    if (t_admit_us) *t_admit_us = r.t_admit;
+    if (t_done_us) *t_done_us = r.t_done;
+    const ldpcx_status st = r.status;
+    r.released = true;
+    srv->maybe_erase(ticket);
+    if (st == LDPCX_E_CANCELLED) return fail(st, "request was cancelled");
+    if (st != LDPCX_OK) return fail(st, "request failed on the device");
+    return LDPCX_OK;
+}
+
+ldpcx_status ldpcx_server_cancel(ldpcx_server *srv, uint64_t ticket) {
+    if (!srv) return fail(LDPCX_E_INVAL, "null argument");
+    std::lock_guard<std::mutex> io(srv->io_mu);
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end() || it->second.released) return fail(LDPCX_E_NOTFOUND, "unknown ticket");
+    srv->finish(ticket, it->second, LDPCX_E_CANCELLED);
+    return LDPCX_OK;
+}
+
+ldpcx_status ldpcx_server_stats(ldpcx_server *srv, uint64_t *completed, uint64_t *codewords, uint64_t *launches,
+                                uint64_t *peak_bytes) {
+    if (!srv) return fail(LDPCX_E_INVAL, "null argument");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (completed) *completed = srv->completed;
+    if (codewords) *codewords = srv->codewords;
+    if (launches) *launches = srv->launches;
+    if (peak_bytes) *peak_bytes = srv->peak;
+    return LDPCX_OK;
+}
+
+ldpcx_status ldpcx_server_destroy(ldpcx_server *srv) {
+    if (!srv) return fail(LDPCX_E_INVAL, "null argument");
+    {
+        std::lock_guard<std::mutex> io(srv->io_mu);
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+        while (!srv->queue.empty()) {
+            auto it = srv->reqs.find(srv->queue.front());
+            if (it != srv->reqs.end()) srv->finish(it->first, it->second, LDPCX_E_CANCELLED);
+            else srv->queue.pop_front();
+        }
+        srv->cv_work.notify_all();
+    }
+    if (srv->th.joinable()) srv->th.join();
+    for (Slot &sl : srv->slots) {
+        if (sl.ev) (void)hipEventDestroy(sl.ev);
+        if (sl.s) (void)hipStreamDestroy(sl.s);
+        if (sl.pin_in) (void)hipHostFree(sl.pin_in);
+        if (sl.pin_out) (void)hipHostFree(sl.pin_out);
+    }
+    delete srv;
+    return LDPCX_OK;
+}
+
+}  // extern "C"

@@ -44,6 +44,14 @@ class DecodeParams(ctypes.Structure):
                 ("oms_offset", ctypes.c_int32), ("msg_max", ctypes.c_int32)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_inflight", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("max_launch_cw", ctypes.c_int32)]
+
+
+SERVE = {"continuous": 0, "per_request": 1}
+
+
 class Job(ctypes.Structure):
     _fields_ = [("code", ctypes.c_void_p), ("params", DecodeParams), ("batch", ctypes.c_int32),
                 ("llr", ctypes.c_void_p), ("hard", ctypes.c_void_p), ("syndrome_ok", ctypes.c_void_p),
@@ -67,7 +75,7 @@ _SIGS = {
                        [ctypes.POINTER(ctypes.c_int32)] * 3,
     "ldpcx_plan_set": [ctypes.c_void_p, ctypes.POINTER(DecodeParams), ctypes.c_int32, ctypes.c_int32,
                        ctypes.c_int32, ctypes.c_int32],
-    "ldpcx_server_create": [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)],
+    "ldpcx_server_create": [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)],
     "ldpcx_server_submit": [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(DecodeParams), ctypes.c_int32,
                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                             ctypes.POINTER(ctypes.c_uint64)],
@@ -164,9 +172,9 @@ def ldpcx_plan_set(code: int, prm: DecodeParams, batch: int, family: int, cw_per
     _check(lib().ldpcx_plan_set(code, ctypes.byref(prm), batch, family, cw_per_wg, threads))
 
 
-def ldpcx_server_create(hbm_budget: int, iters_per_step: int = 0) -> int:
+def ldpcx_server_create(cfg: ServerConfig) -> int:
     h = ctypes.c_void_p()
-    _check(lib().ldpcx_server_create(hbm_budget, iters_per_step, ctypes.byref(h)))
+    _check(lib().ldpcx_server_create(ctypes.byref(cfg), ctypes.byref(h)))
     return h.value
 
 
@@ -256,8 +264,17 @@ def _outputs(code: Code, batch: int, device):
     return hard, ok, it
 
 
+def _check_llr(code: Code, llr) -> None:
+    import torch
+    want = torch.int8 if code.g == 2 else torch.int16
+    shape = (code.n,) if code.g == 2 else (code.n, code.g)
+    if llr.dtype != want or not llr.is_contiguous() or tuple(llr.shape[1:]) != shape:
+        raise ValueError(f"llr must be a contiguous {want} tensor of shape [B, {', '.join(map(str, shape))}]")
+
+
 def decode(code: Code, prm: DecodeParams, llr, stream=None, out=None):
     """llr: device tensor int8 [B, n] (g == 2) or int16 [B, n, g].  Returns (hard, ok, iters, schedule)."""
+    _check_llr(code, llr)
     batch = int(llr.shape[0])
     hard, ok, it = out if out is not None else _outputs(code, batch, llr.device)
     used = ldpcx_decode(code.handle, prm, batch, llr.data_ptr(), hard.data_ptr(), ok.data_ptr(), it.data_ptr(),
@@ -268,6 +285,7 @@ def decode(code: Code, prm: DecodeParams, llr, stream=None, out=None):
 def debug_dump(code: Code, prm: DecodeParams, llr, stream=None):
     """Decode and return the final messages: binary (hard, ok, iters, q, r, lam); GF(g) (..., alpha, beta)."""
     import torch
+    _check_llr(code, llr)
     batch = int(llr.shape[0])
     hard, ok, it = _outputs(code, batch, llr.device)
     if code.g == 2:
@@ -288,6 +306,7 @@ def decode_ragged(items, stream=None):
     """items: list of (Code, DecodeParams, llr tensor).  Returns a list of (hard, ok, iters)."""
     outs, jobs = [], []
     for code, prm, llr in items:
+        _check_llr(code, llr)
         batch = int(llr.shape[0])
         hard, ok, it = _outputs(code, batch, llr.device)
         outs.append((hard, ok, it))
@@ -313,3 +332,68 @@ def plan_set(code: Code, prm: DecodeParams, batch: int, family: str, cw_per_wg: 
 def unpack_bits(hard_packed: np.ndarray, n: int) -> np.ndarray:
     """[B, ceil(n/8)] LSB-first packed decisions -> [B, n] bits."""
     return np.unpackbits(np.asarray(hard_packed, dtype=np.uint8), axis=1, count=n, bitorder="little")
+
+
+class Server:
+    """Continuous-batching server over host buffers (ldpcx_server_*).
+
+    submit() takes a host numpy array of channel LLRs (int8 [B, n] or int16 [B, n, g]),
+    allocates the host outputs and keeps every buffer alive until the request is waited
+    on; wait() returns (hard, ok, iters, (t_submit_us, t_admit_us, t_done_us)).
+    """
+
+    def __init__(self, hbm_budget: int = 8 << 30, max_inflight: int = 4, mode: str = "continuous",
+                 max_launch_cw: int = 0):
+        self.handle = ldpcx_server_create(ServerConfig(int(hbm_budget), int(max_inflight), SERVE[mode],
+                                                       int(max_launch_cw)))
+        self._live = {}
+
+    def submit(self, code: Code, prm: DecodeParams, llr: np.ndarray) -> int:
+        want = np.int8 if code.g == 2 else np.int16
+        if llr.dtype != want or not llr.flags["C_CONTIGUOUS"]:
+            raise ValueError(f"llr must be a C-contiguous {np.dtype(want).name} array")
+        batch = int(llr.shape[0])
+        hard = np.empty(code.hard_shape(batch), dtype=np.uint8)
+        ok = np.empty(batch, dtype=np.uint8)
+        it = np.empty(batch, dtype=np.int16)
+        t = ldpcx_server_submit(self.handle, code.handle, prm, batch, llr.ctypes.data, hard.ctypes.data,
+                                ok.ctypes.data, it.ctypes.data)
+        self._live[t] = (llr, hard, ok, it)
+        return t
+
+    def poll(self, ticket: int) -> bool:
+        return ldpcx_server_poll(self.handle, ticket)
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        st, ts, ta, td = ldpcx_server_wait(self.handle, ticket, timeout_ms)
+        if st == E_TIMEOUT:
+            raise TimeoutError(ldpcx_last_error())
+        bufs = self._live.pop(ticket, None)
+        if st != OK:
+            raise LdpcxError(st, ldpcx_last_error())
+        _, hard, ok, it = bufs
+        return hard, ok, it, (ts, ta, td)
+
+    def cancel(self, ticket: int) -> None:
+        ldpcx_server_cancel(self.handle, ticket)
+
+    def stats(self) -> dict:
+        return ldpcx_server_stats(self.handle)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            ldpcx_server_destroy(self.handle)
+            self.handle = None
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

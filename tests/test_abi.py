@@ -93,3 +93,15 @@ def test_validation_rejects_malformed_codes():
     d, k = _desc(code15)
     _expect(d, L.E_UNSUPPORTED)
     assert L.ldpcx_last_error() != ""
+
+
+def test_server_config_validation():
+    """Bad server configurations are rejected on the host before any device call."""
+    for cfg in (L.ServerConfig(0, 2, 0, 0), L.ServerConfig(1 << 20, 0, 0, 0), L.ServerConfig(1 << 20, 2, 7, 0),
+                L.ServerConfig(1 << 20, 2, 0, -1), L.ServerConfig(1 << 20, 65, 0, 0)):
+        with pytest.raises(L.LdpcxError) as ei:
+            L.ldpcx_server_create(cfg)
+        assert ei.value.status == L.E_INVAL
+    for fn, args in ((L.lib().ldpcx_server_poll, (None, 1, None)), (L.lib().ldpcx_server_cancel, (None, 1)),
+                     (L.lib().ldpcx_server_destroy, (None,)), (L.lib().ldpcx_decode_ragged, (None, -1, None))):
+        assert fn(*args) == L.E_INVAL
