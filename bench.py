@@ -29,10 +29,10 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 # Kernel sources whose hash a counter summary is tied to, per kernel family.
 FAMILY_SOURCES = {
-    "bin_qc_packed": ["k_bin_qc.hip"],
-    "bin_lds": ["k_bin_lds.hip"],
-    "bin_interleaved": ["k_bin_il.hip"],
-    "minmax_interleaved": ["k_nb.hip"],
+    "bin_qc_packed": ["k_bin_qc.hip", "dev_bin_qc.h", "dev_common.h"],
+    "bin_lds": ["k_bin_lds.hip", "dev_bin_lds.h", "dev_common.h"],
+    "bin_interleaved": ["k_bin_il.hip", "dev_bin_il.h", "dev_common.h"],
+    "minmax_interleaved": ["k_nb.hip", "dev_nb.h", "dev_common.h"],
 }
 
 
@@ -86,12 +86,23 @@ def main() -> None:
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle time")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one 256 MiB device-to-device copy (counter calibration)")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving mix instead: Poisson arrivals of mixed requests, continuous batching vs "
+                         "per-request decoding, p50/p99 latency (one JSON line per mode and load)")
+    ap.add_argument("--rho", type=str, default="0.1,0.3,0.5,0.7,0.9,1.1", help="--serve: loads, fractions of capacity")
+    ap.add_argument("--requests", type=int, default=2000, help="--serve: measured requests per load")
+    ap.add_argument("--warm-requests", type=int, default=200, help="--serve: warm-up requests per load")
+    ap.add_argument("--budget-gib", type=float, default=8.0, help="--serve: server HBM budget")
+    ap.add_argument("--modes", type=str, default="continuous,per_request", help="--serve: serving modes")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); codewords are "
               "independent, so a multi-GPU run would split the batch with no exchange step.", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        serve_main(args)
+        return
 
     import torch
     from paper_2508_03567_amd import ldpcx as L
@@ -213,6 +224,125 @@ def main() -> None:
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
+
+
+# ------------------------------------------------------------------ serving mix
+SERVE_MIX = (0.4, 0.3, 0.1, 0.2)      # share of requests per code (n192, n2304, n64800, GF(64) n192)
+SERVE_EBN0_CFG1 = (1.0, 1.5, 2.0, 2.5, 3.0)
+SERVE_MAX_CW = 4096
+
+
+def serve_pools(S, sizes):
+    """Seeded input pools per (code, Eb/N0); a request takes a slice starting at a random
+    offset (wrapping around), so its inputs are fixed by the serving seed alone."""
+    pools = {}
+    for cfg, size in sizes.items():
+        ebs = SERVE_EBN0_CFG1 if cfg == 1 else (None,)
+        for eb in ebs:
+            w = S.workload(cfg, batch=size, ebn0_db=eb)
+            _, llr = S.make_inputs(w, seed_offset=4200)
+            pools[(cfg, eb)] = (w, np.ascontiguousarray(llr))
+            print(f"serve: pool {w.name} Eb/N0 {w.ebn0_db} dB, {size} codewords", file=sys.stderr, flush=True)
+    return pools
+
+
+def serve_requests(pools, n, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(n):
+        cfg = int(rng.choice(4, p=SERVE_MIX))
+        size = int(np.floor(np.exp(rng.uniform(0.0, np.log(SERVE_MAX_CW + 1)))))
+        size = max(1, min(SERVE_MAX_CW, size))
+        eb = float(rng.choice(SERVE_EBN0_CFG1)) if cfg == 1 else None
+        w, pool = pools[(cfg, eb)]
+        off = int(rng.integers(0, pool.shape[0]))
+        idx = (off + np.arange(size)) % pool.shape[0]
+        reqs.append((cfg, w, np.ascontiguousarray(pool[idx])))
+    return reqs
+
+
+def serve_run(L, codes, prms, reqs, mode, budget, arrivals):
+    """Submit reqs at the given arrival offsets (seconds; None = all at once) and wait for
+    every one.  Returns per-request (latency_s, info_bits) and the makespan."""
+    import threading
+    srv = L.Server(hbm_budget=budget, max_inflight=4 if mode == "continuous" else 1, mode=mode)
+    tickets = [None] * len(reqs)
+    t_arr = [0.0] * len(reqs)
+    start = time.perf_counter()
+
+    def client():
+        for i, (cfg, w, llr) in enumerate(reqs):
+            if arrivals is not None:
+                while True:
+                    dt = start + arrivals[i] - time.perf_counter()
+                    if dt <= 0:
+                        break
+                    time.sleep(min(dt, 0.002) if dt > 0.0005 else 0)
+            t_arr[i] = time.perf_counter()
+            tickets[i] = srv.submit(codes[cfg], prms[cfg], llr)
+
+    th = threading.Thread(target=client)
+    th.start()
+    lat, bits = [], []
+    for i, (cfg, w, llr) in enumerate(reqs):
+        while tickets[i] is None:
+            time.sleep(0.0002)
+        _, _, _, (ts, ta, td) = srv.wait(tickets[i])
+        # server clock: submit -> outputs in host memory; the client's own lag before
+        # submit (arrival -> submit) is added from the client's clock
+        lag = max(0.0, t_arr[i] - (start + (arrivals[i] if arrivals is not None else 0.0)))
+        lat.append((td - ts) * 1e-6 + lag)
+        bits.append(w.info_bits_per_cw * llr.shape[0])
+    th.join()
+    makespan = time.perf_counter() - start
+    stats = srv.stats()
+    srv.close()
+    return np.array(lat), np.array(bits, dtype=np.float64), makespan, stats
+
+
+def serve_main(args) -> None:
+    import torch
+    from paper_2508_03567_amd import ldpcx as L
+    from paper_2508_03567_amd import synth as S
+
+    torch.cuda.init()
+    pools = serve_pools(S, {0: SERVE_MAX_CW, 1: SERVE_MAX_CW, 2: 1024, 3: SERVE_MAX_CW})
+    codes, prms = {}, {}
+    for cfg in range(4):
+        w = S.workload(cfg)
+        codes[cfg] = L.Code(w.code)
+        prms[cfg] = L.params(w.rule, w.schedule, w.max_iters, early_stop=True, nms_num=w.nms_num,
+                             nms_shift=w.nms_shift, oms_offset=w.oms_offset, msg_max=w.msg_max)
+    budget = int(args.budget_gib * (1 << 30))
+    modes = args.modes.split(",")
+    n_meas, n_warm = args.requests, args.warm_requests
+    # capacity of the continuous server on this mix: everything submitted at once
+    cap_reqs = serve_requests(pools, max(200, n_meas // 4), seed=41)
+    serve_run(L, codes, prms, cap_reqs[:20], "continuous", budget, None)  # warm-up
+    _, bits, span, _ = serve_run(L, codes, prms, cap_reqs, "continuous", budget, None)
+    capacity = len(cap_reqs) / span
+    print(f"serve: capacity {capacity:.1f} requests/s ({bits.sum() / span / 1e9:.3f} Gbit/s info) on "
+          f"{len(cap_reqs)} requests", file=sys.stderr, flush=True)
+    reqs = serve_requests(pools, n_warm + n_meas, seed=42)
+    for rho in [float(x) for x in args.rho.split(",")]:
+        lam = rho * capacity
+        rng = np.random.default_rng(int(rho * 1000) + 7)
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs)))
+        for mode in modes:
+            lat, bits, span, st = serve_run(L, codes, prms, reqs, mode, budget, arrivals)
+            m = lat[n_warm:]
+            t_first = arrivals[n_warm]
+            res = {"metric": "serving mix: p50/p99 latency and decoded info Gbit/s", "mode": mode, "rho": rho,
+                   "arrival_rate_per_s": round(lam, 2), "requests": n_meas,
+                   "p50_ms": round(float(np.percentile(m, 50)) * 1e3, 3),
+                   "p99_ms": round(float(np.percentile(m, 99)) * 1e3, 3),
+                   "mean_ms": round(float(m.mean()) * 1e3, 3),
+                   "info_gbit_s": round(float(bits[n_warm:].sum()) / max(span - t_first, 1e-9) / 1e9, 4),
+                   "launches": st["launches"], "peak_bytes": st["peak_bytes"], "budget_bytes": budget,
+                   "capacity_req_s": round(capacity, 2), "data": "synthetic seeded BPSK/AWGN mix",
+                   "mix": "40/30/10/20 % of n192 NMS / n2304 OMS layered (Eb/N0 1-3 dB) / n64800 NMS / GF(64) "
+                          "n192 Min-Max, 1-4096 codewords log-uniform, early stop"}
+            print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -205,9 +205,11 @@ typedef struct ldpcx_server ldpcx_server;
  *   CONTINUOUS: whenever one of the `max_inflight` launch slots is free and requests
  *     wait, the scheduler admits waiting codewords in arrival order while the free
  *     budget allows (a request that only partly fits is split at a codeword boundary)
- *     and launches them together on the slot's stream: codes whose decoder state fits
- *     one workgroup as ONE ragged persistent launch (ldpcx_decode_ragged), long codes
- *     (interleaved decoder) as their own launch sequence on the same stream.  Requests
+ *     and launches them on the slot's stream: consecutive chunks of codes whose decoder
+ *     state fits one workgroup as ONE ragged persistent launch (ldpcx_decode_ragged),
+ *     capped at about 1.5 ms of estimated device time; a chunk of a long code
+ *     (interleaved decoder) or of more than 64 Min-Max codewords as a launch of its
+ *     own (the plain decoder's launch sequence, parallel over checks).  Requests
  *     that arrive while launches are in flight are admitted into the next free slot
  *     without waiting for those launches to end, so their work overlaps on the device.
  *   PER_REQUEST: the one-code-per-launch baseline: one request (or budget-sized

@@ -189,6 +189,9 @@ __device__ void nb_group(const JobDesc &J, int g, uint32_t *lds, uint64_t *red) 
     for (long by = 0; by < gy_out; ++by) dev::transpose_block(J.tout, g, by, tile);
 }
 
+// IL: whether the interleaved families are compiled in (they dominate the register
+// budget, so mixes of workgroup-resident codes run a variant without them).
+template <bool IL>
 __device__ __forceinline__ void run_item(const JobDesc &J, const Item &it, uint32_t *lds, uint64_t *red) {
     switch (it.type) {
     case I_QC:
@@ -203,8 +206,11 @@ __device__ __forceinline__ void run_item(const JobDesc &J, const Item &it, uint3
             dev::lds::lds_item<false>(J.C, J.R, J.max_iters, J.early_stop, J.batch, J.cpw, J.io, it.blk,
                                       (unsigned char *)lds);
         break;
-    case I_IL: il_group(J, it.blk, lds, red); break;
+    case I_IL:
+        if (IL) il_group(J, it.blk, lds, red);
+        break;
     default:
+        if (!IL) break;
         switch (J.C.g) {
         case 4: nb_group<4>(J, it.blk, lds, red); break;
         case 8: nb_group<8>(J, it.blk, lds, red); break;
@@ -216,6 +222,7 @@ __device__ __forceinline__ void run_item(const JobDesc &J, const Item &it, uint3
 }
 
 // Workgroup w runs items [wg_ptr[w], wg_ptr[w + 1]) in order.
+template <bool IL>
 __global__ void __launch_bounds__(kThreads) k_ragged(const JobDesc *__restrict__ jobs,
                                                      const Item *__restrict__ items,
                                                      const int *__restrict__ wg_ptr) {
@@ -224,7 +231,7 @@ __global__ void __launch_bounds__(kThreads) k_ragged(const JobDesc *__restrict__
     const int i0 = wg_ptr[blockIdx.x], i1 = wg_ptr[blockIdx.x + 1];
     for (int i = i0; i < i1; ++i) {
         const Item it = items[i];
-        run_item(jobs[it.job], it, lds, red);
+        run_item<IL>(jobs[it.job], it, lds, red);
         __syncthreads();
     }
 }
@@ -358,13 +365,15 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
         // Errors of the calls above were checked where they happened; clear the sticky
         // last-error state so that the launch check below reports the launch only.
         (void)hipGetLastError();
+        bool any_il = false;
+        for (const Item &it : items) any_il |= it.type == I_IL || it.type == I_NB;
+        const void *kern = any_il ? (const void *)k_ragged<true> : (const void *)k_ragged<false>;
         if (lds > 64 * 1024) {
-            hipError_t ea = hipFuncSetAttribute((const void *)k_ragged, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                (int)lds);
+            hipError_t ea = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (ea != hipSuccess) return cleanup(), fail_hip(ea, "persistent kernel LDS attribute");
         }
         int per_cu = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ragged, kThreads, lds);
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, lds);
         if (e != hipSuccess || per_cu < 1) return cleanup(), fail(LDPCX_E_UNSUPPORTED, "persistent kernel does not fit");
         const int grid = (int)std::min<long>((long)per_cu * device_info(device).cus, (long)items.size());
 
@@ -408,7 +417,8 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
         const JobDesc *djobs = (const JobDesc *)dbuf;
         const Item *ditems = (const Item *)(dbuf + o_items);
         const int *dptr = (const int *)(dbuf + o_ptr);
-        hipLaunchKernelGGL(k_ragged, dim3(grid), dim3(kThreads), lds, s, djobs, ditems, dptr);
+        if (any_il) hipLaunchKernelGGL(k_ragged<true>, dim3(grid), dim3(kThreads), lds, s, djobs, ditems, dptr);
+        else hipLaunchKernelGGL(k_ragged<false>, dim3(grid), dim3(kThreads), lds, s, djobs, ditems, dptr);
         e = hipGetLastError();
         cleanup();
         if (e != hipSuccess) {

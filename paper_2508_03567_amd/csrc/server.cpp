@@ -31,8 +31,12 @@ namespace {
 using Clock = std::chrono::steady_clock;
 
 // Interleaved-family chunks with at least this many groups of 64 codewords run as
-// their own launch sequence (parallel over checks), not as per-group ragged items.
-constexpr int kOwnLaunchGroups = 32;
+// their own launch sequence (parallel over checks and codewords), not as per-group
+// ragged items (one workgroup per 64 codewords).
+constexpr int kOwnLaunchGroups = 2;
+// A ragged launch stops taking chunks once its estimated device time reaches this,
+// so that launches stay short and the slots pipeline.
+constexpr double kLaunchTargetUs = 1500.0;
 
 struct Request {
     ldpcx_code *code = nullptr;
@@ -84,6 +88,18 @@ size_t chunk_bytes(const Request &r, int ncw) {
     if (r.family == FAMILY_BIN_IL) b += bin_il_work_bytes(r.code->dev, r.prm.max_iters, ncw);
     else if (r.family == FAMILY_NB) b += nb_work_bytes(r.code->dev, r.prm.max_iters, ncw);
     return b;
+}
+
+// Rough device time of a chunk at the iteration cap (only used to size launches):
+// edge updates per microsecond per family, from the kernels' measured throughput.
+double est_us(const Request &r, int ncw) {
+    const double work = (double)ncw * std::max(1, r.prm.max_iters) * r.code->dev.E;
+    switch (r.family) {
+    case FAMILY_BIN_QC: return work / 2.5e6;
+    case FAMILY_BIN_LDS: return work / 1.0e6;
+    case FAMILY_BIN_IL: return work / 2.5e5;
+    default: return work * ((double)r.code->g * r.code->g / 4096.0) / 3.0e3;
+    }
 }
 
 // Largest n in [0, cap] with chunk_bytes(r, n) <= avail (monotone in n).
@@ -160,9 +176,15 @@ struct ldpcx_server {
         std::vector<Chunk> take;
         size_t charge = 0;
         int cw_total = 0;
+        double us = 0;
         while (!queue.empty()) {
             const uint64_t id = queue.front();
             Request &r = reqs.at(id);
+            const bool own = cfg.mode == LDPCX_SERVE_PER_REQUEST || r.family == FAMILY_BIN_IL ||
+                             (r.family == FAMILY_NB && pad64(r.batch - r.next_cw) / 64 >= kOwnLaunchGroups);
+            // A launch is either one chunk with its own launch sequence or a ragged batch.
+            if (own && !take.empty()) break;
+            if (!take.empty() && us >= kLaunchTargetUs) break;
             const int rem = r.batch - r.next_cw;
             int cap = rem;
             if (cfg.max_launch_cw > 0) cap = std::min(cap, cfg.max_launch_cw - cw_total);
@@ -177,9 +199,9 @@ struct ldpcx_server {
             c.cw0 = r.next_cw;
             c.ncw = n;
             c.charge = chunk_bytes(r, n);
-            c.own_launch = cfg.mode == LDPCX_SERVE_PER_REQUEST || r.family == FAMILY_BIN_IL ||
-                           (r.family == FAMILY_NB && pad64(n) / 64 >= kOwnLaunchGroups);
+            c.own_launch = own;
             take.push_back(c);
+            us += est_us(r, n);
             r.next_cw += n;
             r.inflight += 1;
             if (r.t_admit < 0) r.t_admit = now_us();
@@ -187,7 +209,7 @@ struct ldpcx_server {
             cw_total += n;
             if (r.next_cw < r.batch) break;  // arrival order: nothing passes a partly admitted request
             queue.pop_front();
-            if (cfg.mode == LDPCX_SERVE_PER_REQUEST) break;
+            if (own) break;
         }
         return take;
     }
