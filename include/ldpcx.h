@@ -181,14 +181,17 @@ ldpcx_status ldpcx_tune(const ldpcx_code *code, const ldpcx_decode_params *param
  * kernel family (0 = LDS-resident binary, 1 = interleaved binary, 2 = interleaved
  * min-max, 3 = packed two-codewords-per-lane binary for quasi-cyclic codes, available
  * when every layer of z rows consists of z x z circulant blocks, at most 16 layers and
- * 8 blocks per layer), codewords per workgroup, threads per workgroup. */
+ * 8 blocks per layer), codewords per workgroup (family 1: codewords per launch
+ * sequence; larger batches run as consecutive slices), threads per workgroup. */
 ldpcx_status ldpcx_plan_info(const ldpcx_code *code, const ldpcx_decode_params *params,
                              int32_t batch, int32_t *family, int32_t *cw_per_wg,
                              int32_t *threads);
 
 /* Pin the launch configuration used for (code, params, batch class) instead of the
  * default or tuned one.  family as in ldpcx_plan_info; cw_per_wg and threads are used by
- * family 0 (threads a multiple of 64 in [64, 1024]).  The pinned plan must be able to
+ * family 0 (threads a multiple of 64 in [64, 1024]); cw_per_wg by family 3 (even, the
+ * pairs' rows at most 512 threads) and by family 1 (slice size, rounded up to a multiple
+ * of 128 and capped by the batch and the 31-bit offset limit).  The pinned plan must be able to
  * run the requested schedule (LDPCX_E_UNSUPPORTED otherwise; family 1 and 2 are
  * flooding only).  Results never depend on the plan. */
 ldpcx_status ldpcx_plan_set(ldpcx_code *code, const ldpcx_decode_params *params, int32_t batch,

@@ -7,23 +7,6 @@
 namespace ldpcx {
 namespace dev {
 
-struct PkNorm {
-    v2s num, shift, off;
-};
-
-__device__ __forceinline__ PkNorm pk_norm_params(const BinRule &R) {
-    PkNorm P;
-    const bool nms = R.rule == LDPCX_RULE_NMS, oms = R.rule == LDPCX_RULE_OMS;
-    P.num = splat(nms ? R.nms_num : 1);
-    P.shift = splat(nms ? R.nms_shift : 0);
-    P.off = splat(oms ? R.oms_offset : 0);
-    return P;
-}
-
-__device__ __forceinline__ v2s pk_norm(const PkNorm &P, v2s m) {
-    return pmax(((m * P.num) >> P.shift) - P.off, splat(0));
-}
-
 // Byte offset of the Lambda word of an edge {4 c Z, 4 s} for row i (given as 4 i):
 // 4 (c Z + (i + s) mod Z), with the wrap done as an unsigned minimum (i + s < 2Z
 // since s < Z).  Virtual edges carry {4 n, 0} and map row i to its dummy slot n + i.

@@ -17,6 +17,26 @@ __device__ __forceinline__ v2s pmax(v2s a, v2s b) { return __builtin_elementwise
 __device__ __forceinline__ v2s as_v2s(uint32_t u) { return __builtin_bit_cast(v2s, u); }
 __device__ __forceinline__ uint32_t as_u32(v2s v) { return __builtin_bit_cast(uint32_t, v); }
 
+// Magnitude normalisation of the min-sum variants on packed pairs, one formula for
+// the three rules: f(m) = max(((m * num) >> shift) - off, 0) with (num, shift, off)
+// = (num, shift, 0) for NMS, (1, 0, off) for OMS and (1, 0, 0) for MS.
+struct PkNorm {
+    v2s num, shift, off;
+};
+
+__device__ __forceinline__ PkNorm pk_norm_params(const BinRule &R) {
+    PkNorm P;
+    const bool nms = R.rule == LDPCX_RULE_NMS, oms = R.rule == LDPCX_RULE_OMS;
+    P.num = splat(nms ? R.nms_num : 1);
+    P.shift = splat(nms ? R.nms_shift : 0);
+    P.off = splat(oms ? R.oms_offset : 0);
+    return P;
+}
+
+__device__ __forceinline__ v2s pk_norm(const PkNorm &P, v2s m) {
+    return pmax(((m * P.num) >> P.shift) - P.off, splat(0));
+}
+
 // Tiled transpose, one 64 x 64 tile per block of 256 threads:
 // out[c * ld_out + r] = (r < rows) ? in[r * ld_in + c] : 0 for r < rows_out, c < cols.
 struct TransposeArgs {
@@ -71,6 +91,10 @@ __device__ __forceinline__ void fill_block(const FillArgs &A, long bx) {
 }
 
 __host__ __device__ inline long fill_gx(const FillArgs &A) { return (long)((A.n + 4095) / 4096); }
+
+// Index of the calling wavefront in its workgroup, as a wave-uniform (scalar) value,
+// so that everything derived from it (node and edge indices, offsets) stays scalar.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
 // Wave-wide OR of a 64-bit value (all lanes receive the result).
 __device__ __forceinline__ uint64_t wave_or64(uint64_t v) {

@@ -1,5 +1,10 @@
 // Launch sequence of the interleaved binary min-sum decoder (flooding): one
 // kernel per phase, the phase bodies being the device functions of dev_bin_il.h.
+// A batch larger than the sub-batch runs as consecutive launch sequences over
+// slices of the codewords (each slice's state stays small enough to remain
+// resident in the last-level cache, and every offset fits 31 bits).
+#include <algorithm>
+
 #include "dev_bin_il.h"
 
 namespace ldpcx {
@@ -13,14 +18,15 @@ __global__ void __launch_bounds__(256) k_tr(dev::TransposeArgs T) {
     dev::transpose_block(T, blockIdx.x, blockIdx.y, tile);
 }
 __global__ void __launch_bounds__(256) k_fill(dev::FillArgs F) { dev::fill_block(F, blockIdx.x); }
-__global__ void __launch_bounds__(256) k_init(Args A) { dev::il::init_block(A, blockIdx.x); }
+__global__ void __launch_bounds__(256) k_init_edges(Args A) { dev::il::init_edges_block(A, blockIdx.x, blockIdx.y); }
+__global__ void __launch_bounds__(256) k_init_vars(Args A) { dev::il::init_vars_block(A, blockIdx.x, blockIdx.y); }
 __global__ void __launch_bounds__(256) k_syn(Args A, int slot) { dev::il::syn_block(A, slot, blockIdx.x); }
 __global__ void __launch_bounds__(256) k_cn(Args A, int k) { dev::il::cn_block(A, k, blockIdx.x, blockIdx.y); }
 __global__ void __launch_bounds__(256) k_vn(Args A, int k) { dev::il::vn_block(A, k, blockIdx.x, blockIdx.y); }
 __global__ void __launch_bounds__(256) k_bytes(Args A) { dev::il::bytes_block(A, blockIdx.x); }
 __global__ void __launch_bounds__(256) k_fin(Args A) { dev::il::fin_block(A, blockIdx.x); }
-__global__ void __launch_bounds__(256) k_dump(Args A, int8_t *q_t, int8_t *r_t) {
-    dev::il::dump_block(A, q_t, r_t, blockIdx.x, blockIdx.y);
+__global__ void __launch_bounds__(256) k_lambda(Args A, int16_t *lam_t) {
+    dev::il::lambda_block(A, lam_t, blockIdx.x, blockIdx.y);
 }
 
 hipError_t tr(const dev::TransposeArgs &T, hipStream_t s) {
@@ -42,24 +48,20 @@ hipError_t fill(const dev::FillArgs &F, hipStream_t s) {
         if (e_ != hipSuccess) return e_; \
     } while (0)
 
-}  // namespace
-
-size_t bin_il_work_bytes(const DevCode &C, int max_iters, int batch) {
-    return dev::il::carve(C, max_iters, batch).total;
-}
-
-hipError_t launch_bin_il(const DevCode &C, const BinRule &R, int max_iters, int early_stop, int batch, void *ws,
-                         const DecodeIO &io, int8_t *dump_scratch, hipStream_t s) {
+// One launch sequence over `batch` codewords (batch <= the sub-batch limit).
+hipError_t run_slice(const DevCode &C, const BinRule &R, int max_iters, int early_stop, int batch, void *ws,
+                     const DecodeIO &io, int8_t *dump_scratch, hipStream_t s) {
     const Args A = dev::il::make_args(C, R, max_iters, early_stop, batch, ws, io);
     const dim3 blk(256);
     LDPCX_CHECK(tr(dev::il::tr_in(A), s));
-    hipLaunchKernelGGL(k_init, dim3((unsigned)dev::il::grid_init(A)), blk, 0, s, A);
-    LDPCX_CHECK(hipGetLastError());
-    LDPCX_CHECK(fill(dev::il::fill_st(A), s));
     LDPCX_CHECK(fill(dev::il::fill_unsat(A), s));
     LDPCX_CHECK(fill(dev::il::fill_it(A), s));
-    const dim3 gcn((unsigned)dev::il::grid_cn_x(A), (unsigned)A.Gn);
-    const dim3 gvn((unsigned)dev::il::grid_vn_x(A), (unsigned)A.Gn);
+    const unsigned G = (unsigned)A.G;
+    hipLaunchKernelGGL(k_init_edges, dim3((unsigned)dev::il::grid_edges_x(A), G), blk, 0, s, A);
+    hipLaunchKernelGGL(k_init_vars, dim3((unsigned)dev::il::grid_vars_x(A), G), blk, 0, s, A);
+    LDPCX_CHECK(hipGetLastError());
+    const dim3 gcn((unsigned)dev::il::grid_rows_x(A), G);
+    const dim3 gvn((unsigned)dev::il::grid_vars_x(A), G);
     const dim3 gsyn((unsigned)dev::il::grid_syn(A));
     for (int k = 1; k <= max_iters; ++k) {
         if (early_stop) hipLaunchKernelGGL(k_syn, gsyn, blk, 0, s, A, k);
@@ -73,14 +75,51 @@ hipError_t launch_bin_il(const DevCode &C, const BinRule &R, int max_iters, int 
     LDPCX_CHECK(hipGetLastError());
     LDPCX_CHECK(tr(dev::il::tr_out(A), s));
     if (io.dump_a) {
-        const size_t Bp = A.Bp;
-        int8_t *q_t = dump_scratch;
-        int8_t *r_t = dump_scratch + align_up((size_t)C.E * Bp, 256);
-        hipLaunchKernelGGL(k_dump, gcn, blk, 0, s, A, q_t, r_t);
+        const long Bp = A.Bp;
+        int16_t *lam_t = (int16_t *)dump_scratch;
+        hipLaunchKernelGGL(k_lambda, gvn, blk, 0, s, A, lam_t);
         LDPCX_CHECK(hipGetLastError());
-        LDPCX_CHECK(tr(dev::TransposeArgs{q_t, io.dump_a, C.E, batch, (long)Bp, C.E, C.E, 1}, s));
-        LDPCX_CHECK(tr(dev::TransposeArgs{r_t, io.dump_b, C.E, batch, (long)Bp, C.E, C.E, 1}, s));
-        LDPCX_CHECK(tr(dev::TransposeArgs{A.w.lam, io.dump_c, C.n, batch, (long)Bp, C.n, C.n, 2}, s));
+        LDPCX_CHECK(tr(dev::TransposeArgs{A.w.q, io.dump_a, C.E, batch, Bp, C.E, C.E, 1}, s));
+        LDPCX_CHECK(tr(dev::TransposeArgs{A.w.r, io.dump_b, C.E, batch, Bp, C.E, C.E, 1}, s));
+        LDPCX_CHECK(tr(dev::TransposeArgs{lam_t, io.dump_c, C.n, batch, Bp, C.n, C.n, 2}, s));
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+int bin_il_sub_batch(const DevCode &C, int batch, int want) {
+    int sub = want > 0 ? want : 1024;
+    sub = std::min(sub, dev::il::max_sub_batch(C));
+    sub = dev::il::pad128(std::max(sub, 1));
+    return std::min(sub, dev::il::pad128(std::max(batch, 1)));
+}
+
+size_t bin_il_work_bytes(const DevCode &C, int max_iters, int batch, int sub) {
+    return dev::il::carve(C, max_iters, std::min(batch, bin_il_sub_batch(C, batch, sub))).total;
+}
+
+size_t bin_il_dump_bytes(const DevCode &C, int batch, int sub) {
+    return align_up((size_t)C.n * dev::il::pad128(std::min(batch, bin_il_sub_batch(C, batch, sub))) * 2, 256);
+}
+
+hipError_t launch_bin_il(const DevCode &C, const BinRule &R, int max_iters, int early_stop, int batch, int sub,
+                         void *ws, const DecodeIO &io, int8_t *dump_scratch, hipStream_t s) {
+    const int step = bin_il_sub_batch(C, batch, sub);
+    const size_t nbytes = (size_t)(C.n + 7) / 8;
+    for (int b0 = 0; b0 < batch; b0 += step) {
+        const int nb = std::min(step, batch - b0);
+        DecodeIO sl = io;
+        sl.llr = (const int8_t *)io.llr + (size_t)b0 * C.n;
+        sl.hard = (uint8_t *)io.hard + (size_t)b0 * nbytes;
+        sl.ok = io.ok + b0;
+        sl.iters = io.iters + b0;
+        if (io.dump_a) {
+            sl.dump_a = (int8_t *)io.dump_a + (size_t)b0 * C.E;
+            sl.dump_b = (int8_t *)io.dump_b + (size_t)b0 * C.E;
+            sl.dump_c = (int16_t *)io.dump_c + (size_t)b0 * C.n;
+        }
+        LDPCX_CHECK(run_slice(C, R, max_iters, early_stop, nb, ws, sl, dump_scratch, s));
     }
     return hipSuccess;
 }

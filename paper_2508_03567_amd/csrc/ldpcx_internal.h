@@ -21,6 +21,7 @@ struct DevCode {
     const int *col_idx;    // [E]
     const int *vn_ptr;     // [n + 1]  edges of each variable node (CSC)
     const int *vn_ref;     // [E] binary: (check << 4) | position in row ; g > 2: edge id
+    const int *vn_edge;    // [E] CSR edge id of every CSC entry
     const uint8_t *h;      // [E] GF coefficient (g > 2)
     const uint8_t *hinv;   // [E] its inverse (g > 2)
     const uint8_t *gfmul;  // [g * g] multiplication table (g > 2)
@@ -86,19 +87,23 @@ hipError_t launch_bin_qc(const QcDesc &Q, const DevCode &C, const BinRule &R, in
                          int layered, int batch, int npairs, const DecodeIO &io, hipStream_t s);
 size_t bin_qc_smem_bytes(const QcDesc &Q, const DevCode &C, int layered, int npairs);
 
-// Interleaved (codeword-per-lane) binary flooding decoder, state in device memory.
+// Interleaved binary flooding decoder (two codewords per lane), state in device memory.
 struct BinIlWork {
-    int8_t *L;        // [n][Bp]
-    int16_t *lam;     // [n][Bp]
-    uint32_t *st;     // [m][Bp]
+    int8_t *L;        // [n][Bp] channel LLRs
+    int8_t *q;        // [E][Bp] variable-to-check messages (CSR edge order)
+    int8_t *r;        // [E][Bp] check-to-variable messages
     uint64_t *hb;     // [n][Bp/64] hard-decision bits
     uint64_t *unsat;  // [(max_iters + 1)][Bp/64] unsatisfied-codeword masks per syndrome test
     int16_t *it;      // [Bp]
 };
-size_t bin_il_work_bytes(const DevCode &C, int max_iters, int batch);
-// ws: workspace of bin_il_work_bytes; dump_scratch: 2 x align256(nnz * Bp) bytes when io dumps.
-hipError_t launch_bin_il(const DevCode &C, const BinRule &R, int max_iters, int early_stop, int batch, void *ws,
-                         const DecodeIO &io, int8_t *dump_scratch, hipStream_t s);
+// Codewords per launch sequence for a requested sub-batch (0 = default): a multiple of
+// 128, at most the batch (rounded up) and the 31-bit offset limit of the code.
+int bin_il_sub_batch(const DevCode &C, int batch, int sub);
+size_t bin_il_work_bytes(const DevCode &C, int max_iters, int batch, int sub);
+size_t bin_il_dump_bytes(const DevCode &C, int batch, int sub);
+// ws: workspace of bin_il_work_bytes; dump_scratch: bin_il_dump_bytes when io dumps.
+hipError_t launch_bin_il(const DevCode &C, const BinRule &R, int max_iters, int early_stop, int batch, int sub,
+                         void *ws, const DecodeIO &io, int8_t *dump_scratch, hipStream_t s);
 
 // Interleaved Min-Max decoder over GF(g).
 struct NbWork {

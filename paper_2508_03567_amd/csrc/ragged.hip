@@ -84,64 +84,92 @@ __device__ __forceinline__ uint64_t group_or(uint64_t v, uint64_t *unsat, long s
 }
 
 // ------------------------------------------------ interleaved binary, one group
+// Syndrome of one group of 128 codewords: words 2g and 2g + 1 of slot_k (codeword
+// 128 g + 2 l + h in bit l of word 2 g + h); returns their OR (uniform).
 __device__ uint64_t il_syn(const dev::il::Args &A, int slot_k, int g, uint64_t *red) {
     const DevCode &C = A.C;
-    uint64_t acc = 0;
+    const int W = 2 * A.G;
+    uint64_t acc0 = 0, acc1 = 0;
     for (int row = threadIdx.x; row < C.m; row += kThreads) {
-        uint64_t p = 0;
-        for (int e = C.row_ptr[row]; e < C.row_ptr[row + 1]; ++e) p ^= A.w.hb[(long)C.col_idx[e] * A.Gn + g];
-        acc |= p;
+        uint64_t p0 = 0, p1 = 0;
+        for (int e = C.row_ptr[row]; e < C.row_ptr[row + 1]; ++e) {
+            const uint64_t *h = A.w.hb + (size_t)C.col_idx[e] * W + 2 * g;
+            p0 ^= h[0];
+            p1 ^= h[1];
+        }
+        acc0 |= p0;
+        acc1 |= p1;
     }
-    return group_or(acc, A.w.unsat, (long)slot_k * A.Gn + g, red);
+    acc0 = dev::wave_or64(acc0);
+    acc1 = dev::wave_or64(acc1);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[2 * w] = acc0;
+        red[2 * w + 1] = acc1;
+    }
+    __syncthreads();
+    const uint64_t u0 = red[0] | red[2] | red[4] | red[6];
+    const uint64_t u1 = red[1] | red[3] | red[5] | red[7];
+    if (threadIdx.x == 0) {
+        A.w.unsat[(size_t)slot_k * W + 2 * g] = u0;
+        A.w.unsat[(size_t)slot_k * W + 2 * g + 1] = u1;
+    }
+    __syncthreads();
+    const uint64_t u = u0 | u1;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return ((uint64_t)hi << 32) | lo;
 }
 
+// Every phase of the interleaved binary decoder for codewords [128 g, 128 g + 128).
 __device__ void il_group(const JobDesc &J, int g, uint32_t *lds, uint64_t *red) {
     const dev::il::Args &A = J.il;
     const DevCode &C = A.C;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const long Bp = A.Bp;
-    const int b = g * 64 + lane;
+    const int W = 2 * A.G;
     unsigned char *tile = (unsigned char *)lds;
     const long gx_in = dev::transpose_gx(J.tin);
-    for (long bx = 0; bx < gx_in; ++bx) dev::transpose_block(J.tin, bx, g, tile);
-    for (int s = threadIdx.x; s <= A.max_iters; s += kThreads) A.w.unsat[(long)s * A.Gn + g] = 0;
-    for (int row = w; row < C.m; row += 4) A.w.st[(long)row * Bp + b] = 0u;
-    if (w == 0) A.w.it[b] = 0;
-    // Lambda = L, decisions of iteration 0
-    for (int v = w; v < C.n; v += 4) {
-        const long off = (long)v * Bp + b;
-        const int8_t l = A.w.L[off];
-        A.w.lam[off] = l;
-        const uint64_t bits = __ballot(l < 0 && b < A.batch);
-        if (lane == 0) A.w.hb[(long)v * A.Gn + g] = bits;
+    for (int half = 0; half < 2; ++half)
+        for (long bx = 0; bx < gx_in; ++bx) dev::transpose_block(J.tin, bx, 2 * g + half, tile);
+    for (int s = threadIdx.x; s <= A.max_iters; s += kThreads) {
+        A.w.unsat[(size_t)s * W + 2 * g] = 0;
+        A.w.unsat[(size_t)s * W + 2 * g + 1] = 0;
     }
+    if (threadIdx.x < dev::il::kGroup) A.w.it[g * dev::il::kGroup + threadIdx.x] = 0;
     __syncthreads();
-    const int gcn = (int)dev::il::grid_cn_x(A), gvn = (int)dev::il::grid_vn_x(A);
+    const int ge = (int)dev::il::grid_edges_x(A), gv = (int)dev::il::grid_vars_x(A), gr = (int)dev::il::grid_rows_x(A);
+    for (int bx = 0; bx < ge; ++bx) dev::il::init_edges_block(A, bx, g);
+    for (int bx = 0; bx < gv; ++bx) dev::il::init_vars_block(A, bx, g);
+    __syncthreads();
     for (int k = 1; k <= A.max_iters; ++k) {
         if (A.early_stop && il_syn(A, k, g, red) == 0) break;
-        for (int bx = 0; bx < gcn; ++bx) dev::il::cn_block(A, k, bx, g);
+        for (int bx = 0; bx < gr; ++bx) dev::il::cn_block(A, k, bx, g);
         __syncthreads();
-        for (int bx = 0; bx < gvn; ++bx) dev::il::vn_block(A, k, bx, g);
+        for (int bx = 0; bx < gv; ++bx) dev::il::vn_block(A, k, bx, g);
         __syncthreads();
     }
-    const uint64_t u = il_syn(A, 0, g, red);
-    if (w == 0 && b < A.batch) {
-        A.io.ok[b] = ((u >> lane) & 1ull) ? 0 : 1;
-        A.io.iters[b] = A.w.it[b];
+    il_syn(A, 0, g, red);
+    if (threadIdx.x < dev::il::kGroup) {
+        const int b = g * dev::il::kGroup + threadIdx.x;
+        if (b < A.batch) {
+            const uint64_t w = A.w.unsat[2 * g + (threadIdx.x & 1)];
+            A.io.ok[b] = ((w >> (threadIdx.x >> 1)) & 1ull) ? 0 : 1;
+            A.io.iters[b] = A.w.it[b];
+        }
     }
     const int nbytes = (C.n + 7) >> 3;
-    for (int j = w; j < nbytes; j += 4) {
+    for (int idx = threadIdx.x; idx < nbytes * dev::il::kGroup; idx += kThreads) {
+        const int j = idx / dev::il::kGroup, b = g * dev::il::kGroup + idx % dev::il::kGroup;
         uint32_t byte = 0;
-#pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int v = 8 * j + q;
-            if (v < C.n) byte |= (uint32_t)((A.w.hb[(long)v * A.Gn + g] >> lane) & 1ull) << q;
+            if (v < C.n) byte |= dev::il::hbit(A, v, b) << q;
         }
-        A.bytes_t[(long)j * Bp + b] = (uint8_t)byte;
+        A.bytes_t[(size_t)j * A.Bp + b] = (uint8_t)byte;
     }
     __syncthreads();
     const long gy_out = dev::transpose_gy(J.tout);
-    for (long by = 0; by < gy_out; ++by) dev::transpose_block(J.tout, g, by, tile);
+    for (int half = 0; half < 2; ++half)
+        for (long by = 0; by < gy_out; ++by) dev::transpose_block(J.tout, 2 * g + half, by, tile);
 }
 
 // --------------------------------------------------------- Min-Max, one group
@@ -227,7 +255,7 @@ __global__ void __launch_bounds__(kThreads) k_ragged(const JobDesc *__restrict__
                                                      const Item *__restrict__ items,
                                                      const int *__restrict__ wg_ptr) {
     extern __shared__ __align__(16) uint32_t lds[];
-    __shared__ uint64_t red[4];
+    __shared__ uint64_t red[8];
     const int i0 = wg_ptr[blockIdx.x], i1 = wg_ptr[blockIdx.x + 1];
     for (int i = i0; i < i1; ++i) {
         const Item it = items[i];
@@ -242,7 +270,7 @@ double item_cost(const JobDesc &J, const DevCode &C) {
     switch (J.family) {
     case FAMILY_BIN_QC: return it * E * 2.0 / std::max(1, J.qc.Z);
     case FAMILY_BIN_LDS: return it * E * J.cpw / kThreads;
-    case FAMILY_BIN_IL: return it * E * 64.0 * 4.0 / kThreads;
+    case FAMILY_BIN_IL: return it * E * 128.0 * 2.0 / kThreads;
     default: return it * E * 3.0 * C.g * C.g / 2.0 * 64.0 / kThreads / 8.0;
     }
 }
@@ -336,18 +364,20 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
             }
             // Interleaved families: a workspace per job, one item per group of 64 codewords.
             D.family = pl.family;
-            const size_t bytes = pl.family == FAMILY_BIN_IL ? bin_il_work_bytes(D.C, p.max_iters, jb.batch)
+            if (pl.family == FAMILY_BIN_IL && jb.batch > dev::il::max_sub_batch(D.C))
+                return cleanup(), fail(LDPCX_E_UNSUPPORTED, "batch too large for one interleaved workspace");
+            const size_t bytes = pl.family == FAMILY_BIN_IL ? dev::il::carve(D.C, p.max_iters, jb.batch).total
                                                             : nb_work_bytes(D.C, p.max_iters, jb.batch);
             void *ws = nullptr;
             if (hipMallocAsync(&ws, bytes, s) != hipSuccess) return cleanup(), fail(LDPCX_E_NOMEM, "workspace");
             workspaces.push_back(ws);
-            const long groups = pad64(jb.batch) / 64;
             if (pl.family == FAMILY_BIN_IL) {
                 D.il = dev::il::make_args(D.C, D.R, p.max_iters, p.early_stop, jb.batch, ws, D.io);
                 D.tin = dev::il::tr_in(D.il);
                 D.tout = dev::il::tr_out(D.il);
-                add(I_IL, groups);
+                add(I_IL, D.il.G);
             } else {
+                const long groups = pad64(jb.batch) / 64;
                 D.nb = dev::nb::make_args(D.C, p.max_iters, p.early_stop, jb.batch, ws, D.io);
                 const size_t need = dev::nb::cn_lds_bytes(D.nb, 4);
                 if (need > cap)

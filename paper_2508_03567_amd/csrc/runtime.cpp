@@ -146,7 +146,7 @@ Plan default_plan(const ldpcx_code *c, const ldpcx_decode_params *p, int batch) 
     } else {
         pl.family = FAMILY_BIN_IL;
         pl.schedule = LDPCX_SCHED_FLOODING;
-        pl.cpw = 64;
+        pl.cpw = bin_il_sub_batch(c->dev, batch, 1024);  // codewords per launch sequence
         pl.threads = 256;
     }
     return pl;
@@ -197,11 +197,10 @@ ldpcx_status run_plan(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &p
         ldpcx_status st = run_graph(c, p, pl, batch, io, s);
         if (st != LDPCX_E_UNSUPPORTED) return st;  // else: capture not possible, run eagerly
     }
-    size_t bytes = pl.family == FAMILY_BIN_IL ? bin_il_work_bytes(c->dev, p->max_iters, batch)
+    size_t bytes = pl.family == FAMILY_BIN_IL ? bin_il_work_bytes(c->dev, p->max_iters, batch, pl.cpw)
                                               : nb_work_bytes(c->dev, p->max_iters, batch);
-    const size_t Bp = pad64(batch);
     size_t dump_bytes = 0;
-    if (io.dump_a && pl.family == FAMILY_BIN_IL) dump_bytes = align_up((size_t)c->dev.E * Bp, 256) * 2;
+    if (io.dump_a && pl.family == FAMILY_BIN_IL) dump_bytes = bin_il_dump_bytes(c->dev, batch, pl.cpw);
     void *ws = nullptr;
     e = hipMallocAsync(&ws, bytes + dump_bytes, s);
     if (e != hipSuccess) return fail(LDPCX_E_NOMEM, std::string("workspace allocation: ") + hipGetErrorString(e));
@@ -215,7 +214,8 @@ ldpcx_status run_plan(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &p
 hipError_t enqueue_interleaved(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &pl, int batch, void *ws,
                                const DecodeIO &io, int8_t *dump_scratch, hipStream_t s) {
     if (pl.family == FAMILY_BIN_IL)
-        return launch_bin_il(c->dev, bin_rule(p), p->max_iters, p->early_stop, batch, ws, io, dump_scratch, s);
+        return launch_bin_il(c->dev, bin_rule(p), p->max_iters, p->early_stop, batch, pl.cpw, ws, io, dump_scratch,
+                             s);
     return launch_nb(c->dev, p->max_iters, p->early_stop, batch, ws, io, s);
 }
 
@@ -234,6 +234,7 @@ ldpcx_status run_graph(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &
                        hipStream_t s) {
     GraphKey key{};
     key.family = pl.family;
+    key.cpw = pl.cpw;
     key.batch = batch;
     key.params = *p;
     key.llr = io.llr;
@@ -255,7 +256,7 @@ ldpcx_status run_graph(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &
         }
         GraphEntry g{};
         g.key = key;
-        const size_t bytes = pl.family == FAMILY_BIN_IL ? bin_il_work_bytes(c->dev, p->max_iters, batch)
+        const size_t bytes = pl.family == FAMILY_BIN_IL ? bin_il_work_bytes(c->dev, p->max_iters, batch, pl.cpw)
                                                         : nb_work_bytes(c->dev, p->max_iters, batch);
         if (hipMalloc(&g.ws, bytes) != hipSuccess) return fail(LDPCX_E_NOMEM, "graph workspace allocation");
         hipStream_t cs = nullptr;
@@ -463,12 +464,15 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
             return fail(LDPCX_E_UNSUPPORTED, "variable degree above 250");
         }
         c->vn_ref.assign(E, 0);
+        c->vn_edge.assign(E, 0);
         {
             std::vector<int> fill(n, 0);
             for (int i = 0; i < m; ++i)
                 for (int e = c->row_ptr[i]; e < c->row_ptr[i + 1]; ++e) {
                     const int v = c->col_idx[e];
-                    c->vn_ref[c->vn_ptr[v] + fill[v]++] = g == 2 ? ((i << 4) | (e - c->row_ptr[i])) : e;
+                    const int t = c->vn_ptr[v] + fill[v]++;
+                    c->vn_ref[t] = g == 2 ? ((i << 4) | (e - c->row_ptr[i])) : e;
+                    c->vn_edge[t] = e;
                 }
         }
         // Layers: rows [l z, (l + 1) z) must touch disjoint columns.
@@ -530,7 +534,8 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
         const size_t o_ci = align_up(o_rp + 4 * (size_t)(m + 1), 256);
         const size_t o_vp = align_up(o_ci + 4 * (size_t)E, 256);
         const size_t o_vr = align_up(o_vp + 4 * (size_t)(n + 1), 256);
-        const size_t o_h = align_up(o_vr + 4 * (size_t)E, 256);
+        const size_t o_ve = align_up(o_vr + 4 * (size_t)E, 256);
+        const size_t o_h = align_up(o_ve + 4 * (size_t)E, 256);
         const size_t o_hi = align_up(o_h + (size_t)E, 256);
         const size_t o_mul = align_up(o_hi + (size_t)E, 256);
         const size_t o_qc = align_up(o_mul + (size_t)g * g + 4, 256);
@@ -545,6 +550,7 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
         std::memcpy(host.data() + o_ci, c->col_idx.data(), 4 * (size_t)E);
         std::memcpy(host.data() + o_vp, c->vn_ptr.data(), 4 * (size_t)(n + 1));
         std::memcpy(host.data() + o_vr, c->vn_ref.data(), 4 * (size_t)E);
+        std::memcpy(host.data() + o_ve, c->vn_edge.data(), 4 * (size_t)E);
         if (g > 2) {
             std::memcpy(host.data() + o_h, c->h.data(), E);
             std::memcpy(host.data() + o_hi, c->hinv.data(), E);
@@ -578,6 +584,7 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
         D.col_idx = (const int *)(b + o_ci);
         D.vn_ptr = (const int *)(b + o_vp);
         D.vn_ref = (const int *)(b + o_vr);
+        D.vn_edge = (const int *)(b + o_ve);
         D.h = (const uint8_t *)(b + o_h);
         D.hinv = (const uint8_t *)(b + o_hi);
         D.gfmul = (const uint8_t *)(b + o_mul);
@@ -681,6 +688,15 @@ ldpcx_status ldpcx_plan_set(ldpcx_code *c, const ldpcx_decode_params *params, in
             return fail(LDPCX_E_UNSUPPORTED, "state of cw_per_wg codewords does not fit the LDS");
         pl.cpw = cw_per_wg;
         pl.threads = threads;
+    }
+    if (family == FAMILY_BIN_IL) {
+        if (cw_per_wg < 1) return fail(LDPCX_E_INVAL, "cw_per_wg (codewords per launch sequence) must be positive");
+        pl.cpw = bin_il_sub_batch(c->dev, std::max(1, batch), cw_per_wg);
+        pl.threads = 256;
+    }
+    if (family == FAMILY_NB) {
+        pl.cpw = 64;
+        pl.threads = 256;
     }
     std::lock_guard<std::mutex> lk(c->mu);
     c->tuned[tune_key(params, std::max(1, batch))] = pl;

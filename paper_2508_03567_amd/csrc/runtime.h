@@ -28,7 +28,7 @@ struct DeviceInfo {
 // A captured launch sequence of the interleaved decoders, keyed by everything that is
 // baked into its kernel arguments.
 struct GraphKey {
-    int family, batch;
+    int family, cpw, batch;
     ldpcx_decode_params params;
     const void *llr;
     void *hard;
@@ -54,7 +54,7 @@ struct ldpcx_code {
     bool nb_unsupported = false;
     bool qc_ok = false;
     ldpcx::QcDesc qc{};
-    std::vector<int> row_ptr, col_idx, vn_ptr, vn_ref;
+    std::vector<int> row_ptr, col_idx, vn_ptr, vn_ref, vn_edge;
     std::vector<uint8_t> h, hinv, gfmul;
     void *dmem = nullptr;
     ldpcx::DevCode dev{};

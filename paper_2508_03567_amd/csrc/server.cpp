@@ -85,7 +85,7 @@ size_t io_bytes(const Request &r, int ncw) {
 // Device bytes one chunk of `ncw` codewords holds while in flight.
 size_t chunk_bytes(const Request &r, int ncw) {
     size_t b = io_bytes(r, ncw);
-    if (r.family == FAMILY_BIN_IL) b += bin_il_work_bytes(r.code->dev, r.prm.max_iters, ncw);
+    if (r.family == FAMILY_BIN_IL) b += bin_il_work_bytes(r.code->dev, r.prm.max_iters, ncw, 0);
     else if (r.family == FAMILY_NB) b += nb_work_bytes(r.code->dev, r.prm.max_iters, ncw);
     return b;
 }

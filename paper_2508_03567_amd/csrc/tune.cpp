@@ -60,12 +60,19 @@ std::vector<Plan> candidates(const ldpcx_code *c, const ldpcx_decode_params *p, 
             }
         }
         if (!lay) {
-            Plan pl;
-            pl.family = FAMILY_BIN_IL;
-            pl.schedule = LDPCX_SCHED_FLOODING;
-            pl.cpw = 64;
-            pl.threads = 256;
-            out.push_back(pl);
+            // interleaved: codewords per launch sequence (smaller slices keep their
+            // state resident in the last-level cache)
+            int last = -1;
+            for (int sub : {256, 512, 1024, 2048, 4096}) {
+                Plan pl;
+                pl.family = FAMILY_BIN_IL;
+                pl.schedule = LDPCX_SCHED_FLOODING;
+                pl.cpw = bin_il_sub_batch(c->dev, batch, sub);
+                pl.threads = 256;
+                if (pl.cpw == last) continue;
+                last = pl.cpw;
+                out.push_back(pl);
+            }
         }
     }
     return out;

@@ -287,3 +287,47 @@ def test_qc_packed_rules_and_saturation(rule):
         _check_decisions(w.code, g, ref)
         assert (g[4].astype(np.int32) == ref["r"]).all()
         assert (g[5].astype(np.int32) == ref["lam"]).all()
+
+
+@pytest.mark.parametrize("sub,batch,early", [(128, 300, True), (256, 300, False), (128, 77, True)])
+def test_interleaved_sub_batches(sub, batch, early):
+    """The interleaved decoder in slices of `sub` codewords (several launch sequences,
+    partly filled groups, early stop freezing every message of a stopped codeword)."""
+    w = S.workload(0, batch=batch)
+    cw, llr = S.make_inputs(w, seed_offset=23)
+    d = _prm(w, max_iters=8, early_stop=early)
+    code = L.Code(w.code)
+    L.plan_set(code, L.params(**d), batch, "bin_interleaved", sub)
+    info = L.plan_info(code, L.params(**d), batch)
+    assert info["family"] == "bin_interleaved" and info["cw_per_wg"] == sub
+    g = _gpu(code, d, llr, dump=True)
+    ref = _ref(w.code, d, llr, dump=True)
+    _check_decisions(w.code, g, ref)
+    assert (g[3].astype(np.int32) == ref["q"]).all()
+    assert (g[4].astype(np.int32) == ref["r"]).all()
+    assert (g[5].astype(np.int32) == ref["lam"]).all()
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_interleaved_irregular_degrees(seed):
+    """Check degrees up to 14 and variable degrees above the in-register count."""
+    rng = np.random.default_rng(seed)
+    n, m = 40, 60
+    rows, cols = [], []
+    for i in range(m):
+        d = int(rng.integers(2, 15))
+        c = rng.choice(n, size=d, replace=False)
+        rows += [i] * d
+        cols += list(c)
+    code = S.code_from_pairs("rand_dense", 2, 3, n, m, rows, cols)
+    assert np.bincount(np.array(cols), minlength=n).max() > 8
+    llr = np.random.default_rng(seed + 10).integers(-31, 32, size=(150, n)).astype(np.int8)
+    d = dict(rule="nms", schedule="flooding", max_iters=6, early_stop=True)
+    h = L.Code(code)
+    L.plan_set(h, L.params(**d), 150, "bin_interleaved", 128)
+    g = _gpu(h, d, llr, dump=True)
+    ref = _ref(code, d, llr, dump=True)
+    _check_decisions(code, g, ref)
+    assert (g[3].astype(np.int32) == ref["q"]).all()
+    assert (g[4].astype(np.int32) == ref["r"]).all()
+    assert (g[5].astype(np.int32) == ref["lam"]).all()

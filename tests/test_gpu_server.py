@@ -64,7 +64,7 @@ def _alone(cfg, prm, llr):
 
 @pytest.mark.parametrize("mode,budget,inflight,cap", [
     ("continuous", 256 << 20, 4, 0),
-    ("continuous", 48 << 20, 3, 96),   # small budget and launch cap: requests are split across launches
+    ("continuous", 160 << 20, 3, 96),  # small budget and launch cap: requests are split across launches
     ("per_request", 256 << 20, 1, 0),
 ])
 def test_results_alone_and_in_mix(mode, budget, inflight, cap):
