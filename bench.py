@@ -82,6 +82,8 @@ def main() -> None:
     ap.add_argument("--workload", type=int, default=1, help="0..3: n192 NMS, n2304 OMS layered, n64800 NMS, GF(64)")
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--plan", type=str, default=None,
+                    help="pin the launch plan instead of tuning: family[:cw_per_wg[:threads]], e.g. bin_interleaved:256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle time")
     ap.add_argument("--calib-copy", action="store_true",
@@ -119,7 +121,10 @@ def main() -> None:
     code = L.Code(w.code)
     prm = L.params(w.rule, w.schedule, w.max_iters, early_stop=False, nms_num=w.nms_num, nms_shift=w.nms_shift,
                    oms_offset=w.oms_offset, msg_max=w.msg_max)
-    if not args.no_tune:
+    if args.plan:
+        parts = args.plan.split(":")
+        L.plan_set(code, prm, w.batch, parts[0], *[int(x) for x in parts[1:]])
+    elif not args.no_tune:
         sched, us = L.tune(code, prm, w.batch)
         print(f"bench: tuned plan {L.plan_info(code, prm, w.batch)} ({us:.0f} us)", file=sys.stderr, flush=True)
     plan = L.plan_info(code, prm, w.batch)

@@ -2,18 +2,19 @@
 // state does not fit on chip (e.g. n = 64800), as block-level device functions.
 //
 // Layout: every per-node and per-edge quantity is stored as [node or edge][Bp]
-// with the codeword index fastest (Bp = batch padded to 128).  Each lane holds two
-// adjacent codewords in packed 16-bit arithmetic, so a wavefront covers a group
-// of 128 codewords of one node or edge: every access is one contiguous 128-byte
+// with the codeword index fastest (Bp = batch padded to 256).  Each lane holds four
+// adjacent codewords as two packed int16 pairs, so a wavefront covers a group of
+// 256 codewords of one node or edge: every access is one contiguous 256-byte
 // segment at a wave-uniform index, issued as a buffer load or store whose scalar
-// offset carries the index (no per-lane address arithmetic).
+// offset carries the index (no per-lane address arithmetic), and every wave keeps
+// several kilobytes of loads in flight.
 //
 // Messages live on the edges as int8: the check-node phase reads the
 // variable-to-check messages q of its edges (contiguous in CSR order) and writes
 // the check-to-variable messages r; the variable-node phase gathers r of its
 // edges, forms Lambda = L + sum r (exact in int16), writes q = sat(Lambda - r)
 // back to every edge and the hard decisions as 64-bit lane masks (one per
-// codeword of the lane pair).  Per codeword and iteration this moves about
+// codeword position in the lane).  Per codeword and iteration this moves about
 // 4E + n bytes.  Codewords that stopped (early termination) keep every message:
 // a wave whose lanes are partly stopped merges old and new values per byte.
 //
@@ -28,69 +29,96 @@ namespace ldpcx {
 namespace dev {
 namespace il {
 
-constexpr int kGroup = 128;                   // codewords per wavefront (two per lane)
+constexpr int kPairs = 2;                     // packed int16 pairs per lane
+constexpr int kLaneCw = 2 * kPairs;           // codewords per lane
+constexpr int kGroup = 64 * kLaneCw;          // codewords per wavefront
 constexpr int kVnRegs = 8;                    // check messages a variable keeps in registers
 constexpr uint32_t kRsrcWord3 = 0x00020000u;  // raw (untyped) buffer resource, gfx9 family
 
 struct Args {
     DevCode C;
     BinRule R;
-    int max_iters, early_stop, batch, Bp, G;  // G = Bp / 128 groups
+    int max_iters, early_stop, batch, Bp, G;  // G = Bp / kGroup groups
     BinIlWork w;
     uint8_t *bytes_t;  // [ceil(n/8)][Bp] staging of the packed decisions
     DecodeIO io;
 };
 
+typedef v2s Pk[kPairs];  // the lane's codewords: pair p holds codewords 2p (low half) and 2p + 1
+
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, (int)kRsrcWord3);
 }
 
-// Two int8 codeword values (bytes 0 and 1 of x) -> packed int16 pair, sign extended.
-__device__ __forceinline__ v2s unpack8(uint32_t x) {
-    return as_v2s(__builtin_amdgcn_perm(x, x, 0x010C000Cu)) >> splat(8);
+// The lane's int8 codeword values (bytes 0..3 of x) -> packed int16 pairs, sign extended.
+__device__ __forceinline__ void unpack(uint32_t x, Pk &p) {
+    p[0] = as_v2s(__builtin_amdgcn_perm(x, x, 0x010C000Cu)) >> splat(8);
+    p[1] = as_v2s(__builtin_amdgcn_perm(x, x, 0x030C020Cu)) >> splat(8);
 }
 
-// Packed int16 pair (values in int8 range) -> two bytes.
-__device__ __forceinline__ uint32_t pack8(v2s v) { return __builtin_amdgcn_perm(as_u32(v), as_u32(v), 0x0C0C0200u); }
-
-__device__ __forceinline__ uint32_t ld8x2(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-    return __builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0);
-}
-__device__ __forceinline__ void st8x2(uint32_t v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, r, (int)vo, (int)so, 0);
+// Packed int16 pairs (values in int8 range) -> the lane's four bytes.
+__device__ __forceinline__ uint32_t pack(const Pk &p) {
+    return __builtin_amdgcn_perm(as_u32(p[1]), as_u32(p[0]), 0x06040200u);
 }
 
-// Activity of the two codewords of each lane at iteration k.  Codewords beyond the
-// batch count as active (their inputs are zero and stay zero), so that a wave of a
-// partly filled group is not treated as mixed.
+__device__ __forceinline__ uint32_t ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0);
+}
+__device__ __forceinline__ void st(uint32_t v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)vo, (int)so, 0);
+}
+
+__device__ __forceinline__ uint32_t lane_off() { return kLaneCw * (threadIdx.x & 63); }
+
+// Activity of the lane's codewords at iteration k.  Codewords beyond the batch
+// count as active (their inputs are zero and stay zero), so that a wave of a partly
+// filled group is not treated as mixed.
 struct Act {
-    uint32_t m8;   // per byte: 0xFF where the codeword is active
-    uint32_t m16;  // per int16 half: 0xFFFF where active
+    uint32_t m8;            // per byte: 0xFF where the codeword is active
+    uint32_t m16[kPairs];   // per int16 half of each pair: 0xFFFF where active
     bool any, all;
 };
 
+// Word kLaneCw * g + h of a slot holds codeword kGroup * g + kLaneCw * l + h in bit l.
 __device__ __forceinline__ Act activity(const Args &A, int k, int g, int lane) {
-    Act a{0xFFFFu, 0xFFFFFFFFu, true, true};
+    Act a;
+    a.m8 = 0xFFFFFFFFu;
+    for (int p = 0; p < kPairs; ++p) a.m16[p] = 0xFFFFFFFFu;
+    a.any = a.all = true;
     if (!A.early_stop) return a;
-    const uint64_t *slot = A.w.unsat + (size_t)k * 2 * A.G + 2 * g;
-    const int b0 = g * kGroup + 2 * lane;
-    const bool u0 = (slot[0] >> lane) & 1ull, u1 = (slot[1] >> lane) & 1ull;
-    const bool a0 = u0 || b0 >= A.batch, a1 = u1 || b0 + 1 >= A.batch;
-    a.m8 = (a0 ? 0x00FFu : 0u) | (a1 ? 0xFF00u : 0u);
-    a.m16 = (a0 ? 0x0000FFFFu : 0u) | (a1 ? 0xFFFF0000u : 0u);
-    a.any = __ballot(u0 || u1) != 0;  // only real codewords can be unsatisfied
-    a.all = __ballot(!(a0 && a1)) == 0;
+    const uint64_t *slot = A.w.unsat + ((size_t)k * A.G + g) * kLaneCw;
+    const int b0 = g * kGroup + kLaneCw * lane;
+    bool un = false, inact = false;
+    a.m8 = 0;
+#pragma unroll
+    for (int h = 0; h < kLaneCw; ++h) {
+        const bool u = (slot[h] >> lane) & 1ull;
+        const bool act = u || b0 + h >= A.batch;
+        un |= u;
+        inact |= !act;
+        if (act) a.m8 |= 0xFFu << (8 * h);
+    }
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p)
+        a.m16[p] = ((a.m8 >> (16 * p)) & 0xFFu ? 0x0000FFFFu : 0u) | ((a.m8 >> (16 * p + 8)) & 0xFFu ? 0xFFFF0000u : 0u);
+    a.any = __ballot(un) != 0;  // only real codewords can be unsatisfied
+    a.all = __ballot(inact) == 0;
     return a;
 }
 
 // (M & a) | (~M & b)
 __device__ __forceinline__ uint32_t merge(uint32_t M, uint32_t a, uint32_t b) { return (M & a) | (~M & b); }
 
+// Sign bit of codeword h of the lane (from the packed sums).
+__device__ __forceinline__ bool neg_of(const Pk &S, int h) { return (as_u32(S[h >> 1]) >> (h & 1 ? 31 : 15)) & 1u; }
+
 // Virtual grids (blocks of 256 threads, 4 waves) of the phases.
 __host__ __device__ inline long grid_rows_x(const Args &A) { return (A.C.m + 3) / 4; }
 __host__ __device__ inline long grid_vars_x(const Args &A) { return (A.C.n + 3) / 4; }
 __host__ __device__ inline long grid_edges_x(const Args &A) { return (A.C.E + 3) / 4; }
-__host__ __device__ inline long grid_syn(const Args &A) { return ((long)((A.C.m + 31) / 32) * 2 * A.G + 255) / 256; }
+__host__ __device__ inline long grid_syn(const Args &A) {
+    return ((long)((A.C.m + 31) / 32) * kLaneCw * A.G + 255) / 256;
+}
 __host__ __device__ inline long grid_bytes(const Args &A) { return ((long)((A.C.n + 7) / 8) * A.Bp + 255) / 256; }
 __host__ __device__ inline long grid_fin(const Args &A) { return (A.batch + 255) / 256; }
 
@@ -98,36 +126,52 @@ __host__ __device__ inline long grid_fin(const Args &A) { return (A.batch + 255)
 __device__ __forceinline__ void init_edges_block(const Args &A, int bx, int g) {
     const int e = bx * 4 + wave_id();
     if (e >= A.C.E) return;
-    const uint32_t vo = 2 * (threadIdx.x & 63), gb = (uint32_t)g * kGroup, Bp = (uint32_t)A.Bp;
+    const uint32_t vo = lane_off(), gb = (uint32_t)g * kGroup, Bp = (uint32_t)A.Bp;
     const auto rL = rsrc(A.w.L, (uint32_t)A.C.n * Bp);
     const auto rq = rsrc(A.w.q, (uint32_t)A.C.E * Bp);
     const auto rr = rsrc(A.w.r, (uint32_t)A.C.E * Bp);
     const uint32_t v = (uint32_t)A.C.col_idx[e];
-    const v2s L = unpack8(ld8x2(rL, vo, v * Bp + gb));
-    st8x2(pack8(pmin(pmax(L, splat(-A.R.msg_max)), splat(A.R.msg_max))), rq, vo, (uint32_t)e * Bp + gb);
-    st8x2(0u, rr, vo, (uint32_t)e * Bp + gb);
+    Pk L;
+    unpack(ld(rL, vo, v * Bp + gb), L);
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) L[p] = pmin(pmax(L[p], splat(-A.R.msg_max)), splat(A.R.msg_max));
+    st(pack(L), rq, vo, (uint32_t)e * Bp + gb);
+    st(0u, rr, vo, (uint32_t)e * Bp + gb);
+}
+
+// Decision words of one variable: lane h (< kLaneCw) stores word h.
+__device__ __forceinline__ void store_hb(const Args &A, int v, int g, const Pk &S, const Act *act) {
+    const int lane = threadIdx.x & 63;
+    uint64_t *hb = A.w.hb + ((size_t)v * A.G + g) * kLaneCw;
+    uint64_t mine = 0;
+#pragma unroll
+    for (int h = 0; h < kLaneCw; ++h) {
+        uint64_t b = __ballot(neg_of(S, h));
+        if (act && !act->all) {
+            const uint64_t keep = __ballot((act->m8 >> (8 * h)) & 1u);
+            b = (b & keep) | (hb[h] & ~keep);
+        }
+        if (lane == h) mine = b;
+    }
+    if (lane < kLaneCw) hb[lane] = mine;
 }
 
 // Decisions of iteration 0 (wave per (variable, group)).
 __device__ __forceinline__ void init_vars_block(const Args &A, int bx, int g) {
     const int v = bx * 4 + wave_id();
     if (v >= A.C.n) return;
-    const int lane = threadIdx.x & 63;
-    const uint32_t vo = 2 * lane, gb = (uint32_t)g * kGroup, Bp = (uint32_t)A.Bp;
+    const uint32_t vo = lane_off(), gb = (uint32_t)g * kGroup, Bp = (uint32_t)A.Bp;
     const auto rL = rsrc(A.w.L, (uint32_t)A.C.n * Bp);
-    const uint32_t s = as_u32(unpack8(ld8x2(rL, vo, (uint32_t)v * Bp + gb)));
-    const uint64_t b0 = __ballot((s >> 15) & 1u), b1 = __ballot(s >> 31);
-    uint64_t *hb = A.w.hb + (size_t)v * 2 * A.G + 2 * g;
-    if (lane == 0) hb[0] = b0;
-    if (lane == 1) hb[1] = b1;
+    Pk L;
+    unpack(ld(rL, vo, (uint32_t)v * Bp + gb), L);
+    store_hb(A, v, g, L, nullptr);
 }
 
 // Syndrome test: for every (decision word, block of 32 checks) the OR of the parity
-// masks, accumulated into the unsatisfied-codeword mask of slot_k.  Word 2g + h
-// holds codeword 128 g + 2 l + h in bit l.
+// masks, accumulated into the unsatisfied-codeword mask of slot_k.
 __device__ __forceinline__ void syn_block(const Args &A, int slot_k, long bx) {
     const DevCode &C = A.C;
-    const int W = 2 * A.G;
+    const int W = kLaneCw * A.G;
     uint64_t *slot = A.w.unsat + (size_t)slot_k * W;
     const long t = bx * 256 + threadIdx.x;
     const int wd = (int)(t % W);
@@ -144,9 +188,10 @@ __device__ __forceinline__ void syn_block(const Args &A, int slot_k, long bx) {
     if (acc) atomicOr((unsigned long long *)&slot[wd], (unsigned long long)acc);
 }
 
-// Check-node phase of iteration k: one wave per (check, group of 128 codewords).
-// Outgoing magnitude: f(min2) on the edge holding the minimum, f(min1) elsewhere
-// (equal when the minimum is tied); sign: product of the other signs.
+// Check-node phase of iteration k: one wave per (check, group).  DC bounds the check
+// degree.  Outgoing magnitude: f(min2) on the edge holding the minimum, f(min1)
+// elsewhere (equal when the minimum is tied); sign: product of the other signs.
+template <int DC>
 __device__ __forceinline__ void cn_block(const Args &A, int k, int bx, int g) {
     const DevCode &C = A.C;
     const int lane = threadIdx.x & 63;
@@ -154,41 +199,59 @@ __device__ __forceinline__ void cn_block(const Args &A, int k, int bx, int g) {
     if (row >= C.m) return;
     const Act act = activity(A, k, g, lane);
     if (!act.any) return;
-    const uint32_t vo = 2 * lane, gb = (uint32_t)g * kGroup, Bp = (uint32_t)A.Bp;
+    const uint32_t vo = lane_off(), gb = (uint32_t)g * kGroup, Bp = (uint32_t)A.Bp;
     const auto rq = rsrc(A.w.q, (uint32_t)C.E * Bp);
     const auto rr = rsrc(A.w.r, (uint32_t)C.E * Bp);
     const int e0 = C.row_ptr[row];
     const int dc = C.row_ptr[row + 1] - e0;
     const PkNorm NP = pk_norm_params(A.R);
-    v2s av[kBinDcMax];
-    uint32_t sv[kBinDcMax];
-    v2s m1 = splat(0x7FFF), m2 = splat(0x7FFF);
-    uint32_t stot = 0;
+    uint32_t raw[DC];
 #pragma unroll
-    for (int j = 0; j < kBinDcMax; ++j) {
+    for (int j = 0; j < DC; ++j)
+        if (j < dc) raw[j] = ld(rq, vo, (uint32_t)(e0 + j) * Bp + gb);
+    Pk m1, m2, f2, df;
+    uint32_t stot[kPairs];
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) {
+        m1[p] = m2[p] = splat(0x7FFF);
+        stot[p] = 0;
+    }
+#pragma unroll
+    for (int j = 0; j < DC; ++j) {
         if (j < dc) {
-            const v2s q = unpack8(ld8x2(rq, vo, (uint32_t)(e0 + j) * Bp + gb));
-            const uint32_t sg = as_u32(q >> splat(15));
-            const v2s a = pmax(q, -q);
-            m2 = pmin(m2, pmax(m1, a));
-            m1 = pmin(m1, a);
-            stot ^= sg;
-            av[j] = a;
-            sv[j] = sg;
+            Pk q;
+            unpack(raw[j], q);
+#pragma unroll
+            for (int p = 0; p < kPairs; ++p) {
+                const v2s a = pmax(q[p], -q[p]);
+                m2[p] = pmin(m2[p], pmax(m1[p], a));
+                m1[p] = pmin(m1[p], a);
+                stot[p] ^= as_u32(q[p] >> splat(15));
+            }
         }
     }
-    const v2s f1 = pk_norm(NP, m1), f2 = pk_norm(NP, m2);
-    const v2s df = f1 - f2;
 #pragma unroll
-    for (int j = 0; j < kBinDcMax; ++j) {
+    for (int p = 0; p < kPairs; ++p) {
+        const v2s f1 = pk_norm(NP, m1[p]);
+        f2[p] = pk_norm(NP, m2[p]);
+        df[p] = f1 - f2[p];
+    }
+#pragma unroll
+    for (int j = 0; j < DC; ++j) {
         if (j < dc) {
-            const v2s t = pmin(av[j] - m1, splat(1));  // 0 where this edge holds the minimum
-            const v2s mag = f2 + t * df;
-            const uint32_t sr = stot ^ sv[j];
-            uint32_t rn = pack8(as_v2s(as_u32(mag) ^ sr) - as_v2s(sr));
+            Pk q, rn;
+            unpack(raw[j], q);
+#pragma unroll
+            for (int p = 0; p < kPairs; ++p) {
+                const v2s t = pmin(pmax(q[p], -q[p]) - m1[p], splat(1));  // 0 where this edge holds the minimum
+                const v2s mag = f2[p] + t * df[p];
+                const uint32_t sr = stot[p] ^ as_u32(q[p] >> splat(15));
+                rn[p] = as_v2s(as_u32(mag) ^ sr) - as_v2s(sr);
+            }
+            uint32_t w = pack(rn);
             const uint32_t so = (uint32_t)(e0 + j) * Bp + gb;
-            if (!act.all) rn = merge(act.m8, rn, ld8x2(rr, vo, so));
-            st8x2(rn, rr, vo, so);
+            if (!act.all) w = merge(act.m8, w, ld(rr, vo, so));
+            st(w, rr, vo, so);
         }
     }
 }
@@ -201,60 +264,68 @@ __device__ __forceinline__ void vn_block(const Args &A, int k, int bx, int g) {
     if (v >= C.n) return;
     const Act act = activity(A, k, g, lane);
     if (!act.any) return;
-    const uint32_t vo = 2 * lane, gb = (uint32_t)g * kGroup, Bp = (uint32_t)A.Bp;
+    const uint32_t vo = lane_off(), gb = (uint32_t)g * kGroup, Bp = (uint32_t)A.Bp;
     const auto rL = rsrc(A.w.L, (uint32_t)C.n * Bp);
     const auto rq = rsrc(A.w.q, (uint32_t)C.E * Bp);
     const auto rr = rsrc(A.w.r, (uint32_t)C.E * Bp);
     const int t0 = C.vn_ptr[v];
     const int dv = C.vn_ptr[v + 1] - t0;
-    v2s S = unpack8(ld8x2(rL, vo, (uint32_t)v * Bp + gb));
-    v2s rv[kVnRegs];
-    uint32_t ev[kVnRegs];
+    uint32_t rw[kVnRegs], ev[kVnRegs];
+    const uint32_t lw = ld(rL, vo, (uint32_t)v * Bp + gb);
 #pragma unroll
     for (int t = 0; t < kVnRegs; ++t) {
         if (t < dv) {
             ev[t] = (uint32_t)C.vn_edge[t0 + t] * Bp + gb;
-            rv[t] = unpack8(ld8x2(rr, vo, ev[t]));
-            S = S + rv[t];
+            rw[t] = ld(rr, vo, ev[t]);
         }
     }
-    for (int t = kVnRegs; t < dv; ++t) S = S + unpack8(ld8x2(rr, vo, (uint32_t)C.vn_edge[t0 + t] * Bp + gb));
-    const v2s mm = splat(A.R.msg_max), nmm = splat(-A.R.msg_max);
+    Pk S;
+    unpack(lw, S);
 #pragma unroll
     for (int t = 0; t < kVnRegs; ++t) {
         if (t < dv) {
-            uint32_t qn = pack8(pmin(pmax(S - rv[t], nmm), mm));
-            if (!act.all) qn = merge(act.m8, qn, ld8x2(rq, vo, ev[t]));
-            st8x2(qn, rq, vo, ev[t]);
+            Pk r;
+            unpack(rw[t], r);
+#pragma unroll
+            for (int p = 0; p < kPairs; ++p) S[p] = S[p] + r[p];
         }
     }
     for (int t = kVnRegs; t < dv; ++t) {
+        Pk r;
+        unpack(ld(rr, vo, (uint32_t)C.vn_edge[t0 + t] * Bp + gb), r);
+#pragma unroll
+        for (int p = 0; p < kPairs; ++p) S[p] = S[p] + r[p];
+    }
+    const v2s mm = splat(A.R.msg_max), nmm = splat(-A.R.msg_max);
+    auto qword = [&](uint32_t r_raw, uint32_t so) {
+        Pk r, q;
+        unpack(r_raw, r);
+#pragma unroll
+        for (int p = 0; p < kPairs; ++p) q[p] = pmin(pmax(S[p] - r[p], nmm), mm);
+        uint32_t w = pack(q);
+        if (!act.all) w = merge(act.m8, w, ld(rq, vo, so));
+        st(w, rq, vo, so);
+    };
+#pragma unroll
+    for (int t = 0; t < kVnRegs; ++t)
+        if (t < dv) qword(rw[t], ev[t]);
+    for (int t = kVnRegs; t < dv; ++t) {
         const uint32_t so = (uint32_t)C.vn_edge[t0 + t] * Bp + gb;
-        uint32_t qn = pack8(pmin(pmax(S - unpack8(ld8x2(rr, vo, so)), nmm), mm));
-        if (!act.all) qn = merge(act.m8, qn, ld8x2(rq, vo, so));
-        st8x2(qn, rq, vo, so);
+        qword(ld(rr, vo, so), so);
     }
-    const uint32_t s = as_u32(S);
-    uint64_t b0 = __ballot((s >> 15) & 1u), b1 = __ballot(s >> 31);
-    uint64_t *hb = A.w.hb + (size_t)v * 2 * A.G + 2 * g;
-    if (!act.all) {
-        const uint64_t k0 = __ballot(act.m16 & 1u), k1 = __ballot(act.m16 >> 31);
-        b0 = (b0 & k0) | (hb[0] & ~k0);
-        b1 = (b1 & k1) | (hb[1] & ~k1);
-    }
-    if (lane == 0) hb[0] = b0;
-    if (lane == 1) hb[1] = b1;
+    store_hb(A, v, g, S, &act);
     if (v == 0) {
-        uint32_t *itp = (uint32_t *)(A.w.it + g * kGroup) + lane;
+        uint32_t *itp = (uint32_t *)(A.w.it + (size_t)g * kGroup) + kPairs * lane;
         const uint32_t kk = (uint32_t)k | ((uint32_t)k << 16);
-        *itp = act.all ? kk : merge(act.m16, kk, *itp);
+#pragma unroll
+        for (int p = 0; p < kPairs; ++p) itp[p] = act.all ? kk : merge(act.m16[p], kk, itp[p]);
     }
 }
 
 // Decision bit of codeword b for variable v.
 __device__ __forceinline__ uint32_t hbit(const Args &A, int v, int b) {
     const int g = b / kGroup, rem = b - g * kGroup;
-    return (uint32_t)((A.w.hb[(size_t)v * 2 * A.G + 2 * g + (rem & 1)] >> (rem >> 1)) & 1ull);
+    return (uint32_t)((A.w.hb[((size_t)v * A.G + g) * kLaneCw + (rem % kLaneCw)] >> (rem / kLaneCw)) & 1ull);
 }
 
 // Packed decision bytes in the interleaved layout.
@@ -274,38 +345,49 @@ __device__ __forceinline__ void bytes_block(const Args &A, long bx) {
     A.bytes_t[i] = (uint8_t)byte;
 }
 
+// Unsatisfied bit of codeword b in slot k.
+__device__ __forceinline__ bool unsat_bit(const Args &A, int k, int b) {
+    const int g = b / kGroup, rem = b - g * kGroup;
+    return (A.w.unsat[((size_t)k * A.G + g) * kLaneCw + (rem % kLaneCw)] >> (rem / kLaneCw)) & 1ull;
+}
+
 // Syndrome flags (final test in slot 0) and iteration counts.
 __device__ __forceinline__ void fin_block(const Args &A, long bx) {
     const int b = (int)(bx * 256 + threadIdx.x);
     if (b >= A.batch) return;
-    const int g = b / kGroup, rem = b - g * kGroup;
-    A.io.ok[b] = ((A.w.unsat[2 * g + (rem & 1)] >> (rem >> 1)) & 1ull) ? 0 : 1;
+    A.io.ok[b] = unsat_bit(A, 0, b) ? 0 : 1;
     A.io.iters[b] = A.w.it[b];
 }
 
 // Lambda = L + sum r per variable in the interleaved layout, for the debug dump.
 __device__ __forceinline__ void lambda_block(const Args &A, int16_t *lam_t, int bx, int g) {
     const DevCode &C = A.C;
-    const int lane = threadIdx.x & 63;
     const int v = bx * 4 + wave_id();
     if (v >= C.n) return;
-    const uint32_t vo = 2 * lane, gb = (uint32_t)g * kGroup, Bp = (uint32_t)A.Bp;
+    const uint32_t vo = lane_off(), gb = (uint32_t)g * kGroup, Bp = (uint32_t)A.Bp;
     const auto rL = rsrc(A.w.L, (uint32_t)C.n * Bp);
     const auto rr = rsrc(A.w.r, (uint32_t)C.E * Bp);
-    v2s S = unpack8(ld8x2(rL, vo, (uint32_t)v * Bp + gb));
-    for (int t = C.vn_ptr[v]; t < C.vn_ptr[v + 1]; ++t)
-        S = S + unpack8(ld8x2(rr, vo, (uint32_t)C.vn_edge[t] * Bp + gb));
-    *(uint32_t *)(lam_t + (size_t)v * A.Bp + gb + vo) = as_u32(S);
+    Pk S;
+    unpack(ld(rL, vo, (uint32_t)v * Bp + gb), S);
+    for (int t = C.vn_ptr[v]; t < C.vn_ptr[v + 1]; ++t) {
+        Pk r;
+        unpack(ld(rr, vo, (uint32_t)C.vn_edge[t] * Bp + gb), r);
+#pragma unroll
+        for (int p = 0; p < kPairs; ++p) S[p] = S[p] + r[p];
+    }
+    uint32_t *out = (uint32_t *)(lam_t + (size_t)v * A.Bp + gb + vo);
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) out[p] = as_u32(S[p]);
 }
 
-__host__ __device__ inline int pad128(int b) { return (b + 127) & ~127; }
+__host__ __device__ inline int pad_group(int b) { return (b + kGroup - 1) / kGroup * kGroup; }
 
 struct Carve {
     size_t L, q, r, hb, unsat, it, bytes, total;
 };
 
 inline Carve carve(const DevCode &C, int max_iters, int batch) {
-    const size_t Bp = pad128(batch), W = Bp / 64;
+    const size_t Bp = pad_group(batch), W = Bp / 64;
     Carve c;
     size_t o = 0;
     c.L = o;
@@ -335,7 +417,7 @@ inline Args make_args(const DevCode &C, const BinRule &R, int max_iters, int ear
     A.max_iters = max_iters;
     A.early_stop = early_stop;
     A.batch = batch;
-    A.Bp = pad128(batch);
+    A.Bp = pad_group(batch);
     A.G = A.Bp / kGroup;
     const Carve c = carve(C, max_iters, batch);
     char *p = (char *)base;
@@ -359,7 +441,7 @@ inline TransposeArgs tr_out(const Args &A) {
     return TransposeArgs{A.bytes_t, A.io.hard, nb, A.batch, A.Bp, nb, nb, 1};
 }
 inline FillArgs fill_unsat(const Args &A) {
-    return FillArgs{(uint32_t *)A.w.unsat, (size_t)(A.max_iters + 1) * 2 * A.G * 2, 0u};
+    return FillArgs{(uint32_t *)A.w.unsat, (size_t)(A.max_iters + 1) * kLaneCw * A.G * 2, 0u};
 }
 inline FillArgs fill_it(const Args &A) { return FillArgs{(uint32_t *)A.w.it, (size_t)A.Bp / 2, 0u}; }
 

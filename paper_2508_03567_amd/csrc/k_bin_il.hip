@@ -21,7 +21,8 @@ __global__ void __launch_bounds__(256) k_fill(dev::FillArgs F) { dev::fill_block
 __global__ void __launch_bounds__(256) k_init_edges(Args A) { dev::il::init_edges_block(A, blockIdx.x, blockIdx.y); }
 __global__ void __launch_bounds__(256) k_init_vars(Args A) { dev::il::init_vars_block(A, blockIdx.x, blockIdx.y); }
 __global__ void __launch_bounds__(256) k_syn(Args A, int slot) { dev::il::syn_block(A, slot, blockIdx.x); }
-__global__ void __launch_bounds__(256) k_cn(Args A, int k) { dev::il::cn_block(A, k, blockIdx.x, blockIdx.y); }
+template <int DC>
+__global__ void __launch_bounds__(256) k_cn(Args A, int k) { dev::il::cn_block<DC>(A, k, blockIdx.x, blockIdx.y); }
 __global__ void __launch_bounds__(256) k_vn(Args A, int k) { dev::il::vn_block(A, k, blockIdx.x, blockIdx.y); }
 __global__ void __launch_bounds__(256) k_bytes(Args A) { dev::il::bytes_block(A, blockIdx.x); }
 __global__ void __launch_bounds__(256) k_fin(Args A) { dev::il::fin_block(A, blockIdx.x); }
@@ -65,7 +66,8 @@ hipError_t run_slice(const DevCode &C, const BinRule &R, int max_iters, int earl
     const dim3 gsyn((unsigned)dev::il::grid_syn(A));
     for (int k = 1; k <= max_iters; ++k) {
         if (early_stop) hipLaunchKernelGGL(k_syn, gsyn, blk, 0, s, A, k);
-        hipLaunchKernelGGL(k_cn, gcn, blk, 0, s, A, k);
+        if (C.dc_max <= 8) hipLaunchKernelGGL(k_cn<8>, gcn, blk, 0, s, A, k);
+        else hipLaunchKernelGGL(k_cn<kBinDcMax>, gcn, blk, 0, s, A, k);
         hipLaunchKernelGGL(k_vn, gvn, blk, 0, s, A, k);
         LDPCX_CHECK(hipGetLastError());
     }
@@ -89,10 +91,10 @@ hipError_t run_slice(const DevCode &C, const BinRule &R, int max_iters, int earl
 }  // namespace
 
 int bin_il_sub_batch(const DevCode &C, int batch, int want) {
-    int sub = want > 0 ? want : 1024;
+    int sub = want > 0 ? want : 512;
     sub = std::min(sub, dev::il::max_sub_batch(C));
-    sub = dev::il::pad128(std::max(sub, 1));
-    return std::min(sub, dev::il::pad128(std::max(batch, 1)));
+    sub = dev::il::pad_group(std::max(sub, 1));
+    return std::min(sub, dev::il::pad_group(std::max(batch, 1)));
 }
 
 size_t bin_il_work_bytes(const DevCode &C, int max_iters, int batch, int sub) {
@@ -100,7 +102,7 @@ size_t bin_il_work_bytes(const DevCode &C, int max_iters, int batch, int sub) {
 }
 
 size_t bin_il_dump_bytes(const DevCode &C, int batch, int sub) {
-    return align_up((size_t)C.n * dev::il::pad128(std::min(batch, bin_il_sub_batch(C, batch, sub))) * 2, 256);
+    return align_up((size_t)C.n * dev::il::pad_group(std::min(batch, bin_il_sub_batch(C, batch, sub))) * 2, 256);
 }
 
 hipError_t launch_bin_il(const DevCode &C, const BinRule &R, int max_iters, int early_stop, int batch, int sub,

@@ -84,92 +84,92 @@ __device__ __forceinline__ uint64_t group_or(uint64_t v, uint64_t *unsat, long s
 }
 
 // ------------------------------------------------ interleaved binary, one group
-// Syndrome of one group of 128 codewords: words 2g and 2g + 1 of slot_k (codeword
-// 128 g + 2 l + h in bit l of word 2 g + h); returns their OR (uniform).
+// Syndrome of one group of codewords: the kLaneCw decision words of group g in
+// slot_k; returns their OR (uniform).
 __device__ uint64_t il_syn(const dev::il::Args &A, int slot_k, int g, uint64_t *red) {
+    constexpr int H = dev::il::kLaneCw;
     const DevCode &C = A.C;
-    const int W = 2 * A.G;
-    uint64_t acc0 = 0, acc1 = 0;
+    const int W = H * A.G;
+    uint64_t acc[H];
+    for (int h = 0; h < H; ++h) acc[h] = 0;
     for (int row = threadIdx.x; row < C.m; row += kThreads) {
-        uint64_t p0 = 0, p1 = 0;
+        uint64_t p[H];
+        for (int h = 0; h < H; ++h) p[h] = 0;
         for (int e = C.row_ptr[row]; e < C.row_ptr[row + 1]; ++e) {
-            const uint64_t *h = A.w.hb + (size_t)C.col_idx[e] * W + 2 * g;
-            p0 ^= h[0];
-            p1 ^= h[1];
+            const uint64_t *hw = A.w.hb + (size_t)C.col_idx[e] * W + (size_t)H * g;
+            for (int h = 0; h < H; ++h) p[h] ^= hw[h];
         }
-        acc0 |= p0;
-        acc1 |= p1;
+        for (int h = 0; h < H; ++h) acc[h] |= p[h];
     }
-    acc0 = dev::wave_or64(acc0);
-    acc1 = dev::wave_or64(acc1);
     const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        red[2 * w] = acc0;
-        red[2 * w + 1] = acc1;
+    for (int h = 0; h < H; ++h) {
+        acc[h] = dev::wave_or64(acc[h]);
+        if ((threadIdx.x & 63) == 0) red[H * w + h] = acc[h];
     }
     __syncthreads();
-    const uint64_t u0 = red[0] | red[2] | red[4] | red[6];
-    const uint64_t u1 = red[1] | red[3] | red[5] | red[7];
-    if (threadIdx.x == 0) {
-        A.w.unsat[(size_t)slot_k * W + 2 * g] = u0;
-        A.w.unsat[(size_t)slot_k * W + 2 * g + 1] = u1;
+    uint64_t u = 0;
+    if (threadIdx.x < H) {
+        uint64_t x = 0;
+        for (int q = 0; q < kThreads / 64; ++q) x |= red[H * q + threadIdx.x];
+        A.w.unsat[(size_t)slot_k * W + (size_t)H * g + threadIdx.x] = x;
     }
+    for (int i = 0; i < H * (kThreads / 64); ++i) u |= red[i];
     __syncthreads();
-    const uint64_t u = u0 | u1;
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Every phase of the interleaved binary decoder for codewords [128 g, 128 g + 128).
+// Every phase of the interleaved binary decoder for the codewords of group g.
 __device__ void il_group(const JobDesc &J, int g, uint32_t *lds, uint64_t *red) {
-    const dev::il::Args &A = J.il;
+    using namespace dev::il;
+    const Args &A = J.il;
     const DevCode &C = A.C;
-    const int W = 2 * A.G;
+    constexpr int Q = kGroup / 64;  // 64-row transpose tiles per group
     unsigned char *tile = (unsigned char *)lds;
     const long gx_in = dev::transpose_gx(J.tin);
-    for (int half = 0; half < 2; ++half)
-        for (long bx = 0; bx < gx_in; ++bx) dev::transpose_block(J.tin, bx, 2 * g + half, tile);
-    for (int s = threadIdx.x; s <= A.max_iters; s += kThreads) {
-        A.w.unsat[(size_t)s * W + 2 * g] = 0;
-        A.w.unsat[(size_t)s * W + 2 * g + 1] = 0;
-    }
-    if (threadIdx.x < dev::il::kGroup) A.w.it[g * dev::il::kGroup + threadIdx.x] = 0;
+    for (int qt = 0; qt < Q; ++qt)
+        for (long bx = 0; bx < gx_in; ++bx) dev::transpose_block(J.tin, bx, Q * g + qt, tile);
+    for (int s = threadIdx.x; s < (A.max_iters + 1) * kLaneCw; s += kThreads)
+        A.w.unsat[((size_t)(s / kLaneCw) * A.G + g) * kLaneCw + s % kLaneCw] = 0;
+    for (int t = threadIdx.x; t < kGroup; t += kThreads) A.w.it[g * kGroup + t] = 0;
     __syncthreads();
-    const int ge = (int)dev::il::grid_edges_x(A), gv = (int)dev::il::grid_vars_x(A), gr = (int)dev::il::grid_rows_x(A);
-    for (int bx = 0; bx < ge; ++bx) dev::il::init_edges_block(A, bx, g);
-    for (int bx = 0; bx < gv; ++bx) dev::il::init_vars_block(A, bx, g);
+    const int ge = (int)grid_edges_x(A), gv = (int)grid_vars_x(A), gr = (int)grid_rows_x(A);
+    for (int bx = 0; bx < ge; ++bx) init_edges_block(A, bx, g);
+    for (int bx = 0; bx < gv; ++bx) init_vars_block(A, bx, g);
     __syncthreads();
     for (int k = 1; k <= A.max_iters; ++k) {
         if (A.early_stop && il_syn(A, k, g, red) == 0) break;
-        for (int bx = 0; bx < gr; ++bx) dev::il::cn_block(A, k, bx, g);
+        if (C.dc_max <= 8)
+            for (int bx = 0; bx < gr; ++bx) cn_block<8>(A, k, bx, g);
+        else
+            for (int bx = 0; bx < gr; ++bx) cn_block<kBinDcMax>(A, k, bx, g);
         __syncthreads();
-        for (int bx = 0; bx < gv; ++bx) dev::il::vn_block(A, k, bx, g);
+        for (int bx = 0; bx < gv; ++bx) vn_block(A, k, bx, g);
         __syncthreads();
     }
     il_syn(A, 0, g, red);
-    if (threadIdx.x < dev::il::kGroup) {
-        const int b = g * dev::il::kGroup + threadIdx.x;
+    for (int t = threadIdx.x; t < kGroup; t += kThreads) {
+        const int b = g * kGroup + t;
         if (b < A.batch) {
-            const uint64_t w = A.w.unsat[2 * g + (threadIdx.x & 1)];
-            A.io.ok[b] = ((w >> (threadIdx.x >> 1)) & 1ull) ? 0 : 1;
+            A.io.ok[b] = unsat_bit(A, 0, b) ? 0 : 1;
             A.io.iters[b] = A.w.it[b];
         }
     }
     const int nbytes = (C.n + 7) >> 3;
-    for (int idx = threadIdx.x; idx < nbytes * dev::il::kGroup; idx += kThreads) {
-        const int j = idx / dev::il::kGroup, b = g * dev::il::kGroup + idx % dev::il::kGroup;
+    for (int idx = threadIdx.x; idx < nbytes * kGroup; idx += kThreads) {
+        const int j = idx / kGroup, b = g * kGroup + idx % kGroup;
         uint32_t byte = 0;
         for (int q = 0; q < 8; ++q) {
             const int v = 8 * j + q;
-            if (v < C.n) byte |= dev::il::hbit(A, v, b) << q;
+            if (v < C.n) byte |= hbit(A, v, b) << q;
         }
         A.bytes_t[(size_t)j * A.Bp + b] = (uint8_t)byte;
     }
     __syncthreads();
     const long gy_out = dev::transpose_gy(J.tout);
-    for (int half = 0; half < 2; ++half)
-        for (long by = 0; by < gy_out; ++by) dev::transpose_block(J.tout, 2 * g + half, by, tile);
+    for (int qt = 0; qt < Q; ++qt)
+        for (long by = 0; by < gy_out; ++by) dev::transpose_block(J.tout, Q * g + qt, by, tile);
 }
 
 // --------------------------------------------------------- Min-Max, one group
@@ -255,7 +255,7 @@ __global__ void __launch_bounds__(kThreads) k_ragged(const JobDesc *__restrict__
                                                      const Item *__restrict__ items,
                                                      const int *__restrict__ wg_ptr) {
     extern __shared__ __align__(16) uint32_t lds[];
-    __shared__ uint64_t red[8];
+    __shared__ uint64_t red[4 * dev::il::kLaneCw];
     const int i0 = wg_ptr[blockIdx.x], i1 = wg_ptr[blockIdx.x + 1];
     for (int i = i0; i < i1; ++i) {
         const Item it = items[i];
@@ -270,7 +270,7 @@ double item_cost(const JobDesc &J, const DevCode &C) {
     switch (J.family) {
     case FAMILY_BIN_QC: return it * E * 2.0 / std::max(1, J.qc.Z);
     case FAMILY_BIN_LDS: return it * E * J.cpw / kThreads;
-    case FAMILY_BIN_IL: return it * E * 128.0 * 2.0 / kThreads;
+    case FAMILY_BIN_IL: return it * E * (double)dev::il::kGroup * 2.0 / kThreads;
     default: return it * E * 3.0 * C.g * C.g / 2.0 * 64.0 / kThreads / 8.0;
     }
 }

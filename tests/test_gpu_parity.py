@@ -289,7 +289,7 @@ def test_qc_packed_rules_and_saturation(rule):
         assert (g[5].astype(np.int32) == ref["lam"]).all()
 
 
-@pytest.mark.parametrize("sub,batch,early", [(128, 300, True), (256, 300, False), (128, 77, True)])
+@pytest.mark.parametrize("sub,batch,early", [(256, 600, True), (512, 600, False), (256, 77, True)])
 def test_interleaved_sub_batches(sub, batch, early):
     """The interleaved decoder in slices of `sub` codewords (several launch sequences,
     partly filled groups, early stop freezing every message of a stopped codeword)."""
@@ -299,7 +299,8 @@ def test_interleaved_sub_batches(sub, batch, early):
     code = L.Code(w.code)
     L.plan_set(code, L.params(**d), batch, "bin_interleaved", sub)
     info = L.plan_info(code, L.params(**d), batch)
-    assert info["family"] == "bin_interleaved" and info["cw_per_wg"] == sub
+    pad = lambda x: -(-x // 256) * 256  # slices are whole groups of 256 codewords
+    assert info["family"] == "bin_interleaved" and info["cw_per_wg"] == min(pad(sub), pad(batch))
     g = _gpu(code, d, llr, dump=True)
     ref = _ref(w.code, d, llr, dump=True)
     _check_decisions(w.code, g, ref)
