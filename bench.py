@@ -194,7 +194,7 @@ def main() -> None:
             k = min(w.batch, k * 8)
         k = int(min(w.batch, max(4 * nthreads, args.cpu_seconds / max(per_cw, 1e-9))))
         done_cw, cpu_s, passes = 0, 0.0, 0
-        while cpu_s < args.cpu_seconds and passes < 8:
+        while cpu_s < args.cpu_seconds and passes < 100000:
             t1 = time.perf_counter()
             dec(w.code, prm_o, llr_np[:k], nthreads=nthreads)
             cpu_s += time.perf_counter() - t1

@@ -210,7 +210,8 @@ __device__ __forceinline__ void cn_block(const Args &A, int k, int bx, int g) {
     for (int j = 0; j < DC; ++j)
         if (j < dc) raw[j] = ld(rq, vo, (uint32_t)(e0 + j) * Bp + gb);
     Pk m1, m2, f2, df;
-    uint32_t stot[kPairs];
+    Pk av[DC];
+    uint32_t sv[DC][kPairs], stot[kPairs];
 #pragma unroll
     for (int p = 0; p < kPairs; ++p) {
         m1[p] = m2[p] = splat(0x7FFF);
@@ -226,7 +227,9 @@ __device__ __forceinline__ void cn_block(const Args &A, int k, int bx, int g) {
                 const v2s a = pmax(q[p], -q[p]);
                 m2[p] = pmin(m2[p], pmax(m1[p], a));
                 m1[p] = pmin(m1[p], a);
-                stot[p] ^= as_u32(q[p] >> splat(15));
+                sv[j][p] = as_u32(q[p] >> splat(15));
+                stot[p] ^= sv[j][p];
+                av[j][p] = a;
             }
         }
     }
@@ -239,13 +242,12 @@ __device__ __forceinline__ void cn_block(const Args &A, int k, int bx, int g) {
 #pragma unroll
     for (int j = 0; j < DC; ++j) {
         if (j < dc) {
-            Pk q, rn;
-            unpack(raw[j], q);
+            Pk rn;
 #pragma unroll
             for (int p = 0; p < kPairs; ++p) {
-                const v2s t = pmin(pmax(q[p], -q[p]) - m1[p], splat(1));  // 0 where this edge holds the minimum
+                const v2s t = pmin(av[j][p] - m1[p], splat(1));  // 0 where this edge holds the minimum
                 const v2s mag = f2[p] + t * df[p];
-                const uint32_t sr = stot[p] ^ as_u32(q[p] >> splat(15));
+                const uint32_t sr = stot[p] ^ sv[j][p];
                 rn[p] = as_v2s(as_u32(mag) ^ sr) - as_v2s(sr);
             }
             uint32_t w = pack(rn);

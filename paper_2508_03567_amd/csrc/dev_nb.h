@@ -101,7 +101,7 @@ __device__ __forceinline__ void cn_block(const Args &A, int k, int wpb, int bx, 
     constexpr int H = G / 2;
     const DevCode &C = A.C;
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
+    const int w = wave_id();
     if (w >= wpb) return;
     const int row = bx * wpb + w;
     if (row >= C.m) return;
@@ -165,7 +165,7 @@ __device__ __forceinline__ void vn_block(const Args &A, int k, int bx, int by) {
     const DevCode &C = A.C;
     const long Bp = A.Bp;
     const int lane = threadIdx.x & 63;
-    const int v = bx * 4 + (threadIdx.x >> 6);
+    const int v = bx * 4 + wave_id();
     if (v >= C.n) return;
     const int g = by;
     const int b = g * 64 + lane;
@@ -215,7 +215,7 @@ __device__ __forceinline__ void vn_block(const Args &A, int k, int bx, int by) {
 __device__ __forceinline__ void syn_block(const Args &A, int slot_k, int bx, int by) {
     const DevCode &C = A.C;
     const int lane = threadIdx.x & 63;
-    const int row = bx * 4 + (threadIdx.x >> 6);
+    const int row = bx * 4 + wave_id();
     if (row >= C.m) return;
     const int g = by;
     const int b = g * 64 + lane;
@@ -234,7 +234,7 @@ __device__ __forceinline__ void init_block(const Args &A, int bx, int by) {
     const DevCode &C = A.C;
     const long Bp = A.Bp;
     const int lane = threadIdx.x & 63;
-    const int e = bx * 4 + (threadIdx.x >> 6);
+    const int e = bx * 4 + wave_id();
     const int b = by * 64 + lane;
     if (e < C.E) {
         const int16_t *gp = A.w.gam + (long)C.col_idx[e] * G * Bp + b;

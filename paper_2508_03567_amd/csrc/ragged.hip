@@ -175,7 +175,7 @@ __device__ void il_group(const JobDesc &J, int g, uint32_t *lds, uint64_t *red) 
 // --------------------------------------------------------- Min-Max, one group
 __device__ uint64_t nb_syn(const dev::nb::Args &A, int slot_k, int g, uint64_t *red) {
     const DevCode &C = A.C;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = dev::wave_id();
     const int b = g * 64 + lane;
     uint64_t acc = 0;
     for (int row = w; row < C.m; row += 4) {
