@@ -37,6 +37,10 @@ constexpr int kOwnLaunchGroups = 2;
 // A ragged launch stops taking chunks once its estimated device time reaches this,
 // so that launches stay short and the slots pipeline.
 constexpr double kLaunchTargetUs = 1500.0;
+// In continuous mode a chunk with its own launch sequence is cut to about this much
+// estimated device time, so that one large request spreads over several slots and
+// requests behind it are not held for its whole decode.
+constexpr double kOwnChunkTargetUs = 4000.0;
 
 struct Request {
     ldpcx_code *code = nullptr;
@@ -97,7 +101,7 @@ double est_us(const Request &r, int ncw) {
     switch (r.family) {
     case FAMILY_BIN_QC: return work / 2.5e6;
     case FAMILY_BIN_LDS: return work / 1.0e6;
-    case FAMILY_BIN_IL: return work / 2.5e5;
+    case FAMILY_BIN_IL: return work / 1.1e6;
     default: return work * ((double)r.code->g * r.code->g / 4096.0) / 3.0e3;
     }
 }
@@ -188,6 +192,13 @@ struct ldpcx_server {
             const int rem = r.batch - r.next_cw;
             int cap = rem;
             if (cfg.max_launch_cw > 0) cap = std::min(cap, cfg.max_launch_cw - cw_total);
+            if (own && cfg.mode == LDPCX_SERVE_CONTINUOUS) {
+                const double per_cw = est_us(r, 1024) / 1024.0;
+                int lim = (int)(kOwnChunkTargetUs / std::max(per_cw, 1e-3));
+                const int unit = r.family == FAMILY_BIN_IL ? bin_il_sub_batch(r.code->dev, rem, 0) : 64;
+                lim = std::max(unit, lim / unit * unit);
+                cap = std::min(cap, lim);
+            }
             if (cap <= 0) break;
             const size_t avail = cfg.hbm_budget - in_use - charge;
             const int n = max_fit(r, cap, avail);
