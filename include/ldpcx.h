@@ -166,7 +166,9 @@ typedef struct {
 /* Decode a ragged batch of jobs over different codes and sizes with ONE persistent
  * kernel launch on `stream` (per-codeword early termination inside).  Results are
  * identical to calling ldpcx_decode on each job.  AUTO schedules are resolved per job
- * as in ldpcx_decode. */
+ * as in ldpcx_decode.  Every job is cut into workgroup-local items (no workgroup waits
+ * for another); jobs over GF(128) or GF(256) have no such item and are rejected with
+ * LDPCX_E_UNSUPPORTED (decode them with ldpcx_decode). */
 ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs, void *stream);
 
 /* Autotune the launch configuration of (code, params, batch) by timing the candidate

@@ -75,12 +75,16 @@ hipError_t run(const Args &A, hipStream_t s) {
 
 }  // namespace
 
-bool nb_supported(int g) { return g == 4 || g == 8 || g == 16 || g == 32 || g == 64; }
+bool nb_supported(int g) { return g == 4 || g == 8 || g == 16 || g == 32 || g == 64 || g == 128 || g == 256; }
 
-size_t nb_work_bytes(const DevCode &C, int max_iters, int batch) { return dev::nb::carve(C, max_iters, batch).total; }
+size_t nb_work_bytes(const DevCode &C, int max_iters, int batch) {
+    if (C.g >= 128) return nbw_work_bytes(C, max_iters, batch);
+    return dev::nb::carve(C, max_iters, batch).total;
+}
 
 hipError_t launch_nb(const DevCode &C, int max_iters, int early_stop, int batch, void *ws, const DecodeIO &io,
                      hipStream_t s) {
+    if (C.g >= 128) return launch_nbw(C, max_iters, early_stop, batch, ws, io, s);
     const Args A = dev::nb::make_args(C, max_iters, early_stop, batch, ws, io);
     switch (C.g) {
     case 4: return run<4>(A, s);

@@ -244,7 +244,8 @@ __device__ __forceinline__ void run_item(const JobDesc &J, const Item &it, uint3
         case 8: nb_group<8>(J, it.blk, lds, red); break;
         case 16: nb_group<16>(J, it.blk, lds, red); break;
         case 32: nb_group<32>(J, it.blk, lds, red); break;
-        default: nb_group<64>(J, it.blk, lds, red); break;
+        case 64: nb_group<64>(J, it.blk, lds, red); break;
+        default: break;  // other fields never become items (rejected on the host)
         }
     }
 }
@@ -302,6 +303,9 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
             ldpcx_status st = check_params(c, &jb.params);
             if (st != LDPCX_OK) return cleanup(), st;
             if (c->nb_unsupported) return cleanup(), fail(LDPCX_E_UNSUPPORTED, "no Min-Max kernel for this field size");
+            if (c->g > 64)
+                return cleanup(), fail(LDPCX_E_UNSUPPORTED, "fields above GF(64) have no workgroup-local item; decode them "
+                                                            "with ldpcx_decode");
             if (device < 0) {
                 if ((st = check_device(c)) != LDPCX_OK) return cleanup(), st;
                 device = c->device;

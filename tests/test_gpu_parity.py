@@ -332,3 +332,32 @@ def test_interleaved_irregular_degrees(seed):
     assert (g[3].astype(np.int32) == ref["q"]).all()
     assert (g[4].astype(np.int32) == ref["r"]).all()
     assert (g[5].astype(np.int32) == ref["lam"]).all()
+
+
+@pytest.mark.parametrize("g_size,n,dc,batch,early", [(128, 16, 4, 9, True), (256, 16, 4, 5, True),
+                                                     (256, 16, 4, 4, False), (128, 15, 3, 6, False),
+                                                     (128, 20, 5, 3, True)])
+def test_minmax_large_fields(g_size, n, dc, batch, early):
+    """GF(128) and GF(256): the wide Min-Max kernels (lanes over the field entries)."""
+    m = n * 2 // dc
+    code = S.random_regular_nb_code(n, m, 2, dc, g_size, S.PRIM_POLY[g_size], seed=g_size + dc)
+    cw = S.random_codewords(code, batch, seed=5)
+    gam = S.nb_gamma_int16(cw, g_size, 1.0, seed=6)
+    d = dict(rule="minmax", schedule="flooding", max_iters=4, early_stop=early)
+    g = _gpu(L.Code(code), d, gam, dump=True)
+    ref = _ref(code, d, gam, dump=True)
+    _check_decisions(code, g, ref)
+    assert (g[3].astype(np.int32) == ref["alpha"]).all()
+    assert (g[4].astype(np.int32) == ref["beta"]).all()
+    # the plain decode path (no dump) gives the same decisions
+    g2 = _gpu(L.Code(code), d, gam)
+    _check_decisions(code, g2, ref)
+
+
+def test_ragged_rejects_large_fields():
+    code = S.random_regular_nb_code(16, 8, 2, 4, 128, S.PRIM_POLY[128], seed=1)
+    gam = S.nb_gamma_int16(S.random_codewords(code, 2, seed=1), 128, 1.0, seed=1)
+    h = L.Code(code)
+    with pytest.raises(L.LdpcxError) as ei:
+        L.decode_ragged([(h, L.params("minmax"), torch.from_numpy(gam).to(DEV))])
+    assert ei.value.status == L.E_UNSUPPORTED
