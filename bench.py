@@ -96,6 +96,9 @@ def main() -> None:
     ap.add_argument("--warm-requests", type=int, default=200, help="--serve: warm-up requests per load")
     ap.add_argument("--budget-gib", type=float, default=8.0, help="--serve: server HBM budget")
     ap.add_argument("--modes", type=str, default="continuous,per_request", help="--serve: serving modes")
+    ap.add_argument("--precision", action="store_true",
+                    help="Min-Max message precision: 16-bit vs 8-bit (bound 127) messages on the GF(64) workload, "
+                         "FER over Eb/N0 and fixed-iteration throughput")
     ap.add_argument("--sweep", action="store_true",
                     help="GF-size sweep instead: (2,4)-regular codes of 16/32/64 symbols over GF(4)..GF(256), "
                          "Min-Max, fixed iterations (one JSON line per point)")
@@ -110,6 +113,9 @@ def main() -> None:
         return
     if args.sweep:
         sweep_main(args)
+        return
+    if args.precision:
+        precision_main(args)
         return
 
     import torch
@@ -281,6 +287,42 @@ def sweep_main(args) -> None:
                               "ebn0_db": 2.0, "fer": fer, "data": "synthetic seeded BPSK/AWGN"}), flush=True)
             del gam, out, h
             torch.cuda.empty_cache()
+
+
+def precision_main(args) -> None:
+    """FER and throughput of the GF(64) Min-Max decoder with 16-bit and 8-bit messages."""
+    import torch
+    from paper_2508_03567_amd import ldpcx as L
+    from paper_2508_03567_amd import synth as S
+
+    dev = torch.device("cuda:0")
+    for eb in (1.5, 2.0, 2.5, 3.0):
+        w = S.workload(3, batch=args.batch or 8192, ebn0_db=eb)
+        cw, gam_np = S.make_inputs(w)
+        gam = torch.from_numpy(gam_np).to(dev)
+        h = L.Code(w.code)
+        for bound, name in ((0, "int16"), (127, "int8")):
+            prm = L.params("minmax", "flooding", w.max_iters, early_stop=True, nb_msg_max=bound)
+            hard, ok, it, _ = L.decode(h, prm, gam)
+            torch.cuda.synchronize()
+            fer = float((hard.cpu().numpy() != cw).any(axis=1).mean())
+            mean_it = float(it.float().mean())
+            prm_fixed = L.params("minmax", "flooding", w.max_iters, early_stop=False, nb_msg_max=bound)
+            out = L._outputs(h, w.batch, dev)
+            L.decode(h, prm_fixed, gam, out=out)
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            stream = torch.cuda.current_stream()
+            ev0.record(stream)
+            for _ in range(3):
+                L.decode(h, prm_fixed, gam, stream=stream, out=out)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1) / 3
+            print(json.dumps({"metric": "Min-Max message precision", "messages": name, "ebn0_db": eb, "fer": fer,
+                              "mean_iters": round(mean_it, 3), "workload": w.name, "batch": w.batch,
+                              "fixed_iter_info_gbit_s": round(w.info_bits_per_cw * w.batch / (ms * 1e-3) / 1e9, 4)}),
+                  flush=True)
 
 
 # ------------------------------------------------------------------ serving mix

@@ -96,7 +96,10 @@ typedef struct {
  * schedules: the layered update is Lambda_n <- Lambda_n - r_old + r_new); the check
  * node sees q_mn = clamp(Lambda_n - r_mn, +-msg_max); decision c_n = [Lambda_n < 0].
  * Min-Max arithmetic (eqs. (7)-(15)): messages int16, sums in 32 bit, alpha clamped
- * to 32767; decision = lowest x minimising gamma_n(x) + sum_m beta_mn(x). */
+ * to nb_msg_max (0 = 32767, the 16-bit decoder; 127 gives the 8-bit message variant of
+ * sec. 5, whose channel vectors are clipped to the same range: gamma'(x) =
+ * min(gamma(x), nb_msg_max) is used wherever gamma appears); decision = lowest x
+ * minimising gamma'_n(x) + sum_m beta_mn(x).  nb_msg_max is ignored for binary codes. */
 typedef struct {
     int32_t max_iters;
     int32_t early_stop;
@@ -106,6 +109,7 @@ typedef struct {
     int32_t nms_shift;
     int32_t oms_offset;
     int32_t msg_max;
+    int32_t nb_msg_max;
 } ldpcx_decode_params;
 
 /* Validate `desc`, build the library's device structures (CSR/CSC, layer table, GF

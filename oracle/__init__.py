@@ -63,13 +63,14 @@ class Params(ctypes.Structure):
     _fields_ = [("max_iters", ctypes.c_int32), ("early_stop", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("rule", ctypes.c_int32),
                 ("nms_num", ctypes.c_int32), ("nms_shift", ctypes.c_int32),
-                ("oms_offset", ctypes.c_int32), ("msg_max", ctypes.c_int32)]
+                ("oms_offset", ctypes.c_int32), ("msg_max", ctypes.c_int32),
+                ("nb_msg_max", ctypes.c_int32)]
 
 
 def params(rule="nms", schedule="flooding", max_iters=10, early_stop=True, nms_num=3,
-           nms_shift=2, oms_offset=1, msg_max=127) -> Params:
+           nms_shift=2, oms_offset=1, msg_max=127, nb_msg_max=0) -> Params:
     return Params(max_iters, int(bool(early_stop)), SCHEDULES[schedule], RULES[rule], nms_num,
-                  nms_shift, oms_offset, msg_max)
+                  nms_shift, oms_offset, msg_max, nb_msg_max)
 
 
 def _p(a, ct):

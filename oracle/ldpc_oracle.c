@@ -15,8 +15,11 @@
  *     position exactly as written, including F at the last edge and B at the
  *     first edge, which the outputs never use; the beta messages follow eqs.
  *     (11)-(13) and the variable-node update eqs. (14)-(15).  Messages are
- *     int32; alpha is clamped to 32767 when stored (a reading: the paper does
- *     not state a saturation).  Ties in the hard decision go to the lowest x.
+ *     int32; alpha is clamped when stored, to 32767 by default (a reading: the
+ *     paper does not state a saturation) or to nb_msg_max for the reduced-precision
+ *     variants of sec. 5 (8-bit messages: 127); the channel vector then takes part
+ *     clipped to the same bound, gamma'(x) = min(gamma(x), nb_msg_max).  Ties in the
+ *     hard decision go to the lowest x.
  *   - Binary min-sum is the GF(2) case of the same check-node rule written in
  *     the log-likelihood-ratio form: each outgoing message is the product of
  *     the other edges' signs times a normalised minimum of the other edges'
@@ -51,6 +54,7 @@ typedef struct {
     int32_t nms_shift;
     int32_t oms_offset;
     int32_t msg_max;
+    int32_t nb_msg_max; /* Min-Max message bound, 0 = 32767 */
 } orc_params;
 
 /* ------------------------------------------------------------------ GF(2^p) */
@@ -308,7 +312,7 @@ static void nb_decide(const nb_code *C, const int16_t *gamma, const int32_t *bet
     free(app);
 }
 
-static void nb_decode_one(const nb_code *C, const orc_params *P, const int16_t *gamma,
+static void nb_decode_one(const nb_code *C, const orc_params *P, const int16_t *gamma_in,
                           uint8_t *hard, int16_t *iters_out, uint8_t *ok_out,
                           int32_t *dalpha, int32_t *dbeta, int64_t *pairs)
 {
@@ -318,6 +322,11 @@ static void nb_decode_one(const nb_code *C, const orc_params *P, const int16_t *
     int32_t *beta = (int32_t *)calloc(EG, sizeof(int32_t));
     int32_t *ap = (int32_t *)malloc(sizeof(int32_t) * g);
     int64_t pfb = 0, pb = 0;
+    /* the channel vectors, clipped to the message bound of the chosen precision */
+    int amax = P->nb_msg_max > 0 ? P->nb_msg_max : 32767;
+    int16_t *gclip = (int16_t *)malloc(sizeof(int16_t) * (size_t)(n ? n : 1) * g);
+    for (size_t i = 0; i < (size_t)n * g; i++) gclip[i] = (int16_t)(gamma_in[i] > amax ? amax : gamma_in[i]);
+    const int16_t *gamma = gclip;
     /* Alg. 2 initialisation: alpha^(0) = gamma */
     for (int e = 0; e < E; e++)
         for (int x = 0; x < g; x++) alpha[(size_t)e * g + x] = gamma[(size_t)C->col_idx[e] * g + x];
@@ -348,7 +357,7 @@ static void nb_decode_one(const nb_code *C, const orc_params *P, const int16_t *
                 for (int x = 1; x < g; x++) if (ap[x] < mn) mn = ap[x];
                 for (int x = 0; x < g; x++) {
                     int a = ap[x] - mn;
-                    alpha[(size_t)e * g + x] = a > 32767 ? 32767 : a;
+                    alpha[(size_t)e * g + x] = a > amax ? amax : a;
                 }
             }
         }
@@ -360,7 +369,7 @@ static void nb_decode_one(const nb_code *C, const orc_params *P, const int16_t *
     if (dalpha) memcpy(dalpha, alpha, sizeof(int32_t) * (size_t)E * g);
     if (dbeta) memcpy(dbeta, beta, sizeof(int32_t) * (size_t)E * g);
     if (pairs) { pairs[0] += pfb; pairs[1] += pb; }
-    free(alpha); free(beta); free(ap);
+    free(alpha); free(beta); free(ap); free(gclip);
 }
 
 /* gamma: int16 [batch][n][g]; hard: uint8 [batch][n]; dumps int32 [batch][E][g] (may be NULL);

@@ -28,6 +28,7 @@ namespace nb {
 struct Args {
     DevCode C;
     int max_iters, early_stop, batch, Bp, Gn, fslots;
+    int amax;  // message bound: alpha and the channel vectors are clipped to it
     NbWork w;
     DecodeIO io;
 };
@@ -175,7 +176,7 @@ __device__ __forceinline__ void vn_block(const Args &A, int k, int bx, int by) {
     int S[G];
     const int16_t *gp = A.w.gam + (long)v * G * Bp + b;
 #pragma unroll
-    for (int x = 0; x < G; ++x) S[x] = gp[(long)x * Bp];
+    for (int x = 0; x < G; ++x) S[x] = min((int)gp[(long)x * Bp], A.amax);
     const int t0 = C.vn_ptr[v], t1 = C.vn_ptr[v + 1];
     for (int t = t0; t < t1; ++t) {
         const int16_t *bp = A.w.beta + (long)C.vn_ref[t] * G * Bp + b;
@@ -206,7 +207,7 @@ __device__ __forceinline__ void vn_block(const Args &A, int k, int bx, int by) {
         if (act) {
             int16_t *ap = A.w.alpha + (long)e * G * Bp + b;
 #pragma unroll
-            for (int x = 0; x < G; ++x) ap[(long)x * Bp] = (int16_t)min(a[x] - mn, 32767);
+            for (int x = 0; x < G; ++x) ap[(long)x * Bp] = (int16_t)min(a[x] - mn, A.amax);
         }
     }
 }
@@ -242,16 +243,16 @@ __device__ __forceinline__ void init_block(const Args &A, int bx, int by) {
         int16_t *bp = A.w.beta + (long)e * G * Bp + b;
 #pragma unroll 8
         for (int x = 0; x < G; ++x) {
-            ap[(long)x * Bp] = gp[(long)x * Bp];
+            ap[(long)x * Bp] = (int16_t)min((int)gp[(long)x * Bp], A.amax);
             bp[(long)x * Bp] = 0;
         }
     }
     if (e < C.n) {
         // most likely channel symbol, lowest x on ties
         const int16_t *gp = A.w.gam + (long)e * G * Bp + b;
-        int best = 0, bv = gp[0];
+        int best = 0, bv = min((int)gp[0], A.amax);
         for (int x = 1; x < G; ++x) {
-            const int val = gp[(long)x * Bp];
+            const int val = min((int)gp[(long)x * Bp], A.amax);
             if (val < bv) {
                 bv = val;
                 best = x;
@@ -297,9 +298,11 @@ inline Carve carve(const DevCode &C, int max_iters, int batch) {
     return c;
 }
 
-inline Args make_args(const DevCode &C, int max_iters, int early_stop, int batch, void *base, const DecodeIO &io) {
+inline Args make_args(const DevCode &C, int max_iters, int early_stop, int batch, int amax, void *base,
+                      const DecodeIO &io) {
     Args A;
     A.C = C;
+    A.amax = amax;
     A.max_iters = max_iters;
     A.early_stop = early_stop;
     A.batch = batch;

@@ -33,6 +33,7 @@ namespace nbw {
 struct Args {
     DevCode C;
     int max_iters, early_stop, batch;
+    int amax;  // message bound: alpha and the channel vectors are clipped to it
     NbwWork w;
     DecodeIO io;
 };
@@ -149,7 +150,7 @@ __device__ __forceinline__ void vn_unit(const Args &A, int k, long unit) {
     const int16_t *gam = (const int16_t *)A.io.llr + ((size_t)b * C.n + v) * G;
     int S[NE];
 #pragma unroll
-    for (int i = 0; i < NE; ++i) S[i] = gam[lane + 64 * i];
+    for (int i = 0; i < NE; ++i) S[i] = min((int)gam[lane + 64 * i], A.amax);
     const int t0 = C.vn_ptr[v], t1 = C.vn_ptr[v + 1];
     for (int t = t0; t < t1; ++t) {
         const int16_t *bp = A.w.beta + row_off(C.vn_ref[t], b, A.batch, G);
@@ -177,7 +178,7 @@ __device__ __forceinline__ void vn_unit(const Args &A, int k, long unit) {
         mn = wave_min(mn);
         int16_t *ap = A.w.alpha + row_off(e, b, A.batch, G);
 #pragma unroll
-        for (int i = 0; i < NE; ++i) ap[lane + 64 * i] = (int16_t)min(a[i] - mn, 32767);
+        for (int i = 0; i < NE; ++i) ap[lane + 64 * i] = (int16_t)min(a[i] - mn, A.amax);
     }
 }
 
@@ -193,7 +194,7 @@ __device__ __forceinline__ void init_edge_unit(const Args &A, long unit) {
     uint32_t *bp = (uint32_t *)(A.w.beta + row_off(e, b, A.batch, G));
 #pragma unroll
     for (int p = 0; p < G / 128; ++p) {
-        ap[lane + 64 * p] = gam[lane + 64 * p];
+        ap[lane + 64 * p] = as_u32(pmin(as_v2s(gam[lane + 64 * p]), splat(A.amax)));
         bp[lane + 64 * p] = 0u;
     }
 }
@@ -210,7 +211,7 @@ __device__ __forceinline__ void init_var_unit(const Args &A, long unit) {
     const int16_t *gam = (const int16_t *)A.io.llr + ((size_t)b * C.n + v) * G;
     int key = 0x7FFFFFFF;
 #pragma unroll
-    for (int i = 0; i < NE; ++i) key = min(key, ((int)gam[lane + 64 * i] << 9) | (lane + 64 * i));
+    for (int i = 0; i < NE; ++i) key = min(key, (min((int)gam[lane + 64 * i], A.amax) << 9) | (lane + 64 * i));
     key = wave_min(key);
     if (lane == 0) ((uint8_t *)A.io.hard)[(size_t)b * C.n + v] = (uint8_t)(key & 0x1FF);
 }
@@ -263,9 +264,11 @@ inline Carve carve(const DevCode &C, int max_iters, int batch) {
     return c;
 }
 
-inline Args make_args(const DevCode &C, int max_iters, int early_stop, int batch, void *base, const DecodeIO &io) {
+inline Args make_args(const DevCode &C, int max_iters, int early_stop, int batch, int amax, void *base,
+                      const DecodeIO &io) {
     Args A;
     A.C = C;
+    A.amax = amax;
     A.max_iters = max_iters;
     A.early_stop = early_stop;
     A.batch = batch;

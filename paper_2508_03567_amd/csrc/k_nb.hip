@@ -82,10 +82,10 @@ size_t nb_work_bytes(const DevCode &C, int max_iters, int batch) {
     return dev::nb::carve(C, max_iters, batch).total;
 }
 
-hipError_t launch_nb(const DevCode &C, int max_iters, int early_stop, int batch, void *ws, const DecodeIO &io,
-                     hipStream_t s) {
-    if (C.g >= 128) return launch_nbw(C, max_iters, early_stop, batch, ws, io, s);
-    const Args A = dev::nb::make_args(C, max_iters, early_stop, batch, ws, io);
+hipError_t launch_nb(const DevCode &C, int max_iters, int early_stop, int batch, int amax, void *ws,
+                     const DecodeIO &io, hipStream_t s) {
+    if (C.g >= 128) return launch_nbw(C, max_iters, early_stop, batch, amax, ws, io, s);
+    const Args A = dev::nb::make_args(C, max_iters, early_stop, batch, amax, ws, io);
     switch (C.g) {
     case 4: return run<4>(A, s);
     case 8: return run<8>(A, s);

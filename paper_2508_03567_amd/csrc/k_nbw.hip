@@ -83,9 +83,9 @@ hipError_t run(const Args &A, hipStream_t s) {
 
 size_t nbw_work_bytes(const DevCode &C, int max_iters, int batch) { return dev::nbw::carve(C, max_iters, batch).total; }
 
-hipError_t launch_nbw(const DevCode &C, int max_iters, int early_stop, int batch, void *ws, const DecodeIO &io,
-                      hipStream_t s) {
-    const Args A = dev::nbw::make_args(C, max_iters, early_stop, batch, ws, io);
+hipError_t launch_nbw(const DevCode &C, int max_iters, int early_stop, int batch, int amax, void *ws,
+                      const DecodeIO &io, hipStream_t s) {
+    const Args A = dev::nbw::make_args(C, max_iters, early_stop, batch, amax, ws, io);
     switch (C.g) {
     case 128: return run<128>(A, s);
     case 256: return run<256>(A, s);

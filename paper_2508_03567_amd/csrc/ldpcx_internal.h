@@ -122,14 +122,15 @@ struct NbwWork {
     int16_t *it;     // [batch]
 };
 size_t nb_work_bytes(const DevCode &C, int max_iters, int batch);
-hipError_t launch_nb(const DevCode &C, int max_iters, int early_stop, int batch, void *ws, const DecodeIO &io,
-                     hipStream_t s);
+// amax: message bound (32767 for 16-bit messages, 127 for the 8-bit variant).
+hipError_t launch_nb(const DevCode &C, int max_iters, int early_stop, int batch, int amax, void *ws,
+                     const DecodeIO &io, hipStream_t s);
 // Field sizes with a compiled Min-Max kernel (4..64 interleaved, 128 and 256 wide).
 bool nb_supported(int g);
 // The wide (g >= 128) decoder: workspace bytes and launch sequence.
 size_t nbw_work_bytes(const DevCode &C, int max_iters, int batch);
-hipError_t launch_nbw(const DevCode &C, int max_iters, int early_stop, int batch, void *ws, const DecodeIO &io,
-                      hipStream_t s);
+hipError_t launch_nbw(const DevCode &C, int max_iters, int early_stop, int batch, int amax, void *ws,
+                      const DecodeIO &io, hipStream_t s);
 
 __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 __host__ __device__ inline int pad64(int b) { return (b + 63) & ~63; }

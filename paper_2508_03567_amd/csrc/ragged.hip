@@ -382,7 +382,7 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
                 add(I_IL, D.il.G);
             } else {
                 const long groups = pad64(jb.batch) / 64;
-                D.nb = dev::nb::make_args(D.C, p.max_iters, p.early_stop, jb.batch, ws, D.io);
+                D.nb = dev::nb::make_args(D.C, p.max_iters, p.early_stop, jb.batch, nb_amax(&p), ws, D.io);
                 const size_t need = dev::nb::cn_lds_bytes(D.nb, 4);
                 if (need > cap)
                     return cleanup(), fail(LDPCX_E_UNSUPPORTED, "check degree too large for the persistent engine");

@@ -89,11 +89,14 @@ ldpcx_status check_params(const ldpcx_code *c, const ldpcx_decode_params *p) {
             return fail(LDPCX_E_INVAL, "layered schedule needs a valid layer size");
     } else {
         if (p->rule != LDPCX_RULE_MINMAX) return fail(LDPCX_E_INVAL, "codes over GF(g > 2) take rule MINMAX");
+        if (p->nb_msg_max < 0 || p->nb_msg_max > 32767) return fail(LDPCX_E_INVAL, "nb_msg_max must be in [0, 32767]");
         if (p->schedule == LDPCX_SCHED_LAYERED)
             return fail(LDPCX_E_UNSUPPORTED, "layered Min-Max is not implemented");
     }
     return LDPCX_OK;
 }
+
+int nb_amax(const ldpcx_decode_params *p) { return p->nb_msg_max > 0 ? p->nb_msg_max : 32767; }
 
 BinRule bin_rule(const ldpcx_decode_params *p) {
     BinRule R;
@@ -216,7 +219,7 @@ hipError_t enqueue_interleaved(ldpcx_code *c, const ldpcx_decode_params *p, cons
     if (pl.family == FAMILY_BIN_IL)
         return launch_bin_il(c->dev, bin_rule(p), p->max_iters, p->early_stop, batch, pl.cpw, ws, io, dump_scratch,
                              s);
-    return launch_nb(c->dev, p->max_iters, p->early_stop, batch, ws, io, s);
+    return launch_nb(c->dev, p->max_iters, p->early_stop, batch, nb_amax(p), ws, io, s);
 }
 
 bool graphs_enabled() {

@@ -74,6 +74,7 @@ const DeviceInfo &device_info(int dev);
 ldpcx_status check_params(const ldpcx_code *c, const ldpcx_decode_params *p);
 ldpcx_status check_device(const ldpcx_code *c);
 BinRule bin_rule(const ldpcx_decode_params *p);
+int nb_amax(const ldpcx_decode_params *p);  // Min-Max message bound of the params
 Plan default_plan(const ldpcx_code *c, const ldpcx_decode_params *p, int batch);
 Plan plan_for(ldpcx_code *c, const ldpcx_decode_params *p, int batch);
 uint64_t tune_key(const ldpcx_decode_params *p, int batch);

@@ -41,7 +41,7 @@ class CodeDesc(ctypes.Structure):
 class DecodeParams(ctypes.Structure):
     _fields_ = [("max_iters", ctypes.c_int32), ("early_stop", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("rule", ctypes.c_int32), ("nms_num", ctypes.c_int32), ("nms_shift", ctypes.c_int32),
-                ("oms_offset", ctypes.c_int32), ("msg_max", ctypes.c_int32)]
+                ("oms_offset", ctypes.c_int32), ("msg_max", ctypes.c_int32), ("nb_msg_max", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -213,9 +213,9 @@ def ldpcx_server_destroy(srv: int) -> None:
 
 # ---------------------------------------------------------------- convenience
 def params(rule="nms", schedule="flooding", max_iters=10, early_stop=True, nms_num=3, nms_shift=2, oms_offset=1,
-           msg_max=127) -> DecodeParams:
+           msg_max=127, nb_msg_max=0) -> DecodeParams:
     return DecodeParams(int(max_iters), int(bool(early_stop)), SCHED[schedule], RULE[rule], nms_num, nms_shift,
-                        oms_offset, msg_max)
+                        oms_offset, msg_max, nb_msg_max)
 
 
 class Code:

@@ -361,3 +361,23 @@ def test_ragged_rejects_large_fields():
     with pytest.raises(L.LdpcxError) as ei:
         L.decode_ragged([(h, L.params("minmax"), torch.from_numpy(gam).to(DEV))])
     assert ei.value.status == L.E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("g_size,bound", [(64, 127), (16, 50), (128, 127), (256, 90)])
+def test_minmax_reduced_precision(g_size, bound):
+    """Min-Max with a reduced message bound (127: the 8-bit variant): alpha and the
+    channel vectors clipped to the bound, on both the interleaved and the wide kernels."""
+    if g_size == 64:
+        w = S.workload(3, batch=70)
+        code = w.code
+        cw, gam = S.make_inputs(w, seed_offset=4)
+    else:
+        code = S.random_regular_nb_code(16, 8, 2, 4, g_size, S.PRIM_POLY[g_size], seed=3)
+        gam = S.nb_gamma_int16(S.random_codewords(code, 7, seed=2), g_size, 1.5, seed=3)
+    d = dict(rule="minmax", schedule="flooding", max_iters=5, early_stop=True, nb_msg_max=bound)
+    g = _gpu(L.Code(code), d, gam, dump=True)
+    ref = _ref(code, d, gam, dump=True)
+    _check_decisions(code, g, ref)
+    assert (g[3].astype(np.int32) == ref["alpha"]).all()
+    assert (g[4].astype(np.int32) == ref["beta"]).all()
+    assert ref["alpha"].max() <= bound

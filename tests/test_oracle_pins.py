@@ -246,17 +246,22 @@ def test_tree_code_min_sum_equals_ml():
     assert checked > 50
 
 
-def test_gf2_minmax_decoder_equals_min_sum_decoder():
+@pytest.mark.parametrize("bound", [None, 31, 12])
+def test_gf2_minmax_decoder_equals_min_sum_decoder(bound):
     """Binary min-sum is the GF(2) case of Alg. 2: decisions, iteration counts
-    and every message agree (alpha(1)-alpha(0) = q, beta(1)-beta(0) = r)."""
+    and every message agree (alpha(1)-alpha(0) = q, beta(1)-beta(0) = r).  With a
+    reduced message bound M (the 8-bit style variants) the Min-Max clamp of alpha at M
+    is the min-sum saturation of q at +-M, given channel values within +-M."""
     w = S.workload(0, batch=40)
     cw, llr = S.make_inputs(w)
+    if bound is not None:
+        llr = np.clip(llr, -bound, bound).astype(np.int8)
     code = w.code
     L = llr.astype(np.int32)
     gamma = np.stack([np.maximum(0, -L), np.maximum(0, L)], axis=2).astype(np.int16)
     for iters in [1, 2, 5]:
-        prm_b = O.params("ms", "flooding", iters, True, msg_max=10 ** 6)
-        prm_n = O.params("minmax", "flooding", iters, True)
+        prm_b = O.params("ms", "flooding", iters, True, msg_max=10 ** 6 if bound is None else bound)
+        prm_n = O.params("minmax", "flooding", iters, True, nb_msg_max=0 if bound is None else bound)
         b = O.decode_binary(code, prm_b, llr, dump=True)
         code_nb = S.Code("gf2", 2, 0x3, code.n, code.m, code.row_ptr, code.col_idx,
                          np.ones(code.nnz, dtype=np.uint8))
@@ -266,6 +271,9 @@ def test_gf2_minmax_decoder_equals_min_sum_decoder():
         assert (b["hard"] == nb["hard"]).all()
         assert (nb["alpha"][..., 1] - nb["alpha"][..., 0] == b["q"]).all()
         assert (nb["beta"][..., 1] - nb["beta"][..., 0] == b["r"]).all()
+        if bound is not None:
+            assert nb["alpha"].max() <= bound and nb["beta"].max() <= bound
+            assert (np.abs(b["q"]) == bound).any()  # the saturation did act
 
 
 @pytest.mark.parametrize("cfg", [0, 1, 3])
