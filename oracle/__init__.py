@@ -22,14 +22,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ldpc_oracle.c")
 _SO = os.path.join(_HERE, "libldpc_oracle.so")
 
-RULES = {"ms": 0, "nms": 1, "oms": 2, "minmax": 3}
+RULES = {"ms": 0, "nms": 1, "oms": 2, "minmax": 3, "spa": 4}
 SCHEDULES = {"flooding": 0, "layered": 1}
 
 
 def build() -> str:
     """Compile the oracle with gcc (always recompiles)."""
     tmp = _SO + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp])
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
     os.replace(tmp, _SO)
     return _SO
 
@@ -55,6 +55,12 @@ def lib():
         L.orc_minmax_cn.restype = None
         L.orc_decode_binary.restype = ctypes.c_int
         L.orc_decode_nb.restype = ctypes.c_int
+        L.orc_spa_weight.restype = ctypes.c_int
+        L.orc_spa_weight.argtypes = [ctypes.c_int]
+        L.orc_wht.restype = None
+        L.orc_wht.argtypes = [ctypes.c_int, i32p, i32p]
+        L.orc_spa_cn.restype = None
+        L.orc_decode_spa.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -150,6 +156,8 @@ def decode_binary(code, prm: Params, llr: np.ndarray, dump: bool = False, nthrea
         _p(ok, ctypes.c_uint8), _p(it, ctypes.c_int16),
         None if dq is None else _p(dq, ctypes.c_int32), None if dr is None else _p(dr, ctypes.c_int32),
         None if dl is None else _p(dl, ctypes.c_int32), ctypes.c_int(_nthreads(nthreads)))
+    if rc == -2:
+        raise ValueError("oracle: the fixed-point FFT-SPA covers fields up to GF(64)")
     if rc != 0:
         raise ValueError("oracle: every check must have degree >= 2")
     out = dict(hard=hard, ok=ok, iters=it)
@@ -184,4 +192,58 @@ def decode_nb(code, prm: Params, gamma: np.ndarray, dump: bool = False, nthreads
     out = dict(hard=hard, ok=ok, iters=it, pairs=pairs)
     if dump:
         out.update(alpha=da, beta=db)
+    return out
+
+
+# ------------------------------------------------------------ fixed-point FFT-SPA
+def spa_weight(c: int) -> int:
+    """round(2^24 exp(-c / 4)): channel weight of a symbol with cost c."""
+    return lib().orc_spa_weight(int(c))
+
+
+def wht(x) -> np.ndarray:
+    """Walsh-Hadamard transform of an integer vector (length g)."""
+    x = np.ascontiguousarray(x, dtype=np.int32)
+    out = np.empty_like(x)
+    lib().orc_wht(ctypes.c_int(len(x)), _p(x, ctypes.c_int32), _p(out, ctypes.c_int32))
+    return out
+
+
+def spa_cn(g: int, poly: int, h, u) -> np.ndarray:
+    """Check node of the fixed-point FFT-SPA: u int [dc, g] (Q24) -> v' [dc, g]."""
+    h = np.ascontiguousarray(h, dtype=np.uint8)
+    u = np.ascontiguousarray(u, dtype=np.int32)
+    dc = len(h)
+    v = np.empty((dc, g), dtype=np.int32)
+    lib().orc_spa_cn(ctypes.c_int(g), ctypes.c_uint32(poly), ctypes.c_int(dc), _p(h, ctypes.c_uint8),
+                     _p(u, ctypes.c_int32), _p(v, ctypes.c_int32))
+    return v
+
+
+def decode_spa(code, prm: Params, gamma: np.ndarray, dump: bool = False, nthreads=None) -> dict:
+    """gamma int16 [B, n, g], g <= 64 -> dict(hard, ok, iters, and u/v dumps [B, E, g] in Q24)."""
+    gamma = np.ascontiguousarray(gamma, dtype=np.int16)
+    B, n, g = gamma.shape
+    rp = np.ascontiguousarray(code.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(code.col_idx, dtype=np.int32)
+    hv = np.ascontiguousarray(code.h_val if code.h_val is not None else np.ones(len(ci)), dtype=np.uint8)
+    E = int(rp[-1])
+    hard = np.empty((B, n), dtype=np.uint8)
+    ok = np.empty(B, dtype=np.uint8)
+    it = np.empty(B, dtype=np.int16)
+    du = np.empty((B, E, g), dtype=np.int32) if dump else None
+    dv = np.empty((B, E, g), dtype=np.int32) if dump else None
+    rc = lib().orc_decode_spa(
+        ctypes.c_int(g), ctypes.c_uint32(code.prim_poly), ctypes.c_int(n), ctypes.c_int(code.m),
+        _p(rp, ctypes.c_int32), _p(ci, ctypes.c_int32), _p(hv, ctypes.c_uint8), ctypes.byref(prm),
+        ctypes.c_int(B), _p(gamma, ctypes.c_int16), _p(hard, ctypes.c_uint8), _p(ok, ctypes.c_uint8),
+        _p(it, ctypes.c_int16), None if du is None else _p(du, ctypes.c_int32),
+        None if dv is None else _p(dv, ctypes.c_int32), ctypes.c_int(_nthreads(nthreads)))
+    if rc == -2:
+        raise ValueError("oracle: the fixed-point FFT-SPA covers fields up to GF(64)")
+    if rc != 0:
+        raise ValueError("oracle: every check must have degree >= 2")
+    out = dict(hard=hard, ok=ok, iters=it)
+    if dump:
+        out.update(u=du, v=dv)
     return out

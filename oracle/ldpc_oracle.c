@@ -406,3 +406,188 @@ int orc_decode_nb(int g, uint32_t poly, int n, int m, const int32_t *row_ptr, co
     free(vn_ptr); free(vn_edge); free(fill);
     return 0;
 }
+
+/* ------------------------------------------------ fixed-point FFT-SPA (Alg. 1) */
+/*
+ * Alg. 1 in the probability domain with fixed point Q24 (2^24 = probability 1),
+ * for fields up to GF(64) (so that the transform sums stay within 32 bits).  The
+ * paper runs it in floating point and in 32- and 8-bit fixed point without stating
+ * the fixed-point rules; these are the readings used here:
+ *   - channel: p~(x) = W(gamma(x)) with W(c) = round(2^24 exp(-c / 4)) (gamma is the
+ *     symbol cost in units of a quarter LLR, so exp(-gamma/4) is proportional to
+ *     p(c_n = x | y_n)), then p = norm(p~);
+ *   - norm(z): with S = sum_x z(x) > 0 and R = floor(2^46 / S),
+ *     norm(z)(x) = floor((z(x) R + 2^21) / 2^22); when S = 0 the result is the
+ *     channel vector p_n (uniform 2^24 / g for the channel itself);
+ *   - product of two Q24 numbers: qmul(a, b) = floor((a b + 2^23) / 2^24), applied in
+ *     ascending edge order (the first factor taken as is);
+ *   - eq. (8): the transform over GF(2^q) is the Walsh-Hadamard transform
+ *     F(f) = sum_t (-1)^popcount(f & t) u(t), exact in integers; the inverse is the same
+ *     sum followed by floor division by g and a clamp at 0;
+ *   - permutation (eq. 7) u'(t) = u(h^-1 t) and depermutation v'(x) = v(h x), as in
+ *     the Min-Max reading (the distribution of h c_n);
+ *   - eqs. (10)-(11): z(x) = qmul-product of p_n(x) and the other incoming v'; the
+ *     outgoing message is norm(z);
+ *   - decision: argmax of p_n(x) times every incoming v' (same product rule), lowest
+ *     x on ties; the stop rule and iteration count are those of Alg. 2.
+ */
+#include <math.h>
+
+#define SPA_Q 24
+
+int orc_spa_weight(int c)
+{
+    if (c < 0) c = 0;
+    return (int)floor((double)(1 << SPA_Q) * exp(-(double)c / 4.0) + 0.5);
+}
+
+static int64_t floordiv(int64_t x, int64_t d) { return x >= 0 ? x / d : -((-x + d - 1) / d); }
+
+static int32_t spa_qmul(int32_t a, int32_t b)
+{
+    return (int32_t)floordiv((int64_t)a * b + ((int64_t)1 << (SPA_Q - 1)), (int64_t)1 << SPA_Q);
+}
+
+/* norm(z) into out; returns 0 when sum z = 0 (out untouched) */
+static int spa_norm(int g, const int32_t *z, int32_t *out)
+{
+    int64_t s = 0;
+    for (int x = 0; x < g; x++) s += z[x];
+    if (s <= 0) return 0;
+    int64_t r = ((int64_t)1 << 46) / s;
+    for (int x = 0; x < g; x++) out[x] = (int32_t)(((int64_t)z[x] * r + ((int64_t)1 << 21)) >> 22);
+    return 1;
+}
+
+static int popc(unsigned v) { int c = 0; while (v) { c += v & 1u; v >>= 1; } return c; }
+
+/* out(f) = sum_t (-1)^popcount(f & t) in(t) */
+void orc_wht(int g, const int32_t *in, int32_t *out)
+{
+    for (int f = 0; f < g; f++) {
+        int64_t s = 0;
+        for (int t = 0; t < g; t++) s += (popc((unsigned)(f & t)) & 1) ? -(int64_t)in[t] : in[t];
+        out[f] = (int32_t)s;
+    }
+}
+
+/* Check-node processing of Alg. 1 for one check: u: [dc][g] incoming Q24 messages,
+ * v: [dc][g] outgoing (depermuted) messages. */
+void orc_spa_cn(int g, uint32_t poly, int dc, const uint8_t *h, const int32_t *u, int32_t *v)
+{
+    int32_t *U = (int32_t *)malloc(sizeof(int32_t) * (size_t)dc * g);
+    int32_t *t1 = (int32_t *)malloc(sizeof(int32_t) * g);
+    int32_t *acc = (int32_t *)malloc(sizeof(int32_t) * g);
+    int32_t *vv = (int32_t *)malloc(sizeof(int32_t) * g);
+    for (int j = 0; j < dc; j++) {
+        orc_gf_permute(g, poly, h[j], u + (size_t)j * g, t1);   /* eq. (7) */
+        orc_wht(g, t1, U + (size_t)j * g);                      /* forward transform of eq. (8) */
+    }
+    for (int n = 0; n < dc; n++) {
+        int first = 1;
+        for (int j = 0; j < dc; j++) {
+            if (j == n) continue;
+            for (int f = 0; f < g; f++)
+                acc[f] = first ? U[(size_t)j * g + f] : spa_qmul(acc[f], U[(size_t)j * g + f]);
+            first = 0;
+        }
+        orc_wht(g, acc, t1);                                    /* inverse transform */
+        for (int t = 0; t < g; t++) {
+            int64_t x = floordiv(t1[t], g);
+            vv[t] = x < 0 ? 0 : (int32_t)x;
+        }
+        for (int x = 0; x < g; x++)                              /* eq. (9): v'(x) = v(h x) */
+            v[(size_t)n * g + x] = vv[orc_gf_mul(g, poly, h[n], x)];
+    }
+    free(U); free(t1); free(acc); free(vv);
+}
+
+static void spa_channel(int g, const int16_t *gam, int32_t *p)
+{
+    int32_t *w = (int32_t *)malloc(sizeof(int32_t) * g);
+    for (int x = 0; x < g; x++) w[x] = orc_spa_weight(gam[x]);
+    if (!spa_norm(g, w, p))
+        for (int x = 0; x < g; x++) p[x] = (1 << SPA_Q) / g;
+    free(w);
+}
+
+static void spa_decode_one(const nb_code *C, const orc_params *P, const int16_t *gamma,
+                           uint8_t *hard, int16_t *iters_out, uint8_t *ok_out, int32_t *du, int32_t *dv)
+{
+    int g = C->g, n = C->n, m = C->m, E = C->row_ptr[m];
+    size_t EG = (size_t)(E ? E : 1) * g;
+    int32_t *pch = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1) * g);
+    int32_t *u = (int32_t *)malloc(sizeof(int32_t) * EG);
+    int32_t *v = (int32_t *)calloc(EG, sizeof(int32_t));
+    int32_t *z = (int32_t *)malloc(sizeof(int32_t) * g);
+    for (int i = 0; i < n; i++) spa_channel(g, gamma + (size_t)i * g, pch + (size_t)i * g);
+    for (int e = 0; e < E; e++)                                  /* initialisation: u = p */
+        for (int x = 0; x < g; x++) u[(size_t)e * g + x] = pch[(size_t)C->col_idx[e] * g + x];
+    for (int i = 0; i < n; i++) {
+        int best = 0;
+        for (int x = 1; x < g; x++) if (pch[(size_t)i * g + x] > pch[(size_t)i * g + best]) best = x;
+        hard[i] = (uint8_t)best;
+    }
+    int it = 0;
+    for (int k = 1; k <= P->max_iters; k++) {
+        if (P->early_stop && orc_syndrome_ok(g, C->poly, m, C->row_ptr, C->col_idx, C->h_val, hard)) break;
+        for (int i = 0; i < m; i++) {
+            int b = C->row_ptr[i], dc = C->row_ptr[i + 1] - b;
+            orc_spa_cn(g, C->poly, dc, C->h_val + b, u + (size_t)b * g, v + (size_t)b * g);
+        }
+        for (int i = 0; i < n; i++) {
+            for (int t = C->vn_ptr[i]; t < C->vn_ptr[i + 1]; t++) {
+                int e = C->vn_edge[t];
+                for (int x = 0; x < g; x++) {
+                    int32_t a = pch[(size_t)i * g + x];
+                    for (int w = C->vn_ptr[i]; w < C->vn_ptr[i + 1]; w++)
+                        if (w != t) a = spa_qmul(a, v[(size_t)C->vn_edge[w] * g + x]);
+                    z[x] = a;
+                }
+                if (!spa_norm(g, z, u + (size_t)e * g))
+                    for (int x = 0; x < g; x++) u[(size_t)e * g + x] = pch[(size_t)i * g + x];
+            }
+            /* a posteriori product and decision */
+            int best = 0, bv = -1;
+            for (int x = 0; x < g; x++) {
+                int32_t a = pch[(size_t)i * g + x];
+                for (int w = C->vn_ptr[i]; w < C->vn_ptr[i + 1]; w++) a = spa_qmul(a, v[(size_t)C->vn_edge[w] * g + x]);
+                if (a > bv) { bv = a; best = x; }
+            }
+            hard[i] = (uint8_t)best;
+        }
+        it = k;
+    }
+    *iters_out = (int16_t)it;
+    *ok_out = (uint8_t)orc_syndrome_ok(g, C->poly, m, C->row_ptr, C->col_idx, C->h_val, hard);
+    if (du) memcpy(du, u, sizeof(int32_t) * (size_t)E * g);
+    if (dv) memcpy(dv, v, sizeof(int32_t) * (size_t)E * g);
+    free(pch); free(u); free(v); free(z);
+}
+
+/* gamma: int16 [batch][n][g], g <= 64; hard: uint8 [batch][n]; dumps int32 [batch][E][g]
+ * (may be NULL): u (variable-to-check) and v' (check-to-variable) messages in Q24. */
+int orc_decode_spa(int g, uint32_t poly, int n, int m, const int32_t *row_ptr, const int32_t *col_idx,
+                   const uint8_t *h_val, const orc_params *P, int batch, const int16_t *gamma,
+                   uint8_t *hard, uint8_t *syndrome_ok, int16_t *iters, int32_t *dump_u,
+                   int32_t *dump_v, int nthreads)
+{
+    int E = row_ptr[m];
+    if (g > 64) return -2;
+    for (int i = 0; i < m; i++)
+        if (row_ptr[i + 1] - row_ptr[i] < 2) return -1;
+    int32_t *vn_ptr = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+    int32_t *vn_edge = (int32_t *)malloc(sizeof(int32_t) * (E ? E : 1));
+    int32_t *fill = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+    for (int e = 0; e < E; e++) vn_ptr[col_idx[e] + 1]++;
+    for (int i = 0; i < n; i++) vn_ptr[i + 1] += vn_ptr[i];
+    for (int e = 0; e < E; e++) { int i = col_idx[e]; vn_edge[vn_ptr[i] + fill[i]++] = e; }
+    nb_code C = { g, poly, n, m, row_ptr, col_idx, h_val, vn_ptr, vn_edge };
+    (void)nthreads;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int b = 0; b < batch; b++)
+        spa_decode_one(&C, P, gamma + (size_t)b * n * g, hard + (size_t)b * n, iters + b, syndrome_ok + b,
+                       dump_u ? dump_u + (size_t)b * E * g : NULL, dump_v ? dump_v + (size_t)b * E * g : NULL);
+    free(vn_ptr); free(vn_edge); free(fill);
+    return 0;
+}

@@ -390,3 +390,95 @@ def test_app_is_channel_plus_check_messages(cfg, sched):
             lam[:, v] += out["r"][:, e]
         assert (lam == out["lam"]).all()
         assert (out["q"] == np.clip(out["lam"][:, w.code.col_idx] - out["r"], -127, 127)).all()
+
+
+# ------------------------------------------------------ fixed-point FFT-SPA
+def test_spa_channel_weights():
+    """W(c) = round(2^24 e^(-c/4)): W(0) = 1 in Q24, one LLR unit (4 quarters) divides
+    by e, and the table reaches 0 once 2^24 e^(-c/4) < 1/2 (c > 4 ln 2^25 = 69.3)."""
+    one = 1 << 24
+    assert O.spa_weight(0) == one
+    for c in range(0, 66):
+        w0, w4 = O.spa_weight(c), O.spa_weight(c + 4)
+        assert abs(w4 * np.e - w0) <= 0.5 * np.e + 0.5  # multiplicative in c up to the rounding of both
+        assert O.spa_weight(c + 1) <= w0
+    assert O.spa_weight(69) == 1 and O.spa_weight(70) == 0
+
+
+@pytest.mark.parametrize("g", [2, 4, 8, 16, 32, 64])
+def test_wht_is_an_involution_up_to_g(g):
+    """The Hadamard matrix squares to g I; a point mass transforms to a +-1 pattern."""
+    rng = np.random.default_rng(g)
+    for _ in range(4):
+        x = rng.integers(-40000, 40000, size=g)
+        assert (O.wht(O.wht(x)) == g * x).all()
+    for t0 in range(g):
+        d = np.zeros(g, dtype=np.int64)
+        d[t0] = 1
+        want = [(-1) ** bin(f & t0).count("1") for f in range(g)]
+        assert (O.wht(d) == want).all()
+
+
+def _exact_spa_cn(g, poly, h, u):
+    """Check node of the sum-product algorithm by enumeration, in floating point:
+    v_j(x) = sum over symbols of the other edges with sum h_k c_k = h_j x of prod u_k(c_k)."""
+    gf = S._GFEnc(g, poly)
+    dc = len(h)
+    v = np.zeros((dc, g))
+    for j in range(dc):
+        others = [k for k in range(dc) if k != j]
+        for combo in itertools.product(range(g), repeat=len(others)):
+            s, pr = 0, 1.0
+            for k, c in zip(others, combo):
+                s ^= int(gf.mul(h[k], c))
+                pr *= u[k][c] / float(1 << 24)
+            v[j, int(gf.mul(gf.inv(h[j]), s))] += pr
+    return v * float(1 << 24)
+
+
+@pytest.mark.parametrize("g,dc", [(4, 2), (4, 3), (4, 4), (8, 3), (8, 4), (16, 3)])
+def test_spa_cn_matches_exact_convolution(g, dc):
+    """The transform-domain check node equals the probability convolution it replaces
+    (eq. (8)), within the rounding of the Q15 products; exact for degree 2."""
+    rng = np.random.default_rng(100 * g + dc)
+    poly = S.PRIM_POLY[g]
+    for _ in range(4):
+        h = rng.integers(1, g, size=dc)
+        w = rng.random((dc, g)) ** 3
+        u = np.floor(w / w.sum(axis=1, keepdims=True) * (1 << 24)).astype(np.int64)
+        got = O.spa_cn(g, poly, h, u)
+        want = _exact_spa_cn(g, poly, h, u)
+        tol = 0 if dc == 2 else 2 * dc + 2
+        assert np.abs(got - want).max() <= tol + 1e-9
+        assert (got >= 0).all()
+
+
+def test_spa_noiseless_and_message_sums():
+    w = S.workload(3, batch=6)
+    cw, gam = S.make_inputs(w, noiseless=True)
+    r = O.decode_spa(w.code, O.params("spa", "flooding", 3, True), gam)
+    assert (r["iters"] == 0).all() and (r["ok"] == 1).all() and (r["hard"] == cw).all()
+    r = O.decode_spa(w.code, O.params("spa", "flooding", 3, False), gam)
+    assert (r["hard"] == cw).all() and (r["ok"] == 1).all()
+    # noisy: every variable-to-check message is a Q24 distribution up to the rounding
+    # of its entries (at most 1/2 each, plus the truncated reciprocal)
+    w = S.workload(3, batch=4)
+    cw, gam = S.make_inputs(w)
+    r = O.decode_spa(w.code, O.params("spa", "flooding", 2, False), gam, dump=True)
+    sums = r["u"].sum(axis=2)
+    assert (np.abs(sums - (1 << 24)) <= w.code.g).all()
+
+
+def test_spa_fer_falls_with_snr():
+    """Sum-product is the exact marginalisation Min-Max approximates: it decodes at
+    least as many frames, and its FER falls with SNR."""
+    fers, mm = [], []
+    for eb in (1.0, 2.0, 3.0):
+        w = S.workload(3, batch=24, ebn0_db=eb)
+        cw, gam = S.make_inputs(w)
+        r = O.decode_spa(w.code, O.params("spa", "flooding", 10, True), gam)
+        m = O.decode_nb(w.code, O.params("minmax", "flooding", 10, True), gam)
+        fers.append(float((r["hard"] != cw).any(axis=1).mean()))
+        mm.append(float((m["hard"] != cw).any(axis=1).mean()))
+    assert fers[2] < fers[0] and fers[2] <= 0.05
+    assert sum(fers) <= sum(mm)
