@@ -49,7 +49,7 @@ typedef enum {
 } ldpcx_status;
 
 enum { LDPCX_SCHED_FLOODING = 0, LDPCX_SCHED_LAYERED = 1, LDPCX_SCHED_AUTO = 2 };
-enum { LDPCX_RULE_MS = 0, LDPCX_RULE_NMS = 1, LDPCX_RULE_OMS = 2, LDPCX_RULE_MINMAX = 3 };
+enum { LDPCX_RULE_MS = 0, LDPCX_RULE_NMS = 1, LDPCX_RULE_OMS = 2, LDPCX_RULE_MINMAX = 3, LDPCX_RULE_SPA = 4 };
 
 typedef struct ldpcx_code ldpcx_code;
 
@@ -99,7 +99,15 @@ typedef struct {
  * to nb_msg_max (0 = 32767, the 16-bit decoder; 127 gives the 8-bit message variant of
  * sec. 5, whose channel vectors are clipped to the same range: gamma'(x) =
  * min(gamma(x), nb_msg_max) is used wherever gamma appears); decision = lowest x
- * minimising gamma'_n(x) + sum_m beta_mn(x).  nb_msg_max is ignored for binary codes. */
+ * minimising gamma'_n(x) + sum_m beta_mn(x).  nb_msg_max is ignored for binary codes.
+ * FFT-SPA arithmetic (Alg. 1, rule SPA, GF(4)..GF(64), flooding, check and variable
+ * degrees <= 16; gamma is the same symbol-cost input): probabilities in Q24 (2^24 = 1),
+ * channel p = norm(W(gamma)) with W(c) = round(2^24 exp(-c/4)); eq. (8) with the
+ * Walsh-Hadamard transform exact in integers, products qmul(a, b) = floor((a b + 2^23)
+ * / 2^24) in ascending edge order, inverse = transform then floor(. / g) clamped at 0;
+ * eqs. (10)-(11) with norm(z)(x) = floor((z(x) R + 2^21) / 2^22), R = floor(2^46 /
+ * sum z) (p_n when sum z = 0); decision = lowest x maximising p_n(x) times every
+ * incoming message; permutation and stop rule as for Min-Max. */
 typedef struct {
     int32_t max_iters;
     int32_t early_stop;
@@ -149,7 +157,7 @@ ldpcx_status ldpcx_decode(const ldpcx_code *code, const ldpcx_decode_params *par
  *   g == 2: msg_a = int8 q [batch][nnz] (q_e = clamp(Lambda - r_e)), msg_b = int8 r
  *           [batch][nnz], msg_c = int16 Lambda [batch][n].
  *   g > 2:  msg_a = int16 alpha [batch][nnz][g], msg_b = int16 beta [batch][nnz][g],
- *           msg_c unused (may be NULL).
+ *           msg_c unused (may be NULL); rule SPA: int32 Q24 u and v' [batch][nnz][g].
  * All message pointers are device memory.  Before the first iteration beta = r = 0. */
 ldpcx_status ldpcx_debug_dump(const ldpcx_code *code, const ldpcx_decode_params *params,
                               int32_t batch, const void *llr, void *hard, uint8_t *syndrome_ok,
@@ -184,8 +192,9 @@ ldpcx_status ldpcx_tune(const ldpcx_code *code, const ldpcx_decode_params *param
                         int32_t *chosen_schedule, float *best_us, void *stream);
 
 /* Launch configuration that the next decode of (code, params, batch) would use:
- * kernel family (0 = LDS-resident binary, 1 = interleaved binary, 2 = interleaved
- * min-max, 3 = packed two-codewords-per-lane binary for quasi-cyclic codes, available
+ * kernel family (0 = LDS-resident binary, 1 = interleaved binary, 2 = Min-Max (interleaved
+ * up to GF(64), lanes over entries above), 4 = FFT-SPA (lanes over entries),
+ * 3 = packed two-codewords-per-lane binary for quasi-cyclic codes, available
  * when every layer of z rows consists of z x z circulant blocks, at most 16 layers and
  * 8 blocks per layer), codewords per workgroup (family 1: codewords per launch
  * sequence; larger batches run as consecutive slices), threads per workgroup. */

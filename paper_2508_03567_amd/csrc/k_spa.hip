@@ -1,0 +1,88 @@
+// Launch sequence of the fixed-point FFT-SPA decoder (Alg. 1): one kernel per phase,
+// every wavefront an independent (node, codeword group) unit; the phase bodies are
+// the device functions of dev_spa.h.
+#include "dev_spa.h"
+
+namespace ldpcx {
+
+namespace {
+
+using dev::spa::Args;
+
+__device__ __forceinline__ long unit_id() { return (long)blockIdx.x * 4 + dev::wave_id(); }
+
+__global__ void __launch_bounds__(256) k_fill(dev::FillArgs F) { dev::fill_block(F, blockIdx.x); }
+template <int G>
+__global__ void __launch_bounds__(256) k_init(Args A) { dev::spa::init_unit<G>(A, unit_id()); }
+__global__ void __launch_bounds__(256) k_syn(Args A, int slot) {
+    dev::spa::syn_thread(A, slot, (long)blockIdx.x * 256 + threadIdx.x);
+}
+template <int G>
+__global__ void __launch_bounds__(256) k_cn(Args A, int k) { dev::spa::cn_unit<G>(A, k, unit_id()); }
+template <int G>
+__global__ void __launch_bounds__(256) k_vn(Args A, int k) { dev::spa::vn_unit<G>(A, k, unit_id()); }
+__global__ void __launch_bounds__(256) k_fin(Args A) { dev::spa::fin_thread(A, (long)blockIdx.x * 256 + threadIdx.x); }
+__global__ void __launch_bounds__(256) k_dump(Args A, const int *src, int *dst) {
+    dev::spa::dump_thread(A, src, dst, (long)blockIdx.x * 256 + threadIdx.x);
+}
+
+unsigned blocks(long units, int per) { return (unsigned)((units + per - 1) / per); }
+
+hipError_t fill(const dev::FillArgs &F, hipStream_t s) {
+    if (F.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)dev::fill_gx(F)), dim3(256), 0, s, F);
+    return hipGetLastError();
+}
+
+template <int G>
+hipError_t run(const Args &A, hipStream_t s) {
+    const DevCode &C = A.C;
+    const long B = A.batch;
+    const long groups = (B + 64 / G - 1) / (64 / G);
+    const dim3 blk(256);
+    hipError_t e;
+    const dev::spa::Carve cv = dev::spa::carve(C, A.max_iters, A.batch);
+    if ((e = fill(dev::FillArgs{(uint32_t *)A.w.unsat, (cv.it - cv.unsat) / 4, 0u}, s)) != hipSuccess) return e;
+    if ((e = fill(dev::FillArgs{(uint32_t *)A.w.it, (size_t)(B + 1) / 2, 0u}, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_init<G>, dim3(blocks(C.n * groups, 4)), blk, 0, s, A);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (int k = 1; k <= A.max_iters; ++k) {
+        if (A.early_stop) hipLaunchKernelGGL(k_syn, dim3(blocks(C.m * B, 256)), blk, 0, s, A, k);
+        hipLaunchKernelGGL(k_cn<G>, dim3(blocks(C.m * groups, 4)), blk, 0, s, A, k);
+        hipLaunchKernelGGL(k_vn<G>, dim3(blocks(C.n * groups, 4)), blk, 0, s, A, k);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_syn, dim3(blocks(C.m * B, 256)), blk, 0, s, A, 0);
+    hipLaunchKernelGGL(k_fin, dim3(blocks(B, 256)), blk, 0, s, A);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (A.io.dump_a) {
+        const long total = (long)C.E * B * G;
+        hipLaunchKernelGGL(k_dump, dim3(blocks(total, 256)), blk, 0, s, A, (const int *)A.w.u, (int *)A.io.dump_a);
+        hipLaunchKernelGGL(k_dump, dim3(blocks(total, 256)), blk, 0, s, A, (const int *)A.w.v, (int *)A.io.dump_b);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+bool spa_supported(const DevCode &C) {
+    return C.g >= 4 && C.g <= 64 && C.dc_max <= kNbDcMax && C.dv_max <= dev::spa::kVnRegs;
+}
+
+size_t spa_work_bytes(const DevCode &C, int max_iters, int batch) { return dev::spa::carve(C, max_iters, batch).total; }
+
+hipError_t launch_spa(const DevCode &C, int max_iters, int early_stop, int batch, void *ws, const DecodeIO &io,
+                      hipStream_t s) {
+    const Args A = dev::spa::make_args(C, max_iters, early_stop, batch, ws, io);
+    switch (C.g) {
+    case 4: return run<4>(A, s);
+    case 8: return run<8>(A, s);
+    case 16: return run<16>(A, s);
+    case 32: return run<32>(A, s);
+    case 64: return run<64>(A, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace ldpcx

@@ -13,6 +13,7 @@ namespace ldpcx {
 constexpr int kBinDcMax = 14;  // binary check state: 7b min1 | 7b min2 | 4b argmin | 14 sign bits
 constexpr int kNbDcMax = 16;
 constexpr int kWave = 64;
+constexpr int kSpaWeights = 72;  // symbol costs c >= 70 have weight 0 in Q24
 
 // Read-only device image of a code handle.
 struct DevCode {
@@ -25,6 +26,7 @@ struct DevCode {
     const uint8_t *h;      // [E] GF coefficient (g > 2)
     const uint8_t *hinv;   // [E] its inverse (g > 2)
     const uint8_t *gfmul;  // [g * g] multiplication table (g > 2)
+    const int *spa_w;      // [kSpaWeights] channel weights round(2^24 exp(-c / 4)) of the FFT-SPA decoder
 };
 
 struct BinRule {
@@ -114,6 +116,19 @@ struct NbWork {
     uint64_t *unsat;  // [(max_iters + 1)][Bp/64]
     int16_t *it;      // [Bp]
 };
+// Fixed-point FFT-SPA (g <= 64): codeword-major rows per node / edge, Q24 int32.
+struct SpaWork {
+    int *p;          // [n][batch][g] channel probabilities
+    int *u;          // [E][batch][g] variable-to-check messages
+    int *v;          // [E][batch][g] check-to-variable messages (depermuted)
+    uint8_t *unsat;  // [(max_iters + 1)][batch]
+    int16_t *it;     // [batch]
+};
+bool spa_supported(const DevCode &C);
+size_t spa_work_bytes(const DevCode &C, int max_iters, int batch);
+hipError_t launch_spa(const DevCode &C, int max_iters, int early_stop, int batch, void *ws, const DecodeIO &io,
+                      hipStream_t s);
+
 // Min-Max for g = 128, 256: codeword-major rows per edge.
 struct NbwWork {
     int16_t *alpha;  // [E][batch][g]

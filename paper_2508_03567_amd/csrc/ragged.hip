@@ -303,6 +303,9 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
             ldpcx_status st = check_params(c, &jb.params);
             if (st != LDPCX_OK) return cleanup(), st;
             if (c->nb_unsupported) return cleanup(), fail(LDPCX_E_UNSUPPORTED, "no Min-Max kernel for this field size");
+            if (jb.params.rule == LDPCX_RULE_SPA)
+                return cleanup(), fail(LDPCX_E_UNSUPPORTED, "the FFT-SPA decoder has no workgroup-local item; decode "
+                                                            "it with ldpcx_decode");
             if (c->g > 64)
                 return cleanup(), fail(LDPCX_E_UNSUPPORTED, "fields above GF(64) have no workgroup-local item; decode them "
                                                             "with ldpcx_decode");

@@ -1,6 +1,7 @@
 // Host runtime of libldpcx: code handles, validation, launch planning and the
 // plain per-code decode entry points of the C-ABI.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -88,7 +89,10 @@ ldpcx_status check_params(const ldpcx_code *c, const ldpcx_decode_params *p) {
         if (p->schedule == LDPCX_SCHED_LAYERED && !c->layers_ok)
             return fail(LDPCX_E_INVAL, "layered schedule needs a valid layer size");
     } else {
-        if (p->rule != LDPCX_RULE_MINMAX) return fail(LDPCX_E_INVAL, "codes over GF(g > 2) take rule MINMAX");
+        if (p->rule != LDPCX_RULE_MINMAX && p->rule != LDPCX_RULE_SPA)
+            return fail(LDPCX_E_INVAL, "codes over GF(g > 2) take rule MINMAX or SPA");
+        if (p->rule == LDPCX_RULE_SPA && !spa_supported(c->dev))
+            return fail(LDPCX_E_UNSUPPORTED, "the FFT-SPA decoder covers GF(4)..GF(64), check and variable degrees <= 16");
         if (p->nb_msg_max < 0 || p->nb_msg_max > 32767) return fail(LDPCX_E_INVAL, "nb_msg_max must be in [0, 32767]");
         if (p->schedule == LDPCX_SCHED_LAYERED)
             return fail(LDPCX_E_UNSUPPORTED, "layered Min-Max is not implemented");
@@ -112,6 +116,13 @@ BinRule bin_rule(const ldpcx_decode_params *p) {
 Plan default_plan(const ldpcx_code *c, const ldpcx_decode_params *p, int batch) {
     Plan pl;
     const DeviceInfo &di = device_info(c->device);
+    if (c->g > 2 && p->rule == LDPCX_RULE_SPA) {
+        pl.family = FAMILY_SPA;
+        pl.schedule = LDPCX_SCHED_FLOODING;
+        pl.cpw = 64 / c->g;
+        pl.threads = 256;
+        return pl;
+    }
     if (c->g > 2) {
         pl.family = FAMILY_NB;
         pl.schedule = LDPCX_SCHED_FLOODING;
@@ -171,6 +182,13 @@ uint64_t tune_key(const ldpcx_decode_params *p, int batch) {
            ((uint64_t)std::min(p->max_iters, 65535) << 16) | (uint64_t)cls;
 }
 
+size_t work_bytes(const ldpcx_code *c, const ldpcx_decode_params *p, const Plan &pl, int batch) {
+    if (pl.family == FAMILY_BIN_IL) return bin_il_work_bytes(c->dev, p->max_iters, batch, pl.cpw);
+    if (pl.family == FAMILY_SPA) return spa_work_bytes(c->dev, p->max_iters, batch);
+    if (pl.family == FAMILY_NB) return nb_work_bytes(c->dev, p->max_iters, batch);
+    return 0;
+}
+
 // Enqueue one decode with an explicit plan.
 ldpcx_status run_plan(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &pl, int batch, const DecodeIO &io,
                       hipStream_t s, bool allow_graph) {
@@ -200,8 +218,7 @@ ldpcx_status run_plan(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &p
         ldpcx_status st = run_graph(c, p, pl, batch, io, s);
         if (st != LDPCX_E_UNSUPPORTED) return st;  // else: capture not possible, run eagerly
     }
-    size_t bytes = pl.family == FAMILY_BIN_IL ? bin_il_work_bytes(c->dev, p->max_iters, batch, pl.cpw)
-                                              : nb_work_bytes(c->dev, p->max_iters, batch);
+    size_t bytes = work_bytes(c, p, pl, batch);
     size_t dump_bytes = 0;
     if (io.dump_a && pl.family == FAMILY_BIN_IL) dump_bytes = bin_il_dump_bytes(c->dev, batch, pl.cpw);
     void *ws = nullptr;
@@ -219,6 +236,7 @@ hipError_t enqueue_interleaved(ldpcx_code *c, const ldpcx_decode_params *p, cons
     if (pl.family == FAMILY_BIN_IL)
         return launch_bin_il(c->dev, bin_rule(p), p->max_iters, p->early_stop, batch, pl.cpw, ws, io, dump_scratch,
                              s);
+    if (pl.family == FAMILY_SPA) return launch_spa(c->dev, p->max_iters, p->early_stop, batch, ws, io, s);
     return launch_nb(c->dev, p->max_iters, p->early_stop, batch, nb_amax(p), ws, io, s);
 }
 
@@ -259,8 +277,7 @@ ldpcx_status run_graph(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &
         }
         GraphEntry g{};
         g.key = key;
-        const size_t bytes = pl.family == FAMILY_BIN_IL ? bin_il_work_bytes(c->dev, p->max_iters, batch, pl.cpw)
-                                                        : nb_work_bytes(c->dev, p->max_iters, batch);
+        const size_t bytes = work_bytes(c, p, pl, batch);
         if (hipMalloc(&g.ws, bytes) != hipSuccess) return fail(LDPCX_E_NOMEM, "graph workspace allocation");
         hipStream_t cs = nullptr;
         if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
@@ -542,7 +559,8 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
         const size_t o_hi = align_up(o_h + (size_t)E, 256);
         const size_t o_mul = align_up(o_hi + (size_t)E, 256);
         const size_t o_qc = align_up(o_mul + (size_t)g * g + 4, 256);
-        const size_t total = align_up(o_qc + sizeof(int2) * kQcMaxL * kQcMaxDc, 256);
+        const size_t o_sw = align_up(o_qc + sizeof(int2) * kQcMaxL * kQcMaxDc, 256);
+        const size_t total = align_up(o_sw + sizeof(int) * kSpaWeights, 256);
         e = hipMalloc(&c->dmem, total);
         if (e != hipSuccess) {
             delete c;
@@ -558,6 +576,11 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
             std::memcpy(host.data() + o_h, c->h.data(), E);
             std::memcpy(host.data() + o_hi, c->hinv.data(), E);
             std::memcpy(host.data() + o_mul, c->gfmul.data(), (size_t)g * g);
+        }
+        {
+            // FFT-SPA channel weights W(c) = round(2^24 exp(-c / 4))
+            int *sw = (int *)(host.data() + o_sw);
+            for (int cst = 0; cst < kSpaWeights; ++cst) sw[cst] = (int)std::floor(16777216.0 * std::exp(-cst / 4.0) + 0.5);
         }
         if (c->qc_ok) {
             int2 *qe = (int2 *)(host.data() + o_qc);
@@ -591,6 +614,7 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
         D.h = (const uint8_t *)(b + o_h);
         D.hinv = (const uint8_t *)(b + o_hi);
         D.gfmul = (const uint8_t *)(b + o_mul);
+        D.spa_w = (const int *)(b + o_sw);
         c->qc.edges = (const int2 *)(b + o_qc);
         if (g > 2 && !nb_supported(g)) {
             // Valid code, but no compiled Min-Max kernel for this field size.
@@ -665,9 +689,12 @@ ldpcx_status ldpcx_plan_set(ldpcx_code *c, const ldpcx_decode_params *params, in
     if (!c) return fail(LDPCX_E_INVAL, "code is NULL");
     ldpcx_status st = check_params(c, params);
     if (st != LDPCX_OK) return st;
-    if (family < 0 || family > 3) return fail(LDPCX_E_INVAL, "unknown kernel family");
+    if (family < 0 || family > 4) return fail(LDPCX_E_INVAL, "unknown kernel family");
+    if ((family == FAMILY_SPA) != (params->rule == LDPCX_RULE_SPA))
+        return fail(LDPCX_E_INVAL, "family 4 runs rule SPA, and rule SPA only family 4");
     if (family == FAMILY_BIN_QC && !c->qc_ok) return fail(LDPCX_E_UNSUPPORTED, "code has no quasi-cyclic description");
-    if ((c->g > 2) != (family == FAMILY_NB)) return fail(LDPCX_E_INVAL, "family does not match the field size");
+    if ((c->g > 2) != (family == FAMILY_NB || family == FAMILY_SPA))
+        return fail(LDPCX_E_INVAL, "family does not match the field size");
     Plan pl;
     pl.family = family;
     pl.schedule = params->schedule == LDPCX_SCHED_AUTO ? default_plan(c, params, std::max(1, batch)).schedule
@@ -699,6 +726,10 @@ ldpcx_status ldpcx_plan_set(ldpcx_code *c, const ldpcx_decode_params *params, in
     }
     if (family == FAMILY_NB) {
         pl.cpw = 64;
+        pl.threads = 256;
+    }
+    if (family == FAMILY_SPA) {
+        pl.cpw = 64 / c->g;
         pl.threads = 256;
     }
     std::lock_guard<std::mutex> lk(c->mu);

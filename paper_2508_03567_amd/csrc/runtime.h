@@ -11,7 +11,7 @@
 
 namespace ldpcx {
 
-enum { FAMILY_BIN_LDS = 0, FAMILY_BIN_IL = 1, FAMILY_NB = 2, FAMILY_BIN_QC = 3 };
+enum { FAMILY_BIN_LDS = 0, FAMILY_BIN_IL = 1, FAMILY_NB = 2, FAMILY_BIN_QC = 3, FAMILY_SPA = 4 };
 
 struct Plan {
     int family = FAMILY_BIN_LDS;
@@ -78,6 +78,8 @@ int nb_amax(const ldpcx_decode_params *p);  // Min-Max message bound of the para
 Plan default_plan(const ldpcx_code *c, const ldpcx_decode_params *p, int batch);
 Plan plan_for(ldpcx_code *c, const ldpcx_decode_params *p, int batch);
 uint64_t tune_key(const ldpcx_decode_params *p, int batch);
+// Device workspace of a decode with an interleaved or wave-level family (0 otherwise).
+size_t work_bytes(const ldpcx_code *c, const ldpcx_decode_params *p, const Plan &pl, int batch);
 // allow_graph = false always enqueues the launch sequence itself (no cached graph keyed
 // by the I/O buffers), for callers whose buffers change from call to call.
 ldpcx_status run_plan(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &pl, int batch, const DecodeIO &io,

@@ -91,6 +91,7 @@ size_t chunk_bytes(const Request &r, int ncw) {
     size_t b = io_bytes(r, ncw);
     if (r.family == FAMILY_BIN_IL) b += bin_il_work_bytes(r.code->dev, r.prm.max_iters, ncw, 0);
     else if (r.family == FAMILY_NB) b += nb_work_bytes(r.code->dev, r.prm.max_iters, ncw);
+    else if (r.family == FAMILY_SPA) b += spa_work_bytes(r.code->dev, r.prm.max_iters, ncw);
     return b;
 }
 
@@ -102,6 +103,7 @@ double est_us(const Request &r, int ncw) {
     case FAMILY_BIN_QC: return work / 2.5e6;
     case FAMILY_BIN_LDS: return work / 1.0e6;
     case FAMILY_BIN_IL: return work / 1.1e6;
+    case FAMILY_SPA: return work * ((double)r.code->g / 64.0) / 2.0e4;
     default: return work * ((double)r.code->g * r.code->g / 4096.0) / 3.0e3;
     }
 }
@@ -184,7 +186,7 @@ struct ldpcx_server {
         while (!queue.empty()) {
             const uint64_t id = queue.front();
             Request &r = reqs.at(id);
-            const bool own = cfg.mode == LDPCX_SERVE_PER_REQUEST || r.family == FAMILY_BIN_IL ||
+            const bool own = cfg.mode == LDPCX_SERVE_PER_REQUEST || r.family == FAMILY_BIN_IL || r.family == FAMILY_SPA ||
                              (r.family == FAMILY_NB && (r.code->g > 64 || pad64(r.batch - r.next_cw) / 64 >= kOwnLaunchGroups));
             // A launch is either one chunk with its own launch sequence or a ragged batch.
             if (own && !take.empty()) break;

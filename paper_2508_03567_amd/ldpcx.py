@@ -21,8 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libldpcx.so")
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_BUDGET, E_CANCELLED, E_TIMEOUT, E_NOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7, -8
 SCHED = {"flooding": 0, "layered": 1, "auto": 2}
 SCHED_NAME = {v: k for k, v in SCHED.items()}
-RULE = {"ms": 0, "nms": 1, "oms": 2, "minmax": 3}
-FAMILY_NAME = {0: "bin_lds", 1: "bin_interleaved", 2: "minmax_interleaved", 3: "bin_qc_packed"}
+RULE = {"ms": 0, "nms": 1, "oms": 2, "minmax": 3, "spa": 4}
+FAMILY_NAME = {0: "bin_lds", 1: "bin_interleaved", 2: "minmax_interleaved", 3: "bin_qc_packed", 4: "spa_wave"}
 
 
 class LdpcxError(RuntimeError):
@@ -283,7 +283,8 @@ def decode(code: Code, prm: DecodeParams, llr, stream=None, out=None):
 
 
 def debug_dump(code: Code, prm: DecodeParams, llr, stream=None):
-    """Decode and return the final messages: binary (hard, ok, iters, q, r, lam); GF(g) (..., alpha, beta)."""
+    """Decode and return the final messages: binary (hard, ok, iters, q, r, lam); GF(g) (..., alpha, beta),
+    for rule SPA (..., u, v') in Q24."""
     import torch
     _check_llr(code, llr)
     batch = int(llr.shape[0])
@@ -294,8 +295,9 @@ def debug_dump(code: Code, prm: DecodeParams, llr, stream=None):
         c = torch.empty((batch, code.n), dtype=torch.int16, device=llr.device)
         cp = c.data_ptr()
     else:
-        a = torch.empty((batch, code.nnz, code.g), dtype=torch.int16, device=llr.device)
-        b = torch.empty((batch, code.nnz, code.g), dtype=torch.int16, device=llr.device)
+        dt = torch.int32 if prm.rule == RULE["spa"] else torch.int16
+        a = torch.empty((batch, code.nnz, code.g), dtype=dt, device=llr.device)
+        b = torch.empty((batch, code.nnz, code.g), dtype=dt, device=llr.device)
         c, cp = None, 0
     ldpcx_debug_dump(code.handle, prm, batch, llr.data_ptr(), hard.data_ptr(), ok.data_ptr(), it.data_ptr(),
                      a.data_ptr(), b.data_ptr(), cp, _stream_ptr(stream))

@@ -381,3 +381,38 @@ def test_minmax_reduced_precision(g_size, bound):
     assert (g[3].astype(np.int32) == ref["alpha"]).all()
     assert (g[4].astype(np.int32) == ref["beta"]).all()
     assert ref["alpha"].max() <= bound
+
+
+@pytest.mark.parametrize("g_size,n,dc,batch,early,iters", [
+    (4, 24, 4, 70, True, 6), (8, 24, 4, 33, False, 4), (16, 16, 4, 20, True, 5), (32, 30, 3, 9, True, 4),
+    (64, 16, 4, 5, False, 3), (64, 192, 4, 6, True, 5), (16, 20, 5, 7, True, 4), (4, 12, 2, 40, True, 3)])
+def test_spa_matches_oracle(g_size, n, dc, batch, early, iters):
+    """Fixed-point FFT-SPA (Alg. 1): decisions, flags, iteration counts and every u / v' message."""
+    m = n * 2 // dc
+    code = S.random_regular_nb_code(n, m, 2, dc, g_size, S.PRIM_POLY[g_size], seed=g_size + n + dc)
+    cw = S.random_codewords(code, batch, seed=9)
+    gam = S.nb_gamma_int16(cw, g_size, 1.5, seed=10)
+    prm = dict(rule="spa", schedule="flooding", max_iters=iters, early_stop=early)
+    h = L.Code(code)
+    g = _gpu(h, prm, gam, dump=True)
+    ref = O.decode_spa(code, O.params(**prm), gam, dump=True)
+    _check_decisions(code, g, ref)
+    assert (g[3].astype(np.int64) == ref["u"]).all(), "u messages differ"
+    assert (g[4].astype(np.int64) == ref["v"]).all(), "v' messages differ"
+    g2 = _gpu(h, prm, gam)
+    _check_decisions(code, g2, ref)
+
+
+def test_spa_rejections():
+    code = S.random_regular_nb_code(16, 8, 2, 4, 128, S.PRIM_POLY[128], seed=1)
+    h = L.Code(code)
+    gam = torch.zeros((2, 16, 128), dtype=torch.int16, device=DEV)
+    with pytest.raises(L.LdpcxError) as ei:
+        L.decode(h, L.params("spa", max_iters=2), gam)
+    assert ei.value.status == L.E_UNSUPPORTED
+    c64 = S.random_regular_nb_code(16, 8, 2, 4, 64, S.PRIM_POLY[64], seed=1)
+    h64 = L.Code(c64)
+    g64 = torch.zeros((2, 16, 64), dtype=torch.int16, device=DEV)
+    with pytest.raises(L.LdpcxError) as ei:
+        L.decode_ragged([(h64, L.params("spa", max_iters=2), g64)])
+    assert ei.value.status == L.E_UNSUPPORTED
