@@ -102,6 +102,8 @@ def main() -> None:
     ap.add_argument("--sweep", action="store_true",
                     help="GF-size sweep instead: (2,4)-regular codes of 16/32/64 symbols over GF(4)..GF(256), "
                          "Min-Max, fixed iterations (one JSON line per point)")
+    ap.add_argument("--sweep-rule", type=str, default="minmax", choices=["minmax", "spa"],
+                    help="--sweep: decoder (spa covers GF(4)..GF(64))")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -257,14 +259,17 @@ def sweep_main(args) -> None:
 
     dev = torch.device("cuda:0")
     iters = 20
+    rule = args.sweep_rule
     for n in SWEEP_N:
         for g in SWEEP_G:
+            if rule == "spa" and g > 64:
+                continue
             batch = args.batch or 8192
             code = S.random_regular_nb_code(n, n // 2, 2, 4, g, S.PRIM_POLY[g], seed=100 + n + g, name=f"n{n}_gf{g}")
             cw = S.random_codewords(code, batch, seed=7)
             gam = torch.from_numpy(S.nb_gamma_int16(cw, g, 2.0, seed=8)).to(dev)
             h = L.Code(code)
-            prm = L.params("minmax", "flooding", iters, early_stop=False)
+            prm = L.params(rule, "flooding", iters, early_stop=False)
             out = L._outputs(h, batch, dev)
             for _ in range(max(1, args.warmup)):
                 L.decode(h, prm, gam, out=out)
@@ -281,7 +286,7 @@ def sweep_main(args) -> None:
             p = g.bit_length() - 1
             info = (n // 2) * p * batch / (ms * 1e-3) / 1e9
             fer = float((out[0].cpu().numpy() != cw).any(axis=1).mean())
-            print(json.dumps({"metric": "Min-Max GF-size sweep: decoded info Gbit/s at fixed iters", "n_symbols": n,
+            print(json.dumps({"metric": f"{rule} GF-size sweep: decoded info Gbit/s at fixed iters", "n_symbols": n,
                               "field": g, "iterations": iters, "batch": batch, "ms_per_batch": round(ms, 4),
                               "info_gbit_s": round(info, 5), "coded_gbit_s": round(2 * info, 5),
                               "ebn0_db": 2.0, "fer": fer, "data": "synthetic seeded BPSK/AWGN"}), flush=True)
