@@ -49,30 +49,46 @@ __device__ __forceinline__ void conv(const v2s (&A)[G / 2], const v2s (&B)[G / 2
     }
 }
 
-// a~(t) = msg(hinv * t) for one edge, loaded straight from [edge][x][Bp] memory.
+// Entry t of the (uniform) multiplication-table row: the row is read as 32-bit words
+// through the scalar cache and the byte extracted on the scalar unit.
+__device__ __forceinline__ uint32_t mrow_at(const uint32_t *mw, int t) {
+    return (__builtin_amdgcn_readfirstlane(mw[t >> 2]) >> (8 * (t & 3))) & 0xFFu;
+}
+
+// a~(t) = msg(hinv * t) for one edge, loaded straight from [edge][x][Bp] memory: every
+// load is a buffer load whose scalar offset carries (edge, x), the lane offset b.
 template <int G>
-__device__ __forceinline__ void load_perm(const int16_t *__restrict__ msg, long Bp, int e,
-                                          const uint8_t *__restrict__ mrow, int b, v2s (&A)[G / 2]) {
-    const int16_t *base = msg + (long)e * G * Bp + b;
+__device__ __forceinline__ void load_perm(__amdgpu_buffer_rsrc_t rs, uint32_t Bp2, int e, const uint8_t *mrow,
+                                          uint32_t lane_off, v2s (&A)[G / 2]) {
+    const uint32_t *mw = (const uint32_t *)mrow;
+    const uint32_t base = __builtin_amdgcn_readfirstlane((uint32_t)e * G * Bp2);
 #pragma unroll
     for (int t = 0; t < G; t += 2) {
-        const int x0 = mrow[t], x1 = mrow[t + 1];
-        A[t >> 1] = (v2s){base[(long)x0 * Bp], base[(long)x1 * Bp]};
+        const uint32_t x0 = mrow_at(mw, t), x1 = mrow_at(mw, t + 1);
+        const uint32_t lo = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)lane_off, (int)(base + x0 * Bp2), 0);
+        const uint32_t hi = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)lane_off, (int)(base + x1 * Bp2), 0);
+        A[t >> 1] = as_v2s(lo | (hi << 16));
     }
 }
 
 // msg(x) = v~(h x) stored for one edge: entry t goes to x = hinv * t.
 template <int G>
-__device__ __forceinline__ void store_deperm(int16_t *__restrict__ msg, long Bp, int e,
-                                             const uint8_t *__restrict__ mrow, int b, const v2s (&V)[G / 2], bool act) {
-    int16_t *base = msg + (long)e * G * Bp + b;
+__device__ __forceinline__ void store_deperm(__amdgpu_buffer_rsrc_t rs, uint32_t Bp2, int e, const uint8_t *mrow,
+                                             uint32_t lane_off, const v2s (&V)[G / 2], bool act) {
     if (!act) return;
+    const uint32_t *mw = (const uint32_t *)mrow;
+    const uint32_t base = __builtin_amdgcn_readfirstlane((uint32_t)e * G * Bp2);
 #pragma unroll
     for (int t = 0; t < G; t += 2) {
-        base[(long)mrow[t] * Bp] = V[t >> 1].x;
-        base[(long)mrow[t + 1] * Bp] = V[t >> 1].y;
+        const uint32_t w = as_u32(V[t >> 1]);
+        const uint32_t s0 = base + mrow_at(mw, t) * Bp2;
+        const uint32_t s1 = base + mrow_at(mw, t + 1) * Bp2;
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(w & 0xFFFFu), rs, (int)lane_off, (int)s0, 0);
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(w >> 16), rs, (int)lane_off, (int)s1, 0);
     }
 }
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t msg_rsrc(const int16_t *p, const Args &A);
 
 template <int G>
 __device__ __forceinline__ void lds_put(uint32_t *slot, int lane, const v2s (&V)[G / 2]) {
@@ -111,42 +127,43 @@ __device__ __forceinline__ void cn_block(const Args &A, int k, int wpb, int bx, 
     const uint64_t *slot = A.w.unsat + (size_t)k * A.Gn;
     const bool act = b < A.batch && (!A.early_stop || ((slot[g] >> lane) & 1ull));
     if (__ballot(act) == 0) return;
-    const long Bp = A.Bp;
-    const int16_t *alpha = A.w.alpha;
-    int16_t *beta = A.w.beta;
+    const uint32_t Bp2 = 2u * (uint32_t)A.Bp;  // bytes between entries of one edge
+    const uint32_t lo = 2u * (uint32_t)b;
+    const auto alpha = msg_rsrc(A.w.alpha, A);
+    const auto beta = msg_rsrc(A.w.beta, A);
     uint32_t *fs = lds + (size_t)w * A.fslots * H * 64;
     const int e0 = C.row_ptr[row];
     const int dc = C.row_ptr[row + 1] - e0;
     const uint8_t *mul = C.gfmul;
     v2s X[H], Y[H], R[H];
-    load_perm<G>(alpha, Bp, e0, mul + C.hinv[e0] * G, b, X);
+    load_perm<G>(alpha, Bp2, e0, mul + C.hinv[e0] * G, lo, X);
     const int nf = dc - 2;
     for (int s = 0; s < 3 * nf; ++s) {
         int kind, j;
         if (s < nf) {
             kind = 0;
             j = s + 1;
-            load_perm<G>(alpha, Bp, e0 + j, mul + C.hinv[e0 + j] * G, b, Y);
+            load_perm<G>(alpha, Bp2, e0 + j, mul + C.hinv[e0 + j] * G, lo, Y);
         } else {
             const int t = s - nf;
             j = dc - 2 - (t >> 1);
             if (t == 0) {
                 // X = F_{dc-2} is the output of the last edge (eq. (12)); start the backward pass.
-                store_deperm<G>(beta, Bp, e0 + dc - 1, mul + C.hinv[e0 + dc - 1] * G, b, X, act);
-                load_perm<G>(alpha, Bp, e0 + dc - 1, mul + C.hinv[e0 + dc - 1] * G, b, X);
+                store_deperm<G>(beta, Bp2, e0 + dc - 1, mul + C.hinv[e0 + dc - 1] * G, lo, X, act);
+                load_perm<G>(alpha, Bp2, e0 + dc - 1, mul + C.hinv[e0 + dc - 1] * G, lo, X);
             }
             if ((t & 1) == 0) {
                 kind = 1;  // middle output: F_{j-1} (*) B_{j+1}
-                if (j == 1) load_perm<G>(alpha, Bp, e0, mul + C.hinv[e0] * G, b, Y);
+                if (j == 1) load_perm<G>(alpha, Bp2, e0, mul + C.hinv[e0] * G, lo, Y);
                 else lds_get<G>(fs + (size_t)(j - 2) * H * 64, lane, Y);
             } else {
                 kind = 2;  // B_j = B_{j+1} (*) a~_j
-                load_perm<G>(alpha, Bp, e0 + j, mul + C.hinv[e0 + j] * G, b, Y);
+                load_perm<G>(alpha, Bp2, e0 + j, mul + C.hinv[e0 + j] * G, lo, Y);
             }
         }
         conv<G>(X, Y, R);
         if (kind == 1) {
-            store_deperm<G>(beta, Bp, e0 + j, mul + C.hinv[e0 + j] * G, b, R, act);
+            store_deperm<G>(beta, Bp2, e0 + j, mul + C.hinv[e0 + j] * G, lo, R, act);
         } else {
 #pragma unroll
             for (int p = 0; p < H; ++p) X[p] = R[p];
@@ -154,10 +171,10 @@ __device__ __forceinline__ void cn_block(const Args &A, int k, int wpb, int bx, 
         }
     }
     if (nf == 0) {
-        store_deperm<G>(beta, Bp, e0 + 1, mul + C.hinv[e0 + 1] * G, b, X, act);
-        load_perm<G>(alpha, Bp, e0 + 1, mul + C.hinv[e0 + 1] * G, b, X);
+        store_deperm<G>(beta, Bp2, e0 + 1, mul + C.hinv[e0 + 1] * G, lo, X, act);
+        load_perm<G>(alpha, Bp2, e0 + 1, mul + C.hinv[e0 + 1] * G, lo, X);
     }
-    store_deperm<G>(beta, Bp, e0, mul + C.hinv[e0] * G, b, X, act);
+    store_deperm<G>(beta, Bp2, e0, mul + C.hinv[e0] * G, lo, X, act);
 }
 
 // Variable-node update (eqs. (14)-(15)) and decision: one wave per (variable, group).
@@ -267,6 +284,13 @@ __device__ __forceinline__ void fin_block(const Args &A, long bx) {
     if (b >= A.batch) return;
     A.io.ok[b] = ((A.w.unsat[b >> 6] >> (b & 63)) & 1ull) ? 0 : 1;
     A.io.iters[b] = A.w.it[b];
+}
+
+// Buffer resource over an [E][G][Bp] int16 message array (the host keeps its size
+// within 31 bits by slicing the batch).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t msg_rsrc(const int16_t *p, const Args &A) {
+    const uint32_t bytes = (uint32_t)A.C.E * (uint32_t)A.C.g * (uint32_t)A.Bp * 2u;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<int16_t *>(p), (short)0, (int)bytes, 0x00020000);
 }
 
 __host__ __device__ inline long grid_init_x(const Args &A) { return ((A.C.E > A.C.n ? A.C.E : A.C.n) + 3) / 4; }

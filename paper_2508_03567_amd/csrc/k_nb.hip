@@ -1,5 +1,7 @@
 // Launch sequence of the interleaved Min-Max decoder: one kernel per phase, the
 // phase bodies being the device functions of dev_nb.h.
+#include <algorithm>
+
 #include "dev_nb.h"
 
 namespace ldpcx {
@@ -77,23 +79,47 @@ hipError_t run(const Args &A, hipStream_t s) {
 
 bool nb_supported(int g) { return g == 4 || g == 8 || g == 16 || g == 32 || g == 64 || g == 128 || g == 256; }
 
+int nb_slice(const DevCode &C, int batch) {
+    // every byte offset into an [E][g][Bp] message array must fit 31 bits
+    long step = ((1L << 31) - 1) / (2L * C.E * C.g);
+    step = step / 64 * 64;
+    if (step < 64) step = 64;
+    return (int)std::min<long>(step, std::max(batch, 1));
+}
+
 size_t nb_work_bytes(const DevCode &C, int max_iters, int batch) {
     if (C.g >= 128) return nbw_work_bytes(C, max_iters, batch);
-    return dev::nb::carve(C, max_iters, batch).total;
+    return dev::nb::carve(C, max_iters, nb_slice(C, batch)).total;
 }
 
 hipError_t launch_nb(const DevCode &C, int max_iters, int early_stop, int batch, int amax, void *ws,
                      const DecodeIO &io, hipStream_t s) {
     if (C.g >= 128) return launch_nbw(C, max_iters, early_stop, batch, amax, ws, io, s);
-    const Args A = dev::nb::make_args(C, max_iters, early_stop, batch, amax, ws, io);
-    switch (C.g) {
-    case 4: return run<4>(A, s);
-    case 8: return run<8>(A, s);
-    case 16: return run<16>(A, s);
-    case 32: return run<32>(A, s);
-    case 64: return run<64>(A, s);
-    default: return hipErrorInvalidValue;
+    const int step = nb_slice(C, batch);
+    for (int b0 = 0; b0 < batch; b0 += step) {
+        const int nb = std::min(step, batch - b0);
+        DecodeIO sl = io;
+        sl.llr = (const int16_t *)io.llr + (size_t)b0 * C.n * C.g;
+        sl.hard = (uint8_t *)io.hard + (size_t)b0 * C.n;
+        sl.ok = io.ok + b0;
+        sl.iters = io.iters + b0;
+        if (io.dump_a) {
+            sl.dump_a = (int16_t *)io.dump_a + (size_t)b0 * C.E * C.g;
+            sl.dump_b = (int16_t *)io.dump_b + (size_t)b0 * C.E * C.g;
+        }
+        const Args A = dev::nb::make_args(C, max_iters, early_stop, nb, amax, ws, sl);
+        hipError_t e;
+        switch (C.g) {
+        case 4: e = run<4>(A, s); break;
+        case 8: e = run<8>(A, s); break;
+        case 16: e = run<16>(A, s); break;
+        case 32: e = run<32>(A, s); break;
+        case 64: e = run<64>(A, s); break;
+        default: e = hipErrorInvalidValue;
+        }
+        if (e != hipSuccess) return e;
     }
+    return hipSuccess;
 }
 
 }  // namespace ldpcx

@@ -136,6 +136,8 @@ struct NbwWork {
     uint8_t *unsat;  // [(max_iters + 1)][batch]
     int16_t *it;     // [batch]
 };
+// Codewords per launch sequence of the interleaved Min-Max decoder (31-bit offsets).
+int nb_slice(const DevCode &C, int batch);
 size_t nb_work_bytes(const DevCode &C, int max_iters, int batch);
 // amax: message bound (32767 for 16-bit messages, 127 for the 8-bit variant).
 hipError_t launch_nb(const DevCode &C, int max_iters, int early_stop, int batch, int amax, void *ws,

@@ -371,7 +371,8 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
             }
             // Interleaved families: a workspace per job, one item per group of 64 codewords.
             D.family = pl.family;
-            if (pl.family == FAMILY_BIN_IL && jb.batch > dev::il::max_sub_batch(D.C))
+            if ((pl.family == FAMILY_BIN_IL && jb.batch > dev::il::max_sub_batch(D.C)) ||
+                (pl.family == FAMILY_NB && jb.batch > nb_slice(D.C, jb.batch + 64)))
                 return cleanup(), fail(LDPCX_E_UNSUPPORTED, "batch too large for one interleaved workspace");
             const size_t bytes = pl.family == FAMILY_BIN_IL ? dev::il::carve(D.C, p.max_iters, jb.batch).total
                                                             : nb_work_bytes(D.C, p.max_iters, jb.batch);
