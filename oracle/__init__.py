@@ -55,6 +55,7 @@ def lib():
         L.orc_minmax_cn.restype = None
         L.orc_decode_binary.restype = ctypes.c_int
         L.orc_decode_nb.restype = ctypes.c_int
+        L.orc_nb_layers.restype = ctypes.c_int
         L.orc_spa_weight.restype = ctypes.c_int
         L.orc_spa_weight.argtypes = [ctypes.c_int]
         L.orc_wht.restype = None
@@ -136,6 +137,17 @@ def minmax_cn(g: int, poly: int, h: np.ndarray, alpha: np.ndarray):
     return beta, pfb.value, pb.value
 
 
+def nb_layers(code) -> np.ndarray:
+    """Layer index of every check for the layered Min-Max schedule (greedy colouring in
+    ascending check order: the lowest layer holding no check that shares a variable)."""
+    rp = np.ascontiguousarray(code.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(code.col_idx, dtype=np.int32)
+    out = np.empty(code.m, dtype=np.int32)
+    lib().orc_nb_layers(ctypes.c_int(code.m), _p(rp, ctypes.c_int32), _p(ci, ctypes.c_int32),
+                        _p(out, ctypes.c_int32))
+    return out
+
+
 # ------------------------------------------------------------------- decoders
 def decode_binary(code, prm: Params, llr: np.ndarray, dump: bool = False, nthreads=None) -> dict:
     """llr int8 [B, n] -> dict(hard [B, n] u8, ok [B] u8, iters [B] i16, and q/r/lam dumps)."""
@@ -167,7 +179,10 @@ def decode_binary(code, prm: Params, llr: np.ndarray, dump: bool = False, nthrea
 
 
 def decode_nb(code, prm: Params, gamma: np.ndarray, dump: bool = False, nthreads=None) -> dict:
-    """gamma int16 [B, n, g] -> dict(hard, ok, iters, pairs, and alpha/beta dumps [B, E, g])."""
+    """gamma int16 [B, n, g] -> dict(hard, ok, iters, pairs, and alpha/beta dumps [B, E, g]).
+
+    Schedule "flooding" is the two-phase Alg. 2; "layered" processes one check at a time
+    in the order of nb_layers (alpha of eq. (14) formed from the current betas)."""
     gamma = np.ascontiguousarray(gamma, dtype=np.int16)
     B, n, g = gamma.shape
     rp = np.ascontiguousarray(code.row_ptr, dtype=np.int32)

@@ -19,7 +19,10 @@
  *     paper does not state a saturation) or to nb_msg_max for the reduced-precision
  *     variants of sec. 5 (8-bit messages: 127); the channel vector then takes part
  *     clipped to the same bound, gamma'(x) = min(gamma(x), nb_msg_max).  Ties in the
- *     hard decision go to the lowest x.
+ *     hard decision go to the lowest x.  The layered Min-Max schedule (a reading; the
+ *     paper describes the two-phase one only) runs the same check node one check at a
+ *     time, in the order of orc_nb_layers, forming each incoming alpha from eq. (14)
+ *     with the betas as they stand at that moment; decisions follow each full pass.
  *   - Binary min-sum is the GF(2) case of the same check-node rule written in
  *     the log-likelihood-ratio form: each outgoing message is the product of
  *     the other edges' signs times a normalised minimum of the other edges'
@@ -293,7 +296,54 @@ typedef struct {
     const int32_t *row_ptr, *col_idx;
     const uint8_t *h_val;
     const int32_t *vn_ptr, *vn_edge;   /* edges of each variable node */
+    const int32_t *order;              /* layered schedule: checks in processing order */
 } nb_code;
+
+/* eq. (14) for one edge e: gamma of its variable plus the betas of the variable's
+ * other edges, shifted to minimum 0 and clipped to amax.  ap: g ints of scratch. */
+static void nb_alpha(const nb_code *C, const int16_t *gamma, const int32_t *beta, int e, int amax,
+                     int32_t *ap, int32_t *out)
+{
+    int g = C->g, v = C->col_idx[e];
+    for (int x = 0; x < g; x++) {
+        int s = gamma[(size_t)v * g + x];
+        for (int u = C->vn_ptr[v]; u < C->vn_ptr[v + 1]; u++)
+            if (C->vn_edge[u] != e) s += beta[(size_t)C->vn_edge[u] * g + x];
+        ap[x] = s;
+    }
+    int mn = ap[0];
+    for (int x = 1; x < g; x++) if (ap[x] < mn) mn = ap[x];
+    for (int x = 0; x < g; x++) {
+        int a = ap[x] - mn;
+        out[x] = a > amax ? amax : a;
+    }
+}
+
+/* Layers of the layered Min-Max schedule (a reading: the paper describes only the
+ * two-phase schedule).  Checks are taken in ascending index and each joins the
+ * lowest layer holding no check that shares a variable with it; the schedule then
+ * processes the checks one at a time, layer by layer, ascending within a layer.
+ * Brute force over earlier checks.  Returns the number of layers. */
+int orc_nb_layers(int m, const int32_t *row_ptr, const int32_t *col_idx, int32_t *layer_of)
+{
+    int nl = 0;
+    for (int i = 0; i < m; i++) {
+        int l = 0;
+        for (;; l++) {
+            int clash = 0;
+            for (int j = 0; j < i && !clash; j++) {
+                if (layer_of[j] != l) continue;
+                for (int a = row_ptr[i]; a < row_ptr[i + 1] && !clash; a++)
+                    for (int c = row_ptr[j]; c < row_ptr[j + 1]; c++)
+                        if (col_idx[a] == col_idx[c]) { clash = 1; break; }
+            }
+            if (!clash) break;
+        }
+        layer_of[i] = l;
+        if (l + 1 > nl) nl = l + 1;
+    }
+    return nl;
+}
 
 static void nb_decide(const nb_code *C, const int16_t *gamma, const int32_t *beta, uint8_t *hard)
 {
@@ -321,6 +371,7 @@ static void nb_decode_one(const nb_code *C, const orc_params *P, const int16_t *
     int32_t *alpha = (int32_t *)malloc(sizeof(int32_t) * EG);
     int32_t *beta = (int32_t *)calloc(EG, sizeof(int32_t));
     int32_t *ap = (int32_t *)malloc(sizeof(int32_t) * g);
+    const int32_t *order = C->order;
     int64_t pfb = 0, pb = 0;
     /* the channel vectors, clipped to the message bound of the chosen precision */
     int amax = P->nb_msg_max > 0 ? P->nb_msg_max : 32767;
@@ -339,28 +390,24 @@ static void nb_decode_one(const nb_code *C, const orc_params *P, const int16_t *
     int it = 0;
     for (int k = 1; k <= P->max_iters; k++) {
         if (P->early_stop && orc_syndrome_ok(g, C->poly, m, C->row_ptr, C->col_idx, C->h_val, hard)) break;
-        for (int i = 0; i < m; i++) {
-            int b = C->row_ptr[i], dc = C->row_ptr[i + 1] - b;
-            orc_minmax_cn(g, C->poly, dc, C->h_val + b, alpha + (size_t)b * g, beta + (size_t)b * g, &pfb, &pb);
-        }
-        /* eqs. (14)-(15) */
-        for (int v = 0; v < n; v++) {
-            for (int t = C->vn_ptr[v]; t < C->vn_ptr[v + 1]; t++) {
-                int e = C->vn_edge[t];
-                for (int x = 0; x < g; x++) {
-                    int s = gamma[(size_t)v * g + x];
-                    for (int u = C->vn_ptr[v]; u < C->vn_ptr[v + 1]; u++)
-                        if (u != t) s += beta[(size_t)C->vn_edge[u] * g + x];
-                    ap[x] = s;
-                }
-                int mn = ap[0];
-                for (int x = 1; x < g; x++) if (ap[x] < mn) mn = ap[x];
-                for (int x = 0; x < g; x++) {
-                    int a = ap[x] - mn;
-                    alpha[(size_t)e * g + x] = a > amax ? amax : a;
-                }
+        if (P->schedule == ORC_LAYERED) {
+            /* one check at a time in layer order: its incoming alphas are formed from the
+             * betas as they stand (eq. (14)), then its betas are replaced */
+            for (int q = 0; q < m; q++) {
+                int i = order[q];
+                int b = C->row_ptr[i], dc = C->row_ptr[i + 1] - b;
+                for (int e = b; e < b + dc; e++) nb_alpha(C, gamma, beta, e, amax, ap, alpha + (size_t)e * g);
+                orc_minmax_cn(g, C->poly, dc, C->h_val + b, alpha + (size_t)b * g, beta + (size_t)b * g, &pfb, &pb);
             }
+        } else {
+            for (int i = 0; i < m; i++) {
+                int b = C->row_ptr[i], dc = C->row_ptr[i + 1] - b;
+                orc_minmax_cn(g, C->poly, dc, C->h_val + b, alpha + (size_t)b * g, beta + (size_t)b * g, &pfb, &pb);
+            }
+            /* eq. (14) on every edge */
+            for (int e = 0; e < E; e++) nb_alpha(C, gamma, beta, e, amax, ap, alpha + (size_t)e * g);
         }
+        /* eq. (15) */
         nb_decide(C, gamma, beta, hard);
         it = k;
     }
@@ -388,7 +435,12 @@ int orc_decode_nb(int g, uint32_t poly, int n, int m, const int32_t *row_ptr, co
     for (int e = 0; e < E; e++) vn_ptr[col_idx[e] + 1]++;
     for (int v = 0; v < n; v++) vn_ptr[v + 1] += vn_ptr[v];
     for (int e = 0; e < E; e++) { int v = col_idx[e]; vn_edge[vn_ptr[v] + fill[v]++] = e; }
-    nb_code C = { g, poly, n, m, row_ptr, col_idx, h_val, vn_ptr, vn_edge };
+    int32_t *layer_of = (int32_t *)malloc(sizeof(int32_t) * (m ? m : 1));
+    int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (m ? m : 1));
+    int nl = orc_nb_layers(m, row_ptr, col_idx, layer_of), q = 0;
+    for (int l = 0; l < nl; l++)
+        for (int i = 0; i < m; i++) if (layer_of[i] == l) order[q++] = i;
+    nb_code C = { g, poly, n, m, row_ptr, col_idx, h_val, vn_ptr, vn_edge, order };
     int64_t tot[2] = { 0, 0 };
     (void)nthreads;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
@@ -403,7 +455,7 @@ int orc_decode_nb(int g, uint32_t poly, int n, int m, const int32_t *row_ptr, co
         tot[1] += pr[1];
     }
     if (pairs) { pairs[0] += tot[0]; pairs[1] += tot[1]; }
-    free(vn_ptr); free(vn_edge); free(fill);
+    free(vn_ptr); free(vn_edge); free(fill); free(layer_of); free(order);
     return 0;
 }
 

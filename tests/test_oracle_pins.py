@@ -313,13 +313,14 @@ def test_binary_codeword_sign_flip_equivariance():
         assert (b["hard"][nz] == (a["hard"] ^ c2)[nz]).all()
 
 
-def test_nb_codeword_shift_equivariance():
+@pytest.mark.parametrize("sched", ["flooding", "layered"])
+def test_nb_codeword_shift_equivariance(sched):
     w = S.workload(3, batch=4)
     cw, gamma = S.make_inputs(w)
     c2 = S.random_codewords(w.code, 4, seed=77)
     x = np.arange(64)
     gamma2 = np.take_along_axis(gamma, (x[None, None, :] ^ c2[:, :, None].astype(np.int64)), axis=2)
-    prm = O.params("minmax", "flooding", 4, False)
+    prm = O.params("minmax", sched, 4, False)
     a = O.decode_nb(w.code, prm, gamma, dump=True)
     b = O.decode_nb(w.code, prm, gamma2, dump=True)
     ce = c2[:, w.code.col_idx].astype(np.int64)
@@ -336,13 +337,118 @@ def test_nb_codeword_shift_equivariance():
     assert (b["hard"] == (a["hard"] ^ c2))[unique].all()
 
 
-def test_nb_message_invariants():
+@pytest.mark.parametrize("sched", ["flooding", "layered"])
+def test_nb_message_invariants(sched):
     w = S.workload(3, batch=3)
     cw, gamma = S.make_inputs(w)
+    rp = w.code.row_ptr
     for iters in [1, 3]:
-        out = O.decode_nb(w.code, O.params("minmax", "flooding", iters, False), gamma, dump=True)
+        out = O.decode_nb(w.code, O.params("minmax", sched, iters, False), gamma, dump=True)
         assert (out["alpha"].min(axis=2) == 0).all()
         assert (out["beta"].min(axis=2) == 0).all()
+        if sched == "layered":
+            # the stored alphas are the ones the last check-node pass saw, so every beta
+            # value is one of the other edges' alpha values
+            for b in range(3):
+                for i in range(0, w.code.m, 7):
+                    for e in range(rp[i], rp[i + 1]):
+                        others = np.concatenate([out["alpha"][b, j] for j in range(rp[i], rp[i + 1]) if j != e])
+                        assert np.isin(out["beta"][b, e], others).all()
+
+
+# ---------------------------------------------------------- layered Min-Max
+def _check_greedy_layers(code, lay):
+    """The two properties that fix a greedy colouring in ascending check order: the
+    checks of one layer share no variable, and a check sits in layer l only because
+    each lower layer already holds an earlier check that shares a variable with it."""
+    vs = [set(code.col_idx[code.row_ptr[i]:code.row_ptr[i + 1]].tolist()) for i in range(code.m)]
+    for l in range(lay.max() + 1):
+        members = np.flatnonzero(lay == l)
+        assert len(members) > 0
+        seen = set()
+        for i in members:
+            assert not (seen & vs[i])
+            seen |= vs[i]
+    for i in range(code.m):
+        for l in range(lay[i]):
+            assert any(vs[i] & vs[j] for j in range(i) if lay[j] == l)
+
+
+def test_nb_layers_are_the_greedy_colouring():
+    for code in [S.workload(3).code, S.workload(0).code, S.eq1_code()] + [
+            S.random_regular_nb_code(n, n // 2, 2, 4, g, S.PRIM_POLY[g], seed=100 + n + g)
+            for n, g in [(16, 4), (32, 16), (64, 64)]]:
+        _check_greedy_layers(code, O.nb_layers(code))
+    # on the all-circulant 3 x 6 base matrix the layers are the block rows of Z = 32
+    assert (O.nb_layers(S.workload(0).code) == np.arange(96) // 32).all()
+
+
+@pytest.mark.parametrize("bound", [None, 31, 12])
+def test_gf2_layered_minmax_equals_layered_min_sum(bound):
+    """Over GF(2) the layered Min-Max schedule is layered plain min-sum: on a code whose
+    greedy layers are its block rows, both process the checks in ascending order, and
+    eq. (14) with the current betas is the saturated Lambda - r_old of the binary form."""
+    w = S.workload(0, batch=40)
+    cw, llr = S.make_inputs(w)
+    if bound is not None:
+        llr = np.clip(llr, -bound, bound).astype(np.int8)
+    code = w.code
+    L = llr.astype(np.int32)
+    gamma = np.stack([np.maximum(0, -L), np.maximum(0, L)], axis=2).astype(np.int16)
+    code_nb = S.Code("gf2", 2, 0x3, code.n, code.m, code.row_ptr, code.col_idx, np.ones(code.nnz, dtype=np.uint8))
+    for iters in [1, 2, 5]:
+        prm_b = O.params("ms", "layered", iters, True, msg_max=10 ** 6 if bound is None else bound)
+        prm_n = O.params("minmax", "layered", iters, True, nb_msg_max=0 if bound is None else bound)
+        b = O.decode_binary(code, prm_b, llr, dump=True)
+        nb = O.decode_nb(code_nb, prm_n, gamma, dump=True)
+        assert (b["iters"] == nb["iters"]).all()
+        assert (b["ok"] == nb["ok"]).all()
+        assert (b["hard"] == nb["hard"]).all()
+        assert (nb["beta"][..., 1] - nb["beta"][..., 0] == b["r"]).all()
+        # the a posteriori sums agree too: gamma + sum beta is Lambda in the two-entry form
+        app = gamma.astype(np.int64).copy()
+        for e, v in enumerate(code.col_idx):
+            app[:, v, :] += nb["beta"][:, e, :]
+        assert (app[..., 1] - app[..., 0] == b["lam"]).all()
+        if bound is not None:
+            assert nb["alpha"].max() <= bound
+
+
+def test_layered_equals_flooding_when_no_check_shares_a_variable():
+    """With one layer the layered schedule has nothing to reorder: each alpha is the
+    channel vector in both schedules, so every output and message coincides."""
+    rng = np.random.default_rng(3)
+    g, m, dc = 8, 5, 3
+    rows = np.repeat(np.arange(m), dc)
+    cols = np.arange(m * dc)
+    vals = rng.integers(1, g, size=m * dc).astype(np.uint8)
+    code = S.code_from_pairs("disjoint", g, 0xB, m * dc, m, rows, cols, vals)
+    gamma = rng.integers(0, 60, size=(30, m * dc, g)).astype(np.int16)
+    gamma -= gamma.min(axis=2, keepdims=True)
+    assert (O.nb_layers(code) == 0).all()
+    for iters, early in [(1, False), (3, False), (4, True)]:
+        a = O.decode_nb(code, O.params("minmax", "flooding", iters, early), gamma, dump=True)
+        b = O.decode_nb(code, O.params("minmax", "layered", iters, early), gamma, dump=True)
+        for k in ["hard", "ok", "iters", "alpha", "beta"]:
+            assert (a[k] == b[k]).all(), k
+
+
+def test_layered_minmax_noiseless_and_convergence():
+    w = S.workload(3, batch=12)
+    cw, gamma = S.make_inputs(w, noiseless=True)
+    for early in [True, False]:
+        out = O.decode_nb(w.code, O.params("minmax", "layered", 5, early), gamma)
+        assert (out["hard"] == cw).all() and out["ok"].all()
+        assert (out["iters"] == (0 if early else 5)).all()
+    # each pass uses the betas of the checks already updated in it: at 5 iterations the
+    # layered schedule leaves far fewer frames undecoded than the two-phase one
+    w = S.workload(3, batch=64)
+    cw, gamma = S.make_inputs(w)
+    fer = {}
+    for sched in ["flooding", "layered"]:
+        out = O.decode_nb(w.code, O.params("minmax", sched, 5, False), gamma)
+        fer[sched] = 1 - (out["hard"] == cw).all(axis=1).mean()
+    assert fer["layered"] < 0.5 * fer["flooding"]
 
 
 def test_eq1_decoder_cost_not_below_ml():
