@@ -62,8 +62,9 @@ typedef struct ldpcx_code ldpcx_code;
  *   row_ptr    [m + 1] CSR row offsets, row_ptr[0] = 0.
  *   col_idx    [row_ptr[m]] column of each nonzero, strictly ascending inside a row.
  *   h_val      [row_ptr[m]] nonzero GF(g) coefficient of each entry; NULL when g == 2.
- *   z          layer size for the layered schedule: rows [l*z, (l+1)*z) form layer l and
- *              must touch pairwise disjoint columns; m % z == 0.  0 = no layer structure.
+ *   z          layer size for the binary layered schedule: rows [l*z, (l+1)*z) form layer
+ *              l and must touch pairwise disjoint columns; m % z == 0.  0 = no layer
+ *              structure.  Ignored for g > 2 (see the Min-Max layers under schedule).
  *   k_info     information symbols per codeword used for throughput accounting (n - m).
  * Limits: every check degree in [2, 14] for g == 2 (in [2, 16] for g > 2); n, m >= 1. */
 typedef struct {
@@ -84,8 +85,12 @@ typedef struct {
  *               max_iters iterations (fixed-iteration throughput mode).
  *   schedule    FLOODING (two-phase, Alg. 2), LAYERED (rows of one layer in parallel,
  *               layers in ascending order; binary codes with z > 0 or z == 0 meaning
- *               row by row), or AUTO (the autotuner picks; ldpcx_decode reports the
- *               schedule used).
+ *               row by row; Min-Max over GF(4)..GF(64): layers from a greedy colouring
+ *               of the checks in ascending order, each check in the lowest layer holding
+ *               no check that shares a variable with it, and each check's incoming
+ *               alphas formed by eq. (14) from the betas as they stand when its layer
+ *               runs), or AUTO (the autotuner picks; ldpcx_decode reports the schedule
+ *               used).  The FFT-SPA decoder and GF(128)/GF(256) run FLOODING only.
  *   rule        MS / NMS / OMS for g == 2, MINMAX for g > 2.
  *   nms_num, nms_shift   NMS magnitude f(m) = (nms_num * m) >> nms_shift (0.75 = 3, 2).
  *   oms_offset  OMS magnitude f(m) = max(m - oms_offset, 0).
@@ -179,8 +184,8 @@ typedef struct {
  * kernel launch on `stream` (per-codeword early termination inside).  Results are
  * identical to calling ldpcx_decode on each job.  AUTO schedules are resolved per job
  * as in ldpcx_decode.  Every job is cut into workgroup-local items (no workgroup waits
- * for another); jobs over GF(128) or GF(256) have no such item and are rejected with
- * LDPCX_E_UNSUPPORTED (decode them with ldpcx_decode). */
+ * for another); jobs over GF(128) or GF(256) and layered Min-Max jobs have no such item
+ * and are rejected with LDPCX_E_UNSUPPORTED (decode them with ldpcx_decode). */
 ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs, void *stream);
 
 /* Autotune the launch configuration of (code, params, batch) by timing the candidate

@@ -111,22 +111,20 @@ inline int cn_waves(const Args &A, size_t lds_budget) {
 }
 inline size_t cn_lds_bytes(const Args &A, int waves) { return (size_t)waves * A.fslots * (A.C.g / 2) * 64 * 4; }
 
-// Check-node phase of iteration k: wave (threadIdx.x / 64) of virtual block (bx, by)
-// processes check bx * wpb + wave for codewords [64 by, 64 by + 64).
+// Whether codeword b (lane `lane` of group g) still runs in iteration k.
+__device__ __forceinline__ bool active(const Args &A, int k, int g, int lane) {
+    const int b = g * 64 + lane;
+    return b < A.batch && (!A.early_stop || ((A.w.unsat[(size_t)k * A.Gn + g] >> lane) & 1ull));
+}
+
+// Check node of `row` (eqs. (7)-(13)) for the 64 codewords of group g, run by wave w of
+// the block; only lanes with `act` store.
 template <int G>
-__device__ __forceinline__ void cn_block(const Args &A, int k, int wpb, int bx, int by, uint32_t *lds) {
+__device__ __forceinline__ void cn_row(const Args &A, int row, int w, int g, bool act, uint32_t *lds) {
     constexpr int H = G / 2;
     const DevCode &C = A.C;
     const int lane = threadIdx.x & 63;
-    const int w = wave_id();
-    if (w >= wpb) return;
-    const int row = bx * wpb + w;
-    if (row >= C.m) return;
-    const int g = by;
     const int b = g * 64 + lane;
-    const uint64_t *slot = A.w.unsat + (size_t)k * A.Gn;
-    const bool act = b < A.batch && (!A.early_stop || ((slot[g] >> lane) & 1ull));
-    if (__ballot(act) == 0) return;
     const uint32_t Bp2 = 2u * (uint32_t)A.Bp;  // bytes between entries of one edge
     const uint32_t lo = 2u * (uint32_t)b;
     const auto alpha = msg_rsrc(A.w.alpha, A);
@@ -177,8 +175,70 @@ __device__ __forceinline__ void cn_block(const Args &A, int k, int wpb, int bx, 
     store_deperm<G>(beta, Bp2, e0, mul + C.hinv[e0] * G, lo, X, act);
 }
 
-// Variable-node update (eqs. (14)-(15)) and decision: one wave per (variable, group).
+// Check-node phase of iteration k: wave (threadIdx.x / 64) of virtual block (bx, by)
+// processes check bx * wpb + wave for codewords [64 by, 64 by + 64).
 template <int G>
+__device__ __forceinline__ void cn_block(const Args &A, int k, int wpb, int bx, int by, uint32_t *lds) {
+    const int w = wave_id();
+    if (w >= wpb) return;
+    const int row = bx * wpb + w;
+    if (row >= A.C.m) return;
+    const bool act = active(A, k, by, threadIdx.x & 63);
+    if (__ballot(act) == 0) return;
+    cn_row<G>(A, row, w, by, act, lds);
+}
+
+// Layered schedule: alpha of edge e from eq. (14) with the betas as they stand, i.e. the
+// channel vector of its variable plus the betas of the variable's other edges, shifted
+// to minimum 0 and clipped to the message bound.
+template <int G>
+__device__ __forceinline__ void alpha_edge(const Args &A, int e, int b, bool act) {
+    const DevCode &C = A.C;
+    const long Bp = A.Bp;
+    const int v = C.col_idx[e];
+    int S[G];
+    const int16_t *gp = A.w.gam + (long)v * G * Bp + b;
+#pragma unroll
+    for (int x = 0; x < G; ++x) S[x] = min((int)gp[(long)x * Bp], A.amax);
+    for (int t = C.vn_ptr[v]; t < C.vn_ptr[v + 1]; ++t) {
+        const int f = C.vn_ref[t];
+        if (f == e) continue;
+        const int16_t *bp = A.w.beta + (long)f * G * Bp + b;
+#pragma unroll
+        for (int x = 0; x < G; ++x) S[x] += bp[(long)x * Bp];
+    }
+    int mn = S[0];
+#pragma unroll
+    for (int x = 1; x < G; ++x) mn = min(mn, S[x]);
+    if (act) {
+        int16_t *ap = A.w.alpha + (long)e * G * Bp + b;
+#pragma unroll
+        for (int x = 0; x < G; ++x) ap[(long)x * Bp] = (int16_t)min(S[x] - mn, A.amax);
+    }
+}
+
+// Layered schedule, iteration k, layer `layer` (checks sharing no variable): wave w of
+// virtual block (bx, by) takes the layer's check number bx * wpb + w, forms the alphas of
+// its edges and runs its check node, for codewords [64 by, 64 by + 64).
+template <int G>
+__device__ __forceinline__ void lay_block(const Args &A, int k, int layer, int wpb, int bx, int by, uint32_t *lds) {
+    const DevCode &C = A.C;
+    const int w = wave_id();
+    if (w >= wpb) return;
+    const int i = C.nbl_ptr[layer] + bx * wpb + w;
+    if (i >= C.nbl_ptr[layer + 1]) return;
+    const int row = __builtin_amdgcn_readfirstlane(C.nbl_chk[i]);
+    const int lane = threadIdx.x & 63;
+    const bool act = active(A, k, by, lane);
+    if (__ballot(act) == 0) return;
+    for (int e = C.row_ptr[row]; e < C.row_ptr[row + 1]; ++e) alpha_edge<G>(A, e, by * 64 + lane, act);
+    __threadfence_block();  // the check node reads the alphas just stored by these lanes
+    cn_row<G>(A, row, w, by, act, lds);
+}
+
+// Variable-node update (eqs. (14)-(15)) and decision: one wave per (variable, group).
+// kAlpha = false: the decision only (layered schedule, whose alphas are formed per check).
+template <int G, bool kAlpha = true>
 __device__ __forceinline__ void vn_block(const Args &A, int k, int bx, int by) {
     const DevCode &C = A.C;
     const long Bp = A.Bp;
@@ -211,6 +271,7 @@ __device__ __forceinline__ void vn_block(const Args &A, int k, int bx, int by) {
         A.w.hard[(long)v * Bp + b] = (uint8_t)best;
         if (v == 0) A.w.it[b] = (int16_t)k;
     }
+    if (!kAlpha) return;
     for (int t = t0; t < t1; ++t) {
         const int e = C.vn_ref[t];
         const int16_t *bp = A.w.beta + (long)e * G * Bp + b;

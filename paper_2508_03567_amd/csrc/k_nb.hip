@@ -25,6 +25,15 @@ __global__ void __launch_bounds__(256) k_cn(Args A, int k, int wpb) {
 }
 template <int G>
 __global__ void __launch_bounds__(256) k_vn(Args A, int k) { dev::nb::vn_block<G>(A, k, blockIdx.x, blockIdx.y); }
+template <int G>
+__global__ void __launch_bounds__(256) k_lay(Args A, int k, int layer, int wpb) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    dev::nb::lay_block<G>(A, k, layer, wpb, blockIdx.x, blockIdx.y, lds);
+}
+template <int G>
+__global__ void __launch_bounds__(256) k_dec(Args A, int k) {
+    dev::nb::vn_block<G, false>(A, k, blockIdx.x, blockIdx.y);
+}
 __global__ void __launch_bounds__(256) k_fin(Args A) { dev::nb::fin_block(A, blockIdx.x); }
 
 hipError_t tr(const dev::TransposeArgs &T, hipStream_t s) {
@@ -41,7 +50,7 @@ hipError_t fill(const dev::FillArgs &F, hipStream_t s) {
 }
 
 template <int G>
-hipError_t run(const Args &A, hipStream_t s) {
+hipError_t run(const Args &A, bool layered, hipStream_t s) {
     hipError_t e;
     if ((e = tr(dev::nb::tr_in(A), s)) != hipSuccess) return e;
     const dim3 blk(256);
@@ -55,10 +64,17 @@ hipError_t run(const Args &A, hipStream_t s) {
     const dim3 gcn((unsigned)((A.C.m + wpb - 1) / wpb), (unsigned)A.Gn);
     const dim3 gsy((unsigned)dev::nb::grid_rows_x(A), (unsigned)A.Gn);
     const dim3 gvn((unsigned)dev::nb::grid_vn_x(A), (unsigned)A.Gn);
+    const dim3 glay((unsigned)((A.C.nb_lmax + wpb - 1) / wpb), (unsigned)A.Gn);
     for (int k = 1; k <= A.max_iters; ++k) {
         if (A.early_stop) hipLaunchKernelGGL(k_syn, gsy, blk, 0, s, A, k);
-        hipLaunchKernelGGL(k_cn<G>, gcn, dim3(64 * wpb), smem, s, A, k, wpb);
-        hipLaunchKernelGGL(k_vn<G>, gvn, blk, 0, s, A, k);
+        if (layered) {
+            // one launch per layer: the checks of a layer share no variable
+            for (int l = 0; l < A.C.nb_nl; ++l) hipLaunchKernelGGL(k_lay<G>, glay, dim3(64 * wpb), smem, s, A, k, l, wpb);
+            hipLaunchKernelGGL(k_dec<G>, gvn, blk, 0, s, A, k);
+        } else {
+            hipLaunchKernelGGL(k_cn<G>, gcn, dim3(64 * wpb), smem, s, A, k, wpb);
+            hipLaunchKernelGGL(k_vn<G>, gvn, blk, 0, s, A, k);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_syn, gsy, blk, 0, s, A, 0);
@@ -92,9 +108,13 @@ size_t nb_work_bytes(const DevCode &C, int max_iters, int batch) {
     return dev::nb::carve(C, max_iters, nb_slice(C, batch)).total;
 }
 
-hipError_t launch_nb(const DevCode &C, int max_iters, int early_stop, int batch, int amax, void *ws,
+hipError_t launch_nb(const DevCode &C, int max_iters, int early_stop, int layered, int batch, int amax, void *ws,
                      const DecodeIO &io, hipStream_t s) {
-    if (C.g >= 128) return launch_nbw(C, max_iters, early_stop, batch, amax, ws, io, s);
+    if (C.g >= 128) {
+        if (layered) return hipErrorInvalidValue;
+        return launch_nbw(C, max_iters, early_stop, batch, amax, ws, io, s);
+    }
+    if (layered && (C.nb_nl < 1 || C.nb_lmax < 1)) return hipErrorInvalidValue;
     const int step = nb_slice(C, batch);
     for (int b0 = 0; b0 < batch; b0 += step) {
         const int nb = std::min(step, batch - b0);
@@ -110,11 +130,11 @@ hipError_t launch_nb(const DevCode &C, int max_iters, int early_stop, int batch,
         const Args A = dev::nb::make_args(C, max_iters, early_stop, nb, amax, ws, sl);
         hipError_t e;
         switch (C.g) {
-        case 4: e = run<4>(A, s); break;
-        case 8: e = run<8>(A, s); break;
-        case 16: e = run<16>(A, s); break;
-        case 32: e = run<32>(A, s); break;
-        case 64: e = run<64>(A, s); break;
+        case 4: e = run<4>(A, layered != 0, s); break;
+        case 8: e = run<8>(A, layered != 0, s); break;
+        case 16: e = run<16>(A, layered != 0, s); break;
+        case 32: e = run<32>(A, layered != 0, s); break;
+        case 64: e = run<64>(A, layered != 0, s); break;
         default: e = hipErrorInvalidValue;
         }
         if (e != hipSuccess) return e;

@@ -27,6 +27,11 @@ struct DevCode {
     const uint8_t *hinv;   // [E] its inverse (g > 2)
     const uint8_t *gfmul;  // [g * g] multiplication table (g > 2)
     const int *spa_w;      // [kSpaWeights] channel weights round(2^24 exp(-c / 4)) of the FFT-SPA decoder
+    // Layers of the layered Min-Max schedule (g > 2): greedy colouring of the checks in
+    // ascending order, each check in the lowest layer that holds no check sharing a variable.
+    int nb_nl, nb_lmax;    // number of layers, checks in the largest
+    const int *nbl_ptr;    // [nb_nl + 1]
+    const int *nbl_chk;    // [m] checks layer by layer, ascending within a layer
 };
 
 struct BinRule {
@@ -139,8 +144,9 @@ struct NbwWork {
 // Codewords per launch sequence of the interleaved Min-Max decoder (31-bit offsets).
 int nb_slice(const DevCode &C, int batch);
 size_t nb_work_bytes(const DevCode &C, int max_iters, int batch);
-// amax: message bound (32767 for 16-bit messages, 127 for the 8-bit variant).
-hipError_t launch_nb(const DevCode &C, int max_iters, int early_stop, int batch, int amax, void *ws,
+// amax: message bound (32767 for 16-bit messages, 127 for the 8-bit variant).  layered:
+// the layered schedule over the layers of DevCode (g <= 64).
+hipError_t launch_nb(const DevCode &C, int max_iters, int early_stop, int layered, int batch, int amax, void *ws,
                      const DecodeIO &io, hipStream_t s);
 // Field sizes with a compiled Min-Max kernel (4..64 interleaved, 128 and 256 wide).
 bool nb_supported(int g);

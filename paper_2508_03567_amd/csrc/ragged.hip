@@ -331,6 +331,8 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
             D.batch = jb.batch;
             D.io = DecodeIO{jb.llr, jb.hard, jb.syndrome_ok, jb.iters, nullptr, nullptr, nullptr};
             D.layered = pl.schedule == LDPCX_SCHED_LAYERED;
+            if (pl.family == FAMILY_NB && D.layered)
+                return cleanup(), fail(LDPCX_E_UNSUPPORTED, "layered Min-Max runs through ldpcx_decode only");
             auto add = [&](int type, long count) {
                 for (long i = 0; i < count; ++i) items.push_back(Item{type, j, (int)i, 0});
                 const double cst = item_cost(D, D.C);

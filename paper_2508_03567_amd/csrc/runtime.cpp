@@ -94,8 +94,10 @@ ldpcx_status check_params(const ldpcx_code *c, const ldpcx_decode_params *p) {
         if (p->rule == LDPCX_RULE_SPA && !spa_supported(c->dev))
             return fail(LDPCX_E_UNSUPPORTED, "the FFT-SPA decoder covers GF(4)..GF(64), check and variable degrees <= 16");
         if (p->nb_msg_max < 0 || p->nb_msg_max > 32767) return fail(LDPCX_E_INVAL, "nb_msg_max must be in [0, 32767]");
-        if (p->schedule == LDPCX_SCHED_LAYERED)
-            return fail(LDPCX_E_UNSUPPORTED, "layered Min-Max is not implemented");
+        if (p->schedule == LDPCX_SCHED_LAYERED && p->rule == LDPCX_RULE_SPA)
+            return fail(LDPCX_E_UNSUPPORTED, "the FFT-SPA decoder runs the flooding schedule only");
+        if (p->schedule == LDPCX_SCHED_LAYERED && c->g > 64)
+            return fail(LDPCX_E_UNSUPPORTED, "layered Min-Max covers GF(4)..GF(64)");
     }
     return LDPCX_OK;
 }
@@ -125,7 +127,7 @@ Plan default_plan(const ldpcx_code *c, const ldpcx_decode_params *p, int batch) 
     }
     if (c->g > 2) {
         pl.family = FAMILY_NB;
-        pl.schedule = LDPCX_SCHED_FLOODING;
+        pl.schedule = p->schedule == LDPCX_SCHED_LAYERED ? LDPCX_SCHED_LAYERED : LDPCX_SCHED_FLOODING;
         pl.cpw = 64;
         pl.threads = 256;
         return pl;
@@ -237,7 +239,8 @@ hipError_t enqueue_interleaved(ldpcx_code *c, const ldpcx_decode_params *p, cons
         return launch_bin_il(c->dev, bin_rule(p), p->max_iters, p->early_stop, batch, pl.cpw, ws, io, dump_scratch,
                              s);
     if (pl.family == FAMILY_SPA) return launch_spa(c->dev, p->max_iters, p->early_stop, batch, ws, io, s);
-    return launch_nb(c->dev, p->max_iters, p->early_stop, batch, nb_amax(p), ws, io, s);
+    return launch_nb(c->dev, p->max_iters, p->early_stop, pl.schedule == LDPCX_SCHED_LAYERED, batch, nb_amax(p), ws,
+                     io, s);
 }
 
 bool graphs_enabled() {
@@ -255,6 +258,7 @@ ldpcx_status run_graph(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &
                        hipStream_t s) {
     GraphKey key{};
     key.family = pl.family;
+    key.schedule = pl.schedule;
     key.cpw = pl.cpw;
     key.batch = batch;
     key.params = *p;
@@ -543,6 +547,32 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
                 c->qc_ok = qc;
             }
         }
+        // Layers of the layered Min-Max schedule: checks in ascending order, each in the
+        // lowest layer none of whose checks shares a variable with it.
+        std::vector<int> nbl_ptr(1, 0), nbl_chk;
+        int nb_lmax = 0;
+        if (g > 2) {
+            std::vector<std::vector<uint8_t>> used;  // [layer][variable]
+            std::vector<int> layer_of(m);
+            for (int i = 0; i < m; ++i) {
+                size_t l = 0;
+                for (; l < used.size(); ++l) {
+                    bool clash = false;
+                    for (int e = c->row_ptr[i]; e < c->row_ptr[i + 1] && !clash; ++e) clash = used[l][c->col_idx[e]] != 0;
+                    if (!clash) break;
+                }
+                if (l == used.size()) used.emplace_back(n, 0);
+                for (int e = c->row_ptr[i]; e < c->row_ptr[i + 1]; ++e) used[l][c->col_idx[e]] = 1;
+                layer_of[i] = (int)l;
+            }
+            for (size_t l = 0; l < used.size(); ++l) {
+                for (int i = 0; i < m; ++i)
+                    if (layer_of[i] == (int)l) nbl_chk.push_back(i);
+                nbl_ptr.push_back((int)nbl_chk.size());
+                nb_lmax = std::max(nb_lmax, nbl_ptr.back() - nbl_ptr[nbl_ptr.size() - 2]);
+            }
+        }
+        const int nb_nl = (int)nbl_ptr.size() - 1;
         hipError_t e = hipGetDevice(&c->device);
         if (e != hipSuccess) {
             delete c;
@@ -560,7 +590,9 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
         const size_t o_mul = align_up(o_hi + (size_t)E, 256);
         const size_t o_qc = align_up(o_mul + (size_t)g * g + 4, 256);
         const size_t o_sw = align_up(o_qc + sizeof(int2) * kQcMaxL * kQcMaxDc, 256);
-        const size_t total = align_up(o_sw + sizeof(int) * kSpaWeights, 256);
+        const size_t o_lp = align_up(o_sw + sizeof(int) * kSpaWeights, 256);
+        const size_t o_lc = align_up(o_lp + sizeof(int) * nbl_ptr.size(), 256);
+        const size_t total = align_up(o_lc + sizeof(int) * (nbl_chk.size() + 1), 256);
         e = hipMalloc(&c->dmem, total);
         if (e != hipSuccess) {
             delete c;
@@ -582,6 +614,8 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
             int *sw = (int *)(host.data() + o_sw);
             for (int cst = 0; cst < kSpaWeights; ++cst) sw[cst] = (int)std::floor(16777216.0 * std::exp(-cst / 4.0) + 0.5);
         }
+        std::memcpy(host.data() + o_lp, nbl_ptr.data(), sizeof(int) * nbl_ptr.size());
+        if (!nbl_chk.empty()) std::memcpy(host.data() + o_lc, nbl_chk.data(), sizeof(int) * nbl_chk.size());
         if (c->qc_ok) {
             int2 *qe = (int2 *)(host.data() + o_qc);
             for (int l = 0; l < c->qc.nl; ++l)
@@ -615,6 +649,10 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
         D.hinv = (const uint8_t *)(b + o_hi);
         D.gfmul = (const uint8_t *)(b + o_mul);
         D.spa_w = (const int *)(b + o_sw);
+        D.nb_nl = nb_nl;
+        D.nb_lmax = nb_lmax;
+        D.nbl_ptr = (const int *)(b + o_lp);
+        D.nbl_chk = (const int *)(b + o_lc);
         c->qc.edges = (const int2 *)(b + o_qc);
         if (g > 2 && !nb_supported(g)) {
             // Valid code, but no compiled Min-Max kernel for this field size.
@@ -699,8 +737,10 @@ ldpcx_status ldpcx_plan_set(ldpcx_code *c, const ldpcx_decode_params *params, in
     pl.family = family;
     pl.schedule = params->schedule == LDPCX_SCHED_AUTO ? default_plan(c, params, std::max(1, batch)).schedule
                                                         : params->schedule;
-    if (family != FAMILY_BIN_LDS && family != FAMILY_BIN_QC && pl.schedule == LDPCX_SCHED_LAYERED)
+    if (family != FAMILY_BIN_LDS && family != FAMILY_BIN_QC && family != FAMILY_NB && pl.schedule == LDPCX_SCHED_LAYERED)
         return fail(LDPCX_E_UNSUPPORTED, "this kernel family runs the flooding schedule only");
+    if (family == FAMILY_NB && pl.schedule == LDPCX_SCHED_LAYERED && c->g > 64)
+        return fail(LDPCX_E_UNSUPPORTED, "layered Min-Max covers GF(4)..GF(64)");
     if (family == FAMILY_BIN_QC) {
         if (cw_per_wg < 2 || cw_per_wg % 2 || c->qc.Z * cw_per_wg / 2 > 512)
             return fail(LDPCX_E_INVAL, "cw_per_wg must be even with Z * cw_per_wg / 2 <= 512");

@@ -28,7 +28,7 @@ struct DeviceInfo {
 // A captured launch sequence of the interleaved decoders, keyed by everything that is
 // baked into its kernel arguments.
 struct GraphKey {
-    int family, cpw, batch;
+    int family, schedule, cpw, batch;
     ldpcx_decode_params params;
     const void *llr;
     void *hard;

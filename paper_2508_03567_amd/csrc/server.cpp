@@ -187,7 +187,8 @@ struct ldpcx_server {
             const uint64_t id = queue.front();
             Request &r = reqs.at(id);
             const bool own = cfg.mode == LDPCX_SERVE_PER_REQUEST || r.family == FAMILY_BIN_IL || r.family == FAMILY_SPA ||
-                             (r.family == FAMILY_NB && (r.code->g > 64 || pad64(r.batch - r.next_cw) / 64 >= kOwnLaunchGroups));
+                             (r.family == FAMILY_NB && (r.code->g > 64 || r.prm.schedule != LDPCX_SCHED_FLOODING ||
+                                                         pad64(r.batch - r.next_cw) / 64 >= kOwnLaunchGroups));
             // A launch is either one chunk with its own launch sequence or a ragged batch.
             if (own && !take.empty()) break;
             if (!take.empty() && us >= kLaunchTargetUs) break;

@@ -17,7 +17,15 @@ std::vector<Plan> candidates(const ldpcx_code *c, const ldpcx_decode_params *p, 
     std::vector<Plan> out;
     const Plan def = default_plan(c, p, batch);
     out.push_back(def);
-    if (c->g > 2) return out;
+    if (c->g > 2) {
+        // Min-Max: under AUTO the layered schedule is the other candidate (GF(4)..GF(64))
+        if (p->schedule == LDPCX_SCHED_AUTO && p->rule == LDPCX_RULE_MINMAX && c->g <= 64) {
+            Plan pl = def;
+            pl.schedule = LDPCX_SCHED_LAYERED;
+            out.push_back(pl);
+        }
+        return out;
+    }
     std::vector<int> scheds;
     if (p->schedule == LDPCX_SCHED_AUTO) {
         scheds.push_back(LDPCX_SCHED_FLOODING);

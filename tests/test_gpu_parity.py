@@ -384,6 +384,89 @@ def test_minmax_reduced_precision(g_size, bound):
 
 
 @pytest.mark.parametrize("g_size,n,dc,batch,early,iters", [
+    (4, 24, 4, 70, True, 6), (8, 12, 2, 130, True, 4), (16, 20, 5, 33, False, 4), (32, 30, 3, 9, True, 5),
+    (64, 16, 4, 5, False, 3), (64, 40, 8, 66, True, 4)])
+def test_minmax_layered_matches_oracle(g_size, n, dc, batch, early, iters):
+    """Layered Min-Max: one launch per layer of checks sharing no variable, each check
+    forming its alphas from the current betas; decisions, flags, iteration counts and
+    every alpha / beta equal the oracle's one-check-at-a-time schedule."""
+    m = n * 2 // dc
+    code = S.random_regular_nb_code(n, m, 2, dc, g_size, S.PRIM_POLY[g_size], seed=g_size + 3 * n + dc)
+    cw = S.random_codewords(code, batch, seed=11)
+    gam = S.nb_gamma_int16(cw, g_size, 1.5, seed=12)
+    d = dict(rule="minmax", schedule="layered", max_iters=iters, early_stop=early)
+    h = L.Code(code)
+    g = _gpu(h, d, gam, dump=True)
+    ref = _ref(code, d, gam, dump=True)
+    _check_decisions(code, g, ref)
+    assert (g[3].astype(np.int32) == ref["alpha"]).all(), "alpha differs"
+    assert (g[4].astype(np.int32) == ref["beta"]).all(), "beta differs"
+    g2 = _gpu(h, d, gam)
+    _check_decisions(code, g2, ref)
+
+
+@pytest.mark.parametrize("batch,early,bound", [(67, True, 0), (130, False, 0), (64, True, 127)])
+def test_minmax_layered_gf64_workload(batch, early, bound):
+    w = S.workload(3, batch=batch)
+    cw, gam = S.make_inputs(w, seed_offset=5)
+    d = dict(rule="minmax", schedule="layered", max_iters=8, early_stop=early, nb_msg_max=bound)
+    g = _gpu(_handle(w.code), d, gam, dump=True)
+    ref = _ref(w.code, d, gam, dump=True)
+    _check_decisions(w.code, g, ref)
+    assert (g[3].astype(np.int32) == ref["alpha"]).all()
+    assert (g[4].astype(np.int32) == ref["beta"]).all()
+
+
+def test_minmax_layered_full_size_sampled():
+    """GF(64) workload at its full batch of 8192 codewords, layered, 20 iterations with
+    early stop: sampled codewords against the oracle."""
+    w = S.workload(3)
+    cw, gam = S.make_inputs(w)
+    d = dict(rule="minmax", schedule="layered", max_iters=w.max_iters, early_stop=True)
+    g = _gpu(_handle(w.code), d, gam)
+    idx = np.random.default_rng(4).choice(w.batch, size=24, replace=False)
+    ref = _ref(w.code, d, gam[idx])
+    _check_decisions(w.code, g, ref, idx)
+
+
+def test_minmax_auto_schedule_is_tuned_and_reported():
+    w = S.workload(3, batch=256)
+    cw, gam = S.make_inputs(w, seed_offset=6)
+    h = L.Code(w.code)
+    prm = L.params("minmax", "auto", 6, True)
+    chosen, us = L.tune(h, prm, 256)
+    assert chosen in ("flooding", "layered") and us > 0
+    x = torch.from_numpy(gam).to(DEV)
+    hard, ok, it, used = L.decode(h, prm, x)
+    assert used == chosen
+    ref = O.decode_nb(w.code, O.params("minmax", used, 6, True), gam)
+    assert (hard.cpu().numpy() == ref["hard"]).all() and (it.cpu().numpy() == ref["iters"]).all()
+    # pinned the other way round, each schedule still gives its own result
+    for sched in ("flooding", "layered"):
+        hard, ok, it, used = L.decode(h, L.params("minmax", sched, 6, True), x)
+        assert used == sched
+        ref = O.decode_nb(w.code, O.params("minmax", sched, 6, True), gam)
+        assert (hard.cpu().numpy() == ref["hard"]).all() and (it.cpu().numpy() == ref["iters"]).all()
+
+
+def test_minmax_layered_rejections():
+    c128 = S.random_regular_nb_code(16, 8, 2, 4, 128, S.PRIM_POLY[128], seed=1)
+    with pytest.raises(L.LdpcxError) as ei:
+        L.decode(L.Code(c128), L.params("minmax", "layered", 2), torch.zeros((2, 16, 128), dtype=torch.int16, device=DEV))
+    assert ei.value.status == L.E_UNSUPPORTED
+    c64 = S.random_regular_nb_code(16, 8, 2, 4, 64, S.PRIM_POLY[64], seed=1)
+    h64 = L.Code(c64)
+    g64 = torch.zeros((2, 16, 64), dtype=torch.int16, device=DEV)
+    for prm in (L.params("spa", "layered", 2), ):
+        with pytest.raises(L.LdpcxError) as ei:
+            L.decode(h64, prm, g64)
+        assert ei.value.status == L.E_UNSUPPORTED
+    with pytest.raises(L.LdpcxError) as ei:
+        L.decode_ragged([(h64, L.params("minmax", "layered", 2), g64)])
+    assert ei.value.status == L.E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("g_size,n,dc,batch,early,iters", [
     (4, 24, 4, 70, True, 6), (8, 24, 4, 33, False, 4), (16, 16, 4, 20, True, 5), (32, 30, 3, 9, True, 4),
     (64, 16, 4, 5, False, 3), (64, 192, 4, 6, True, 5), (16, 20, 5, 7, True, 4), (4, 12, 2, 40, True, 3)])
 def test_spa_matches_oracle(g_size, n, dc, batch, early, iters):
