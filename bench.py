@@ -99,6 +99,11 @@ def main() -> None:
     ap.add_argument("--precision", action="store_true",
                     help="Min-Max message precision: 16-bit vs 8-bit (bound 127) messages on the GF(64) workload, "
                          "FER over Eb/N0 and fixed-iteration throughput")
+    ap.add_argument("--schedule", type=str, default=None, choices=["flooding", "layered"],
+                    help="override the workload's schedule (the workload name then carries it)")
+    ap.add_argument("--schedules", action="store_true",
+                    help="Min-Max flooding vs layered on the GF(64) workload: FER at fixed iteration counts, "
+                         "mean iterations and time with early stop, fixed-iteration throughput")
     ap.add_argument("--sweep", action="store_true",
                     help="GF-size sweep instead: (2,4)-regular codes of 16/32/64 symbols over GF(4)..GF(256), "
                          "Min-Max, fixed iterations (one JSON line per point)")
@@ -119,12 +124,18 @@ def main() -> None:
     if args.precision:
         precision_main(args)
         return
+    if args.schedules:
+        schedules_main(args)
+        return
 
     import torch
     from paper_2508_03567_amd import ldpcx as L
     from paper_2508_03567_amd import synth as S
 
     w = S.workload(args.workload, batch=args.batch)
+    if args.schedule and args.schedule != w.schedule:
+        import dataclasses
+        w = dataclasses.replace(w, schedule=args.schedule, name=f"{w.name}_{args.schedule}")
     t0 = time.time()
     cw, llr_np = S.make_inputs(w)
     gen_s = time.time() - t0
@@ -328,6 +339,52 @@ def precision_main(args) -> None:
                               "mean_iters": round(mean_it, 3), "workload": w.name, "batch": w.batch,
                               "fixed_iter_info_gbit_s": round(w.info_bits_per_cw * w.batch / (ms * 1e-3) / 1e9, 4)}),
                   flush=True)
+
+
+def _time_decode(L, torch, h, prm, gam, out, reps=3):
+    stream = torch.cuda.current_stream()
+    L.decode(h, prm, gam, stream=stream, out=out)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        L.decode(h, prm, gam, stream=stream, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / reps
+
+
+def schedules_main(args) -> None:
+    """Min-Max with the two-phase (flooding) and the layered schedule on the GF(64) workload."""
+    import torch
+    from paper_2508_03567_amd import ldpcx as L
+    from paper_2508_03567_amd import synth as S
+
+    dev = torch.device("cuda:0")
+    for eb in (1.5, 2.0, 2.5):
+        w = S.workload(3, batch=args.batch or 8192, ebn0_db=eb)
+        cw, gam_np = S.make_inputs(w)
+        gam = torch.from_numpy(gam_np).to(dev)
+        h = L.Code(w.code)
+        out = L._outputs(h, w.batch, dev)
+        for sched in ("flooding", "layered"):
+            rec = {"metric": "Min-Max schedule", "schedule": sched, "ebn0_db": eb, "workload": w.name,
+                   "batch": w.batch}
+            for iters in (5, 10, 20):
+                hard, ok, it, _ = L.decode(h, L.params("minmax", sched, iters, early_stop=False), gam, out=out)
+                torch.cuda.synchronize()
+                rec[f"fer_{iters}it"] = float((hard.cpu().numpy() != cw).any(axis=1).mean())
+            prm_es = L.params("minmax", sched, w.max_iters, early_stop=True)
+            hard, ok, it, _ = L.decode(h, prm_es, gam, out=out)
+            torch.cuda.synchronize()
+            rec["mean_iters_early_stop"] = round(float(it.float().mean()), 3)
+            ms_es = _time_decode(L, torch, h, prm_es, gam, out)
+            ms_fx = _time_decode(L, torch, h, L.params("minmax", sched, w.max_iters, early_stop=False), gam, out)
+            rec["ms_early_stop"] = round(ms_es, 3)
+            rec["info_gbit_s_early_stop"] = round(w.info_bits_per_cw * w.batch / (ms_es * 1e-3) / 1e9, 4)
+            rec["ms_fixed_20it"] = round(ms_fx, 3)
+            rec["info_gbit_s_fixed_20it"] = round(w.info_bits_per_cw * w.batch / (ms_fx * 1e-3) / 1e9, 4)
+            print(json.dumps(rec), flush=True)
 
 
 # ------------------------------------------------------------------ serving mix

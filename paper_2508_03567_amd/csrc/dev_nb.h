@@ -217,22 +217,32 @@ __device__ __forceinline__ void alpha_edge(const Args &A, int e, int b, bool act
     }
 }
 
-// Layered schedule, iteration k, layer `layer` (checks sharing no variable): wave w of
-// virtual block (bx, by) takes the layer's check number bx * wpb + w, forms the alphas of
-// its edges and runs its check node, for codewords [64 by, 64 by + 64).
+// Layered schedule, iteration k, layer `layer` (checks sharing no variable), first
+// step: the alphas of the layer's edges.  Wave per (edge of the layer, group).
 template <int G>
-__device__ __forceinline__ void lay_block(const Args &A, int k, int layer, int wpb, int bx, int by, uint32_t *lds) {
+__device__ __forceinline__ void lay_alpha_block(const Args &A, int k, int layer, int bx, int by) {
+    const DevCode &C = A.C;
+    const int i = C.nbl_eptr[layer] + bx * 4 + wave_id();
+    if (i >= C.nbl_eptr[layer + 1]) return;
+    const int e = __builtin_amdgcn_readfirstlane(C.nbl_edge[i]);
+    const int lane = threadIdx.x & 63;
+    const bool act = active(A, k, by, lane);
+    if (__ballot(act) == 0) return;
+    alpha_edge<G>(A, e, by * 64 + lane, act);
+}
+
+// Second step: the check nodes of the layer.  Wave w of virtual block (bx, by) takes the
+// layer's check number bx * wpb + w for codewords [64 by, 64 by + 64).
+template <int G>
+__device__ __forceinline__ void lay_cn_block(const Args &A, int k, int layer, int wpb, int bx, int by, uint32_t *lds) {
     const DevCode &C = A.C;
     const int w = wave_id();
     if (w >= wpb) return;
     const int i = C.nbl_ptr[layer] + bx * wpb + w;
     if (i >= C.nbl_ptr[layer + 1]) return;
     const int row = __builtin_amdgcn_readfirstlane(C.nbl_chk[i]);
-    const int lane = threadIdx.x & 63;
-    const bool act = active(A, k, by, lane);
+    const bool act = active(A, k, by, threadIdx.x & 63);
     if (__ballot(act) == 0) return;
-    for (int e = C.row_ptr[row]; e < C.row_ptr[row + 1]; ++e) alpha_edge<G>(A, e, by * 64 + lane, act);
-    __threadfence_block();  // the check node reads the alphas just stored by these lanes
     cn_row<G>(A, row, w, by, act, lds);
 }
 

@@ -15,24 +15,36 @@ __global__ void __launch_bounds__(256) k_tr(dev::TransposeArgs T) {
     dev::transpose_block(T, blockIdx.x, blockIdx.y, tile);
 }
 __global__ void __launch_bounds__(256) k_fill(dev::FillArgs F) { dev::fill_block(F, blockIdx.x); }
+// Node-by-group kernels run on a 1-D grid numbered group-fastest: consecutive blocks take
+// the same nodes for neighbouring groups of 64 codewords, so the rows that run together
+// are adjacent in the [node][entry][codeword] arrays.
+__device__ __forceinline__ int blk_node(int Gn) { return (int)(blockIdx.x / (unsigned)Gn); }
+__device__ __forceinline__ int blk_group(int Gn) { return (int)(blockIdx.x % (unsigned)Gn); }
+
 template <int G>
-__global__ void __launch_bounds__(256) k_init(Args A) { dev::nb::init_block<G>(A, blockIdx.x, blockIdx.y); }
-__global__ void __launch_bounds__(256) k_syn(Args A, int slot) { dev::nb::syn_block(A, slot, blockIdx.x, blockIdx.y); }
+__global__ void __launch_bounds__(256) k_init(Args A) { dev::nb::init_block<G>(A, blk_node(A.Gn), blk_group(A.Gn)); }
+__global__ void __launch_bounds__(256) k_syn(Args A, int slot) {
+    dev::nb::syn_block(A, slot, blk_node(A.Gn), blk_group(A.Gn));
+}
 template <int G>
 __global__ void __launch_bounds__(256) k_cn(Args A, int k, int wpb) {
     extern __shared__ __align__(16) uint32_t lds[];
-    dev::nb::cn_block<G>(A, k, wpb, blockIdx.x, blockIdx.y, lds);
+    dev::nb::cn_block<G>(A, k, wpb, blk_node(A.Gn), blk_group(A.Gn), lds);
 }
 template <int G>
-__global__ void __launch_bounds__(256) k_vn(Args A, int k) { dev::nb::vn_block<G>(A, k, blockIdx.x, blockIdx.y); }
+__global__ void __launch_bounds__(256) k_vn(Args A, int k) { dev::nb::vn_block<G>(A, k, blk_node(A.Gn), blk_group(A.Gn)); }
 template <int G>
-__global__ void __launch_bounds__(256) k_lay(Args A, int k, int layer, int wpb) {
+__global__ void __launch_bounds__(256) k_lal(Args A, int k, int layer) {
+    dev::nb::lay_alpha_block<G>(A, k, layer, blk_node(A.Gn), blk_group(A.Gn));
+}
+template <int G>
+__global__ void __launch_bounds__(256) k_lcn(Args A, int k, int layer, int wpb) {
     extern __shared__ __align__(16) uint32_t lds[];
-    dev::nb::lay_block<G>(A, k, layer, wpb, blockIdx.x, blockIdx.y, lds);
+    dev::nb::lay_cn_block<G>(A, k, layer, wpb, blk_node(A.Gn), blk_group(A.Gn), lds);
 }
 template <int G>
 __global__ void __launch_bounds__(256) k_dec(Args A, int k) {
-    dev::nb::vn_block<G, false>(A, k, blockIdx.x, blockIdx.y);
+    dev::nb::vn_block<G, false>(A, k, blk_node(A.Gn), blk_group(A.Gn));
 }
 __global__ void __launch_bounds__(256) k_fin(Args A) { dev::nb::fin_block(A, blockIdx.x); }
 
@@ -49,27 +61,36 @@ hipError_t fill(const dev::FillArgs &F, hipStream_t s) {
     return hipGetLastError();
 }
 
+dim3 lin(long nodes, int Gn) { return dim3((unsigned)(nodes * Gn)); }
+
 template <int G>
 hipError_t run(const Args &A, bool layered, hipStream_t s) {
     hipError_t e;
+    const long most = std::max<long>({dev::nb::grid_init_x(A), A.C.m, A.C.nb_emax});
+    if (most * A.Gn >= (1L << 31)) return hipErrorInvalidConfiguration;
     if ((e = tr(dev::nb::tr_in(A), s)) != hipSuccess) return e;
     const dim3 blk(256);
-    hipLaunchKernelGGL(k_init<G>, dim3((unsigned)dev::nb::grid_init_x(A), (unsigned)A.Gn), blk, 0, s, A);
+    hipLaunchKernelGGL(k_init<G>, lin(dev::nb::grid_init_x(A), A.Gn), blk, 0, s, A);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = fill(dev::nb::fill_unsat(A), s)) != hipSuccess) return e;
     if ((e = fill(dev::nb::fill_it(A), s)) != hipSuccess) return e;
     const int wpb = dev::nb::cn_waves(A, 64 * 1024);
     if (wpb < 1) return hipErrorInvalidConfiguration;
     const size_t smem = dev::nb::cn_lds_bytes(A, wpb);
-    const dim3 gcn((unsigned)((A.C.m + wpb - 1) / wpb), (unsigned)A.Gn);
-    const dim3 gsy((unsigned)dev::nb::grid_rows_x(A), (unsigned)A.Gn);
-    const dim3 gvn((unsigned)dev::nb::grid_vn_x(A), (unsigned)A.Gn);
-    const dim3 glay((unsigned)((A.C.nb_lmax + wpb - 1) / wpb), (unsigned)A.Gn);
+    const dim3 gcn = lin((A.C.m + wpb - 1) / wpb, A.Gn);
+    const dim3 gsy = lin(dev::nb::grid_rows_x(A), A.Gn);
+    const dim3 gvn = lin(dev::nb::grid_vn_x(A), A.Gn);
+    const dim3 glay = lin((A.C.nb_lmax + wpb - 1) / wpb, A.Gn);
+    const dim3 glal = lin((A.C.nb_emax + 3) / 4, A.Gn);
     for (int k = 1; k <= A.max_iters; ++k) {
         if (A.early_stop) hipLaunchKernelGGL(k_syn, gsy, blk, 0, s, A, k);
         if (layered) {
-            // one launch per layer: the checks of a layer share no variable
-            for (int l = 0; l < A.C.nb_nl; ++l) hipLaunchKernelGGL(k_lay<G>, glay, dim3(64 * wpb), smem, s, A, k, l, wpb);
+            // two launches per layer (its alphas, then its check nodes): the checks of a
+            // layer share no variable
+            for (int l = 0; l < A.C.nb_nl; ++l) {
+                hipLaunchKernelGGL(k_lal<G>, glal, blk, 0, s, A, k, l);
+                hipLaunchKernelGGL(k_lcn<G>, glay, dim3(64 * wpb), smem, s, A, k, l, wpb);
+            }
             hipLaunchKernelGGL(k_dec<G>, gvn, blk, 0, s, A, k);
         } else {
             hipLaunchKernelGGL(k_cn<G>, gcn, dim3(64 * wpb), smem, s, A, k, wpb);
@@ -114,7 +135,7 @@ hipError_t launch_nb(const DevCode &C, int max_iters, int early_stop, int layere
         if (layered) return hipErrorInvalidValue;
         return launch_nbw(C, max_iters, early_stop, batch, amax, ws, io, s);
     }
-    if (layered && (C.nb_nl < 1 || C.nb_lmax < 1)) return hipErrorInvalidValue;
+    if (layered && (C.nb_nl < 1 || C.nb_lmax < 1 || C.nb_emax < 1)) return hipErrorInvalidValue;
     const int step = nb_slice(C, batch);
     for (int b0 = 0; b0 < batch; b0 += step) {
         const int nb = std::min(step, batch - b0);

@@ -29,9 +29,11 @@ struct DevCode {
     const int *spa_w;      // [kSpaWeights] channel weights round(2^24 exp(-c / 4)) of the FFT-SPA decoder
     // Layers of the layered Min-Max schedule (g > 2): greedy colouring of the checks in
     // ascending order, each check in the lowest layer that holds no check sharing a variable.
-    int nb_nl, nb_lmax;    // number of layers, checks in the largest
+    int nb_nl, nb_lmax, nb_emax;  // number of layers, checks and edges in the largest
     const int *nbl_ptr;    // [nb_nl + 1]
     const int *nbl_chk;    // [m] checks layer by layer, ascending within a layer
+    const int *nbl_eptr;   // [nb_nl + 1]
+    const int *nbl_edge;   // [E] edges of those checks in the same order
 };
 
 struct BinRule {

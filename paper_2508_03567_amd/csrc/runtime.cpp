@@ -549,8 +549,8 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
         }
         // Layers of the layered Min-Max schedule: checks in ascending order, each in the
         // lowest layer none of whose checks shares a variable with it.
-        std::vector<int> nbl_ptr(1, 0), nbl_chk;
-        int nb_lmax = 0;
+        std::vector<int> nbl_ptr(1, 0), nbl_chk, nbl_eptr(1, 0), nbl_edge;
+        int nb_lmax = 0, nb_emax = 0;
         if (g > 2) {
             std::vector<std::vector<uint8_t>> used;  // [layer][variable]
             std::vector<int> layer_of(m);
@@ -567,9 +567,14 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
             }
             for (size_t l = 0; l < used.size(); ++l) {
                 for (int i = 0; i < m; ++i)
-                    if (layer_of[i] == (int)l) nbl_chk.push_back(i);
+                    if (layer_of[i] == (int)l) {
+                        nbl_chk.push_back(i);
+                        for (int e = c->row_ptr[i]; e < c->row_ptr[i + 1]; ++e) nbl_edge.push_back(e);
+                    }
                 nbl_ptr.push_back((int)nbl_chk.size());
+                nbl_eptr.push_back((int)nbl_edge.size());
                 nb_lmax = std::max(nb_lmax, nbl_ptr.back() - nbl_ptr[nbl_ptr.size() - 2]);
+                nb_emax = std::max(nb_emax, nbl_eptr.back() - nbl_eptr[nbl_eptr.size() - 2]);
             }
         }
         const int nb_nl = (int)nbl_ptr.size() - 1;
@@ -592,7 +597,9 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
         const size_t o_sw = align_up(o_qc + sizeof(int2) * kQcMaxL * kQcMaxDc, 256);
         const size_t o_lp = align_up(o_sw + sizeof(int) * kSpaWeights, 256);
         const size_t o_lc = align_up(o_lp + sizeof(int) * nbl_ptr.size(), 256);
-        const size_t total = align_up(o_lc + sizeof(int) * (nbl_chk.size() + 1), 256);
+        const size_t o_lep = align_up(o_lc + sizeof(int) * (nbl_chk.size() + 1), 256);
+        const size_t o_le = align_up(o_lep + sizeof(int) * nbl_eptr.size(), 256);
+        const size_t total = align_up(o_le + sizeof(int) * (nbl_edge.size() + 1), 256);
         e = hipMalloc(&c->dmem, total);
         if (e != hipSuccess) {
             delete c;
@@ -616,6 +623,8 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
         }
         std::memcpy(host.data() + o_lp, nbl_ptr.data(), sizeof(int) * nbl_ptr.size());
         if (!nbl_chk.empty()) std::memcpy(host.data() + o_lc, nbl_chk.data(), sizeof(int) * nbl_chk.size());
+        std::memcpy(host.data() + o_lep, nbl_eptr.data(), sizeof(int) * nbl_eptr.size());
+        if (!nbl_edge.empty()) std::memcpy(host.data() + o_le, nbl_edge.data(), sizeof(int) * nbl_edge.size());
         if (c->qc_ok) {
             int2 *qe = (int2 *)(host.data() + o_qc);
             for (int l = 0; l < c->qc.nl; ++l)
@@ -651,6 +660,9 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
         D.spa_w = (const int *)(b + o_sw);
         D.nb_nl = nb_nl;
         D.nb_lmax = nb_lmax;
+        D.nb_emax = nb_emax;
+        D.nbl_eptr = (const int *)(b + o_lep);
+        D.nbl_edge = (const int *)(b + o_le);
         D.nbl_ptr = (const int *)(b + o_lp);
         D.nbl_chk = (const int *)(b + o_lc);
         c->qc.edges = (const int2 *)(b + o_qc);
