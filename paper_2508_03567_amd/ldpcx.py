@@ -96,6 +96,10 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        # PyTorch ships its own HIP runtime under the same soname as the system one the
+        # library links; loading torch first makes the whole process use torch's copy
+        # (a second copy loaded first leaves torch without devices).
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, args in _SIGS.items():
             f = getattr(L, name)
