@@ -124,7 +124,7 @@ def main() -> None:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); codewords are "
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); codewords are "
               "independent, so a multi-GPU run would split the batch with no exchange step.", file=sys.stderr)
         sys.exit(2)
     if args.serve:
