@@ -111,6 +111,8 @@ def main() -> None:
     ap.add_argument("--precision", action="store_true",
                     help="Min-Max message precision: 16-bit vs 8-bit (bound 127) messages on the GF(64) workload, "
                          "FER over Eb/N0 and fixed-iteration throughput")
+    ap.add_argument("--ragged", action="store_true",
+                    help="ragged batch of small mixed jobs: one persistent launch vs one decode call per job")
     ap.add_argument("--schedule", type=str, default=None, choices=["flooding", "layered"],
                     help="override the workload's schedule (the workload name then carries it)")
     ap.add_argument("--schedules", action="store_true",
@@ -138,6 +140,9 @@ def main() -> None:
         return
     if args.schedules:
         schedules_main(args)
+        return
+    if args.ragged:
+        ragged_main(args)
         return
 
     import torch
@@ -426,6 +431,68 @@ def schedules_main(args) -> None:
             rec["ms_fixed_20it"] = round(ms_fx, 3)
             rec["info_gbit_s_fixed_20it"] = round(w.info_bits_per_cw * w.batch / (ms_fx * 1e-3) / 1e9, 4)
             print(json.dumps(rec), flush=True)
+
+
+def ragged_main(args) -> None:
+    """Many small jobs of the three short codes (n = 192 binary, n = 2304 binary, GF(64)),
+    1 to 256 codewords each (log-uniform), early stop on: one ldpcx_decode_ragged launch
+    against a loop of ldpcx_decode calls, one per job, on the same stream."""
+    # Plain per-job decodes run their launch sequences eagerly: graph replays are keyed by
+    # the I/O buffers and would be captured anew for every job slice.
+    os.environ["LDPCX_GRAPHS"] = "0"
+    import torch
+    from paper_2508_03567_amd import ldpcx as L
+    from paper_2508_03567_amd import synth as S
+
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(31)
+    pools, codes, prms = {}, {}, {}
+    for cfg in (0, 1, 3):
+        w = S.workload(cfg, batch=512)
+        _, llr = S.make_inputs(w, seed_offset=310)
+        pools[cfg] = torch.from_numpy(np.ascontiguousarray(llr)).to(dev)
+        codes[cfg] = L.Code(w.code)
+        prms[cfg] = L.params(w.rule, w.schedule, w.max_iters, early_stop=True, nms_num=w.nms_num,
+                             nms_shift=w.nms_shift, oms_offset=w.oms_offset, msg_max=w.msg_max)
+        info = w.info_bits_per_cw
+        pools[cfg] = (pools[cfg], info)
+    for mix, njobs in (("binary", 16), ("binary", 64), ("binary", 256), ("with_gf64", 16), ("with_gf64", 64),
+                       ("with_gf64", 256)):
+        jobs, bits = [], 0
+        for _ in range(njobs):
+            cfg = int(rng.choice([0, 1, 3], p=[0.5, 0.3, 0.2] if mix == "with_gf64" else [0.6, 0.4, 0.0]))
+            size = int(np.exp(rng.uniform(0, np.log(257))))
+            off = int(rng.integers(0, 512 - size + 1))
+            x, info = pools[cfg]
+            jobs.append((codes[cfg], prms[cfg], x[off:off + size]))
+            bits += info * size
+        stream = torch.cuda.current_stream()
+
+        def run_ragged():
+            L.decode_ragged(jobs, stream=stream)
+
+        def run_loop():
+            for h, prm, x in jobs:
+                L.decode(h, prm, x, stream=stream)
+
+        res = {}
+        for name, fn in (("ragged_one_launch", run_ragged), ("one_decode_per_job", run_loop)):
+            for _ in range(2):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = 5
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            res[name] = (time.perf_counter() - t0) * 1e3 / reps
+        print(json.dumps({"metric": "ragged batch vs one decode per job", "mix": mix, "jobs": njobs,
+                          "codewords": sum(int(x.shape[0]) for _, _, x in jobs),
+                          "ms_ragged": round(res["ragged_one_launch"], 3),
+                          "ms_per_job_calls": round(res["one_decode_per_job"], 3),
+                          "speedup": round(res["one_decode_per_job"] / res["ragged_one_launch"], 2),
+                          "info_gbit_s_ragged": round(bits / (res["ragged_one_launch"] * 1e-3) / 1e9, 4)}),
+              flush=True)
 
 
 # ------------------------------------------------------------------ serving mix

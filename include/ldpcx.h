@@ -180,12 +180,17 @@ typedef struct {
     int16_t *iters;
 } ldpcx_job;
 
-/* Decode a ragged batch of jobs over different codes and sizes with ONE persistent
- * kernel launch on `stream` (per-codeword early termination inside).  Results are
- * identical to calling ldpcx_decode on each job.  AUTO schedules are resolved per job
- * as in ldpcx_decode.  Every job is cut into workgroup-local items (no workgroup waits
- * for another); jobs over GF(128) or GF(256) and layered Min-Max jobs have no such item
- * and are rejected with LDPCX_E_UNSUPPORTED (decode them with ldpcx_decode). */
+/* Decode a ragged batch of jobs over different codes and sizes on `stream`.  Jobs of
+ * the workgroup-local families (quasi-cyclic packed and LDS-resident binary decoders)
+ * run as items of ONE persistent kernel launch, with per-codeword early termination
+ * inside; every job is cut into items that share nothing, so no workgroup waits for
+ * another.  Jobs whose iterations need the whole device (binary codes in the
+ * interleaved layout, Min-Max and FFT-SPA over GF(g > 2)) are gathered per (code,
+ * parameters, resolved schedule) into one batch each and decoded by that batch's own
+ * launch sequence on the same stream, after the persistent kernel.  Results are
+ * identical to calling ldpcx_decode on each job; AUTO schedules are resolved per job
+ * as in ldpcx_decode.  The library allocates stream-ordered scratch for the item
+ * tables and the gathered batches and frees it on the stream. */
 ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs, void *stream);
 
 /* Autotune the launch configuration of (code, params, batch) by timing the candidate

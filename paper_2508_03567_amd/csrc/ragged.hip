@@ -1,41 +1,39 @@
-// Ragged persistent engine: one kernel launch decodes a batch of jobs over
-// different codes, sizes and decoder families.
+// Ragged batches: one call decodes a batch of jobs over different codes, sizes and
+// decoder families.
 //
-// Every job is cut into workgroup-local items that share nothing with other
-// items, so no workgroup ever waits for another and the launch cannot deadlock
-// whatever the residency of its workgroups:
+// Jobs of the workgroup-local families run as items of ONE persistent kernel launch.
+// Every such job is cut into items that share nothing with other items, so no
+// workgroup ever waits for another and the launch cannot deadlock whatever the
+// residency of its workgroups:
 //   - quasi-cyclic jobs: one item per 2 * npairs codewords (packed decoder);
 //   - other binary codes whose state fits on chip: one item per cpw codewords
-//     (LDS-resident decoder);
-//   - long binary codes (interleaved layout) and Min-Max jobs: one item per
-//     group of 64 codewords, running every phase of the interleaved decoder
-//     (layout transpose, init, per iteration syndrome test, check nodes and
-//     variable nodes, then the final test and the outputs) inside one
-//     workgroup, with a barrier between phases.  Items of one job touch
-//     disjoint lanes of the job's workspace.  An item stops iterating as soon
-//     as none of its codewords is unsatisfied, which gives the same results as
-//     running the remaining iterations with every lane inactive.
-// The host estimates the cost of every item, sorts them longest first and
-// assigns them greedily to the least-loaded workgroup of a grid sized to the
-// resident capacity of the device (LPT schedule); each workgroup then runs its
-// own list.
+//     (LDS-resident decoder).
+// The host estimates the cost of every item, sorts them longest first and assigns
+// them greedily to the least-loaded workgroup of a grid sized to the resident
+// capacity of the device (LPT schedule); each workgroup then runs its own list.
+//
+// Jobs whose iterations need the whole device (long binary codes in the interleaved
+// layout, Min-Max and FFT-SPA over GF(g > 2)) would leave one workgroup to sweep
+// every check and variable of a group of codewords, each iteration, alone.  They are
+// gathered instead per (code, parameters, resolved schedule) into one batch and run
+// as that batch's own launch sequence on the same stream, after the persistent
+// kernel; codewords are decoded independently, so every job still gets exactly what
+// a decode of it alone gives.
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <queue>
 #include <vector>
 
-#include "dev_bin_il.h"
 #include "dev_bin_lds.h"
 #include "dev_bin_qc.h"
-#include "dev_nb.h"
 #include "runtime.h"
 
 namespace ldpcx {
 
 namespace {
 
-enum ItemType { I_QC = 0, I_LDS = 1, I_IL = 2, I_NB = 3 };
+enum ItemType { I_QC = 0, I_LDS = 1 };
 
 struct JobDesc {
     int family, layered, npairs, cpw, ml, md;
@@ -44,9 +42,6 @@ struct JobDesc {
     BinRule R;
     int max_iters, early_stop, batch;
     DecodeIO io;
-    dev::il::Args il;
-    dev::nb::Args nb;
-    dev::TransposeArgs tin, tout;
 };
 
 struct Item {
@@ -54,7 +49,6 @@ struct Item {
 };
 
 constexpr int kThreads = 256;
-constexpr size_t kTileBytes = 64 * 65 * 2;
 constexpr size_t kStaticLds = 256;  // upper bound of the kernel's static LDS
 
 template <bool LAYERED>
@@ -69,198 +63,28 @@ __device__ __forceinline__ void run_qc(const JobDesc &J, int blk, uint32_t *lds)
 #undef LDPCX_QC_RUN
 }
 
-// OR of one 64-bit mask per wave over the workgroup, written to unsat[slot][g];
-// returns the result (uniform).
-__device__ __forceinline__ uint64_t group_or(uint64_t v, uint64_t *unsat, long slot_word, uint64_t *red) {
-    v = dev::wave_or64(v);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    const uint64_t u = red[0] | red[1] | red[2] | red[3];
-    if (threadIdx.x == 0) unsat[slot_word] = u;
-    __syncthreads();
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
-// ------------------------------------------------ interleaved binary, one group
-// Syndrome of one group of codewords: the kLaneCw decision words of group g in
-// slot_k; returns their OR (uniform).
-__device__ uint64_t il_syn(const dev::il::Args &A, int slot_k, int g, uint64_t *red) {
-    constexpr int H = dev::il::kLaneCw;
-    const DevCode &C = A.C;
-    const int W = H * A.G;
-    uint64_t acc[H];
-    for (int h = 0; h < H; ++h) acc[h] = 0;
-    for (int row = threadIdx.x; row < C.m; row += kThreads) {
-        uint64_t p[H];
-        for (int h = 0; h < H; ++h) p[h] = 0;
-        for (int e = C.row_ptr[row]; e < C.row_ptr[row + 1]; ++e) {
-            const uint64_t *hw = A.w.hb + (size_t)C.col_idx[e] * W + (size_t)H * g;
-            for (int h = 0; h < H; ++h) p[h] ^= hw[h];
-        }
-        for (int h = 0; h < H; ++h) acc[h] |= p[h];
-    }
-    const int w = threadIdx.x >> 6;
-    for (int h = 0; h < H; ++h) {
-        acc[h] = dev::wave_or64(acc[h]);
-        if ((threadIdx.x & 63) == 0) red[H * w + h] = acc[h];
-    }
-    __syncthreads();
-    uint64_t u = 0;
-    if (threadIdx.x < H) {
-        uint64_t x = 0;
-        for (int q = 0; q < kThreads / 64; ++q) x |= red[H * q + threadIdx.x];
-        A.w.unsat[(size_t)slot_k * W + (size_t)H * g + threadIdx.x] = x;
-    }
-    for (int i = 0; i < H * (kThreads / 64); ++i) u |= red[i];
-    __syncthreads();
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
-// Every phase of the interleaved binary decoder for the codewords of group g.
-__device__ void il_group(const JobDesc &J, int g, uint32_t *lds, uint64_t *red) {
-    using namespace dev::il;
-    const Args &A = J.il;
-    const DevCode &C = A.C;
-    constexpr int Q = kGroup / 64;  // 64-row transpose tiles per group
-    unsigned char *tile = (unsigned char *)lds;
-    const long gx_in = dev::transpose_gx(J.tin);
-    for (int qt = 0; qt < Q; ++qt)
-        for (long bx = 0; bx < gx_in; ++bx) dev::transpose_block(J.tin, bx, Q * g + qt, tile);
-    for (int s = threadIdx.x; s < (A.max_iters + 1) * kLaneCw; s += kThreads)
-        A.w.unsat[((size_t)(s / kLaneCw) * A.G + g) * kLaneCw + s % kLaneCw] = 0;
-    for (int t = threadIdx.x; t < kGroup; t += kThreads) A.w.it[g * kGroup + t] = 0;
-    __syncthreads();
-    const int ge = (int)grid_edges_x(A), gv = (int)grid_vars_x(A), gr = (int)grid_rows_x(A);
-    for (int bx = 0; bx < ge; ++bx) init_edges_block(A, bx, g);
-    for (int bx = 0; bx < gv; ++bx) init_vars_block(A, bx, g);
-    __syncthreads();
-    for (int k = 1; k <= A.max_iters; ++k) {
-        if (A.early_stop && il_syn(A, k, g, red) == 0) break;
-        if (C.dc_max <= 8)
-            for (int bx = 0; bx < gr; ++bx) cn_block<8>(A, k, bx, g);
-        else
-            for (int bx = 0; bx < gr; ++bx) cn_block<kBinDcMax>(A, k, bx, g);
-        __syncthreads();
-        for (int bx = 0; bx < gv; ++bx) vn_block(A, k, bx, g);
-        __syncthreads();
-    }
-    il_syn(A, 0, g, red);
-    for (int t = threadIdx.x; t < kGroup; t += kThreads) {
-        const int b = g * kGroup + t;
-        if (b < A.batch) {
-            A.io.ok[b] = unsat_bit(A, 0, b) ? 0 : 1;
-            A.io.iters[b] = A.w.it[b];
-        }
-    }
-    const int nbytes = (C.n + 7) >> 3;
-    for (int idx = threadIdx.x; idx < nbytes * kGroup; idx += kThreads) {
-        const int j = idx / kGroup, b = g * kGroup + idx % kGroup;
-        uint32_t byte = 0;
-        for (int q = 0; q < 8; ++q) {
-            const int v = 8 * j + q;
-            if (v < C.n) byte |= hbit(A, v, b) << q;
-        }
-        A.bytes_t[(size_t)j * A.Bp + b] = (uint8_t)byte;
-    }
-    __syncthreads();
-    const long gy_out = dev::transpose_gy(J.tout);
-    for (int qt = 0; qt < Q; ++qt)
-        for (long by = 0; by < gy_out; ++by) dev::transpose_block(J.tout, Q * g + qt, by, tile);
-}
-
-// --------------------------------------------------------- Min-Max, one group
-__device__ uint64_t nb_syn(const dev::nb::Args &A, int slot_k, int g, uint64_t *red) {
-    const DevCode &C = A.C;
-    const int lane = threadIdx.x & 63, w = dev::wave_id();
-    const int b = g * 64 + lane;
-    uint64_t acc = 0;
-    for (int row = w; row < C.m; row += 4) {
-        int s = 0;
-        for (int e = C.row_ptr[row]; e < C.row_ptr[row + 1]; ++e)
-            s ^= C.gfmul[C.h[e] * C.g + A.w.hard[(long)C.col_idx[e] * A.Bp + b]];
-        acc |= __ballot(s != 0 && b < A.batch);
-    }
-    return group_or(acc, A.w.unsat, (long)slot_k * A.Gn + g, red);
-}
-
-template <int G>
-__device__ void nb_group(const JobDesc &J, int g, uint32_t *lds, uint64_t *red) {
-    const dev::nb::Args &A = J.nb;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int b = g * 64 + lane;
-    unsigned char *tile = (unsigned char *)lds;
-    const long gx_in = dev::transpose_gx(J.tin);
-    for (long bx = 0; bx < gx_in; ++bx) dev::transpose_block(J.tin, bx, g, tile);
-    for (int s = threadIdx.x; s <= A.max_iters; s += kThreads) A.w.unsat[(long)s * A.Gn + g] = 0;
-    if (w == 0) A.w.it[b] = 0;
-    const int gi = (int)dev::nb::grid_init_x(A);
-    for (int bx = 0; bx < gi; ++bx) dev::nb::init_block<G>(A, bx, g);
-    __syncthreads();
-    const int gr = (int)dev::nb::grid_rows_x(A), gv = (int)dev::nb::grid_vn_x(A);
-    for (int k = 1; k <= A.max_iters; ++k) {
-        if (A.early_stop && nb_syn(A, k, g, red) == 0) break;
-        for (int bx = 0; bx < gr; ++bx) dev::nb::cn_block<G>(A, k, 4, bx, g, lds);
-        __syncthreads();
-        for (int bx = 0; bx < gv; ++bx) dev::nb::vn_block<G>(A, k, bx, g);
-        __syncthreads();
-    }
-    const uint64_t u = nb_syn(A, 0, g, red);
-    if (w == 0 && b < A.batch) {
-        A.io.ok[b] = ((u >> lane) & 1ull) ? 0 : 1;
-        A.io.iters[b] = A.w.it[b];
-    }
-    const long gy_out = dev::transpose_gy(J.tout);
-    for (long by = 0; by < gy_out; ++by) dev::transpose_block(J.tout, g, by, tile);
-}
-
-// IL: whether the interleaved families are compiled in (they dominate the register
-// budget, so mixes of workgroup-resident codes run a variant without them).
-template <bool IL>
-__device__ __forceinline__ void run_item(const JobDesc &J, const Item &it, uint32_t *lds, uint64_t *red) {
-    switch (it.type) {
-    case I_QC:
+__device__ __forceinline__ void run_item(const JobDesc &J, const Item &it, uint32_t *lds) {
+    if (it.type == I_QC) {
         if (J.layered) run_qc<true>(J, it.blk, lds);
         else run_qc<false>(J, it.blk, lds);
-        break;
-    case I_LDS:
-        if (J.layered)
-            dev::lds::lds_item<true>(J.C, J.R, J.max_iters, J.early_stop, J.batch, J.cpw, J.io, it.blk,
-                                     (unsigned char *)lds);
-        else
-            dev::lds::lds_item<false>(J.C, J.R, J.max_iters, J.early_stop, J.batch, J.cpw, J.io, it.blk,
-                                      (unsigned char *)lds);
-        break;
-    case I_IL:
-        if (IL) il_group(J, it.blk, lds, red);
-        break;
-    default:
-        if (!IL) break;
-        switch (J.C.g) {
-        case 4: nb_group<4>(J, it.blk, lds, red); break;
-        case 8: nb_group<8>(J, it.blk, lds, red); break;
-        case 16: nb_group<16>(J, it.blk, lds, red); break;
-        case 32: nb_group<32>(J, it.blk, lds, red); break;
-        case 64: nb_group<64>(J, it.blk, lds, red); break;
-        default: break;  // other fields never become items (rejected on the host)
-        }
+    } else if (J.layered) {
+        dev::lds::lds_item<true>(J.C, J.R, J.max_iters, J.early_stop, J.batch, J.cpw, J.io, it.blk,
+                                 (unsigned char *)lds);
+    } else {
+        dev::lds::lds_item<false>(J.C, J.R, J.max_iters, J.early_stop, J.batch, J.cpw, J.io, it.blk,
+                                  (unsigned char *)lds);
     }
 }
 
 // Workgroup w runs items [wg_ptr[w], wg_ptr[w + 1]) in order.
-template <bool IL>
 __global__ void __launch_bounds__(kThreads) k_ragged(const JobDesc *__restrict__ jobs,
                                                      const Item *__restrict__ items,
                                                      const int *__restrict__ wg_ptr) {
     extern __shared__ __align__(16) uint32_t lds[];
-    __shared__ uint64_t red[4 * dev::il::kLaneCw];
     const int i0 = wg_ptr[blockIdx.x], i1 = wg_ptr[blockIdx.x + 1];
     for (int i = i0; i < i1; ++i) {
         const Item it = items[i];
-        run_item<IL>(jobs[it.job], it, lds, red);
+        run_item(jobs[it.job], it, lds);
         __syncthreads();
     }
 }
@@ -268,12 +92,81 @@ __global__ void __launch_bounds__(kThreads) k_ragged(const JobDesc *__restrict__
 // Relative cost of one item (arbitrary units, only compared with each other).
 double item_cost(const JobDesc &J, const DevCode &C) {
     const double it = std::max(1, J.max_iters), E = C.E;
-    switch (J.family) {
-    case FAMILY_BIN_QC: return it * E * 2.0 / std::max(1, J.qc.Z);
-    case FAMILY_BIN_LDS: return it * E * J.cpw / kThreads;
-    case FAMILY_BIN_IL: return it * E * (double)dev::il::kGroup * 2.0 / kThreads;
-    default: return it * E * 3.0 * C.g * C.g / 2.0 * 64.0 / kThreads / 8.0;
+    if (J.family == FAMILY_BIN_QC) return it * E * 2.0 / std::max(1, J.qc.Z);
+    return it * E * J.cpw / kThreads;
+}
+
+// A job run outside the persistent kernel, with the schedule its plan resolved to.
+struct WideJob {
+    int job;
+    ldpcx_code *code;
+    ldpcx_decode_params params;
+};
+
+// Decode the wide jobs: one launch sequence per (code, parameters), over the jobs'
+// codewords gathered into one batch (a single job decodes in place).
+ldpcx_status run_wide(const ldpcx_job *jobs, std::vector<WideJob> &wide, hipStream_t s) {
+    std::vector<bool> done(wide.size(), false);
+    for (size_t a = 0; a < wide.size(); ++a) {
+        if (done[a]) continue;
+        std::vector<size_t> grp;
+        for (size_t b = a; b < wide.size(); ++b)
+            if (!done[b] && wide[b].code == wide[a].code &&
+                std::memcmp(&wide[b].params, &wide[a].params, sizeof(ldpcx_decode_params)) == 0) {
+                grp.push_back(b);
+                done[b] = true;
+            }
+        ldpcx_code *c = wide[a].code;
+        const ldpcx_decode_params &p = wide[a].params;
+        const size_t n = c->dev.n, g = c->g;
+        const size_t in_cw = g == 2 ? n : n * g * 2, out_cw = g == 2 ? (n + 7) / 8 : n;
+        if (grp.size() == 1) {
+            const ldpcx_job &jb = jobs[wide[a].job];
+            const DecodeIO io{jb.llr, jb.hard, jb.syndrome_ok, jb.iters, nullptr, nullptr, nullptr};
+            const ldpcx_status st = run_plan(c, &p, plan_for(c, &p, jb.batch), jb.batch, io, s, false);
+            if (st != LDPCX_OK) return st;
+            continue;
+        }
+        size_t total = 0;
+        for (size_t i : grp) total += (size_t)jobs[wide[i].job].batch;
+        if (total > (size_t)INT32_MAX) return fail(LDPCX_E_UNSUPPORTED, "too many codewords in one ragged batch");
+        const size_t o_hard = align_up(total * in_cw, 256);
+        const size_t o_ok = align_up(o_hard + total * out_cw, 256);
+        const size_t o_it = align_up(o_ok + total, 256);
+        const size_t bytes = align_up(o_it + 2 * total, 256);
+        char *buf = nullptr;
+        if (hipMallocAsync((void **)&buf, bytes, s) != hipSuccess) return fail(LDPCX_E_NOMEM, "ragged gather buffers");
+        hipError_t e = hipSuccess;
+        size_t off = 0;
+        for (size_t i : grp) {
+            const ldpcx_job &jb = jobs[wide[i].job];
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(buf + off * in_cw, jb.llr, (size_t)jb.batch * in_cw, hipMemcpyDeviceToDevice, s);
+            off += (size_t)jb.batch;
+        }
+        ldpcx_status st = LDPCX_OK;
+        if (e == hipSuccess) {
+            const DecodeIO io{buf, buf + o_hard, (uint8_t *)(buf + o_ok), (int16_t *)(buf + o_it), nullptr, nullptr,
+                              nullptr};
+            st = run_plan(c, &p, plan_for(c, &p, (int)total), (int)total, io, s, false);
+        }
+        off = 0;
+        for (size_t i : grp) {
+            const ldpcx_job &jb = jobs[wide[i].job];
+            const size_t nb = (size_t)jb.batch;
+            if (st == LDPCX_OK && e == hipSuccess)
+                e = hipMemcpyAsync(jb.hard, buf + o_hard + off * out_cw, nb * out_cw, hipMemcpyDeviceToDevice, s);
+            if (st == LDPCX_OK && e == hipSuccess)
+                e = hipMemcpyAsync(jb.syndrome_ok, buf + o_ok + off, nb, hipMemcpyDeviceToDevice, s);
+            if (st == LDPCX_OK && e == hipSuccess)
+                e = hipMemcpyAsync(jb.iters, buf + o_it + 2 * off, 2 * nb, hipMemcpyDeviceToDevice, s);
+            off += nb;
+        }
+        (void)hipFreeAsync(buf, s);
+        if (st != LDPCX_OK) return st;
+        if (e != hipSuccess) return fail_hip(e, "ragged gather copies");
     }
+    return LDPCX_OK;
 }
 
 }  // namespace
@@ -291,11 +184,12 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
         std::vector<Item> items;
         std::vector<double> cost;
         std::vector<void *> workspaces;
+        std::vector<WideJob> wide;
         auto cleanup = [&]() {
             for (void *w : workspaces) (void)hipFreeAsync(w, s);
         };
         int device = -1;
-        size_t lds = kTileBytes;
+        size_t lds = 0;
         for (int j = 0; j < njobs; ++j) {
             const ldpcx_job &jb = jobs[j];
             if (!jb.code) return cleanup(), fail(LDPCX_E_INVAL, "job without code");
@@ -303,12 +197,6 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
             ldpcx_status st = check_params(c, &jb.params);
             if (st != LDPCX_OK) return cleanup(), st;
             if (c->nb_unsupported) return cleanup(), fail(LDPCX_E_UNSUPPORTED, "no Min-Max kernel for this field size");
-            if (jb.params.rule == LDPCX_RULE_SPA)
-                return cleanup(), fail(LDPCX_E_UNSUPPORTED, "the FFT-SPA decoder has no workgroup-local item; decode "
-                                                            "it with ldpcx_decode");
-            if (c->g > 64)
-                return cleanup(), fail(LDPCX_E_UNSUPPORTED, "fields above GF(64) have no workgroup-local item; decode them "
-                                                            "with ldpcx_decode");
             if (device < 0) {
                 if ((st = check_device(c)) != LDPCX_OK) return cleanup(), st;
                 device = c->device;
@@ -331,8 +219,6 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
             D.batch = jb.batch;
             D.io = DecodeIO{jb.llr, jb.hard, jb.syndrome_ok, jb.iters, nullptr, nullptr, nullptr};
             D.layered = pl.schedule == LDPCX_SCHED_LAYERED;
-            if (pl.family == FAMILY_NB && D.layered)
-                return cleanup(), fail(LDPCX_E_UNSUPPORTED, "layered Min-Max runs through ldpcx_decode only");
             auto add = [&](int type, long count) {
                 for (long i = 0; i < count; ++i) items.push_back(Item{type, j, (int)i, 0});
                 const double cst = item_cost(D, D.C);
@@ -371,43 +257,20 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
                 add(I_LDS, (jb.batch + cpw - 1) / cpw);
                 continue;
             }
-            // Interleaved families: a workspace per job, one item per group of 64 codewords.
-            D.family = pl.family;
-            if ((pl.family == FAMILY_BIN_IL && jb.batch > dev::il::max_sub_batch(D.C)) ||
-                (pl.family == FAMILY_NB && jb.batch > nb_slice(D.C, jb.batch + 64)))
-                return cleanup(), fail(LDPCX_E_UNSUPPORTED, "batch too large for one interleaved workspace");
-            const size_t bytes = pl.family == FAMILY_BIN_IL ? dev::il::carve(D.C, p.max_iters, jb.batch).total
-                                                            : nb_work_bytes(D.C, p.max_iters, jb.batch);
-            void *ws = nullptr;
-            if (hipMallocAsync(&ws, bytes, s) != hipSuccess) return cleanup(), fail(LDPCX_E_NOMEM, "workspace");
-            workspaces.push_back(ws);
-            if (pl.family == FAMILY_BIN_IL) {
-                D.il = dev::il::make_args(D.C, D.R, p.max_iters, p.early_stop, jb.batch, ws, D.io);
-                D.tin = dev::il::tr_in(D.il);
-                D.tout = dev::il::tr_out(D.il);
-                add(I_IL, D.il.G);
-            } else {
-                const long groups = pad64(jb.batch) / 64;
-                D.nb = dev::nb::make_args(D.C, p.max_iters, p.early_stop, jb.batch, nb_amax(&p), ws, D.io);
-                const size_t need = dev::nb::cn_lds_bytes(D.nb, 4);
-                if (need > cap)
-                    return cleanup(), fail(LDPCX_E_UNSUPPORTED, "check degree too large for the persistent engine");
-                lds = std::max(lds, need);
-                D.tin = dev::nb::tr_in(D.nb);
-                D.tout = dev::nb::tr_out(D.nb);
-                add(I_NB, groups);
-            }
+            // The whole-device families: decoded after the persistent kernel, with the
+            // schedule resolved as for this job alone.
+            WideJob wj{j, c, p};
+            wj.params.schedule = pl.schedule;
+            wide.push_back(wj);
         }
-        if (items.empty()) return cleanup(), LDPCX_OK;
+        if (items.empty()) return cleanup(), run_wide(jobs, wide, s);
         if (lds > (size_t)device_info(device).lds_per_block - kStaticLds)
             return cleanup(), fail(LDPCX_E_UNSUPPORTED, "job mix needs more LDS than one workgroup has");
 
         // Errors of the calls above were checked where they happened; clear the sticky
         // last-error state so that the launch check below reports the launch only.
         (void)hipGetLastError();
-        bool any_il = false;
-        for (const Item &it : items) any_il |= it.type == I_IL || it.type == I_NB;
-        const void *kern = any_il ? (const void *)k_ragged<true> : (const void *)k_ragged<false>;
+        const void *kern = (const void *)k_ragged;
         if (lds > 64 * 1024) {
             hipError_t ea = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (ea != hipSuccess) return cleanup(), fail_hip(ea, "persistent kernel LDS attribute");
@@ -457,8 +320,7 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
         const JobDesc *djobs = (const JobDesc *)dbuf;
         const Item *ditems = (const Item *)(dbuf + o_items);
         const int *dptr = (const int *)(dbuf + o_ptr);
-        if (any_il) hipLaunchKernelGGL(k_ragged<true>, dim3(grid), dim3(kThreads), lds, s, djobs, ditems, dptr);
-        else hipLaunchKernelGGL(k_ragged<false>, dim3(grid), dim3(kThreads), lds, s, djobs, ditems, dptr);
+        hipLaunchKernelGGL(k_ragged, dim3(grid), dim3(kThreads), lds, s, djobs, ditems, dptr);
         e = hipGetLastError();
         cleanup();
         if (e != hipSuccess) {
@@ -466,7 +328,7 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
             snprintf(msg, sizeof msg, "persistent kernel launch (grid %d, %zu bytes of LDS)", grid, lds);
             return fail_hip(e, msg);
         }
-        return LDPCX_OK;
+        return run_wide(jobs, wide, s);
     } catch (const std::exception &ex) {
         return fail(LDPCX_E_NOMEM, ex.what());
     }

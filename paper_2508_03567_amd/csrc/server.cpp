@@ -92,6 +92,8 @@ size_t chunk_bytes(const Request &r, int ncw) {
     if (r.family == FAMILY_BIN_IL) b += bin_il_work_bytes(r.code->dev, r.prm.max_iters, ncw, 0);
     else if (r.family == FAMILY_NB) b += nb_work_bytes(r.code->dev, r.prm.max_iters, ncw);
     else if (r.family == FAMILY_SPA) b += spa_work_bytes(r.code->dev, r.prm.max_iters, ncw);
+    // a chunk of a whole-device family inside a ragged batch is decoded from a gathered copy
+    if (r.family != FAMILY_BIN_QC && r.family != FAMILY_BIN_LDS) b += io_bytes(r, ncw);
     return b;
 }
 

@@ -354,13 +354,18 @@ def test_minmax_large_fields(g_size, n, dc, batch, early):
     _check_decisions(code, g2, ref)
 
 
-def test_ragged_rejects_large_fields():
+def test_ragged_takes_large_fields():
+    """GF(128) jobs in a ragged batch run as their own launch sequence, gathered per
+    (code, parameters), and give what a plain decode gives."""
     code = S.random_regular_nb_code(16, 8, 2, 4, 128, S.PRIM_POLY[128], seed=1)
-    gam = S.nb_gamma_int16(S.random_codewords(code, 2, seed=1), 128, 1.0, seed=1)
+    gam = torch.from_numpy(S.nb_gamma_int16(S.random_codewords(code, 9, seed=1), 128, 1.0, seed=1)).to(DEV)
     h = L.Code(code)
-    with pytest.raises(L.LdpcxError) as ei:
-        L.decode_ragged([(h, L.params("minmax"), torch.from_numpy(gam).to(DEV))])
-    assert ei.value.status == L.E_UNSUPPORTED
+    prm = L.params("minmax", max_iters=4)
+    outs = L.decode_ragged([(h, prm, gam[:2]), (h, prm, gam[2:9])])
+    ref = L.decode(h, prm, gam)
+    for o, sl in zip(outs, [slice(0, 2), slice(2, 9)]):
+        for a, b in zip(o, ref[:3]):
+            assert torch.equal(a, b[sl])
 
 
 @pytest.mark.parametrize("g_size,bound", [(64, 127), (16, 50), (128, 127), (256, 90)])
@@ -449,7 +454,7 @@ def test_minmax_auto_schedule_is_tuned_and_reported():
         assert (hard.cpu().numpy() == ref["hard"]).all() and (it.cpu().numpy() == ref["iters"]).all()
 
 
-def test_minmax_layered_rejections():
+def test_minmax_layered_rejections_and_ragged():
     c128 = S.random_regular_nb_code(16, 8, 2, 4, 128, S.PRIM_POLY[128], seed=1)
     with pytest.raises(L.LdpcxError) as ei:
         L.decode(L.Code(c128), L.params("minmax", "layered", 2), torch.zeros((2, 16, 128), dtype=torch.int16, device=DEV))
@@ -461,9 +466,14 @@ def test_minmax_layered_rejections():
         with pytest.raises(L.LdpcxError) as ei:
             L.decode(h64, prm, g64)
         assert ei.value.status == L.E_UNSUPPORTED
-    with pytest.raises(L.LdpcxError) as ei:
-        L.decode_ragged([(h64, L.params("minmax", "layered", 2), g64)])
-    assert ei.value.status == L.E_UNSUPPORTED
+    # ragged batches run layered Min-Max jobs as their own launch sequences
+    x = torch.from_numpy(S.nb_gamma_int16(S.random_codewords(c64, 7, seed=4), 64, 1.5, seed=5)).to(DEV)
+    prm = L.params("minmax", "layered", 4)
+    outs = L.decode_ragged([(h64, prm, x[:3]), (h64, prm, x[3:])])
+    ref = L.decode(h64, prm, x)
+    for o, sl in zip(outs, [slice(0, 3), slice(3, 7)]):
+        for a, b in zip(o, ref[:3]):
+            assert torch.equal(a, b[sl])
 
 
 @pytest.mark.parametrize("g_size,n,dc,batch,early,iters", [
@@ -493,9 +503,11 @@ def test_spa_rejections():
     with pytest.raises(L.LdpcxError) as ei:
         L.decode(h, L.params("spa", max_iters=2), gam)
     assert ei.value.status == L.E_UNSUPPORTED
+    # in a ragged batch the FFT-SPA runs as its own launch sequence
     c64 = S.random_regular_nb_code(16, 8, 2, 4, 64, S.PRIM_POLY[64], seed=1)
     h64 = L.Code(c64)
-    g64 = torch.zeros((2, 16, 64), dtype=torch.int16, device=DEV)
-    with pytest.raises(L.LdpcxError) as ei:
-        L.decode_ragged([(h64, L.params("spa", max_iters=2), g64)])
-    assert ei.value.status == L.E_UNSUPPORTED
+    g64 = torch.from_numpy(S.nb_gamma_int16(S.random_codewords(c64, 5, seed=2), 64, 1.5, seed=3)).to(DEV)
+    prm = L.params("spa", max_iters=3)
+    (hard, ok, it), = L.decode_ragged([(h64, prm, g64)])
+    ref = L.decode(h64, prm, g64)
+    assert torch.equal(hard, ref[0]) and torch.equal(ok, ref[1]) and torch.equal(it, ref[2])

@@ -123,3 +123,21 @@ def test_graph_replays_match_eager(cfg):
         assert float(y.abs().sum()) > 0
         assert (_np(out[0]) == _np(eager[0])).all()
         assert (_np(out[1]) == ref["ok"]).all() and (_np(out[2]) == ref["iters"]).all()
+
+
+def test_ragged_gathers_whole_device_jobs():
+    """Long-code, Min-Max (flooding, layered, AUTO, 8-bit bound) and FFT-SPA jobs next to
+    short binary jobs: the whole-device jobs are gathered per (code, parameters) into one
+    launch sequence each, and every job gets what a decode of it alone gives."""
+    specs = [(3, 20, {}), (0, 50, {}), (3, 70, {}), (3, 5, dict(schedule="layered")), (2, 3, dict(max_iters=6)),
+             (3, 9, dict(schedule="layered")), (1, 40, {}), (3, 12, dict(nb_msg_max=127)), (2, 2, dict(max_iters=6)),
+             (3, 33, dict(schedule="auto")), (3, 4, dict(rule="spa", max_iters=5))]
+    items = []
+    for i, (cfg, batch, kw) in enumerate(specs):
+        w, d, llr = _mk(cfg, batch, 400 + i, max_iters=kw.pop("max_iters", 8), **kw)
+        items.append((_code(cfg), L.params(**d), torch.from_numpy(np.ascontiguousarray(llr)).to(DEV)))
+    outs = L.decode_ragged(items)
+    torch.cuda.synchronize()
+    for (h, prm, x), (hard, ok, it) in zip(items, outs):
+        ref = L.decode(h, prm, x)
+        assert torch.equal(hard, ref[0]) and torch.equal(ok, ref[1]) and torch.equal(it, ref[2])
