@@ -19,12 +19,8 @@ __device__ __forceinline__ uint32_t &lds_word(uint32_t *base, uint32_t off) {
     return *(uint32_t *)((char *)base + off);
 }
 
-// (M & a) | (~M & b) in one v_bfi_b32.
-__device__ __forceinline__ uint32_t bfi(uint32_t M, uint32_t a, uint32_t b) {
-    uint32_t d;
-    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(d) : "v"(M), "v"(a), "v"(b));
-    return d;
-}
+// (M & a) | (~M & b) (one v_bfi_b32).
+__device__ __forceinline__ uint32_t bfi(uint32_t M, uint32_t a, uint32_t b) { return (M & a) | (~M & b); }
 
 // Dummy slot contents for virtual edges: +16383 in both halves.  Minus any check
 // message (|r| <= 127) it stays positive and above msg_max, so a virtual edge
@@ -35,8 +31,9 @@ constexpr uint32_t kDummy = 0x3FFF3FFFu;
 
 // Decode codewords [2 npairs blk, 2 npairs (blk + 1)) with the calling workgroup.
 // Threads beyond Z * npairs take part in the barriers only.  Ends with a barrier,
-// so the caller may reuse the LDS right after.
-template <int ML, int MD, bool LAYERED>
+// so the caller may reuse the LDS right after.  ES = false compiles the early-stop
+// logic out (only valid with early_stop == 0).
+template <int ML, int MD, bool LAYERED, bool ES = true>
 __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const BinRule &R, int max_iters, int early_stop, int batch,
                         int npairs, const DecodeIO &io, int blk, uint32_t *lds) {
     const int n = C.n, E = C.E, Z = Q.Z, nl = Q.nl;
@@ -48,7 +45,10 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
     const int cw0 = blk * npairs * 2;
     if (cw0 >= batch) return;
     int2 *sdesc = (int2 *)lds;                     // [ML][MD] layer descriptors
-    uint32_t *lam = lds + 2 * ML * MD;             // [npairs][ld] packed Lambda
+    // [ML][Z] rows of 8 16-bit byte offsets of the rows' Lambda words (one 16-byte LDS
+    // read per row and layer instead of the index arithmetic of every edge)
+    uint16_t *offs = (uint16_t *)(lds + 2 * ML * MD);
+    uint32_t *lam = lds + 2 * ML * MD + 4 * ML * Z;  // [npairs][ld] packed Lambda
     uint32_t *Lch = lam + (size_t)npairs * ld;     // [npairs][ld] packed channel LLRs (flooding)
     int *unsat = (int *)(lam + (size_t)(LAYERED ? 1 : 2) * npairs * ld);
     int *done = unsat + npairs;
@@ -60,6 +60,13 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
         const int l = idx / MD, j = idx - l * MD;
         const int2 e = (l < nl && j < Q.dc[l]) ? Q.edges[l * kQcMaxDc + j] : make_int2(n, 0);
         sdesc[idx] = make_int2(4 * e.x, 4 * e.y);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < ML * Z; idx += T) {
+        const int l = idx / Z, i = idx - l * Z;
+        uint16_t *o = offs + 8 * idx;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) o[j] = j < MD ? (uint16_t)qc_off(sdesc[l * MD + j], 4 * i, Z4) : (uint16_t)0;
     }
     const int8_t *llr = (const int8_t *)io.llr;
     for (int idx = tid; idx < npairs * ld; idx += T) {
@@ -89,6 +96,13 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
         for (int j = 0; j < MD; ++j) r[l][j] = splat(0);
 
     uint32_t *lamp = lam + (size_t)p * ld;
+    // byte offsets of this thread's row in layer l
+    auto row_offs = [&](int l, uint32_t (&vv)[MD]) {
+        const uint4 w = *(const uint4 *)(offs + 8 * (l * Z + i0));
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int j = 0; j < MD; ++j) vv[j] = (j & 1) ? ws[j >> 1] >> 16 : ws[j >> 1] & 0xFFFFu;
+    };
 
     // Parity of the current hard decisions of this thread's rows, as a 2-bit mask
     // (one bit per codeword); virtual edges read a dummy slot whose sign bits are 0.
@@ -98,12 +112,11 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
 #pragma unroll
         for (int l = 0; l < ML; ++l) {
             if (l < nl) {
-                uint32_t i4 = 4 * i0;
-                asm volatile("" : "+v"(i4));
-                const int2 *wl = sdesc + l * MD;
+                uint32_t vv[MD];
+                row_offs(l, vv);
                 uint32_t x = 0;
 #pragma unroll
-                for (int j = 0; j < MD; ++j) x ^= lds_word(lamp, qc_off(wl[j], i4, Z4));
+                for (int j = 0; j < MD; ++j) x ^= lds_word(lamp, vv[j]);
                 any |= (int)((x >> 15) & 1u) | (int)((x >> 30) & 2u);
             }
         }
@@ -112,7 +125,7 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
 
     uint32_t M = 0xFFFFFFFFu;  // halves (codewords) still being decoded
     for (int k = 1; k <= max_iters; ++k) {
-        if (early_stop) {
+        if (ES && early_stop) {
             const int any = row_parities();
             if (any) atomicOr(&unsat[p], any);
             __syncthreads();
@@ -131,16 +144,11 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
         for (int l = 0; l < ML; ++l) {
             if (l < nl) {
               if (act) {
-                // Column indices are recomputed every layer rather than kept live.
-                uint32_t i4 = 4 * i0;
-                asm volatile("" : "+v"(i4));
                 int dc = __builtin_amdgcn_readfirstlane(Q.dc[l]);  // uniform by construction
                 asm volatile("" : "+s"(dc));
-                const int2 *wl = sdesc + l * MD;
                 uint32_t vv[MD];
                 v2s lv[MD];
-#pragma unroll
-                for (int j = 0; j < MD; ++j) vv[j] = qc_off(wl[j], i4, Z4);
+                row_offs(l, vv);
 #pragma unroll
                 for (int j = 0; j < MD; ++j) lv[j] = as_v2s(lds_word(lamp, vv[j]));
                 v2s m1 = splat(0x7FFF), m2 = splat(0x7FFF);
@@ -168,7 +176,7 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
                     const v2s mag = f2 + t * df;
                     const uint32_t sr = stot ^ sv[j];
                     const v2s rn = as_v2s(as_u32(mag) ^ sr) - as_v2s(sr);
-                    const v2s rk = as_v2s(bfi(M, as_u32(rn), as_u32(r[l][j])));
+                    const v2s rk = ES ? as_v2s(bfi(M, as_u32(rn), as_u32(r[l][j]))) : rn;
                     r[l][j] = rk;
                     if (LAYERED) lds_word(lamp, vv[j]) = as_u32(qv[j] + rk);
                 }
@@ -185,14 +193,13 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
 #pragma unroll
             for (int l = 0; l < ML; ++l) {
                 if (l < nl) {
-                    uint32_t i4 = 4 * i0;
-                    asm volatile("" : "+v"(i4));
                     const int dc = Q.dc[l];
-                    const int2 *wl = sdesc + l * MD;
+                    uint32_t vv[MD];
+                    row_offs(l, vv);
 #pragma unroll
                     for (int j = 0; j < MD; ++j) {
                         if (act && j < dc) {
-                            uint32_t &w = lds_word(lamp, qc_off(wl[j], i4, Z4));
+                            uint32_t &w = lds_word(lamp, vv[j]);
                             w = as_u32(as_v2s(w) + r[l][j]);
                         }
                     }
@@ -278,7 +285,8 @@ inline void qc_shape_of(const QcDesc &Q, int &ml, int &md) {
 }
 
 inline size_t qc_smem_bytes(int ML, int MD, const DevCode &C, int Z, int layered, int npairs) {
-    return sizeof(int2) * ML * MD + (size_t)(layered ? 1 : 2) * npairs * (C.n + Z) * 4 + (size_t)npairs * 16;
+    return sizeof(int2) * ML * MD + (size_t)ML * Z * 16 + (size_t)(layered ? 1 : 2) * npairs * (C.n + Z) * 4 +
+           (size_t)npairs * 16;
 }
 
 }  // namespace dev

@@ -31,28 +31,36 @@ namespace {
 
 using namespace dev;
 
-template <int ML, int MD, bool LAYERED>
+// ES: early termination compiled in (the fixed-iteration variant drops its merges).
+template <int ML, int MD, bool LAYERED, bool ES>
 __global__ void __launch_bounds__(512) k_bin_qc(QcDesc Q, DevCode C, BinRule R, int max_iters, int early_stop,
                                                 int batch, int npairs, DecodeIO io) {
     extern __shared__ __align__(16) uint32_t lds[];
-    qc_item<ML, MD, LAYERED>(Q, C, R, max_iters, early_stop, batch, npairs, io, blockIdx.x, lds);
+    qc_item<ML, MD, LAYERED, ES>(Q, C, R, max_iters, early_stop, batch, npairs, io, blockIdx.x, lds);
 }
 
-template <int ML, int MD, bool LAYERED>
-hipError_t launch_shape(const QcDesc &Q, const DevCode &C, const BinRule &R, int max_iters, int early_stop,
-                        int batch, int npairs, const DecodeIO &io, hipStream_t s) {
+template <int ML, int MD, bool LAYERED, bool ES>
+hipError_t launch_es(const QcDesc &Q, const DevCode &C, const BinRule &R, int max_iters, int early_stop, int batch,
+                     int npairs, const DecodeIO &io, hipStream_t s) {
     const size_t smem = qc_smem_bytes(ML, MD, C, Q.Z, LAYERED, npairs);
     const int pairs = (batch + 1) / 2;
     const int grid = (pairs + npairs - 1) / npairs;
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void *)k_bin_qc<ML, MD, LAYERED>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024);
+        (void)hipFuncSetAttribute((const void *)k_bin_qc<ML, MD, LAYERED, ES>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
-    hipLaunchKernelGGL((k_bin_qc<ML, MD, LAYERED>), dim3(grid), dim3(Q.Z * npairs), smem, s, Q, C, R, max_iters,
+    hipLaunchKernelGGL((k_bin_qc<ML, MD, LAYERED, ES>), dim3(grid), dim3(Q.Z * npairs), smem, s, Q, C, R, max_iters,
                        early_stop, batch, npairs, io);
     return hipGetLastError();
+}
+
+template <int ML, int MD, bool LAYERED>
+hipError_t launch_shape(const QcDesc &Q, const DevCode &C, const BinRule &R, int max_iters, int early_stop,
+                        int batch, int npairs, const DecodeIO &io, hipStream_t s) {
+    return early_stop ? launch_es<ML, MD, LAYERED, true>(Q, C, R, max_iters, early_stop, batch, npairs, io, s)
+                      : launch_es<ML, MD, LAYERED, false>(Q, C, R, max_iters, early_stop, batch, npairs, io, s);
 }
 
 template <bool LAYERED>

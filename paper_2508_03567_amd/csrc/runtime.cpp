@@ -520,7 +520,8 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
             }
             c->layers_ok = ok;
             // Quasi-cyclic structure: every layer of z rows made of z x z circulant blocks.
-            if (ok && d->z > 0 && n % d->z == 0 && m / d->z <= kQcMaxL) {
+            // (Lambda offsets of the packed decoder are 16-bit: 4 (n + z) < 65536)
+            if (ok && d->z > 0 && n % d->z == 0 && m / d->z <= kQcMaxL && 4L * (n + d->z) < 65536) {
                 const int Z = d->z, nl = m / Z;
                 bool qc = true;
                 c->qc.Z = Z;
