@@ -97,6 +97,7 @@ def main() -> None:
     ap.add_argument("--plan", type=str, default=None,
                     help="pin the launch plan instead of tuning: family[:cw_per_wg[:threads]], e.g. bin_interleaved:256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-e2e", action="store_true", help="skip the end-to-end (PCIe-inclusive) leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle time")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one 256 MiB device-to-device copy (counter calibration)")
@@ -198,10 +199,11 @@ def main() -> None:
 
     # End to end, PCIe included: pinned host LLRs in, decisions, flags and iteration
     # counts back to pinned host memory, on the same stream.
+    e2e = None
+    e2e_steps = 0 if args.no_e2e else max(1, min(args.steps, 5))
     llr_host = torch.from_numpy(llr_np).pin_memory()
     host_out = [torch.empty(o.shape, dtype=o.dtype, pin_memory=True) for o in out]
     llr_dev = torch.empty_like(llr)
-    e2e_steps = max(1, min(args.steps, 5))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(e2e_steps):
@@ -210,10 +212,11 @@ def main() -> None:
         for ho, o in zip(host_out, out):
             ho.copy_(o, non_blocking=True)
     torch.cuda.synchronize()
-    e2e_ms = (time.perf_counter() - t1) * 1e3 / e2e_steps
-    e2e = {"info_gbit_s": round(w.info_bits_per_cw * w.batch / (e2e_ms * 1e-3) / 1e9, 4),
-           "ms_per_batch": round(e2e_ms, 4), "steps": e2e_steps,
-           "what": "pinned host LLRs -> device, decode, outputs -> pinned host"}
+    if e2e_steps:
+        e2e_ms = (time.perf_counter() - t1) * 1e3 / e2e_steps
+        e2e = {"info_gbit_s": round(w.info_bits_per_cw * w.batch / (e2e_ms * 1e-3) / 1e9, 4),
+               "ms_per_batch": round(e2e_ms, 4), "steps": e2e_steps,
+               "what": "pinned host LLRs -> device, decode, outputs -> pinned host"}
 
     if args.calib_copy:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.int32, device=dev)
