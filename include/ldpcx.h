@@ -217,8 +217,9 @@ ldpcx_status ldpcx_plan_info(const ldpcx_code *code, const ldpcx_decode_params *
  * family 0 (threads a multiple of 64 in [64, 1024]); cw_per_wg by family 3 (even, the
  * pairs' rows at most 512 threads) and by family 1 (slice size, rounded up to a multiple
  * of 128 and capped by the batch and the 31-bit offset limit).  The pinned plan must be able to
- * run the requested schedule (LDPCX_E_UNSUPPORTED otherwise; family 1 and 2 are
- * flooding only).  Results never depend on the plan. */
+ * run the requested schedule (LDPCX_E_UNSUPPORTED otherwise; families 1 and 4 are
+ * flooding only, family 2 runs the layered schedule up to GF(64)).  Results never
+ * depend on the plan. */
 ldpcx_status ldpcx_plan_set(ldpcx_code *code, const ldpcx_decode_params *params, int32_t batch,
                             int32_t family, int32_t cw_per_wg, int32_t threads);
 
@@ -233,11 +234,12 @@ typedef struct ldpcx_server ldpcx_server;
  *   CONTINUOUS: whenever one of the `max_inflight` launch slots is free and requests
  *     wait, the scheduler admits waiting codewords in arrival order while the free
  *     budget allows (a request that only partly fits is split at a codeword boundary)
- *     and launches them on the slot's stream: consecutive chunks of codes whose decoder
- *     state fits one workgroup as ONE ragged persistent launch (ldpcx_decode_ragged),
- *     capped at about 1.5 ms of estimated device time; a chunk of a long code
- *     (interleaved decoder) or of more than 64 Min-Max codewords as a launch of its
- *     own (the plain decoder's launch sequence, parallel over checks).  Requests
+ *     and launches them on the slot's stream: consecutive chunks of short codes as ONE
+ *     ragged batch (ldpcx_decode_ragged: workgroup-local codes in its persistent
+ *     kernel, small flooding Min-Max chunks gathered per code), capped at about 1.5 ms
+ *     of estimated device time; a chunk of a long code (interleaved decoder), of
+ *     FFT-SPA, of layered Min-Max or of more than 64 Min-Max codewords as a launch of
+ *     its own (the plain decoder's launch sequence, parallel over checks).  Requests
  *     that arrive while launches are in flight are admitted into the next free slot
  *     without waiting for those launches to end, so their work overlaps on the device.
  *   PER_REQUEST: the one-code-per-launch baseline: one request (or budget-sized
