@@ -35,6 +35,7 @@ FAMILY_SOURCES = {
     "bin_lds": ["k_bin_lds.hip", "dev_bin_lds.h", "dev_common.h"],
     "bin_interleaved": ["k_bin_il.hip", "dev_bin_il.h", "dev_common.h"],
     "minmax_interleaved": ["k_nb.hip", "dev_nb.h", "dev_common.h"],
+    "minmax_lds": ["k_nb.hip", "dev_nb.h", "dev_common.h"],
 }
 
 
@@ -330,6 +331,9 @@ def sweep_main(args) -> None:
             gam = torch.from_numpy(S.nb_gamma_int16(cw, g, 2.0, seed=8)).to(dev)
             h = L.Code(code)
             prm = L.params(rule, "flooding", iters, early_stop=False)
+            if not args.no_tune:
+                L.tune(h, prm, batch)
+            plan = L.plan_info(h, prm, batch)
             out = L._outputs(h, batch, dev)
             for _ in range(max(1, args.warmup)):
                 L.decode(h, prm, gam, out=out)
@@ -346,7 +350,8 @@ def sweep_main(args) -> None:
             p = g.bit_length() - 1
             info = (n // 2) * p * batch / (ms * 1e-3) / 1e9
             fer = float((out[0].cpu().numpy() != cw).any(axis=1).mean())
-            print(json.dumps({"metric": f"{rule} GF-size sweep: decoded info Gbit/s at fixed iters", "n_symbols": n,
+            print(json.dumps({"metric": f"{rule} GF-size sweep: decoded info Gbit/s at fixed iters", "plan": plan,
+                              "n_symbols": n,
                               "field": g, "iterations": iters, "batch": batch, "ms_per_batch": round(ms, 4),
                               "info_gbit_s": round(info, 5), "coded_gbit_s": round(2 * info, 5),
                               "ebn0_db": 2.0, "fer": fer, "data": "synthetic seeded BPSK/AWGN"}), flush=True)

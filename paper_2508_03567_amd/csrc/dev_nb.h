@@ -55,38 +55,72 @@ __device__ __forceinline__ uint32_t mrow_at(const uint32_t *mw, int t) {
     return (__builtin_amdgcn_readfirstlane(mw[t >> 2]) >> (8 * (t & 3))) & 0xFFu;
 }
 
-// a~(t) = msg(hinv * t) for one edge, loaded straight from [edge][x][Bp] memory: every
-// load is a buffer load whose scalar offset carries (edge, x), the lane offset b.
-template <int G>
-__device__ __forceinline__ void load_perm(__amdgpu_buffer_rsrc_t rs, uint32_t Bp2, int e, const uint8_t *mrow,
-                                          uint32_t lane_off, v2s (&A)[G / 2]) {
-    const uint32_t *mw = (const uint32_t *)mrow;
-    const uint32_t base = __builtin_amdgcn_readfirstlane((uint32_t)e * G * Bp2);
-#pragma unroll
-    for (int t = 0; t < G; t += 2) {
-        const uint32_t x0 = mrow_at(mw, t), x1 = mrow_at(mw, t + 1);
-        const uint32_t lo = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)lane_off, (int)(base + x0 * Bp2), 0);
-        const uint32_t hi = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)lane_off, (int)(base + x1 * Bp2), 0);
-        A[t >> 1] = as_v2s(lo | (hi << 16));
-    }
-}
+// Message arrays in the interleaved layout in HBM, [edge][x][Bp] int16.  Every access is
+// a buffer load or store whose scalar offset carries (edge, x) and whose lane offset is
+// the codeword.
+struct HbmMsg {
+    __amdgpu_buffer_rsrc_t rs;
+    uint32_t Bp2;       // bytes between entries of one edge
+    uint32_t lane_off;  // 2 b
 
-// msg(x) = v~(h x) stored for one edge: entry t goes to x = hinv * t.
-template <int G>
-__device__ __forceinline__ void store_deperm(__amdgpu_buffer_rsrc_t rs, uint32_t Bp2, int e, const uint8_t *mrow,
-                                             uint32_t lane_off, const v2s (&V)[G / 2], bool act) {
-    if (!act) return;
-    const uint32_t *mw = (const uint32_t *)mrow;
-    const uint32_t base = __builtin_amdgcn_readfirstlane((uint32_t)e * G * Bp2);
+    // a~(t) = msg(hinv * t) for one edge (mrow: the multiplication-table row of hinv).
+    template <int G>
+    __device__ __forceinline__ void load_perm(int e, const uint8_t *mrow, v2s (&A)[G / 2]) const {
+        const uint32_t *mw = (const uint32_t *)mrow;
+        const uint32_t base = __builtin_amdgcn_readfirstlane((uint32_t)e * G * Bp2);
 #pragma unroll
-    for (int t = 0; t < G; t += 2) {
-        const uint32_t w = as_u32(V[t >> 1]);
-        const uint32_t s0 = base + mrow_at(mw, t) * Bp2;
-        const uint32_t s1 = base + mrow_at(mw, t + 1) * Bp2;
-        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(w & 0xFFFFu), rs, (int)lane_off, (int)s0, 0);
-        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(w >> 16), rs, (int)lane_off, (int)s1, 0);
+        for (int t = 0; t < G; t += 2) {
+            const uint32_t x0 = mrow_at(mw, t), x1 = mrow_at(mw, t + 1);
+            const uint32_t lo = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)lane_off, (int)(base + x0 * Bp2), 0);
+            const uint32_t hi = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)lane_off, (int)(base + x1 * Bp2), 0);
+            A[t >> 1] = as_v2s(lo | (hi << 16));
+        }
     }
-}
+    // msg(x) = v~(h x) stored for one edge: entry t goes to x = hinv * t.
+    template <int G>
+    __device__ __forceinline__ void store_deperm(int e, const uint8_t *mrow, const v2s (&V)[G / 2], bool act) const {
+        if (!act) return;
+        const uint32_t *mw = (const uint32_t *)mrow;
+        const uint32_t base = __builtin_amdgcn_readfirstlane((uint32_t)e * G * Bp2);
+#pragma unroll
+        for (int t = 0; t < G; t += 2) {
+            const uint32_t w = as_u32(V[t >> 1]);
+            const uint32_t s0 = base + mrow_at(mw, t) * Bp2;
+            const uint32_t s1 = base + mrow_at(mw, t + 1) * Bp2;
+            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(w & 0xFFFFu), rs, (int)lane_off, (int)s0, 0);
+            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(w >> 16), rs, (int)lane_off, (int)s1, 0);
+        }
+    }
+};
+
+// Message arrays of one group of 64 codewords resident in LDS, [edge][x][64] int16.
+struct LdsMsg {
+    uint16_t *p;
+    int lane;
+
+    template <int G>
+    __device__ __forceinline__ void load_perm(int e, const uint8_t *mrow, v2s (&A)[G / 2]) const {
+        const uint32_t *mw = (const uint32_t *)mrow;
+        const uint16_t *q = p + (size_t)e * G * 64 + lane;
+#pragma unroll
+        for (int t = 0; t < G; t += 2) {
+            const uint32_t lo = q[mrow_at(mw, t) * 64], hi = q[mrow_at(mw, t + 1) * 64];
+            A[t >> 1] = as_v2s(lo | (hi << 16));
+        }
+    }
+    template <int G>
+    __device__ __forceinline__ void store_deperm(int e, const uint8_t *mrow, const v2s (&V)[G / 2], bool act) const {
+        if (!act) return;
+        const uint32_t *mw = (const uint32_t *)mrow;
+        uint16_t *q = p + (size_t)e * G * 64 + lane;
+#pragma unroll
+        for (int t = 0; t < G; t += 2) {
+            const uint32_t w = as_u32(V[t >> 1]);
+            q[mrow_at(mw, t) * 64] = (uint16_t)(w & 0xFFFFu);
+            q[mrow_at(mw, t + 1) * 64] = (uint16_t)(w >> 16);
+        }
+    }
+};
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t msg_rsrc(const int16_t *p, const Args &A);
 
@@ -117,51 +151,46 @@ __device__ __forceinline__ bool active(const Args &A, int k, int g, int lane) {
     return b < A.batch && (!A.early_stop || ((A.w.unsat[(size_t)k * A.Gn + g] >> lane) & 1ull));
 }
 
-// Check node of `row` (eqs. (7)-(13)) for the 64 codewords of group g, run by wave w of
-// the block; only lanes with `act` store.
-template <int G>
-__device__ __forceinline__ void cn_row(const Args &A, int row, int w, int g, bool act, uint32_t *lds) {
+// Check node of `row` (eqs. (7)-(13)) for the 64 codewords of one group: alpha read and
+// beta written through the message accessors; fs: this wave's forward-vector slots in
+// LDS; only lanes with `act` store.
+// mul, hinv: the multiplication table and the inverse coefficients (HBM or LDS copies).
+template <int G, class M>
+__device__ __forceinline__ void cn_core(const DevCode &C, const uint8_t *mul, const uint8_t *hinv, const M &alpha,
+                                        const M &beta, int row, bool act, uint32_t *fs) {
     constexpr int H = G / 2;
-    const DevCode &C = A.C;
     const int lane = threadIdx.x & 63;
-    const int b = g * 64 + lane;
-    const uint32_t Bp2 = 2u * (uint32_t)A.Bp;  // bytes between entries of one edge
-    const uint32_t lo = 2u * (uint32_t)b;
-    const auto alpha = msg_rsrc(A.w.alpha, A);
-    const auto beta = msg_rsrc(A.w.beta, A);
-    uint32_t *fs = lds + (size_t)w * A.fslots * H * 64;
     const int e0 = C.row_ptr[row];
     const int dc = C.row_ptr[row + 1] - e0;
-    const uint8_t *mul = C.gfmul;
     v2s X[H], Y[H], R[H];
-    load_perm<G>(alpha, Bp2, e0, mul + C.hinv[e0] * G, lo, X);
+    alpha.template load_perm<G>(e0, mul + hinv[e0] * G, X);
     const int nf = dc - 2;
     for (int s = 0; s < 3 * nf; ++s) {
         int kind, j;
         if (s < nf) {
             kind = 0;
             j = s + 1;
-            load_perm<G>(alpha, Bp2, e0 + j, mul + C.hinv[e0 + j] * G, lo, Y);
+            alpha.template load_perm<G>(e0 + j, mul + hinv[e0 + j] * G, Y);
         } else {
             const int t = s - nf;
             j = dc - 2 - (t >> 1);
             if (t == 0) {
                 // X = F_{dc-2} is the output of the last edge (eq. (12)); start the backward pass.
-                store_deperm<G>(beta, Bp2, e0 + dc - 1, mul + C.hinv[e0 + dc - 1] * G, lo, X, act);
-                load_perm<G>(alpha, Bp2, e0 + dc - 1, mul + C.hinv[e0 + dc - 1] * G, lo, X);
+                beta.template store_deperm<G>(e0 + dc - 1, mul + hinv[e0 + dc - 1] * G, X, act);
+                alpha.template load_perm<G>(e0 + dc - 1, mul + hinv[e0 + dc - 1] * G, X);
             }
             if ((t & 1) == 0) {
                 kind = 1;  // middle output: F_{j-1} (*) B_{j+1}
-                if (j == 1) load_perm<G>(alpha, Bp2, e0, mul + C.hinv[e0] * G, lo, Y);
+                if (j == 1) alpha.template load_perm<G>(e0, mul + hinv[e0] * G, Y);
                 else lds_get<G>(fs + (size_t)(j - 2) * H * 64, lane, Y);
             } else {
                 kind = 2;  // B_j = B_{j+1} (*) a~_j
-                load_perm<G>(alpha, Bp2, e0 + j, mul + C.hinv[e0 + j] * G, lo, Y);
+                alpha.template load_perm<G>(e0 + j, mul + hinv[e0 + j] * G, Y);
             }
         }
         conv<G>(X, Y, R);
         if (kind == 1) {
-            store_deperm<G>(beta, Bp2, e0 + j, mul + C.hinv[e0 + j] * G, lo, R, act);
+            beta.template store_deperm<G>(e0 + j, mul + hinv[e0 + j] * G, R, act);
         } else {
 #pragma unroll
             for (int p = 0; p < H; ++p) X[p] = R[p];
@@ -169,10 +198,19 @@ __device__ __forceinline__ void cn_row(const Args &A, int row, int w, int g, boo
         }
     }
     if (nf == 0) {
-        store_deperm<G>(beta, Bp2, e0 + 1, mul + C.hinv[e0 + 1] * G, lo, X, act);
-        load_perm<G>(alpha, Bp2, e0 + 1, mul + C.hinv[e0 + 1] * G, lo, X);
+        beta.template store_deperm<G>(e0 + 1, mul + hinv[e0 + 1] * G, X, act);
+        alpha.template load_perm<G>(e0 + 1, mul + hinv[e0 + 1] * G, X);
     }
-    store_deperm<G>(beta, Bp2, e0, mul + C.hinv[e0] * G, lo, X, act);
+    beta.template store_deperm<G>(e0, mul + hinv[e0] * G, X, act);
+}
+
+// The check node on the HBM-resident messages, wave w of the block.
+template <int G>
+__device__ __forceinline__ void cn_row(const Args &A, int row, int w, int g, bool act, uint32_t *lds) {
+    const uint32_t lo = 2u * (uint32_t)(g * 64 + (threadIdx.x & 63));
+    const HbmMsg alpha{msg_rsrc(A.w.alpha, A), 2u * (uint32_t)A.Bp, lo};
+    const HbmMsg beta{msg_rsrc(A.w.beta, A), 2u * (uint32_t)A.Bp, lo};
+    cn_core<G>(A.C, A.C.gfmul, A.C.hinv, alpha, beta, row, act, lds + (size_t)w * A.fslots * (G / 2) * 64);
 }
 
 // Check-node phase of iteration k: wave (threadIdx.x / 64) of virtual block (bx, by)
@@ -347,6 +385,235 @@ __device__ __forceinline__ void init_block(const Args &A, int bx, int by) {
             }
         }
         A.w.hard[(long)e * Bp + b] = (uint8_t)best;
+    }
+}
+
+// ------------------------------------ one group per workgroup, messages resident in LDS
+// For codes whose alpha and beta for one group of 64 codewords fit in LDS: a workgroup
+// of `waves` waves decodes one group through every iteration with alpha, beta and the
+// decisions in LDS ([edge][x][64] and [variable][64]), reading the channel vectors from
+// the transposed input in HBM; waves split the checks and the variables of each phase,
+// with a barrier between phases.  The arithmetic is that of the kernels above.
+
+struct LdsPlan {
+    size_t gam, alpha, beta, hard, mul, fs, red, total;
+};
+
+// gam_lds: the clipped channel vectors are staged in LDS too ([variable][x][64]).
+__host__ __device__ inline LdsPlan lds_plan(const DevCode &C, int fslots, int waves, bool gam_lds) {
+    LdsPlan L;
+    size_t o = 0;
+    L.gam = o;
+    if (gam_lds) o += (size_t)C.n * C.g * 128;
+    L.alpha = o;
+    o += (size_t)C.E * C.g * 128;
+    L.beta = o;
+    o += (size_t)C.E * C.g * 128;
+    L.hard = o;
+    o += ((size_t)C.n * 64 + 15) / 16 * 16;
+    L.mul = o;  // multiplication table, then hinv and h of every edge
+    o += ((size_t)C.g * C.g + 2 * (size_t)C.E + 15) / 16 * 16;
+    L.fs = o;
+    o += (size_t)waves * fslots * (C.g / 2) * 64 * 4;
+    L.red = o;
+    o += 8 * (size_t)waves;
+    L.total = o;
+    return L;
+}
+
+// Unsatisfied codewords of the group (bit = lane), uniform over the workgroup.
+__device__ __forceinline__ uint64_t lds_syndrome(const DevCode &C, const uint8_t *mul, const uint8_t *h,
+                                                 const uint8_t *hl, bool valid, int waves, uint64_t *red) {
+    const int lane = threadIdx.x & 63, w = wave_id();
+    uint64_t acc = 0;
+    for (int r = w; r < C.m; r += waves) {
+        int s = 0;
+        for (int e = C.row_ptr[r]; e < C.row_ptr[r + 1]; ++e) s ^= mul[h[e] * C.g + hl[C.col_idx[e] * 64 + lane]];
+        acc |= __ballot(s != 0 && valid);
+    }
+    if (lane == 0) red[w] = acc;
+    __syncthreads();
+    uint64_t u = 0;
+    for (int q = 0; q < waves; ++q) u |= red[q];
+    __syncthreads();
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Variable node v on the LDS messages (eqs. (14)-(15)); kAlpha = false: decision only.
+// The clipped channel vector gamma'(x) of variable v for the lane's codeword, from LDS
+// ([variable][x][64]) or from the transposed input in HBM.
+template <int G, bool GL>
+struct Gamma {
+    const int16_t *hbm;  // A.w.gam + b
+    const uint16_t *lds;  // staged copy + lane
+    long Bp;
+    int amax;
+    __device__ __forceinline__ int at(int v, int x) const {
+        if (GL) return (int16_t)lds[((size_t)v * G + x) * 64];
+        return min((int)hbm[((long)v * G + x) * Bp], amax);
+    }
+};
+
+template <int G, bool kAlpha, bool GL>
+__device__ __forceinline__ void lds_vn(const Args &A, const Gamma<G, GL> &gam, uint16_t *al, const uint16_t *bl,
+                                       uint8_t *hl, int v, bool act) {
+    const DevCode &C = A.C;
+    const int lane = threadIdx.x & 63;
+    int S[G];
+#pragma unroll
+    for (int x = 0; x < G; ++x) S[x] = gam.at(v, x);
+    const int t0 = C.vn_ptr[v], t1 = C.vn_ptr[v + 1];
+    for (int t = t0; t < t1; ++t) {
+        const uint16_t *bp = bl + (size_t)C.vn_ref[t] * G * 64 + lane;
+#pragma unroll
+        for (int x = 0; x < G; ++x) S[x] += (int16_t)bp[x * 64];
+    }
+    int best = 0, bv = S[0];
+#pragma unroll
+    for (int x = 1; x < G; ++x)
+        if (S[x] < bv) {
+            bv = S[x];
+            best = x;
+        }
+    if (act) hl[v * 64 + lane] = (uint8_t)best;
+    if (!kAlpha) return;
+    for (int t = t0; t < t1; ++t) {
+        const int e = C.vn_ref[t];
+        const uint16_t *bp = bl + (size_t)e * G * 64 + lane;
+        int a[G];
+        int mn = 0x7fffffff;
+#pragma unroll
+        for (int x = 0; x < G; ++x) {
+            a[x] = S[x] - (int16_t)bp[x * 64];
+            mn = min(mn, a[x]);
+        }
+        if (act) {
+            uint16_t *ap = al + (size_t)e * G * 64 + lane;
+#pragma unroll
+            for (int x = 0; x < G; ++x) ap[x * 64] = (uint16_t)min(a[x] - mn, A.amax);
+        }
+    }
+}
+
+// Layered schedule: alpha of edge e from eq. (14) with the LDS betas as they stand.
+template <int G, bool GL>
+__device__ __forceinline__ void lds_alpha_edge(const Args &A, const Gamma<G, GL> &gam, uint16_t *al,
+                                               const uint16_t *bl, int e, bool act) {
+    const DevCode &C = A.C;
+    const int lane = threadIdx.x & 63;
+    const int v = C.col_idx[e];
+    int S[G];
+#pragma unroll
+    for (int x = 0; x < G; ++x) S[x] = gam.at(v, x);
+    for (int t = C.vn_ptr[v]; t < C.vn_ptr[v + 1]; ++t) {
+        const int f = C.vn_ref[t];
+        if (f == e) continue;
+        const uint16_t *bp = bl + (size_t)f * G * 64 + lane;
+#pragma unroll
+        for (int x = 0; x < G; ++x) S[x] += (int16_t)bp[x * 64];
+    }
+    int mn = S[0];
+#pragma unroll
+    for (int x = 1; x < G; ++x) mn = min(mn, S[x]);
+    if (act) {
+        uint16_t *ap = al + (size_t)e * G * 64 + lane;
+#pragma unroll
+        for (int x = 0; x < G; ++x) ap[x * 64] = (uint16_t)min(S[x] - mn, A.amax);
+    }
+}
+
+// The whole decode of group g (every phase, every iteration) by the calling workgroup.
+template <int G, bool GL>
+__device__ __forceinline__ void lds_group(const Args &A, bool layered, int waves, int g, unsigned char *lds) {
+    const DevCode &C = A.C;
+    const int lane = threadIdx.x & 63, w = wave_id();
+    const int b = g * 64 + lane;
+    const bool valid = b < A.batch;
+    const LdsPlan P = lds_plan(C, A.fslots, waves, GL);
+    uint16_t *gl = (uint16_t *)(lds + P.gam);
+    uint16_t *al = (uint16_t *)(lds + P.alpha);
+    uint16_t *bl = (uint16_t *)(lds + P.beta);
+    uint8_t *hl = lds + P.hard;
+    uint8_t *ml = lds + P.mul;
+    uint8_t *hinvl = ml + G * G, *hl_h = hinvl + C.E;
+    uint32_t *fs = (uint32_t *)(lds + P.fs) + (size_t)w * A.fslots * (G / 2) * 64;
+    uint64_t *red = (uint64_t *)(lds + P.red);
+    for (int i = threadIdx.x; i < G * G; i += 64 * waves) ml[i] = C.gfmul[i];
+    for (int i = threadIdx.x; i < C.E; i += 64 * waves) {
+        hinvl[i] = C.hinv[i];
+        hl_h[i] = C.h[i];
+    }
+    const Gamma<G, false> ghbm{A.w.gam + b, nullptr, A.Bp, A.amax};
+    const Gamma<G, GL> gam{A.w.gam + b, gl + lane, A.Bp, A.amax};
+    if (GL) {
+        for (int v = w; v < C.n; v += waves)
+#pragma unroll 8
+            for (int x = 0; x < G; ++x) gl[((size_t)v * G + x) * 64 + lane] = (uint16_t)ghbm.at(v, x);
+    }
+    // alpha^(0) = gamma', beta = 0, decision of iteration 0
+    for (int e = w; e < C.E; e += waves) {
+        const int v = C.col_idx[e];
+#pragma unroll 8
+        for (int x = 0; x < G; ++x) {
+            al[((size_t)e * G + x) * 64 + lane] = (uint16_t)ghbm.at(v, x);
+            bl[((size_t)e * G + x) * 64 + lane] = 0;
+        }
+    }
+    for (int v = w; v < C.n; v += waves) {
+        int best = 0, bv = ghbm.at(v, 0);
+        for (int x = 1; x < G; ++x) {
+            const int val = ghbm.at(v, x);
+            if (val < bv) {
+                bv = val;
+                best = x;
+            }
+        }
+        hl[v * 64 + lane] = (uint8_t)best;
+    }
+    __syncthreads();
+    int it = 0;
+    for (int k = 1; k <= A.max_iters; ++k) {
+        bool act = valid;
+        if (A.early_stop) {
+            const uint64_t u = lds_syndrome(C, ml, hl_h, hl, valid, waves, red);
+            if (u == 0) break;  // every codeword of the group is done
+            act = act && ((u >> lane) & 1ull);
+        }
+        const LdsMsg am{al, lane}, bm{bl, lane};
+        if (!layered) {
+            for (int r = w; r < C.m; r += waves) cn_core<G>(C, ml, hinvl, am, bm, r, act, fs);
+            __syncthreads();
+            for (int v = w; v < C.n; v += waves) lds_vn<G, true, GL>(A, gam, al, bl, hl, v, act);
+            __syncthreads();
+        } else {
+            for (int l = 0; l < C.nb_nl; ++l) {
+                for (int i = C.nbl_eptr[l] + w; i < C.nbl_eptr[l + 1]; i += waves)
+                    lds_alpha_edge<G, GL>(A, gam, al, bl, __builtin_amdgcn_readfirstlane(C.nbl_edge[i]), act);
+                __syncthreads();
+                for (int i = C.nbl_ptr[l] + w; i < C.nbl_ptr[l + 1]; i += waves)
+                    cn_core<G>(C, ml, hinvl, am, bm, __builtin_amdgcn_readfirstlane(C.nbl_chk[i]), act, fs);
+                __syncthreads();
+            }
+            for (int v = w; v < C.n; v += waves) lds_vn<G, false, GL>(A, gam, al, bl, hl, v, act);
+            __syncthreads();
+        }
+        if (act) it = k;
+    }
+    const uint64_t u0 = lds_syndrome(C, ml, hl_h, hl, valid, waves, red);
+    if (w == 0 && valid) {
+        A.io.ok[b] = ((u0 >> lane) & 1ull) ? 0 : 1;
+        A.io.iters[b] = (int16_t)it;
+    }
+    // decisions (and, for the debug dump, the messages) back to the HBM layout
+    for (int v = w; v < C.n; v += waves) A.w.hard[(long)v * A.Bp + b] = hl[v * 64 + lane];
+    if (A.io.dump_a) {
+        for (int e = w; e < C.E; e += waves)
+            for (int x = 0; x < G; ++x) {
+                A.w.alpha[((long)e * G + x) * A.Bp + b] = (int16_t)al[((size_t)e * G + x) * 64 + lane];
+                A.w.beta[((long)e * G + x) * A.Bp + b] = (int16_t)bl[((size_t)e * G + x) * 64 + lane];
+            }
     }
 }
 

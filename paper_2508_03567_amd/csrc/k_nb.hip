@@ -47,6 +47,12 @@ __global__ void __launch_bounds__(256) k_dec(Args A, int k) {
     dev::nb::vn_block<G, false>(A, k, blk_node(A.Gn), blk_group(A.Gn));
 }
 __global__ void __launch_bounds__(256) k_fin(Args A) { dev::nb::fin_block(A, blockIdx.x); }
+// One group of 64 codewords per workgroup, messages in LDS.
+template <int G, bool GL>
+__global__ void __launch_bounds__(1024) k_nbl(Args A, int layered, int waves) {
+    extern __shared__ __align__(16) unsigned char lds8[];
+    dev::nb::lds_group<G, GL>(A, layered != 0, waves, blockIdx.x, lds8);
+}
 
 hipError_t tr(const dev::TransposeArgs &T, hipStream_t s) {
     if (T.cols <= 0 || T.rows_out <= 0) return hipSuccess;
@@ -112,7 +118,75 @@ hipError_t run(const Args &A, bool layered, hipStream_t s) {
     return hipSuccess;
 }
 
+template <int G, bool GL>
+hipError_t launch_group_kernel(const Args &A, bool layered, int waves, hipStream_t s) {
+    const size_t lds = dev::nb::lds_plan(A.C, A.fslots, waves, GL).total;
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k_nbl<G, GL>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_nbl<G, GL>), dim3((unsigned)A.Gn), dim3(64 * waves), lds, s, A, layered ? 1 : 0, waves);
+    return hipGetLastError();
+}
+
+template <int G>
+hipError_t run_lds(const Args &A, bool layered, int waves, hipStream_t s) {
+    hipError_t e;
+    if ((e = tr(dev::nb::tr_in(A), s)) != hipSuccess) return e;
+    // channel vectors staged in LDS too when they fit
+    const bool gl = dev::nb::lds_plan(A.C, A.fslots, waves, true).total <= (size_t)160 * 1024;
+    e = gl ? launch_group_kernel<G, true>(A, layered, waves, s) : launch_group_kernel<G, false>(A, layered, waves, s);
+    if (e != hipSuccess) return e;
+    if ((e = tr(dev::nb::tr_out(A), s)) != hipSuccess) return e;
+    if (A.io.dump_a) {
+        const long rows = (long)A.C.E * G;
+        if ((e = tr(dev::TransposeArgs{A.w.alpha, A.io.dump_a, rows, A.batch, A.Bp, rows, rows, 2}, s)) != hipSuccess)
+            return e;
+        if ((e = tr(dev::TransposeArgs{A.w.beta, A.io.dump_b, rows, A.batch, A.Bp, rows, rows, 2}, s)) != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
 }  // namespace
+
+size_t nb_lds_bytes(const DevCode &C, int waves) {
+    const int fslots = C.dc_max > 3 ? C.dc_max - 3 : 1;
+    return dev::nb::lds_plan(C, fslots, waves, false).total;
+}
+
+hipError_t launch_nb_lds(const DevCode &C, int max_iters, int early_stop, int layered, int batch, int amax, int waves,
+                         void *ws, const DecodeIO &io, hipStream_t s) {
+    if (C.g > 64 || (waves != 4 && waves != 8 && waves != 16) || nb_lds_bytes(C, waves) > (size_t)160 * 1024)
+        return hipErrorInvalidValue;
+    if (layered && (C.nb_nl < 1 || C.nb_lmax < 1 || C.nb_emax < 1)) return hipErrorInvalidValue;
+    const int step = nb_slice(C, batch);
+    for (int b0 = 0; b0 < batch; b0 += step) {
+        const int nb = std::min(step, batch - b0);
+        DecodeIO sl = io;
+        sl.llr = (const int16_t *)io.llr + (size_t)b0 * C.n * C.g;
+        sl.hard = (uint8_t *)io.hard + (size_t)b0 * C.n;
+        sl.ok = io.ok + b0;
+        sl.iters = io.iters + b0;
+        if (io.dump_a) {
+            sl.dump_a = (int16_t *)io.dump_a + (size_t)b0 * C.E * C.g;
+            sl.dump_b = (int16_t *)io.dump_b + (size_t)b0 * C.E * C.g;
+        }
+        const Args A = dev::nb::make_args(C, max_iters, early_stop, nb, amax, ws, sl);
+        hipError_t e;
+        switch (C.g) {
+        case 4: e = run_lds<4>(A, layered != 0, waves, s); break;
+        case 8: e = run_lds<8>(A, layered != 0, waves, s); break;
+        case 16: e = run_lds<16>(A, layered != 0, waves, s); break;
+        case 32: e = run_lds<32>(A, layered != 0, waves, s); break;
+        case 64: e = run_lds<64>(A, layered != 0, waves, s); break;
+        default: e = hipErrorInvalidValue;
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
 
 bool nb_supported(int g) { return g == 4 || g == 8 || g == 16 || g == 32 || g == 64 || g == 128 || g == 256; }
 

@@ -146,6 +146,12 @@ struct NbwWork {
 // Codewords per launch sequence of the interleaved Min-Max decoder (31-bit offsets).
 int nb_slice(const DevCode &C, int batch);
 size_t nb_work_bytes(const DevCode &C, int max_iters, int batch);
+// Min-Max with one group of 64 codewords per workgroup and its messages in LDS (g <= 64,
+// waves = 4, 8 or 16 per workgroup, nb_lds_bytes(C, waves) <= 160 KB); same workspace as
+// launch_nb.
+size_t nb_lds_bytes(const DevCode &C, int waves);
+hipError_t launch_nb_lds(const DevCode &C, int max_iters, int early_stop, int layered, int batch, int amax, int waves,
+                         void *ws, const DecodeIO &io, hipStream_t s);
 // amax: message bound (32767 for 16-bit messages, 127 for the 8-bit variant).  layered:
 // the layered schedule over the layers of DevCode (g <= 64).
 hipError_t launch_nb(const DevCode &C, int max_iters, int early_stop, int layered, int batch, int amax, void *ws,

@@ -187,7 +187,7 @@ uint64_t tune_key(const ldpcx_decode_params *p, int batch) {
 size_t work_bytes(const ldpcx_code *c, const ldpcx_decode_params *p, const Plan &pl, int batch) {
     if (pl.family == FAMILY_BIN_IL) return bin_il_work_bytes(c->dev, p->max_iters, batch, pl.cpw);
     if (pl.family == FAMILY_SPA) return spa_work_bytes(c->dev, p->max_iters, batch);
-    if (pl.family == FAMILY_NB) return nb_work_bytes(c->dev, p->max_iters, batch);
+    if (pl.family == FAMILY_NB || pl.family == FAMILY_NB_LDS) return nb_work_bytes(c->dev, p->max_iters, batch);
     return 0;
 }
 
@@ -239,6 +239,9 @@ hipError_t enqueue_interleaved(ldpcx_code *c, const ldpcx_decode_params *p, cons
         return launch_bin_il(c->dev, bin_rule(p), p->max_iters, p->early_stop, batch, pl.cpw, ws, io, dump_scratch,
                              s);
     if (pl.family == FAMILY_SPA) return launch_spa(c->dev, p->max_iters, p->early_stop, batch, ws, io, s);
+    if (pl.family == FAMILY_NB_LDS)
+        return launch_nb_lds(c->dev, p->max_iters, p->early_stop, pl.schedule == LDPCX_SCHED_LAYERED, batch, nb_amax(p),
+                             pl.threads / 64, ws, io, s);
     return launch_nb(c->dev, p->max_iters, p->early_stop, pl.schedule == LDPCX_SCHED_LAYERED, batch, nb_amax(p), ws,
                      io, s);
 }
@@ -260,6 +263,7 @@ ldpcx_status run_graph(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &
     key.family = pl.family;
     key.schedule = pl.schedule;
     key.cpw = pl.cpw;
+    key.threads = pl.threads;
     key.batch = batch;
     key.params = *p;
     key.llr = io.llr;
@@ -740,17 +744,18 @@ ldpcx_status ldpcx_plan_set(ldpcx_code *c, const ldpcx_decode_params *params, in
     if (!c) return fail(LDPCX_E_INVAL, "code is NULL");
     ldpcx_status st = check_params(c, params);
     if (st != LDPCX_OK) return st;
-    if (family < 0 || family > 4) return fail(LDPCX_E_INVAL, "unknown kernel family");
+    if (family < 0 || family > 5) return fail(LDPCX_E_INVAL, "unknown kernel family");
     if ((family == FAMILY_SPA) != (params->rule == LDPCX_RULE_SPA))
         return fail(LDPCX_E_INVAL, "family 4 runs rule SPA, and rule SPA only family 4");
     if (family == FAMILY_BIN_QC && !c->qc_ok) return fail(LDPCX_E_UNSUPPORTED, "code has no quasi-cyclic description");
-    if ((c->g > 2) != (family == FAMILY_NB || family == FAMILY_SPA))
+    if ((c->g > 2) != (family == FAMILY_NB || family == FAMILY_SPA || family == FAMILY_NB_LDS))
         return fail(LDPCX_E_INVAL, "family does not match the field size");
     Plan pl;
     pl.family = family;
     pl.schedule = params->schedule == LDPCX_SCHED_AUTO ? default_plan(c, params, std::max(1, batch)).schedule
                                                         : params->schedule;
-    if (family != FAMILY_BIN_LDS && family != FAMILY_BIN_QC && family != FAMILY_NB && pl.schedule == LDPCX_SCHED_LAYERED)
+    if (family != FAMILY_BIN_LDS && family != FAMILY_BIN_QC && family != FAMILY_NB && family != FAMILY_NB_LDS &&
+        pl.schedule == LDPCX_SCHED_LAYERED)
         return fail(LDPCX_E_UNSUPPORTED, "this kernel family runs the flooding schedule only");
     if (family == FAMILY_NB && pl.schedule == LDPCX_SCHED_LAYERED && c->g > 64)
         return fail(LDPCX_E_UNSUPPORTED, "layered Min-Max covers GF(4)..GF(64)");
@@ -780,6 +785,16 @@ ldpcx_status ldpcx_plan_set(ldpcx_code *c, const ldpcx_decode_params *params, in
     if (family == FAMILY_NB) {
         pl.cpw = 64;
         pl.threads = 256;
+    }
+    if (family == FAMILY_NB_LDS) {
+        if (c->g > 64 || params->rule != LDPCX_RULE_MINMAX)
+            return fail(LDPCX_E_UNSUPPORTED, "family 5 runs Min-Max over GF(4)..GF(64)");
+        if (threads != 256 && threads != 512 && threads != 1024)
+            return fail(LDPCX_E_INVAL, "family 5 takes 256, 512 or 1024 threads");
+        if (nb_lds_bytes(c->dev, threads / 64) > (size_t)160 * 1024)
+            return fail(LDPCX_E_UNSUPPORTED, "the messages of 64 codewords do not fit the LDS of one workgroup");
+        pl.cpw = 64;
+        pl.threads = threads;
     }
     if (family == FAMILY_SPA) {
         pl.cpw = 64 / c->g;

@@ -11,7 +11,7 @@
 
 namespace ldpcx {
 
-enum { FAMILY_BIN_LDS = 0, FAMILY_BIN_IL = 1, FAMILY_NB = 2, FAMILY_BIN_QC = 3, FAMILY_SPA = 4 };
+enum { FAMILY_BIN_LDS = 0, FAMILY_BIN_IL = 1, FAMILY_NB = 2, FAMILY_BIN_QC = 3, FAMILY_SPA = 4, FAMILY_NB_LDS = 5 };
 
 struct Plan {
     int family = FAMILY_BIN_LDS;
@@ -28,7 +28,7 @@ struct DeviceInfo {
 // A captured launch sequence of the interleaved decoders, keyed by everything that is
 // baked into its kernel arguments.
 struct GraphKey {
-    int family, schedule, cpw, batch;
+    int family, schedule, cpw, threads, batch;
     ldpcx_decode_params params;
     const void *llr;
     void *hard;

@@ -90,7 +90,7 @@ size_t io_bytes(const Request &r, int ncw) {
 size_t chunk_bytes(const Request &r, int ncw) {
     size_t b = io_bytes(r, ncw);
     if (r.family == FAMILY_BIN_IL) b += bin_il_work_bytes(r.code->dev, r.prm.max_iters, ncw, 0);
-    else if (r.family == FAMILY_NB) b += nb_work_bytes(r.code->dev, r.prm.max_iters, ncw);
+    else if (r.family == FAMILY_NB || r.family == FAMILY_NB_LDS) b += nb_work_bytes(r.code->dev, r.prm.max_iters, ncw);
     else if (r.family == FAMILY_SPA) b += spa_work_bytes(r.code->dev, r.prm.max_iters, ncw);
     // a chunk of a whole-device family inside a ragged batch is decoded from a gathered copy
     if (r.family != FAMILY_BIN_QC && r.family != FAMILY_BIN_LDS) b += io_bytes(r, ncw);
@@ -189,8 +189,9 @@ struct ldpcx_server {
             const uint64_t id = queue.front();
             Request &r = reqs.at(id);
             const bool own = cfg.mode == LDPCX_SERVE_PER_REQUEST || r.family == FAMILY_BIN_IL || r.family == FAMILY_SPA ||
-                             (r.family == FAMILY_NB && (r.code->g > 64 || r.prm.schedule != LDPCX_SCHED_FLOODING ||
-                                                         pad64(r.batch - r.next_cw) / 64 >= kOwnLaunchGroups));
+                             ((r.family == FAMILY_NB || r.family == FAMILY_NB_LDS) &&
+                              (r.code->g > 64 || r.prm.schedule != LDPCX_SCHED_FLOODING ||
+                               pad64(r.batch - r.next_cw) / 64 >= kOwnLaunchGroups));
             // A launch is either one chunk with its own launch sequence or a ragged batch.
             if (own && !take.empty()) break;
             if (!take.empty() && us >= kLaunchTargetUs) break;

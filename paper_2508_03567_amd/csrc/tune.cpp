@@ -18,11 +18,22 @@ std::vector<Plan> candidates(const ldpcx_code *c, const ldpcx_decode_params *p, 
     const Plan def = default_plan(c, p, batch);
     out.push_back(def);
     if (c->g > 2) {
-        // Min-Max: under AUTO the layered schedule is the other candidate (GF(4)..GF(64))
-        if (p->schedule == LDPCX_SCHED_AUTO && p->rule == LDPCX_RULE_MINMAX && c->g <= 64) {
+        if (p->rule != LDPCX_RULE_MINMAX || c->g > 64) return out;
+        // Min-Max: under AUTO the layered schedule is the other candidate; for codes whose
+        // messages of 64 codewords fit in LDS, the one-group-per-workgroup kernel too
+        std::vector<int> scheds{def.schedule};
+        if (p->schedule == LDPCX_SCHED_AUTO) scheds.push_back(LDPCX_SCHED_LAYERED);
+        for (int sched : scheds) {
             Plan pl = def;
-            pl.schedule = LDPCX_SCHED_LAYERED;
-            out.push_back(pl);
+            pl.schedule = sched;
+            if (sched != def.schedule) out.push_back(pl);
+            for (int thr : {256, 512, 1024}) {
+                if (nb_lds_bytes(c->dev, thr / 64) > (size_t)160 * 1024) continue;
+                Plan q = pl;
+                q.family = FAMILY_NB_LDS;
+                q.threads = thr;
+                out.push_back(q);
+            }
         }
         return out;
     }

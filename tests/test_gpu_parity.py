@@ -410,6 +410,46 @@ def test_minmax_layered_matches_oracle(g_size, n, dc, batch, early, iters):
     _check_decisions(code, g2, ref)
 
 
+@pytest.mark.parametrize("g_size,n,dc,batch,early,sched,threads,bound", [
+    (4, 24, 4, 70, True, "flooding", 256, 0), (8, 16, 4, 130, False, "flooding", 512, 0),
+    (16, 16, 4, 33, True, "layered", 256, 0), (32, 8, 4, 9, True, "flooding", 256, 0),
+    (8, 24, 8, 64, True, "flooding", 256, 0), (4, 12, 2, 129, True, "layered", 512, 0),
+    (8, 20, 5, 65, False, "layered", 1024, 0), (16, 16, 4, 40, True, "flooding", 256, 50),
+    (4, 16, 4, 200, True, "flooding", 1024, 0)])
+def test_minmax_lds_family_matches_oracle(g_size, n, dc, batch, early, sched, threads, bound):
+    """Min-Max with one group of 64 codewords per workgroup and alpha, beta and the
+    decisions in LDS: every message, decision, flag and iteration count equals the
+    oracle's, flooding and layered."""
+    m = n * 2 // dc
+    code = S.random_regular_nb_code(n, m, 2, dc, g_size, S.PRIM_POLY[g_size], seed=g_size + 5 * n + dc)
+    cw = S.random_codewords(code, batch, seed=13)
+    gam = S.nb_gamma_int16(cw, g_size, 1.5, seed=14)
+    d = dict(rule="minmax", schedule=sched, max_iters=5, early_stop=early, nb_msg_max=bound)
+    h = L.Code(code)
+    L.plan_set(h, L.params(**d), batch, "minmax_lds", 64, threads)
+    assert L.plan_info(h, L.params(**d), batch)["family"] == "minmax_lds"
+    g = _gpu(h, d, gam, dump=True)
+    ref = _ref(code, d, gam, dump=True)
+    _check_decisions(code, g, ref)
+    assert (g[3].astype(np.int32) == ref["alpha"]).all(), "alpha differs"
+    assert (g[4].astype(np.int32) == ref["beta"]).all(), "beta differs"
+    g2 = _gpu(h, d, gam)
+    _check_decisions(code, g2, ref)
+
+
+def test_minmax_lds_family_limits():
+    w = S.workload(3)
+    h = _handle(w.code)
+    prm = L.params("minmax", max_iters=3)
+    with pytest.raises(L.LdpcxError) as ei:  # GF(64) messages of 64 codewords exceed the LDS
+        L.plan_set(h, prm, 64, "minmax_lds", 64, 256)
+    assert ei.value.status == L.E_UNSUPPORTED
+    small = L.Code(S.random_regular_nb_code(16, 8, 2, 4, 8, S.PRIM_POLY[8], seed=3))
+    with pytest.raises(L.LdpcxError) as ei:
+        L.plan_set(small, prm, 64, "minmax_lds", 64, 128)
+    assert ei.value.status == L.E_INVAL
+
+
 @pytest.mark.parametrize("batch,early,bound", [(67, True, 0), (130, False, 0), (64, True, 127)])
 def test_minmax_layered_gf64_workload(batch, early, bound):
     w = S.workload(3, batch=batch)
