@@ -130,6 +130,16 @@ Plan default_plan(const ldpcx_code *c, const ldpcx_decode_params *p, int batch) 
         pl.schedule = p->schedule == LDPCX_SCHED_LAYERED ? LDPCX_SCHED_LAYERED : LDPCX_SCHED_FLOODING;
         pl.cpw = 64;
         pl.threads = 256;
+        // Short codes whose messages of 64 codewords fit in LDS: one workgroup per group,
+        // with as many waves as fit (measured faster wherever it fits)
+        if (c->g <= 64) {
+            for (int thr : {1024, 512, 256})
+                if (nb_lds_bytes(c->dev, thr / 64) <= (size_t)160 * 1024) {
+                    pl.family = FAMILY_NB_LDS;
+                    pl.threads = thr;
+                    break;
+                }
+        }
         return pl;
     }
     int sched = p->schedule;

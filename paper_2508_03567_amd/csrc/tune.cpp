@@ -26,7 +26,9 @@ std::vector<Plan> candidates(const ldpcx_code *c, const ldpcx_decode_params *p, 
         for (int sched : scheds) {
             Plan pl = def;
             pl.schedule = sched;
-            if (sched != def.schedule) out.push_back(pl);
+            pl.family = FAMILY_NB;
+            pl.threads = 256;
+            out.push_back(pl);
             for (int thr : {256, 512, 1024}) {
                 if (nb_lds_bytes(c->dev, thr / 64) > (size_t)160 * 1024) continue;
                 Plan q = pl;

@@ -171,13 +171,19 @@ def test_adversarial_binary_inputs(kind):
         assert (g[3].astype(np.int32) == ref["q"]).all()
 
 
+@pytest.mark.parametrize("family", [None, "minmax_interleaved"])
 @pytest.mark.parametrize("g_size", [4, 8, 16, 32, 64])
-def test_minmax_field_sizes(g_size):
+def test_minmax_field_sizes(g_size, family):
+    """Default plan (the LDS-resident family where the messages fit) and the interleaved
+    family pinned."""
     code = S.random_regular_nb_code(24, 12, 2, 4, g_size, S.PRIM_POLY[g_size], seed=g_size)
     cw = S.random_codewords(code, 70, seed=1)
     gam = S.nb_gamma_int16(cw, g_size, 1.5, seed=2)
     d = dict(rule="minmax", schedule="flooding", max_iters=6, early_stop=True)
-    g = _gpu(L.Code(code), d, gam, dump=True)
+    h = L.Code(code)
+    if family:
+        L.plan_set(h, L.params(**d), 70, family, 64, 256)
+    g = _gpu(h, d, gam, dump=True)
     ref = _ref(code, d, gam, dump=True)
     _check_decisions(code, g, ref)
     assert (g[3].astype(np.int32) == ref["alpha"]).all()
@@ -394,13 +400,15 @@ def test_minmax_reduced_precision(g_size, bound):
 def test_minmax_layered_matches_oracle(g_size, n, dc, batch, early, iters):
     """Layered Min-Max: one launch per layer of checks sharing no variable, each check
     forming its alphas from the current betas; decisions, flags, iteration counts and
-    every alpha / beta equal the oracle's one-check-at-a-time schedule."""
+    every alpha / beta equal the oracle's one-check-at-a-time schedule (interleaved
+    family pinned; the LDS-resident family has its own test)."""
     m = n * 2 // dc
     code = S.random_regular_nb_code(n, m, 2, dc, g_size, S.PRIM_POLY[g_size], seed=g_size + 3 * n + dc)
     cw = S.random_codewords(code, batch, seed=11)
     gam = S.nb_gamma_int16(cw, g_size, 1.5, seed=12)
     d = dict(rule="minmax", schedule="layered", max_iters=iters, early_stop=early)
     h = L.Code(code)
+    L.plan_set(h, L.params(**d), batch, "minmax_interleaved", 64, 256)
     g = _gpu(h, d, gam, dump=True)
     ref = _ref(code, d, gam, dump=True)
     _check_decisions(code, g, ref)
