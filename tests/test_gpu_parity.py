@@ -204,6 +204,38 @@ def test_minmax_check_degrees(dc):
     assert (g[4].astype(np.int32) == ref["beta"]).all()
 
 
+@pytest.mark.parametrize("g_size,sched,family", [(4, "flooding", None), (4, "layered", None),
+                                                 (16, "flooding", "minmax_interleaved"),
+                                                 (16, "layered", "minmax_interleaved")])
+def test_minmax_largest_check_degree(g_size, sched, family):
+    """Checks of the largest supported degree (16): the most forward vectors kept per wave."""
+    n, m, dc = 32, 4, 16
+    code = S.random_regular_nb_code(n, m, 2, dc, g_size, S.PRIM_POLY[g_size], seed=61)
+    cw = S.random_codewords(code, 70, seed=7)
+    gam = S.nb_gamma_int16(cw, g_size, 3.0, seed=8)
+    d = dict(rule="minmax", schedule=sched, max_iters=4, early_stop=True)
+    h = L.Code(code)
+    if family:
+        L.plan_set(h, L.params(**d), 70, family, 64, 256)
+    g = _gpu(h, d, gam, dump=True)
+    ref = _ref(code, d, gam, dump=True)
+    _check_decisions(code, g, ref)
+    assert (g[3].astype(np.int32) == ref["alpha"]).all()
+    assert (g[4].astype(np.int32) == ref["beta"]).all()
+
+
+def test_spa_largest_check_degree():
+    n, m, dc = 32, 4, 16
+    code = S.random_regular_nb_code(n, m, 2, dc, 4, S.PRIM_POLY[4], seed=62)
+    cw = S.random_codewords(code, 20, seed=9)
+    gam = S.nb_gamma_int16(cw, 4, 3.0, seed=10)
+    prm = dict(rule="spa", schedule="flooding", max_iters=4, early_stop=True)
+    g = _gpu(L.Code(code), prm, gam, dump=True)
+    ref = O.decode_spa(code, O.params(**prm), gam, dump=True)
+    _check_decisions(code, g, ref)
+    assert (g[3].astype(np.int64) == ref["u"]).all() and (g[4].astype(np.int64) == ref["v"]).all()
+
+
 def test_eq1_code_exhaustive_noise():
     code = S.eq1_code()
     rng = np.random.default_rng(8)
