@@ -19,8 +19,7 @@
 // a wave whose lanes are partly stopped merges old and new values per byte.
 //
 // All functions assume blocks of 256 threads (4 waves); the block index is passed
-// explicitly so that the same code runs from its own kernel launch or inside one
-// workgroup of the persistent ragged engine.
+// explicitly, so a launch may map its blocks onto (node, group) in any order.
 #pragma once
 
 #include "dev_common.h"

@@ -1,7 +1,6 @@
-// Device helpers shared by every decoder: packed 16-bit types, layout transposes
-// and fills written as block-level device functions (block index passed
-// explicitly), so that the same code runs from a dedicated kernel launch or from
-// the persistent ragged engine.
+// Device helpers shared by every decoder: packed 16-bit types and operations, the
+// magnitude normalisation of the min-sum variants, and layout transposes and fills
+// written as block-level device functions (block index passed explicitly).
 #pragma once
 
 #include "ldpcx_internal.h"

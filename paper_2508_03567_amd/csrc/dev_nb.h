@@ -17,6 +17,14 @@
 // vectors needed by later middle outputs go through LDS.  Forward at the last
 // edge and backward at the first edge are never used by eqs. (11)-(13) and are
 // not computed (3(dc-2) convolutions per check instead of 4dc-6).
+//
+// The check node (cn_core) reads and writes messages through an accessor, so the
+// same code serves three arrangements: the messages in HBM with one launch per
+// phase (flooding: cn_block / vn_block), the layered schedule (layers of checks
+// sharing no variable, alphas formed per check from the current betas:
+// lay_alpha_block / lay_cn_block), and short codes whose messages of one group of 64
+// codewords fit in LDS, decoded by one workgroup through every iteration
+// (lds_group).
 #pragma once
 
 #include "dev_common.h"

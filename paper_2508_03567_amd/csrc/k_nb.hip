@@ -1,5 +1,6 @@
-// Launch sequence of the interleaved Min-Max decoder: one kernel per phase, the
-// phase bodies being the device functions of dev_nb.h.
+// Launch sequences of the Min-Max decoders over GF(4)..GF(64) (the device functions
+// of dev_nb.h): one kernel per phase for the flooding and layered schedules on
+// HBM-resident messages, or one kernel per batch slice for the LDS-resident family.
 #include <algorithm>
 
 #include "dev_nb.h"
