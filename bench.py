@@ -113,6 +113,9 @@ def main() -> None:
     ap.add_argument("--precision", action="store_true",
                     help="Min-Max message precision: 16-bit vs 8-bit (bound 127) messages on the GF(64) workload, "
                          "FER over Eb/N0 and fixed-iteration throughput")
+    ap.add_argument("--peaks", action="store_true",
+                    help="measured device peaks: copy bandwidth over buffer sizes and the packed 16-bit VALU "
+                         "issue rate, against the spec figures")
     ap.add_argument("--ragged", action="store_true",
                     help="ragged batch of small mixed jobs: one persistent launch vs one decode call per job")
     ap.add_argument("--schedule", type=str, default=None, choices=["flooding", "layered"],
@@ -145,6 +148,9 @@ def main() -> None:
         return
     if args.ragged:
         ragged_main(args)
+        return
+    if args.peaks:
+        peaks_main(args)
         return
 
     import torch
@@ -439,6 +445,50 @@ def schedules_main(args) -> None:
             rec["ms_fixed_20it"] = round(ms_fx, 3)
             rec["info_gbit_s_fixed_20it"] = round(w.info_bits_per_cw * w.batch / (ms_fx * 1e-3) / 1e9, 4)
             print(json.dumps(rec), flush=True)
+
+
+def peaks_main(args) -> None:
+    """Measured peaks of this GPU next to the spec ones: device-to-device copy rate
+    (read + write bytes) over buffer sizes, and the packed 16-bit VALU issue rate."""
+    import torch
+    from paper_2508_03567_amd import ldpcx as L
+
+    dev = torch.device("cuda:0")
+    for mb in (16, 64, 128, 256, 512, 2048):
+        n = mb * 1024 * 1024 // 4
+        src = torch.ones(n, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        reps = max(5, 4096 // mb)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        print(json.dumps({"metric": "device copy rate (read + write bytes)", "buffer_mb": mb,
+                          "tb_s": round(2 * mb * 2 ** 20 / (ms * 1e-3) / 1e12, 3), "spec_tb_s": HBM_PEAK_GBS / 1e3}),
+              flush=True)
+        del src, dst
+    stream = torch.cuda.current_stream()
+    blocks, iters = 256 * 8 * 4, 4096
+    L.valu_probe(blocks, 64, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    L.valu_probe(blocks, iters, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    wave_instr = blocks * 4 * iters * 16
+    rate = wave_instr / (ms * 1e-3)
+    print(json.dumps({"metric": "packed 16-bit VALU issue rate", "wave_instr_per_s": round(rate / 1e9, 2),
+                      "int16_tops": round(rate * 128 / 1e12, 2), "spec_wave_instr_per_s": VALU_PEAK_WAVE_INSTR / 1e9,
+                      "spec_int16_tops": round(ALU_PEAK_TOPS_I16, 2), "frac_of_spec": round(rate / VALU_PEAK_WAVE_INSTR, 4),
+                      "ms": round(ms, 3)}), flush=True)
 
 
 def ragged_main(args) -> None:

@@ -225,6 +225,13 @@ ldpcx_status ldpcx_plan_info(const ldpcx_code *code, const ldpcx_decode_params *
 ldpcx_status ldpcx_plan_set(ldpcx_code *code, const ldpcx_decode_params *params, int32_t batch,
                             int32_t family, int32_t cw_per_wg, int32_t threads);
 
+/* Measurement aid (no passage of the paper): run `blocks` workgroups of 256 threads
+ * on `stream`, every lane doing `iters` rounds of 8 independent chains of one packed
+ * 16-bit add and one packed 16-bit max (16 VALU wave instructions per round and
+ * wave).  The caller times it to measure the device's VALU issue rate, the peak that
+ * the integer rooflines are quoted against.  LDPCX_E_INVAL for non-positive sizes. */
+ldpcx_status ldpcx_valu_probe(int32_t blocks, int32_t iters, void *stream);
+
 /* ------------------------------------------------------------------ serving */
 typedef struct ldpcx_server ldpcx_server;
 

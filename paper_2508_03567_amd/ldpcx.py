@@ -76,6 +76,7 @@ _SIGS = {
                        [ctypes.POINTER(ctypes.c_int32)] * 3,
     "ldpcx_plan_set": [ctypes.c_void_p, ctypes.POINTER(DecodeParams), ctypes.c_int32, ctypes.c_int32,
                        ctypes.c_int32, ctypes.c_int32],
+    "ldpcx_valu_probe": [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p],
     "ldpcx_server_create": [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)],
     "ldpcx_server_submit": [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(DecodeParams), ctypes.c_int32,
                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -334,6 +335,15 @@ def plan_info(code: Code, prm: DecodeParams, batch: int) -> dict:
 def plan_set(code: Code, prm: DecodeParams, batch: int, family: str, cw_per_wg: int = 1, threads: int = 256):
     fam = {v: k for k, v in FAMILY_NAME.items()}[family]
     ldpcx_plan_set(code.handle, prm, batch, fam, cw_per_wg, threads)
+
+
+def ldpcx_valu_probe(blocks: int, iters: int, stream: int = 0) -> None:
+    _check(lib().ldpcx_valu_probe(blocks, iters, ctypes.c_void_p(stream)))
+
+
+def valu_probe(blocks: int, iters: int, stream=None) -> None:
+    """Enqueue the packed 16-bit VALU issue-rate probe (16 wave instructions per round)."""
+    ldpcx_valu_probe(blocks, iters, _stream_ptr(stream))
 
 
 def unpack_bits(hard_packed: np.ndarray, n: int) -> np.ndarray:
