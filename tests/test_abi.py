@@ -105,3 +105,11 @@ def test_server_config_validation():
     for fn, args in ((L.lib().ldpcx_server_poll, (None, 1, None)), (L.lib().ldpcx_server_cancel, (None, 1)),
                      (L.lib().ldpcx_server_destroy, (None,)), (L.lib().ldpcx_decode_ragged, (None, -1, None))):
         assert fn(*args) == L.E_INVAL
+
+
+def test_valu_probe_validation():
+    """The measurement probe rejects non-positive sizes on the host."""
+    for blocks, iters in ((0, 1), (1, 0), (-3, 5)):
+        with pytest.raises(L.LdpcxError) as ei:
+            L.ldpcx_valu_probe(blocks, iters)
+        assert ei.value.status == L.E_INVAL
