@@ -591,3 +591,9 @@ def test_spa_rejections():
     (hard, ok, it), = L.decode_ragged([(h64, prm, g64)])
     ref = L.decode(h64, prm, g64)
     assert torch.equal(hard, ref[0]) and torch.equal(ok, ref[1]) and torch.equal(it, ref[2])
+
+
+def test_valu_probe_runs():
+    """The VALU rate probe completes on the device (its timing is bench.py --peaks)."""
+    L.valu_probe(64, 16)
+    torch.cuda.synchronize()
