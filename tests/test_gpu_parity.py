@@ -597,3 +597,23 @@ def test_valu_probe_runs():
     """The VALU rate probe completes on the device (its timing is bench.py --peaks)."""
     L.valu_probe(64, 16)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("sched", ["flooding", "layered"])
+def test_minmax_batch_sliced_for_31_bit_offsets(sched):
+    """A Min-Max batch whose message arrays would exceed 31-bit byte offsets runs as
+    consecutive slices (E = 8192 edges over GF(64): 1984 codewords per slice); sampled
+    codewords of both slices, including both sides of the boundary, match the oracle."""
+    code = S.random_regular_nb_code(4096, 2048, 2, 4, 64, S.PRIM_POLY[64], seed=71)
+    batch = 2100
+    gen = torch.Generator(device=DEV).manual_seed(5)
+    gam = torch.randint(0, 300, (batch, code.n, 64), dtype=torch.int16, device=DEV, generator=gen)
+    gam -= gam.min(dim=2, keepdim=True).values
+    d = dict(rule="minmax", schedule=sched, max_iters=2, early_stop=True)
+    hard, ok, it, _ = L.decode(_handle(code), L.params(**d), gam)
+    torch.cuda.synchronize()
+    idx = np.array([0, 1500, 1983, 1984, 1985, batch - 1])
+    sample = gam[torch.from_numpy(idx).to(DEV)].cpu().numpy()
+    ref = _ref(code, d, sample)
+    assert (hard.cpu().numpy()[idx] == ref["hard"]).all()
+    assert (ok.cpu().numpy()[idx] == ref["ok"]).all() and (it.cpu().numpy()[idx] == ref["iters"]).all()
