@@ -32,19 +32,11 @@ hipError_t launch_bin_lds(const DevCode &C, const BinRule &R, int max_iters, int
     const size_t smem = bin_lds_smem_bytes(C, layered, cpw);
     const int grid = (batch + cpw - 1) / cpw;
     if (layered) {
-        static bool attr = false;
-        if (!attr) {
-            (void)hipFuncSetAttribute((const void *)k_bin_lds<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            attr = true;
-        }
+        allow_full_lds((const void *)k_bin_lds<true>);
         hipLaunchKernelGGL(k_bin_lds<true>, dim3(grid), dim3(threads), smem, s, C, R, max_iters, early_stop,
                            batch, cpw, io);
     } else {
-        static bool attr = false;
-        if (!attr) {
-            (void)hipFuncSetAttribute((const void *)k_bin_lds<false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            attr = true;
-        }
+        allow_full_lds((const void *)k_bin_lds<false>);
         hipLaunchKernelGGL(k_bin_lds<false>, dim3(grid), dim3(threads), smem, s, C, R, max_iters, early_stop,
                            batch, cpw, io);
     }

@@ -45,12 +45,7 @@ hipError_t launch_es(const QcDesc &Q, const DevCode &C, const BinRule &R, int ma
     const size_t smem = qc_smem_bytes(ML, MD, C, Q.Z, LAYERED, npairs);
     const int pairs = (batch + 1) / 2;
     const int grid = (pairs + npairs - 1) / npairs;
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute((const void *)k_bin_qc<ML, MD, LAYERED, ES>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr = true;
-    }
+    allow_full_lds((const void *)k_bin_qc<ML, MD, LAYERED, ES>);
     hipLaunchKernelGGL((k_bin_qc<ML, MD, LAYERED, ES>), dim3(grid), dim3(Q.Z * npairs), smem, s, Q, C, R, max_iters,
                        early_stop, batch, npairs, io);
     return hipGetLastError();

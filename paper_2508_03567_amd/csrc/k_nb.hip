@@ -122,11 +122,7 @@ hipError_t run(const Args &A, bool layered, hipStream_t s) {
 template <int G, bool GL>
 hipError_t launch_group_kernel(const Args &A, bool layered, int waves, hipStream_t s) {
     const size_t lds = dev::nb::lds_plan(A.C, A.fslots, waves, GL).total;
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute((const void *)k_nbl<G, GL>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr = true;
-    }
+    allow_full_lds((const void *)k_nbl<G, GL>);
     hipLaunchKernelGGL((k_nbl<G, GL>), dim3((unsigned)A.Gn), dim3(64 * waves), lds, s, A, layered ? 1 : 0, waves);
     return hipGetLastError();
 }

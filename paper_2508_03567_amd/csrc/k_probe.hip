@@ -34,12 +34,13 @@ using namespace ldpcx;
 
 extern "C" ldpcx_status ldpcx_valu_probe(int32_t blocks, int32_t iters, void *stream) {
     if (blocks < 1 || iters < 1) return fail(LDPCX_E_INVAL, "blocks and iters must be positive");
-    static uint32_t *out = nullptr;
-    if (!out && hipMalloc((void **)&out, 64 * sizeof(uint32_t)) != hipSuccess)
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *out = nullptr;
+    if (hipMallocAsync((void **)&out, 64 * sizeof(uint32_t), s) != hipSuccess)
         return fail(LDPCX_E_NOMEM, "probe output");
-    hipLaunchKernelGGL(k_valu_probe, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, iters, 0x2545F491u,
-                       out);
+    hipLaunchKernelGGL(k_valu_probe, dim3((unsigned)blocks), dim3(256), 0, s, iters, 0x2545F491u, out);
     const hipError_t e = hipGetLastError();
+    (void)hipFreeAsync(out, s);
     if (e != hipSuccess) return fail_hip(e, "VALU probe launch");
     return LDPCX_OK;
 }

@@ -71,6 +71,11 @@ __device__ __forceinline__ int bin_r(int j, int fm1, int fm2, int idx, uint32_t 
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Raise a kernel's dynamic-LDS limit to 160 KB on the current device, once per (kernel,
+// device); thread-safe, best effort (a kernel whose launch needs more than 64 KB then
+// fails at launch if the attribute could not be set).
+void allow_full_lds(const void *kernel);
+
 // ---------------------------------------------------------------- launchers
 // Each returns a hipError_t from the launch (hipSuccess when enqueued).
 

@@ -5,7 +5,9 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <set>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "runtime.h"
@@ -54,6 +56,20 @@ bool build_gf(int g, uint32_t poly, std::vector<uint8_t> &mul, std::vector<uint8
 }
 
 }  // namespace
+
+void allow_full_lds(const void *kernel) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    static std::mutex mu;
+    static std::set<std::pair<const void *, int>> done;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!done.insert(std::make_pair(kernel, dev)).second) return;
+    (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipGetLastError();
+}
 
 const DeviceInfo &device_info(int dev) {
     std::lock_guard<std::mutex> lk(g_dev_mu);
