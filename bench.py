@@ -113,6 +113,9 @@ def main() -> None:
     ap.add_argument("--precision", action="store_true",
                     help="Min-Max message precision: 16-bit vs 8-bit (bound 127) messages on the GF(64) workload, "
                          "FER over Eb/N0 and fixed-iteration throughput")
+    ap.add_argument("--ebn0-sweep", action="store_true",
+                    help="headline code over its Eb/N0 sweep (1.0-3.0 dB): FER, mean iterations and throughput "
+                         "with syndrome early stop, and at fixed iterations")
     ap.add_argument("--peaks", action="store_true",
                     help="measured device peaks: copy bandwidth over buffer sizes and the packed 16-bit VALU "
                          "issue rate, against the spec figures")
@@ -151,6 +154,9 @@ def main() -> None:
         return
     if args.peaks:
         peaks_main(args)
+        return
+    if args.ebn0_sweep:
+        ebn0_main(args)
         return
 
     import torch
@@ -445,6 +451,39 @@ def schedules_main(args) -> None:
             rec["ms_fixed_20it"] = round(ms_fx, 3)
             rec["info_gbit_s_fixed_20it"] = round(w.info_bits_per_cw * w.batch / (ms_fx * 1e-3) / 1e9, 4)
             print(json.dumps(rec), flush=True)
+
+
+def ebn0_main(args) -> None:
+    """The headline n = 2304 QC code (OMS, layered, I_max = 20, 65536 codewords) over its
+    Eb/N0 sweep: with syndrome early stop (FER, mean iterations, throughput) and at fixed
+    iterations."""
+    import torch
+    from paper_2508_03567_amd import ldpcx as L
+    from paper_2508_03567_amd import synth as S
+
+    dev = torch.device("cuda:0")
+    for eb in (1.0, 1.5, 2.0, 2.5, 3.0):
+        w = S.workload(1, batch=args.batch, ebn0_db=eb)
+        cw, llr_np = S.make_inputs(w)
+        llr = torch.from_numpy(llr_np).to(dev)
+        h = L.Code(w.code)
+        out = L._outputs(h, w.batch, dev)
+        rec = {"metric": "headline code over Eb/N0", "workload": w.name, "ebn0_db": eb, "batch": w.batch}
+        for es in (True, False):
+            prm = L.params(w.rule, w.schedule, w.max_iters, early_stop=es, nms_num=w.nms_num, nms_shift=w.nms_shift,
+                           oms_offset=w.oms_offset, msg_max=w.msg_max)
+            L.tune(h, prm, w.batch)
+            ms = _time_decode(L, torch, h, prm, llr, out, reps=5)
+            key = "early_stop" if es else "fixed_20it"
+            rec[f"info_gbit_s_{key}"] = round(w.info_bits_per_cw * w.batch / (ms * 1e-3) / 1e9, 3)
+            rec[f"ms_{key}"] = round(ms, 3)
+            if es:
+                hard, ok, it = out
+                torch.cuda.synchronize()
+                h_np = L.unpack_bits(hard.cpu().numpy(), w.code.n)
+                rec["fer"] = float((h_np != cw).any(axis=1).mean())
+                rec["mean_iters"] = round(float(it.float().mean()), 3)
+        print(json.dumps(rec), flush=True)
 
 
 def peaks_main(args) -> None:
