@@ -9,11 +9,21 @@
 // channel vectors come from the symbol costs gamma through the weights
 // W(c) = round(2^24 exp(-c / 4)).
 //
-// Mapping: a wavefront covers 64 / g codewords of one node, a segment of g lanes per
-// codeword with lane x holding entry x.  The transform butterflies, the segment sums
-// and the arg-max are xor-shuffles inside the segment; the permutation by the edge
-// coefficient is folded into the loads, the depermutation is one indexed shuffle.
-// Messages are stored codeword-major per edge, [edge][codeword][x] (int32).
+// Mapping: a wavefront covers 64 / S codewords of one node, a segment of S = min(g, 16)
+// lanes per codeword; lane j of a segment holds the R = g / S consecutive entries
+// x = j R .. j R + R - 1 in registers.  The transform runs its butterflies over the
+// register bits in registers and over the lane bits with DPP moves inside a row of 16
+// lanes (quad_perm for directions 1 and 2, row_half_mirror for direction 7,
+// row_ror:8 for direction 8).  Directions {1, 2, 7, 8} span the lane index space, so
+// with each butterfly's sign taken from the dual basis (j0^j2, j1^j2, j2, j3) the
+// lane part is the Walsh-Hadamard transform in linearly relabelled coordinates: the
+// transformed values are those of the plain transform at fixed permuted positions,
+// the elementwise products see the same integer pairs, and forward then inverse
+// gives exactly g times the XOR convolution in the original index.  Segment sums,
+// maxima and the arg-max reduce over the same four directions.  The permutation by
+// the edge coefficient is folded into the check node's loads (gather) and the
+// depermutation into its stores (scatter to the same positions).  Messages are stored
+// codeword-major per edge, [edge][codeword][x] (int32).
 #pragma once
 
 #include "dev_common.h"
@@ -23,7 +33,7 @@ namespace dev {
 namespace spa {
 
 constexpr int kQ = 24;
-constexpr int kVnRegs = 16;  // incoming check messages a variable keeps in registers
+constexpr int kVnRegs = 16;  // largest variable degree (its incoming messages stay in registers)
 
 struct Args {
     DevCode C;
@@ -32,48 +42,134 @@ struct Args {
     DecodeIO io;
 };
 
+// Lanes per codeword, entries per lane, codewords per wave, log2(g).
+template <int G>
+struct Geo {
+    static constexpr int S = G < 16 ? G : 16;
+    static constexpr int R = G / S;
+    static constexpr int CPW = 64 / S;
+    static constexpr int P = G == 64 ? 6 : G == 32 ? 5 : G == 16 ? 4 : G == 8 ? 3 : 2;
+};
+
 __device__ __forceinline__ int qmul(int a, int b) {
     return (int)(((long long)a * b + (1ll << (kQ - 1))) >> kQ);
 }
 
-// Walsh-Hadamard transform of the segment (lane x holds entry x).
+// floor(2^46 / s) for 0 < s < 2^31: the double quotient is within one unit of the
+// exact one (its error is far below 1 for quotients < 2^47), and two integer checks
+// make it exact.
+__device__ __forceinline__ long long recip46(int s) {
+    long long q = (long long)(70368744177664.0 / (double)s);
+    if (q * s > (1ll << 46)) --q;
+    if ((q + 1) * s <= (1ll << 46)) ++q;
+    return q;
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+constexpr int kDppXor1 = 0xB1;    // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;    // quad_perm [2,3,0,1]
+constexpr int kDppMirror8 = 0x141;  // row_half_mirror: j -> j ^ 7 inside 8 lanes
+constexpr int kDppRor8 = 0x128;   // row_ror:8: j -> j ^ 8 inside 16 lanes
+
+// Butterfly signs of the lane directions 1, 2, 7, 8 (the dual basis of the lane index).
+struct Signs {
+    bool d1, d2, d7, d8;
+};
+
 template <int G>
-__device__ __forceinline__ int wht(int val, int x) {
-#pragma unroll
-    for (int s = 1; s < G; s <<= 1) {
-        const int o = __shfl_xor(val, s, 64);
-        val = (x & s) ? o - val : val + o;
+__device__ __forceinline__ Signs signs_of(int j) {
+    Signs s;
+    if (Geo<G>::S >= 8) {
+        s.d1 = ((j ^ (j >> 2)) & 1) != 0;
+        s.d2 = (((j >> 1) ^ (j >> 2)) & 1) != 0;
+        s.d7 = ((j >> 2) & 1) != 0;
+        s.d8 = ((j >> 3) & 1) != 0;
+    } else {
+        s.d1 = (j & 1) != 0;
+        s.d2 = ((j >> 1) & 1) != 0;
+        s.d7 = s.d8 = false;
     }
-    return val;
+    return s;
+}
+
+template <int CTRL, int R>
+__device__ __forceinline__ void lane_stage(int (&v)[R], bool upper) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int o = dpp<CTRL>(v[r]);
+        v[r] = upper ? o - v[r] : v[r] + o;
+    }
+}
+
+// Walsh-Hadamard transform of the segment (relabelled in the lane bits, see above).
+template <int G>
+__device__ __forceinline__ void wht(int (&v)[Geo<G>::R], const Signs &sg) {
+    constexpr int R = Geo<G>::R, S = Geo<G>::S;
+#pragma unroll
+    for (int s = 1; s < R; s <<= 1) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (!(r & s)) {
+                const int a = v[r], b = v[r | s];
+                v[r] = a + b;
+                v[r | s] = a - b;
+            }
+        }
+    }
+    lane_stage<kDppXor1>(v, sg.d1);
+    lane_stage<kDppXor2>(v, sg.d2);
+    if (S >= 8) lane_stage<kDppMirror8>(v, sg.d7);
+    if (S >= 16) lane_stage<kDppRor8>(v, sg.d8);
 }
 
 template <int G>
 __device__ __forceinline__ int seg_sum(int v) {
-#pragma unroll
-    for (int s = 1; s < G; s <<= 1) v += __shfl_xor(v, s, 64);
+    v += dpp<kDppXor1>(v);
+    v += dpp<kDppXor2>(v);
+    if (Geo<G>::S >= 8) v += dpp<kDppMirror8>(v);
+    if (Geo<G>::S >= 16) v += dpp<kDppRor8>(v);
     return v;
 }
 
 template <int G>
 __device__ __forceinline__ int seg_max(int v) {
-#pragma unroll
-    for (int s = 1; s < G; s <<= 1) v = max(v, __shfl_xor(v, s, 64));
+    v = max(v, dpp<kDppXor1>(v));
+    v = max(v, dpp<kDppXor2>(v));
+    if (Geo<G>::S >= 8) v = max(v, dpp<kDppMirror8>(v));
+    if (Geo<G>::S >= 16) v = max(v, dpp<kDppRor8>(v));
     return v;
 }
 
-// norm(z) for this lane's entry; `fallback` when the segment sum is 0.
+// out = norm(z) for this lane's entries; `fallback` when the segment sum is 0.
 template <int G>
-__device__ __forceinline__ int normalise(int z, int fallback) {
-    const int s = seg_sum<G>(z);
-    if (s <= 0) return fallback;
-    const long long r = (1ll << 46) / s;
-    return (int)(((long long)z * r + (1ll << 21)) >> 22);
+__device__ __forceinline__ void normalise(const int (&z)[Geo<G>::R], const int (&fallback)[Geo<G>::R],
+                                          int (&out)[Geo<G>::R]) {
+    constexpr int R = Geo<G>::R;
+    int s = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) s += z[r];
+    s = seg_sum<G>(s);
+    if (s <= 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) out[r] = fallback[r];
+        return;
+    }
+    const long long q = recip46(s);
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[r] = (int)(((long long)z[r] * q + (1ll << 21)) >> 22);
 }
 
-// Arg-max over the segment with the lowest x on ties (values < 2^25).
+// Arg-max over the segment with the lowest x on ties (values < 2^25); x0 = this
+// lane's first entry.
 template <int G>
-__device__ __forceinline__ int seg_argmax(int val, int x) {
-    const int key = seg_max<G>(val * 64 + (63 - x));
+__device__ __forceinline__ int seg_argmax(const int (&val)[Geo<G>::R], int x0) {
+    int key = val[0] * 64 + (63 - x0);
+#pragma unroll
+    for (int r = 1; r < Geo<G>::R; ++r) key = max(key, val[r] * 64 + (63 - x0 - r));
+    key = seg_max<G>(key);
     return 63 - (key & 63);
 }
 
@@ -83,90 +179,143 @@ __device__ __forceinline__ bool active(const Args &A, int k, int b) {
     return b < A.batch && (!A.early_stop || A.w.unsat[(size_t)k * A.batch + b]);
 }
 
-// Lane geometry of wave `unit` = (node, group of 64 / G codewords).
+// Lane geometry of wave `unit` = (node, group of 64 / S codewords).
 struct Lane {
-    int node, b, x, seg_base;
+    int node, b, j, x0;
 };
 
 template <int G>
 __device__ __forceinline__ Lane lane_of(const Args &A, long unit) {
-    constexpr int CPW = 64 / G;
+    constexpr int S = Geo<G>::S, CPW = Geo<G>::CPW;
     const int lane = threadIdx.x & 63;
     const long groups = (A.batch + CPW - 1) / CPW;
     Lane L;
     L.node = (int)(unit / groups);
     const int grp = (int)(unit - (long)L.node * groups);
-    L.b = grp * CPW + lane / G;
-    L.x = lane % G;
-    L.seg_base = lane - L.x;
+    L.b = grp * CPW + lane / S;
+    L.j = lane % S;
+    L.x0 = L.j * Geo<G>::R;
     return L;
+}
+
+// The R consecutive entries x0 .. x0 + R - 1 of a row.
+template <int R>
+__device__ __forceinline__ void load_row(const int *p, int (&v)[R]) {
+    if constexpr (R == 4) {
+        const int4 t = *(const int4 *)p;
+        v[0] = t.x, v[1] = t.y, v[2] = t.z, v[3] = t.w;
+    } else if constexpr (R == 2) {
+        const int2 t = *(const int2 *)p;
+        v[0] = t.x, v[1] = t.y;
+    } else {
+        v[0] = p[0];
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void store_row(int *p, const int (&v)[R]) {
+    if constexpr (R == 4) {
+        *(int4 *)p = make_int4(v[0], v[1], v[2], v[3]);
+    } else if constexpr (R == 2) {
+        *(int2 *)p = make_int2(v[0], v[1]);
+    } else {
+        p[0] = v[0];
+    }
+}
+
+// Row c of the multiplication table at entries x0 .. x0 + R - 1, one byte each
+// (the table is 256-byte aligned and x0 a multiple of R).
+template <int G>
+__device__ __forceinline__ uint32_t mul_row(const DevCode &C, int c, int x0) {
+    constexpr int R = Geo<G>::R;
+    const uint8_t *t = C.gfmul + c * G + x0;
+    if constexpr (R == 4) return *(const uint32_t *)t;
+    else if constexpr (R == 2) return *(const uint16_t *)t;
+    else return *t;
 }
 
 // Channel vectors, u = p on every edge of the variable, decision of iteration 0:
 // wave `unit` = (variable, group).
 template <int G>
 __device__ __forceinline__ void init_unit(const Args &A, long unit) {
+    constexpr int R = Geo<G>::R;
     const DevCode &C = A.C;
     const Lane L = lane_of<G>(A, unit);
     if (L.node >= C.n) return;
     const bool real = L.b < A.batch;
-    int c = real ? ((const int16_t *)A.io.llr)[((size_t)L.b * C.n + L.node) * G + L.x] : 0;
-    c = min(max(c, 0), kSpaWeights - 1);
-    const int w = C.spa_w[c];
-    const int p = normalise<G>(w, (1 << kQ) / G);
-    const int best = seg_argmax<G>(p, L.x);
+    const int16_t *src = (const int16_t *)A.io.llr + ((size_t)(real ? L.b : 0) * C.n + L.node) * G + L.x0;
+    int w[R], fb[R], p[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int c = real ? min(max((int)src[r], 0), kSpaWeights - 1) : 0;
+        w[r] = C.spa_w[c];
+        fb[r] = (1 << kQ) / G;
+    }
+    normalise<G>(w, fb, p);
+    const int best = seg_argmax<G>(p, L.x0);
     if (!real) return;
-    A.w.p[row(L.node, L.b, A.batch, G) + L.x] = p;
-    for (int t = C.vn_ptr[L.node]; t < C.vn_ptr[L.node + 1]; ++t) A.w.u[row(C.vn_ref[t], L.b, A.batch, G) + L.x] = p;
-    if (L.x == 0) ((uint8_t *)A.io.hard)[(size_t)L.b * C.n + L.node] = (uint8_t)best;
+    store_row<R>(A.w.p + row(L.node, L.b, A.batch, G) + L.x0, p);
+    for (int t = C.vn_ptr[L.node]; t < C.vn_ptr[L.node + 1]; ++t)
+        store_row<R>(A.w.u + row(C.vn_ref[t], L.b, A.batch, G) + L.x0, p);
+    if (L.j == 0) ((uint8_t *)A.io.hard)[(size_t)L.b * C.n + L.node] = (uint8_t)best;
 }
 
-// Check-node phase of iteration k (eqs. (7)-(9)): wave `unit` = (check, group).
-template <int G>
+// Check-node phase of iteration k (eqs. (7)-(9)): wave `unit` = (check, group), for
+// check degrees up to DC.
+template <int G, int DC>
 __device__ __forceinline__ void cn_unit(const Args &A, int k, long unit) {
-    constexpr int P = G == 64 ? 6 : G == 32 ? 5 : G == 16 ? 4 : G == 8 ? 3 : G == 4 ? 2 : 1;
+    constexpr int R = Geo<G>::R, P = Geo<G>::P;
     const DevCode &C = A.C;
     const Lane L = lane_of<G>(A, unit);
     if (L.node >= C.m) return;
     const bool act = active(A, k, L.b);
     if (__ballot(act) == 0) return;
+    const Signs sg = signs_of<G>(L.j);
     const int e0 = C.row_ptr[L.node];
     const int dc = C.row_ptr[L.node + 1] - e0;
     const int bb = L.b < A.batch ? L.b : A.batch - 1;  // lanes past the batch read a valid row
-    int U[kNbDcMax];
+    int U[DC][R];
+    uint32_t ix[DC];  // positions h^-1 x of this lane's entries, one byte each
 #pragma unroll
-    for (int j = 0; j < kNbDcMax; ++j) {
+    for (int j = 0; j < DC; ++j) {
         if (j < dc) {
             const int e = e0 + j;
-            const int idx = C.gfmul[C.hinv[e] * G + L.x];  // u'(t) = u(h^-1 t)
-            U[j] = wht<G>(A.w.u[row(e, bb, A.batch, G) + idx], L.x);
+            ix[j] = mul_row<G>(C, C.hinv[e], L.x0);
+            const int *src = A.w.u + row(e, bb, A.batch, G);
+#pragma unroll
+            for (int r = 0; r < R; ++r) U[j][r] = src[(ix[j] >> (8 * r)) & 0xFF];  // u'(t) = u(h^-1 t)
+            wht<G>(U[j], sg);
         }
     }
 #pragma unroll
-    for (int n = 0; n < kNbDcMax; ++n) {
+    for (int n = 0; n < DC; ++n) {
         if (n < dc) {
-            int acc = 0;
+            int acc[R];
             bool first = true;
 #pragma unroll
-            for (int j = 0; j < kNbDcMax; ++j) {
+            for (int j = 0; j < DC; ++j) {
                 if (j < dc && j != n) {
-                    acc = first ? U[j] : qmul(acc, U[j]);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[r] = first ? U[j][r] : qmul(acc[r], U[j][r]);
                     first = false;
                 }
             }
-            const int t = wht<G>(acc, L.x) >> P;  // floor(. / g)
-            const int v = max(t, 0);
-            const int e = e0 + n;
-            const int vp = __shfl(v, L.seg_base + C.gfmul[C.h[e] * G + L.x], 64);  // v'(x) = v(h x)
-            if (act) A.w.v[row(e, L.b, A.batch, G) + L.x] = vp;
+            wht<G>(acc, sg);
+            if (act) {
+                // v'(h^-1 z) = v(z): entry z goes to the position its load came from
+                int *dst = A.w.v + row(e0 + n, L.b, A.batch, G);
+#pragma unroll
+                for (int r = 0; r < R; ++r) dst[(ix[n] >> (8 * r)) & 0xFF] = max(acc[r] >> P, 0);  // floor(. / g)
+            }
         }
     }
 }
 
 // Variable-node phase of iteration k (eqs. (10)-(11)) and decision: wave `unit` =
-// (variable, group).
-template <int G>
+// (variable, group), for variable degrees up to DV.
+template <int G, int DV>
 __device__ __forceinline__ void vn_unit(const Args &A, int k, long unit) {
+    constexpr int R = Geo<G>::R;
     const DevCode &C = A.C;
     const Lane L = lane_of<G>(A, unit);
     if (L.node >= C.n) return;
@@ -175,28 +324,39 @@ __device__ __forceinline__ void vn_unit(const Args &A, int k, long unit) {
     const int bb = L.b < A.batch ? L.b : A.batch - 1;
     const int t0 = C.vn_ptr[L.node];
     const int dv = C.vn_ptr[L.node + 1] - t0;
-    const int p = A.w.p[row(L.node, bb, A.batch, G) + L.x];
-    int vv[kVnRegs];
+    int p[R];
+    load_row<R>(A.w.p + row(L.node, bb, A.batch, G) + L.x0, p);
+    int vv[DV][R];
 #pragma unroll
-    for (int t = 0; t < kVnRegs; ++t)
-        if (t < dv) vv[t] = A.w.v[row(C.vn_ref[t0 + t], bb, A.batch, G) + L.x];
+    for (int t = 0; t < DV; ++t)
+        if (t < dv) load_row<R>(A.w.v + row(C.vn_ref[t0 + t], bb, A.batch, G) + L.x0, vv[t]);
 #pragma unroll
-    for (int m = 0; m < kVnRegs; ++m) {
+    for (int m = 0; m < DV; ++m) {
         if (m < dv) {
-            int z = p;
+            int z[R], u[R];
 #pragma unroll
-            for (int t = 0; t < kVnRegs; ++t)
-                if (t < dv && t != m) z = qmul(z, vv[t]);
-            const int u = normalise<G>(z, p);
-            if (act) A.w.u[row(C.vn_ref[t0 + m], L.b, A.batch, G) + L.x] = u;
+            for (int r = 0; r < R; ++r) z[r] = p[r];
+#pragma unroll
+            for (int t = 0; t < DV; ++t)
+                if (t < dv && t != m) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) z[r] = qmul(z[r], vv[t][r]);
+                }
+            normalise<G>(z, p, u);
+            if (act) store_row<R>(A.w.u + row(C.vn_ref[t0 + m], L.b, A.batch, G) + L.x0, u);
         }
     }
-    int app = p;
+    int app[R];
 #pragma unroll
-    for (int t = 0; t < kVnRegs; ++t)
-        if (t < dv) app = qmul(app, vv[t]);
-    const int best = seg_argmax<G>(app, L.x);
-    if (act && L.x == 0) {
+    for (int r = 0; r < R; ++r) app[r] = p[r];
+#pragma unroll
+    for (int t = 0; t < DV; ++t)
+        if (t < dv) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) app[r] = qmul(app[r], vv[t][r]);
+        }
+    const int best = seg_argmax<G>(app, L.x0);
+    if (act && L.j == 0) {
         ((uint8_t *)A.io.hard)[(size_t)L.b * C.n + L.node] = (uint8_t)best;
         if (L.node == 0) A.w.it[L.b] = (int16_t)k;
     }

@@ -17,10 +17,10 @@ __global__ void __launch_bounds__(256) k_init(Args A) { dev::spa::init_unit<G>(A
 __global__ void __launch_bounds__(256) k_syn(Args A, int slot) {
     dev::spa::syn_thread(A, slot, (long)blockIdx.x * 256 + threadIdx.x);
 }
-template <int G>
-__global__ void __launch_bounds__(256) k_cn(Args A, int k) { dev::spa::cn_unit<G>(A, k, unit_id()); }
-template <int G>
-__global__ void __launch_bounds__(256) k_vn(Args A, int k) { dev::spa::vn_unit<G>(A, k, unit_id()); }
+template <int G, int DC>
+__global__ void __launch_bounds__(256) k_cn(Args A, int k) { dev::spa::cn_unit<G, DC>(A, k, unit_id()); }
+template <int G, int DV>
+__global__ void __launch_bounds__(256) k_vn(Args A, int k) { dev::spa::vn_unit<G, DV>(A, k, unit_id()); }
 __global__ void __launch_bounds__(256) k_fin(Args A) { dev::spa::fin_thread(A, (long)blockIdx.x * 256 + threadIdx.x); }
 __global__ void __launch_bounds__(256) k_dump(Args A, const int *src, int *dst) {
     dev::spa::dump_thread(A, src, dst, (long)blockIdx.x * 256 + threadIdx.x);
@@ -34,11 +34,14 @@ hipError_t fill(const dev::FillArgs &F, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int G>
+// The register arrays of the check and variable phases are sized by degree bounds
+// (4 or 16 for checks, 4 or 16 for variables) chosen from the code's largest degrees.
+template <int G, int DC, int DV>
 hipError_t run(const Args &A, hipStream_t s) {
     const DevCode &C = A.C;
     const long B = A.batch;
-    const long groups = (B + 64 / G - 1) / (64 / G);
+    constexpr int CPW = dev::spa::Geo<G>::CPW;
+    const long groups = (B + CPW - 1) / CPW;
     const dim3 blk(256);
     hipError_t e;
     const dev::spa::Carve cv = dev::spa::carve(C, A.max_iters, A.batch);
@@ -48,8 +51,8 @@ hipError_t run(const Args &A, hipStream_t s) {
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int k = 1; k <= A.max_iters; ++k) {
         if (A.early_stop) hipLaunchKernelGGL(k_syn, dim3(blocks(C.m * B, 256)), blk, 0, s, A, k);
-        hipLaunchKernelGGL(k_cn<G>, dim3(blocks(C.m * groups, 4)), blk, 0, s, A, k);
-        hipLaunchKernelGGL(k_vn<G>, dim3(blocks(C.n * groups, 4)), blk, 0, s, A, k);
+        hipLaunchKernelGGL((k_cn<G, DC>), dim3(blocks(C.m * groups, 4)), blk, 0, s, A, k);
+        hipLaunchKernelGGL((k_vn<G, DV>), dim3(blocks(C.n * groups, 4)), blk, 0, s, A, k);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_syn, dim3(blocks(C.m * B, 256)), blk, 0, s, A, 0);
@@ -64,6 +67,13 @@ hipError_t run(const Args &A, hipStream_t s) {
     return hipSuccess;
 }
 
+template <int G>
+hipError_t run_degrees(const Args &A, bool small_dc, bool small_dv, hipStream_t s) {
+    constexpr int D = kNbDcMax, V = dev::spa::kVnRegs;
+    if (small_dc) return small_dv ? run<G, 4, 4>(A, s) : run<G, 4, V>(A, s);
+    return small_dv ? run<G, D, 4>(A, s) : run<G, D, V>(A, s);
+}
+
 }  // namespace
 
 bool spa_supported(const DevCode &C) {
@@ -75,12 +85,13 @@ size_t spa_work_bytes(const DevCode &C, int max_iters, int batch) { return dev::
 hipError_t launch_spa(const DevCode &C, int max_iters, int early_stop, int batch, void *ws, const DecodeIO &io,
                       hipStream_t s) {
     const Args A = dev::spa::make_args(C, max_iters, early_stop, batch, ws, io);
+    const bool small_dc = C.dc_max <= 4, small_dv = C.dv_max <= 4;
     switch (C.g) {
-    case 4: return run<4>(A, s);
-    case 8: return run<8>(A, s);
-    case 16: return run<16>(A, s);
-    case 32: return run<32>(A, s);
-    case 64: return run<64>(A, s);
+    case 4: return run_degrees<4>(A, small_dc, small_dv, s);
+    case 8: return run_degrees<8>(A, small_dc, small_dv, s);
+    case 16: return run_degrees<16>(A, small_dc, small_dv, s);
+    case 32: return run_degrees<32>(A, small_dc, small_dv, s);
+    case 64: return run_degrees<64>(A, small_dc, small_dv, s);
     default: return hipErrorInvalidValue;
     }
 }

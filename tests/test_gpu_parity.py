@@ -556,13 +556,15 @@ def test_minmax_layered_rejections_and_ragged():
             assert torch.equal(a, b[sl])
 
 
-@pytest.mark.parametrize("g_size,n,dc,batch,early,iters", [
-    (4, 24, 4, 70, True, 6), (8, 24, 4, 33, False, 4), (16, 16, 4, 20, True, 5), (32, 30, 3, 9, True, 4),
-    (64, 16, 4, 5, False, 3), (64, 192, 4, 6, True, 5), (16, 20, 5, 7, True, 4), (4, 12, 2, 40, True, 3)])
-def test_spa_matches_oracle(g_size, n, dc, batch, early, iters):
-    """Fixed-point FFT-SPA (Alg. 1): decisions, flags, iteration counts and every u / v' message."""
-    m = n * 2 // dc
-    code = S.random_regular_nb_code(n, m, 2, dc, g_size, S.PRIM_POLY[g_size], seed=g_size + n + dc)
+@pytest.mark.parametrize("g_size,n,dc,batch,early,iters,dv", [
+    (4, 24, 4, 70, True, 6, 2), (8, 24, 4, 33, False, 4, 2), (16, 16, 4, 20, True, 5, 2), (32, 30, 3, 9, True, 4, 2),
+    (64, 16, 4, 5, False, 3, 2), (64, 192, 4, 6, True, 5, 2), (16, 20, 5, 7, True, 4, 2), (4, 12, 2, 40, True, 3, 2),
+    (64, 16, 6, 9, True, 4, 3), (32, 24, 8, 13, False, 3, 4), (8, 24, 4, 21, True, 4, 6), (64, 16, 4, 6, True, 3, 5), (64, 20, 5, 10, False, 3, 5)])
+def test_spa_matches_oracle(g_size, n, dc, batch, early, iters, dv):
+    """Fixed-point FFT-SPA (Alg. 1): decisions, flags, iteration counts and every u / v' message,
+    for check and variable degrees on both sides of the kernels' register bounds (4)."""
+    m = n * dv // dc
+    code = S.random_regular_nb_code(n, m, dv, dc, g_size, S.PRIM_POLY[g_size], seed=g_size + n + dc)
     cw = S.random_codewords(code, batch, seed=9)
     gam = S.nb_gamma_int16(cw, g_size, 1.5, seed=10)
     prm = dict(rule="spa", schedule="flooding", max_iters=iters, early_stop=early)
