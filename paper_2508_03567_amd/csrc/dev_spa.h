@@ -9,21 +9,24 @@
 // channel vectors come from the symbol costs gamma through the weights
 // W(c) = round(2^24 exp(-c / 4)).
 //
-// Mapping: a wavefront covers 64 / S codewords of one node, a segment of S = min(g, 16)
-// lanes per codeword; lane j of a segment holds the R = g / S consecutive entries
-// x = j R .. j R + R - 1 in registers.  The transform runs its butterflies over the
-// register bits in registers and over the lane bits with DPP moves inside a row of 16
-// lanes (quad_perm for directions 1 and 2, row_half_mirror for direction 7,
-// row_ror:8 for direction 8).  Directions {1, 2, 7, 8} span the lane index space, so
-// with each butterfly's sign taken from the dual basis (j0^j2, j1^j2, j2, j3) the
-// lane part is the Walsh-Hadamard transform in linearly relabelled coordinates: the
-// transformed values are those of the plain transform at fixed permuted positions,
-// the elementwise products see the same integer pairs, and forward then inverse
-// gives exactly g times the XOR convolution in the original index.  Segment sums,
-// maxima and the arg-max reduce over the same four directions.  The permutation by
-// the edge coefficient is folded into the check node's loads (gather) and the
-// depermutation into its stores (scatter to the same positions).  Messages are stored
-// codeword-major per edge, [edge][codeword][x] (int32).
+// Mapping: a wavefront covers 64 / S codewords of one node, a segment of S lanes per
+// codeword (S = 4, 8 or 16, at most g, chosen per kernel from the degree bound: the
+// more entries a lane holds, the more butterflies stay in registers, but the more
+// registers each message takes, which costs occupancy beyond 4 entries); lane j of a segment holds the
+// R = g / S consecutive entries x = j R .. j R + R - 1.  The transform runs its
+// butterflies over the register bits in registers and over the lane bits with DPP
+// moves inside a row of 16 lanes (quad_perm for directions 1 and 2, row_half_mirror
+// for direction 7, row_ror:8 for direction 8).  Directions {1, 2, 7, 8} span the lane
+// index space, so with each butterfly's sign taken from the dual basis (j0^j2, j1^j2,
+// j2, j3; j0, j1 for S = 4) the lane part is the Walsh-Hadamard transform in linearly
+// relabelled coordinates: the transformed values are those of the plain transform at
+// fixed permuted positions, the elementwise products see the same integer pairs, and
+// forward then inverse gives exactly g times the XOR convolution in the original
+// index.  Segment sums, maxima and the arg-max reduce over the same directions.  The
+// permutation by the edge coefficient is folded into the check node's loads (gather)
+// and the depermutation into its stores (scatter to the same positions).  Messages
+// are stored codeword-major per edge, [edge][codeword][x] (int32), whatever S is.
+// Products that share a leading run of factors (ascending order) are computed once.
 #pragma once
 
 #include "dev_common.h"
@@ -42,10 +45,17 @@ struct Args {
     DecodeIO io;
 };
 
-// Lanes per codeword, entries per lane, codewords per wave, log2(g).
-template <int G>
+// Lanes per codeword for a kernel whose register arrays hold D messages: up to 4
+// entries per lane for degrees up to 4, fewer above.
+template <int G, int D>
+constexpr int lanes_for() {
+    return D <= 4 ? (G / 4 > 4 ? G / 4 : 4) : (G < 16 ? G : 16);
+}
+
+// Entries per lane, codewords per wave, log2(g).
+template <int G, int S>
 struct Geo {
-    static constexpr int S = G < 16 ? G : 16;
+    static_assert(S == 4 || S == 8 || S == 16, "segments of 4, 8 or 16 lanes");
     static constexpr int R = G / S;
     static constexpr int CPW = 64 / S;
     static constexpr int P = G == 64 ? 6 : G == 32 ? 5 : G == 16 ? 4 : G == 8 ? 3 : 2;
@@ -69,20 +79,20 @@ template <int CTRL>
 __device__ __forceinline__ int dpp(int v) {
     return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
 }
-constexpr int kDppXor1 = 0xB1;    // quad_perm [1,0,3,2]
-constexpr int kDppXor2 = 0x4E;    // quad_perm [2,3,0,1]
+constexpr int kDppXor1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;      // quad_perm [2,3,0,1]
 constexpr int kDppMirror8 = 0x141;  // row_half_mirror: j -> j ^ 7 inside 8 lanes
-constexpr int kDppRor8 = 0x128;   // row_ror:8: j -> j ^ 8 inside 16 lanes
+constexpr int kDppRor8 = 0x128;     // row_ror:8: j -> j ^ 8 inside 16 lanes
 
 // Butterfly signs of the lane directions 1, 2, 7, 8 (the dual basis of the lane index).
 struct Signs {
     bool d1, d2, d7, d8;
 };
 
-template <int G>
+template <int S>
 __device__ __forceinline__ Signs signs_of(int j) {
     Signs s;
-    if (Geo<G>::S >= 8) {
+    if (S >= 8) {
         s.d1 = ((j ^ (j >> 2)) & 1) != 0;
         s.d2 = (((j >> 1) ^ (j >> 2)) & 1) != 0;
         s.d7 = ((j >> 2) & 1) != 0;
@@ -105,9 +115,8 @@ __device__ __forceinline__ void lane_stage(int (&v)[R], bool upper) {
 }
 
 // Walsh-Hadamard transform of the segment (relabelled in the lane bits, see above).
-template <int G>
-__device__ __forceinline__ void wht(int (&v)[Geo<G>::R], const Signs &sg) {
-    constexpr int R = Geo<G>::R, S = Geo<G>::S;
+template <int S, int R>
+__device__ __forceinline__ void wht(int (&v)[R], const Signs &sg) {
 #pragma unroll
     for (int s = 1; s < R; s <<= 1) {
 #pragma unroll
@@ -125,33 +134,31 @@ __device__ __forceinline__ void wht(int (&v)[Geo<G>::R], const Signs &sg) {
     if (S >= 16) lane_stage<kDppRor8>(v, sg.d8);
 }
 
-template <int G>
+template <int S>
 __device__ __forceinline__ int seg_sum(int v) {
     v += dpp<kDppXor1>(v);
     v += dpp<kDppXor2>(v);
-    if (Geo<G>::S >= 8) v += dpp<kDppMirror8>(v);
-    if (Geo<G>::S >= 16) v += dpp<kDppRor8>(v);
+    if (S >= 8) v += dpp<kDppMirror8>(v);
+    if (S >= 16) v += dpp<kDppRor8>(v);
     return v;
 }
 
-template <int G>
+template <int S>
 __device__ __forceinline__ int seg_max(int v) {
     v = max(v, dpp<kDppXor1>(v));
     v = max(v, dpp<kDppXor2>(v));
-    if (Geo<G>::S >= 8) v = max(v, dpp<kDppMirror8>(v));
-    if (Geo<G>::S >= 16) v = max(v, dpp<kDppRor8>(v));
+    if (S >= 8) v = max(v, dpp<kDppMirror8>(v));
+    if (S >= 16) v = max(v, dpp<kDppRor8>(v));
     return v;
 }
 
 // out = norm(z) for this lane's entries; `fallback` when the segment sum is 0.
-template <int G>
-__device__ __forceinline__ void normalise(const int (&z)[Geo<G>::R], const int (&fallback)[Geo<G>::R],
-                                          int (&out)[Geo<G>::R]) {
-    constexpr int R = Geo<G>::R;
+template <int S, int R>
+__device__ __forceinline__ void normalise(const int (&z)[R], const int (&fallback)[R], int (&out)[R]) {
     int s = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) s += z[r];
-    s = seg_sum<G>(s);
+    s = seg_sum<S>(s);
     if (s <= 0) {
 #pragma unroll
         for (int r = 0; r < R; ++r) out[r] = fallback[r];
@@ -164,12 +171,12 @@ __device__ __forceinline__ void normalise(const int (&z)[Geo<G>::R], const int (
 
 // Arg-max over the segment with the lowest x on ties (values < 2^25); x0 = this
 // lane's first entry.
-template <int G>
-__device__ __forceinline__ int seg_argmax(const int (&val)[Geo<G>::R], int x0) {
+template <int S, int R>
+__device__ __forceinline__ int seg_argmax(const int (&val)[R], int x0) {
     int key = val[0] * 64 + (63 - x0);
 #pragma unroll
-    for (int r = 1; r < Geo<G>::R; ++r) key = max(key, val[r] * 64 + (63 - x0 - r));
-    key = seg_max<G>(key);
+    for (int r = 1; r < R; ++r) key = max(key, val[r] * 64 + (63 - x0 - r));
+    key = seg_max<S>(key);
     return 63 - (key & 63);
 }
 
@@ -184,9 +191,9 @@ struct Lane {
     int node, b, j, x0;
 };
 
-template <int G>
+template <int G, int S>
 __device__ __forceinline__ Lane lane_of(const Args &A, long unit) {
-    constexpr int S = Geo<G>::S, CPW = Geo<G>::CPW;
+    constexpr int CPW = Geo<G, S>::CPW;
     const int lane = threadIdx.x & 63;
     const long groups = (A.batch + CPW - 1) / CPW;
     Lane L;
@@ -194,16 +201,19 @@ __device__ __forceinline__ Lane lane_of(const Args &A, long unit) {
     const int grp = (int)(unit - (long)L.node * groups);
     L.b = grp * CPW + lane / S;
     L.j = lane % S;
-    L.x0 = L.j * Geo<G>::R;
+    L.x0 = L.j * Geo<G, S>::R;
     return L;
 }
 
-// The R consecutive entries x0 .. x0 + R - 1 of a row.
+// The R consecutive entries x0 .. x0 + R - 1 of a row (16-byte aligned for R >= 4).
 template <int R>
 __device__ __forceinline__ void load_row(const int *p, int (&v)[R]) {
-    if constexpr (R == 4) {
-        const int4 t = *(const int4 *)p;
-        v[0] = t.x, v[1] = t.y, v[2] = t.z, v[3] = t.w;
+    if constexpr (R >= 4) {
+#pragma unroll
+        for (int q = 0; q < R / 4; ++q) {
+            const int4 t = ((const int4 *)p)[q];
+            v[4 * q] = t.x, v[4 * q + 1] = t.y, v[4 * q + 2] = t.z, v[4 * q + 3] = t.w;
+        }
     } else if constexpr (R == 2) {
         const int2 t = *(const int2 *)p;
         v[0] = t.x, v[1] = t.y;
@@ -214,8 +224,9 @@ __device__ __forceinline__ void load_row(const int *p, int (&v)[R]) {
 
 template <int R>
 __device__ __forceinline__ void store_row(int *p, const int (&v)[R]) {
-    if constexpr (R == 4) {
-        *(int4 *)p = make_int4(v[0], v[1], v[2], v[3]);
+    if constexpr (R >= 4) {
+#pragma unroll
+        for (int q = 0; q < R / 4; ++q) ((int4 *)p)[q] = make_int4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
     } else if constexpr (R == 2) {
         *(int2 *)p = make_int2(v[0], v[1]);
     } else {
@@ -223,24 +234,33 @@ __device__ __forceinline__ void store_row(int *p, const int (&v)[R]) {
     }
 }
 
-// Row c of the multiplication table at entries x0 .. x0 + R - 1, one byte each
-// (the table is 256-byte aligned and x0 a multiple of R).
-template <int G>
-__device__ __forceinline__ uint32_t mul_row(const DevCode &C, int c, int x0) {
-    constexpr int R = Geo<G>::R;
-    const uint8_t *t = C.gfmul + c * G + x0;
-    if constexpr (R == 4) return *(const uint32_t *)t;
-    else if constexpr (R == 2) return *(const uint16_t *)t;
-    else return *t;
-}
+// Row c of the multiplication table at entries x0 .. x0 + R - 1, one byte each, packed
+// four to a word (the table is 256-byte aligned and x0 a multiple of R).
+template <int G, int R>
+struct MulRow {
+    static constexpr int W = (R + 3) / 4;
+    uint32_t w[W];
+    __device__ __forceinline__ void load(const DevCode &C, int c, int x0) {
+        const uint8_t *t = C.gfmul + c * G + x0;
+        if constexpr (R >= 4) {
+#pragma unroll
+            for (int q = 0; q < W; ++q) w[q] = ((const uint32_t *)t)[q];
+        } else if constexpr (R == 2) {
+            w[0] = *(const uint16_t *)t;
+        } else {
+            w[0] = *t;
+        }
+    }
+    __device__ __forceinline__ int operator[](int r) const { return (w[r >> 2] >> (8 * (r & 3))) & 0xFF; }
+};
 
 // Channel vectors, u = p on every edge of the variable, decision of iteration 0:
 // wave `unit` = (variable, group).
-template <int G>
+template <int G, int S>
 __device__ __forceinline__ void init_unit(const Args &A, long unit) {
-    constexpr int R = Geo<G>::R;
+    constexpr int R = Geo<G, S>::R;
     const DevCode &C = A.C;
-    const Lane L = lane_of<G>(A, unit);
+    const Lane L = lane_of<G, S>(A, unit);
     if (L.node >= C.n) return;
     const bool real = L.b < A.batch;
     const int16_t *src = (const int16_t *)A.io.llr + ((size_t)(real ? L.b : 0) * C.n + L.node) * G + L.x0;
@@ -251,8 +271,8 @@ __device__ __forceinline__ void init_unit(const Args &A, long unit) {
         w[r] = C.spa_w[c];
         fb[r] = (1 << kQ) / G;
     }
-    normalise<G>(w, fb, p);
-    const int best = seg_argmax<G>(p, L.x0);
+    normalise<S>(w, fb, p);
+    const int best = seg_argmax<S>(p, L.x0);
     if (!real) return;
     store_row<R>(A.w.p + row(L.node, L.b, A.batch, G) + L.x0, p);
     for (int t = C.vn_ptr[L.node]; t < C.vn_ptr[L.node + 1]; ++t)
@@ -264,49 +284,54 @@ __device__ __forceinline__ void init_unit(const Args &A, long unit) {
 // check degrees up to DC.
 template <int G, int DC>
 __device__ __forceinline__ void cn_unit(const Args &A, int k, long unit) {
-    constexpr int R = Geo<G>::R, P = Geo<G>::P;
+    constexpr int S = lanes_for<G, DC>(), R = Geo<G, S>::R, P = Geo<G, S>::P;
     const DevCode &C = A.C;
-    const Lane L = lane_of<G>(A, unit);
+    const Lane L = lane_of<G, S>(A, unit);
     if (L.node >= C.m) return;
     const bool act = active(A, k, L.b);
     if (__ballot(act) == 0) return;
-    const Signs sg = signs_of<G>(L.j);
+    const Signs sg = signs_of<S>(L.j);
     const int e0 = C.row_ptr[L.node];
     const int dc = C.row_ptr[L.node + 1] - e0;
     const int bb = L.b < A.batch ? L.b : A.batch - 1;  // lanes past the batch read a valid row
     int U[DC][R];
-    uint32_t ix[DC];  // positions h^-1 x of this lane's entries, one byte each
+    MulRow<G, R> ix[DC];  // positions h^-1 x of this lane's entries
 #pragma unroll
     for (int j = 0; j < DC; ++j) {
         if (j < dc) {
             const int e = e0 + j;
-            ix[j] = mul_row<G>(C, C.hinv[e], L.x0);
+            ix[j].load(C, C.hinv[e], L.x0);
             const int *src = A.w.u + row(e, bb, A.batch, G);
 #pragma unroll
-            for (int r = 0; r < R; ++r) U[j][r] = src[(ix[j] >> (8 * r)) & 0xFF];  // u'(t) = u(h^-1 t)
-            wht<G>(U[j], sg);
+            for (int r = 0; r < R; ++r) U[j][r] = src[ix[j][r]];  // u'(t) = u(h^-1 t)
+            wht<S>(U[j], sg);
         }
     }
+    // Output n takes the product of every other transformed input in ascending order;
+    // pre holds the product of inputs 0 .. n-1, shared by the outputs after it.
+    int pre[R];
 #pragma unroll
     for (int n = 0; n < DC; ++n) {
         if (n < dc) {
             int acc[R];
-            bool first = true;
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = n > 0 ? pre[r] : (dc > 1 ? U[1][r] : 0);
 #pragma unroll
             for (int j = 0; j < DC; ++j) {
-                if (j < dc && j != n) {
+                if (j < dc && j > (n > 0 ? n : 1)) {
 #pragma unroll
-                    for (int r = 0; r < R; ++r) acc[r] = first ? U[j][r] : qmul(acc[r], U[j][r]);
-                    first = false;
+                    for (int r = 0; r < R; ++r) acc[r] = qmul(acc[r], U[j][r]);
                 }
             }
-            wht<G>(acc, sg);
+            wht<S>(acc, sg);
             if (act) {
                 // v'(h^-1 z) = v(z): entry z goes to the position its load came from
                 int *dst = A.w.v + row(e0 + n, L.b, A.batch, G);
 #pragma unroll
-                for (int r = 0; r < R; ++r) dst[(ix[n] >> (8 * r)) & 0xFF] = max(acc[r] >> P, 0);  // floor(. / g)
+                for (int r = 0; r < R; ++r) dst[ix[n][r]] = max(acc[r] >> P, 0);  // floor(. / g)
             }
+#pragma unroll
+            for (int r = 0; r < R; ++r) pre[r] = n > 0 ? qmul(pre[r], U[n][r]) : U[0][r];
         }
     }
 }
@@ -315,9 +340,9 @@ __device__ __forceinline__ void cn_unit(const Args &A, int k, long unit) {
 // (variable, group), for variable degrees up to DV.
 template <int G, int DV>
 __device__ __forceinline__ void vn_unit(const Args &A, int k, long unit) {
-    constexpr int R = Geo<G>::R;
+    constexpr int S = lanes_for<G, DV>(), R = Geo<G, S>::R;
     const DevCode &C = A.C;
-    const Lane L = lane_of<G>(A, unit);
+    const Lane L = lane_of<G, S>(A, unit);
     if (L.node >= C.n) return;
     const bool act = active(A, k, L.b);
     if (__ballot(act) == 0) return;
@@ -330,32 +355,30 @@ __device__ __forceinline__ void vn_unit(const Args &A, int k, long unit) {
 #pragma unroll
     for (int t = 0; t < DV; ++t)
         if (t < dv) load_row<R>(A.w.v + row(C.vn_ref[t0 + t], bb, A.batch, G) + L.x0, vv[t]);
+    // u_m = norm(p times every incoming message but m, ascending); pre holds p times
+    // messages 0 .. m-1, and after the last edge it is the a posteriori product.
+    int pre[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) pre[r] = p[r];
 #pragma unroll
     for (int m = 0; m < DV; ++m) {
         if (m < dv) {
             int z[R], u[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) z[r] = p[r];
+            for (int r = 0; r < R; ++r) z[r] = pre[r];
 #pragma unroll
             for (int t = 0; t < DV; ++t)
-                if (t < dv && t != m) {
+                if (t < dv && t > m) {
 #pragma unroll
                     for (int r = 0; r < R; ++r) z[r] = qmul(z[r], vv[t][r]);
                 }
-            normalise<G>(z, p, u);
+            normalise<S>(z, p, u);
             if (act) store_row<R>(A.w.u + row(C.vn_ref[t0 + m], L.b, A.batch, G) + L.x0, u);
+#pragma unroll
+            for (int r = 0; r < R; ++r) pre[r] = qmul(pre[r], vv[m][r]);
         }
     }
-    int app[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) app[r] = p[r];
-#pragma unroll
-    for (int t = 0; t < DV; ++t)
-        if (t < dv) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) app[r] = qmul(app[r], vv[t][r]);
-        }
-    const int best = seg_argmax<G>(app, L.x0);
+    const int best = seg_argmax<S>(pre, L.x0);
     if (act && L.j == 0) {
         ((uint8_t *)A.io.hard)[(size_t)L.b * C.n + L.node] = (uint8_t)best;
         if (L.node == 0) A.w.it[L.b] = (int16_t)k;

@@ -12,8 +12,9 @@ using dev::spa::Args;
 __device__ __forceinline__ long unit_id() { return (long)blockIdx.x * 4 + dev::wave_id(); }
 
 __global__ void __launch_bounds__(256) k_fill(dev::FillArgs F) { dev::fill_block(F, blockIdx.x); }
+constexpr int kInitLanes = 4;  // lanes per codeword of the channel-vector kernel
 template <int G>
-__global__ void __launch_bounds__(256) k_init(Args A) { dev::spa::init_unit<G>(A, unit_id()); }
+__global__ void __launch_bounds__(256) k_init(Args A) { dev::spa::init_unit<G, kInitLanes>(A, unit_id()); }
 __global__ void __launch_bounds__(256) k_syn(Args A, int slot) {
     dev::spa::syn_thread(A, slot, (long)blockIdx.x * 256 + threadIdx.x);
 }
@@ -40,19 +41,22 @@ template <int G, int DC, int DV>
 hipError_t run(const Args &A, hipStream_t s) {
     const DevCode &C = A.C;
     const long B = A.batch;
-    constexpr int CPW = dev::spa::Geo<G>::CPW;
-    const long groups = (B + CPW - 1) / CPW;
+    // codeword groups of each kernel (its lanes per codeword set the group size)
+    constexpr int CI = dev::spa::Geo<G, kInitLanes>::CPW;
+    constexpr int CC = dev::spa::Geo<G, dev::spa::lanes_for<G, DC>()>::CPW;
+    constexpr int CV = dev::spa::Geo<G, dev::spa::lanes_for<G, DV>()>::CPW;
+    const long gi = (B + CI - 1) / CI, gc = (B + CC - 1) / CC, gv = (B + CV - 1) / CV;
     const dim3 blk(256);
     hipError_t e;
     const dev::spa::Carve cv = dev::spa::carve(C, A.max_iters, A.batch);
     if ((e = fill(dev::FillArgs{(uint32_t *)A.w.unsat, (cv.it - cv.unsat) / 4, 0u}, s)) != hipSuccess) return e;
     if ((e = fill(dev::FillArgs{(uint32_t *)A.w.it, (size_t)(B + 1) / 2, 0u}, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_init<G>, dim3(blocks(C.n * groups, 4)), blk, 0, s, A);
+    hipLaunchKernelGGL(k_init<G>, dim3(blocks(C.n * gi, 4)), blk, 0, s, A);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int k = 1; k <= A.max_iters; ++k) {
         if (A.early_stop) hipLaunchKernelGGL(k_syn, dim3(blocks(C.m * B, 256)), blk, 0, s, A, k);
-        hipLaunchKernelGGL((k_cn<G, DC>), dim3(blocks(C.m * groups, 4)), blk, 0, s, A, k);
-        hipLaunchKernelGGL((k_vn<G, DV>), dim3(blocks(C.n * groups, 4)), blk, 0, s, A, k);
+        hipLaunchKernelGGL((k_cn<G, DC>), dim3(blocks(C.m * gc, 4)), blk, 0, s, A, k);
+        hipLaunchKernelGGL((k_vn<G, DV>), dim3(blocks(C.n * gv, 4)), blk, 0, s, A, k);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_syn, dim3(blocks(C.m * B, 256)), blk, 0, s, A, 0);
@@ -79,6 +83,8 @@ hipError_t run_degrees(const Args &A, bool small_dc, bool small_dv, hipStream_t 
 bool spa_supported(const DevCode &C) {
     return C.g >= 4 && C.g <= 64 && C.dc_max <= kNbDcMax && C.dv_max <= dev::spa::kVnRegs;
 }
+
+int spa_cw_per_wave(const DevCode &C) { return C.dc_max <= 4 ? 64 / std::max(4, C.g / 4) : 64 / std::min(C.g, 16); }
 
 size_t spa_work_bytes(const DevCode &C, int max_iters, int batch) { return dev::spa::carve(C, max_iters, batch).total; }
 

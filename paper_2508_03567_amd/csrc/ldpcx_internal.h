@@ -138,6 +138,7 @@ struct SpaWork {
 };
 bool spa_supported(const DevCode &C);
 size_t spa_work_bytes(const DevCode &C, int max_iters, int batch);
+int spa_cw_per_wave(const DevCode &C);  // codewords per wave of the check-node kernel
 hipError_t launch_spa(const DevCode &C, int max_iters, int early_stop, int batch, void *ws, const DecodeIO &io,
                       hipStream_t s);
 

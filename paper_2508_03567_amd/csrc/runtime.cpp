@@ -137,7 +137,7 @@ Plan default_plan(const ldpcx_code *c, const ldpcx_decode_params *p, int batch) 
     if (c->g > 2 && p->rule == LDPCX_RULE_SPA) {
         pl.family = FAMILY_SPA;
         pl.schedule = LDPCX_SCHED_FLOODING;
-        pl.cpw = 64 / std::min(c->g, 16);  // codewords per wave
+        pl.cpw = spa_cw_per_wave(c->dev);
         pl.threads = 256;
         return pl;
     }
@@ -823,7 +823,7 @@ ldpcx_status ldpcx_plan_set(ldpcx_code *c, const ldpcx_decode_params *params, in
         pl.threads = threads;
     }
     if (family == FAMILY_SPA) {
-        pl.cpw = 64 / std::min(c->g, 16);  // codewords per wave
+        pl.cpw = spa_cw_per_wave(c->dev);
         pl.threads = 256;
     }
     std::lock_guard<std::mutex> lk(c->mu);
