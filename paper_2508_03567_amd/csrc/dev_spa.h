@@ -75,43 +75,59 @@ __device__ __forceinline__ long long recip46(int s) {
     return q;
 }
 
+// DPP move of v inside each row of 16 lanes; every control used reads a lane of the
+// same row, so no lane is out of bounds and the move needs no old value.
 template <int CTRL>
 __device__ __forceinline__ int dpp(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
 }
 constexpr int kDppXor1 = 0xB1;      // quad_perm [1,0,3,2]
 constexpr int kDppXor2 = 0x4E;      // quad_perm [2,3,0,1]
 constexpr int kDppMirror8 = 0x141;  // row_half_mirror: j -> j ^ 7 inside 8 lanes
 constexpr int kDppRor8 = 0x128;     // row_ror:8: j -> j ^ 8 inside 16 lanes
 
-// Butterfly signs of the lane directions 1, 2, 7, 8 (the dual basis of the lane index).
+// Butterfly signs of the lane directions 1, 2, 7, 8 (the dual basis of the lane index)
+// as masks (-1 on the lane that takes the difference, 0 on the one that takes the sum),
+// and the per-lane constant the xor form of the lane stages leaves behind.
 struct Signs {
-    bool d1, d2, d7, d8;
+    int d1, d2, d7, d8, corr;
 };
+
+// One lane stage in two VALU operations: o + (v ^ mask) is o + v on a sum lane and
+// o - v - 1 on a difference lane.  The stages are affine with a data-independent
+// offset, so the transform of x comes out as T(x) + T'(0); wht subtracts corr = T'(0).
+template <int CTRL, int R>
+__device__ __forceinline__ void lane_stage(int (&v)[R], int mask) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = dpp<CTRL>(v[r]) + (v[r] ^ mask);
+}
+
+template <int S, int R>
+__device__ __forceinline__ void lane_stages(int (&v)[R], const Signs &sg) {
+    lane_stage<kDppXor1>(v, sg.d1);
+    lane_stage<kDppXor2>(v, sg.d2);
+    if (S >= 8) lane_stage<kDppMirror8>(v, sg.d7);
+    if (S >= 16) lane_stage<kDppRor8>(v, sg.d8);
+}
 
 template <int S>
 __device__ __forceinline__ Signs signs_of(int j) {
     Signs s;
     if (S >= 8) {
-        s.d1 = ((j ^ (j >> 2)) & 1) != 0;
-        s.d2 = (((j >> 1) ^ (j >> 2)) & 1) != 0;
-        s.d7 = ((j >> 2) & 1) != 0;
-        s.d8 = ((j >> 3) & 1) != 0;
+        s.d1 = -((j ^ (j >> 2)) & 1);
+        s.d2 = -(((j >> 1) ^ (j >> 2)) & 1);
+        s.d7 = -((j >> 2) & 1);
+        s.d8 = -((j >> 3) & 1);
     } else {
-        s.d1 = (j & 1) != 0;
-        s.d2 = ((j >> 1) & 1) != 0;
-        s.d7 = s.d8 = false;
+        s.d1 = -(j & 1);
+        s.d2 = -((j >> 1) & 1);
+        s.d7 = s.d8 = 0;
     }
+    int z[1] = {0};
+    s.corr = 0;
+    lane_stages<S>(z, s);
+    s.corr = z[0];
     return s;
-}
-
-template <int CTRL, int R>
-__device__ __forceinline__ void lane_stage(int (&v)[R], bool upper) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int o = dpp<CTRL>(v[r]);
-        v[r] = upper ? o - v[r] : v[r] + o;
-    }
 }
 
 // Walsh-Hadamard transform of the segment (relabelled in the lane bits, see above).
@@ -128,10 +144,9 @@ __device__ __forceinline__ void wht(int (&v)[R], const Signs &sg) {
             }
         }
     }
-    lane_stage<kDppXor1>(v, sg.d1);
-    lane_stage<kDppXor2>(v, sg.d2);
-    if (S >= 8) lane_stage<kDppMirror8>(v, sg.d7);
-    if (S >= 16) lane_stage<kDppRor8>(v, sg.d8);
+    lane_stages<S>(v, sg);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] -= sg.corr;
 }
 
 template <int S>
@@ -330,8 +345,10 @@ __device__ __forceinline__ void cn_unit(const Args &A, int k, long unit) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) dst[ix[n][r]] = max(acc[r] >> P, 0);  // floor(. / g)
             }
+            if (n + 1 < dc) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) pre[r] = n > 0 ? qmul(pre[r], U[n][r]) : U[0][r];
+                for (int r = 0; r < R; ++r) pre[r] = n > 0 ? qmul(pre[r], U[n][r]) : U[0][r];
+            }
         }
     }
 }
