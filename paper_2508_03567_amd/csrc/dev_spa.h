@@ -220,6 +220,10 @@ __device__ __forceinline__ Lane lane_of(const Args &A, long unit) {
     return L;
 }
 
+// Make this wave's LDS writes visible to its other lanes (and its reads complete)
+// before the next LDS access.
+__device__ __forceinline__ void lds_sync_wave() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
 // The R consecutive entries x0 .. x0 + R - 1 of a row (16-byte aligned for R >= 4).
 template <int R>
 __device__ __forceinline__ void load_row(const int *p, int (&v)[R]) {
@@ -309,6 +313,10 @@ __device__ __forceinline__ void cn_unit(const Args &A, int k, long unit) {
     const int e0 = C.row_ptr[L.node];
     const int dc = C.row_ptr[L.node + 1] - e0;
     const int bb = L.b < A.batch ? L.b : A.batch - 1;  // lanes past the batch read a valid row
+    // Rows move between HBM and registers whole (R consecutive entries per lane); the
+    // permutations go through this wave's LDS row of each codeword.
+    __shared__ __align__(16) int stage[4][64 * R];
+    int *srow = stage[threadIdx.x >> 6] + ((threadIdx.x & 63) / S) * G;
     int U[DC][R];
     MulRow<G, R> ix[DC];  // positions h^-1 x of this lane's entries
 #pragma unroll
@@ -316,9 +324,13 @@ __device__ __forceinline__ void cn_unit(const Args &A, int k, long unit) {
         if (j < dc) {
             const int e = e0 + j;
             ix[j].load(C, C.hinv[e], L.x0);
-            const int *src = A.w.u + row(e, bb, A.batch, G);
+            int t[R];
+            load_row<R>(A.w.u + row(e, bb, A.batch, G) + L.x0, t);
+            store_row<R>(srow + L.x0, t);
+            lds_sync_wave();
 #pragma unroll
-            for (int r = 0; r < R; ++r) U[j][r] = src[ix[j][r]];  // u'(t) = u(h^-1 t)
+            for (int r = 0; r < R; ++r) U[j][r] = srow[ix[j][r]];  // u'(t) = u(h^-1 t)
+            lds_sync_wave();
             wht<S>(U[j], sg);
         }
     }
@@ -339,12 +351,14 @@ __device__ __forceinline__ void cn_unit(const Args &A, int k, long unit) {
                 }
             }
             wht<S>(acc, sg);
-            if (act) {
-                // v'(h^-1 z) = v(z): entry z goes to the position its load came from
-                int *dst = A.w.v + row(e0 + n, L.b, A.batch, G);
+            // v'(h^-1 z) = v(z): entry z goes to the position its load came from
 #pragma unroll
-                for (int r = 0; r < R; ++r) dst[ix[n][r]] = max(acc[r] >> P, 0);  // floor(. / g)
-            }
+            for (int r = 0; r < R; ++r) srow[ix[n][r]] = max(acc[r] >> P, 0);  // floor(. / g)
+            lds_sync_wave();
+            int t[R];
+            load_row<R>(srow + L.x0, t);
+            lds_sync_wave();
+            if (act) store_row<R>(A.w.v + row(e0 + n, L.b, A.batch, G) + L.x0, t);
             if (n + 1 < dc) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) pre[r] = n > 0 ? qmul(pre[r], U[n][r]) : U[0][r];
