@@ -203,9 +203,14 @@ ldpcx_status ldpcx_tune(const ldpcx_code *code, const ldpcx_decode_params *param
 
 /* Launch configuration that the next decode of (code, params, batch) would use:
  * kernel family (0 = LDS-resident binary, 1 = interleaved binary, 2 = Min-Max (interleaved
- * up to GF(64), lanes over entries above), 4 = FFT-SPA (lanes over entries), 5 = Min-Max
+ * up to GF(64), lanes over entries above), 4 = FFT-SPA (one wave per node and group of
+ * codewords, lanes over entries; codewords per workgroup reports codewords per wave of
+ * the check-node kernel), 5 = Min-Max
  * with one group of 64 codewords per workgroup and its messages in LDS (GF(4)..GF(64),
  * codes whose alpha and beta for 64 codewords fit 160 KB; 256, 512 or 1024 threads),
+ * 6 = FFT-SPA with cw_per_wg codewords per workgroup and every vector in LDS, all
+ * iterations in one launch (check and variable degrees <= 4, the vectors of cw_per_wg
+ * codewords within 160 KB; 256, 512 or 1024 threads),
  * 3 = packed two-codewords-per-lane binary for quasi-cyclic codes, available
  * when every layer of z rows consists of z x z circulant blocks, at most 16 layers and
  * 8 blocks per layer), codewords per workgroup (family 1: codewords per launch
@@ -219,9 +224,10 @@ ldpcx_status ldpcx_plan_info(const ldpcx_code *code, const ldpcx_decode_params *
  * family 0 (threads a multiple of 64 in [64, 1024]); cw_per_wg by family 3 (even, the
  * pairs' rows at most 512 threads) and by family 1 (slice size, rounded up to a multiple
  * of 128 and capped by the batch and the 31-bit offset limit).  The pinned plan must be able to
- * run the requested schedule (LDPCX_E_UNSUPPORTED otherwise; families 1 and 4 are
+ * run the requested schedule (LDPCX_E_UNSUPPORTED otherwise; families 1, 4 and 6 are
  * flooding only, families 2 and 5 run the layered schedule up to GF(64)); family 5
- * takes threads = 256, 512 or 1024.  Results never depend on the plan. */
+ * takes threads = 256, 512 or 1024, family 6 cw_per_wg in [1, 64] and threads = 256,
+ * 512 or 1024.  Results never depend on the plan. */
 ldpcx_status ldpcx_plan_set(ldpcx_code *code, const ldpcx_decode_params *params, int32_t batch,
                             int32_t family, int32_t cw_per_wg, int32_t threads);
 

@@ -273,8 +273,8 @@ struct MulRow {
     __device__ __forceinline__ int operator[](int r) const { return (w[r >> 2] >> (8 * (r & 3))) & 0xFF; }
 };
 
-// Channel vectors, u = p on every edge of the variable, decision of iteration 0:
-// wave `unit` = (variable, group).
+// Channel vectors, u = p and v = 0 on every edge of the variable, decision of
+// iteration 0: wave `unit` = (variable, group).
 template <int G, int S>
 __device__ __forceinline__ void init_unit(const Args &A, long unit) {
     constexpr int R = Geo<G, S>::R;
@@ -294,48 +294,33 @@ __device__ __forceinline__ void init_unit(const Args &A, long unit) {
     const int best = seg_argmax<S>(p, L.x0);
     if (!real) return;
     store_row<R>(A.w.p + row(L.node, L.b, A.batch, G) + L.x0, p);
-    for (int t = C.vn_ptr[L.node]; t < C.vn_ptr[L.node + 1]; ++t)
+    const int zero[R] = {};
+    for (int t = C.vn_ptr[L.node]; t < C.vn_ptr[L.node + 1]; ++t) {
         store_row<R>(A.w.u + row(C.vn_ref[t], L.b, A.batch, G) + L.x0, p);
+        store_row<R>(A.w.v + row(C.vn_ref[t], L.b, A.batch, G) + L.x0, zero);  // v = 0 until a check writes it
+    }
     if (L.j == 0) ((uint8_t *)A.io.hard)[(size_t)L.b * C.n + L.node] = (uint8_t)best;
 }
 
-// Check-node phase of iteration k (eqs. (7)-(9)): wave `unit` = (check, group), for
-// check degrees up to DC.
-template <int G, int DC>
-__device__ __forceinline__ void cn_unit(const Args &A, int k, long unit) {
-    constexpr int S = lanes_for<G, DC>(), R = Geo<G, S>::R, P = Geo<G, S>::P;
-    const DevCode &C = A.C;
-    const Lane L = lane_of<G, S>(A, unit);
-    if (L.node >= C.m) return;
-    const bool act = active(A, k, L.b);
-    if (__ballot(act) == 0) return;
-    const Signs sg = signs_of<S>(L.j);
-    const int e0 = C.row_ptr[L.node];
-    const int dc = C.row_ptr[L.node + 1] - e0;
-    const int bb = L.b < A.batch ? L.b : A.batch - 1;  // lanes past the batch read a valid row
-    // Rows move between HBM and registers whole (R consecutive entries per lane); the
-    // permutations go through this wave's LDS row of each codeword.
-    __shared__ __align__(16) int stage[4][64 * R];
-    int *srow = stage[threadIdx.x >> 6] + ((threadIdx.x & 63) / S) * G;
+// Check-node arithmetic of eqs. (7)-(9) for one lane: load_u(j, ix, U) fills the
+// permuted inputs u'(t) = u(h^-1 t) of edge j (ix: positions h^-1 x of this lane's
+// entries), store_v(n, ix, v) writes output n at the same positions (v'(h^-1 z) = v(z)).
+// Output n takes the product of every other transformed input in ascending order; pre
+// holds the product of inputs 0 .. n-1, shared by the outputs after it.
+template <int G, int S, int DC, class LoadU, class StoreV>
+__device__ __forceinline__ void cn_core(const DevCode &C, int e0, int dc, int x0, const Signs &sg, LoadU load_u,
+                                        StoreV store_v) {
+    constexpr int R = Geo<G, S>::R, P = Geo<G, S>::P;
     int U[DC][R];
-    MulRow<G, R> ix[DC];  // positions h^-1 x of this lane's entries
+    MulRow<G, R> ix[DC];
 #pragma unroll
     for (int j = 0; j < DC; ++j) {
         if (j < dc) {
-            const int e = e0 + j;
-            ix[j].load(C, C.hinv[e], L.x0);
-            int t[R];
-            load_row<R>(A.w.u + row(e, bb, A.batch, G) + L.x0, t);
-            store_row<R>(srow + L.x0, t);
-            lds_sync_wave();
-#pragma unroll
-            for (int r = 0; r < R; ++r) U[j][r] = srow[ix[j][r]];  // u'(t) = u(h^-1 t)
-            lds_sync_wave();
+            ix[j].load(C, C.hinv[e0 + j], x0);
+            load_u(j, ix[j], U[j]);
             wht<S>(U[j], sg);
         }
     }
-    // Output n takes the product of every other transformed input in ascending order;
-    // pre holds the product of inputs 0 .. n-1, shared by the outputs after it.
     int pre[R];
 #pragma unroll
     for (int n = 0; n < DC; ++n) {
@@ -351,14 +336,9 @@ __device__ __forceinline__ void cn_unit(const Args &A, int k, long unit) {
                 }
             }
             wht<S>(acc, sg);
-            // v'(h^-1 z) = v(z): entry z goes to the position its load came from
 #pragma unroll
-            for (int r = 0; r < R; ++r) srow[ix[n][r]] = max(acc[r] >> P, 0);  // floor(. / g)
-            lds_sync_wave();
-            int t[R];
-            load_row<R>(srow + L.x0, t);
-            lds_sync_wave();
-            if (act) store_row<R>(A.w.v + row(e0 + n, L.b, A.batch, G) + L.x0, t);
+            for (int r = 0; r < R; ++r) acc[r] = max(acc[r] >> P, 0);  // floor(. / g), clamped at 0
+            store_v(n, ix[n], acc);
             if (n + 1 < dc) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) pre[r] = n > 0 ? qmul(pre[r], U[n][r]) : U[0][r];
@@ -367,8 +347,75 @@ __device__ __forceinline__ void cn_unit(const Args &A, int k, long unit) {
     }
 }
 
-// Variable-node phase of iteration k (eqs. (10)-(11)) and decision: wave `unit` =
-// (variable, group), for variable degrees up to DV.
+// Variable-node arithmetic of eqs. (10)-(11) for one lane: vv holds the dv incoming
+// messages, store_u(m, u) writes u_m = norm(p times every incoming message but m,
+// ascending); pre holds p times messages 0 .. m-1 and ends as the a posteriori product,
+// whose arg-max is returned.
+template <int S, int R, int DV, class StoreU>
+__device__ __forceinline__ int vn_core(int dv, int x0, const int (&p)[R], const int (&vv)[DV][R], StoreU store_u) {
+    int pre[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) pre[r] = p[r];
+#pragma unroll
+    for (int m = 0; m < DV; ++m) {
+        if (m < dv) {
+            int z[R], u[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) z[r] = pre[r];
+#pragma unroll
+            for (int t = 0; t < DV; ++t)
+                if (t < dv && t > m) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) z[r] = qmul(z[r], vv[t][r]);
+                }
+            normalise<S>(z, p, u);
+            store_u(m, u);
+#pragma unroll
+            for (int r = 0; r < R; ++r) pre[r] = qmul(pre[r], vv[m][r]);
+        }
+    }
+    return seg_argmax<S>(pre, x0);
+}
+
+// Check-node phase of iteration k: wave `unit` = (check, group), for check degrees up
+// to DC.  Rows move between HBM and registers whole (R consecutive entries per lane);
+// the permutations go through this wave's LDS row of each codeword.
+template <int G, int DC>
+__device__ __forceinline__ void cn_unit(const Args &A, int k, long unit) {
+    constexpr int S = lanes_for<G, DC>(), R = Geo<G, S>::R;
+    const DevCode &C = A.C;
+    const Lane L = lane_of<G, S>(A, unit);
+    if (L.node >= C.m) return;
+    const bool act = active(A, k, L.b);
+    if (__ballot(act) == 0) return;
+    const int e0 = C.row_ptr[L.node];
+    const int dc = C.row_ptr[L.node + 1] - e0;
+    const int bb = L.b < A.batch ? L.b : A.batch - 1;  // lanes past the batch read a valid row
+    __shared__ __align__(16) int stage[4][64 * R];
+    int *srow = stage[threadIdx.x >> 6] + ((threadIdx.x & 63) / S) * G;
+    auto load_u = [&](int j, const MulRow<G, R> &ix, int (&U)[R]) {
+        int t[R];
+        load_row<R>(A.w.u + row(e0 + j, bb, A.batch, G) + L.x0, t);
+        store_row<R>(srow + L.x0, t);
+        lds_sync_wave();
+#pragma unroll
+        for (int r = 0; r < R; ++r) U[r] = srow[ix[r]];
+        lds_sync_wave();
+    };
+    auto store_v = [&](int n, const MulRow<G, R> &ix, const int (&v)[R]) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) srow[ix[r]] = v[r];
+        lds_sync_wave();
+        int t[R];
+        load_row<R>(srow + L.x0, t);
+        lds_sync_wave();
+        if (act) store_row<R>(A.w.v + row(e0 + n, L.b, A.batch, G) + L.x0, t);
+    };
+    cn_core<G, S, DC>(C, e0, dc, L.x0, signs_of<S>(L.j), load_u, store_v);
+}
+
+// Variable-node phase of iteration k and decision: wave `unit` = (variable, group), for
+// variable degrees up to DV.
 template <int G, int DV>
 __device__ __forceinline__ void vn_unit(const Args &A, int k, long unit) {
     constexpr int S = lanes_for<G, DV>(), R = Geo<G, S>::R;
@@ -386,33 +433,175 @@ __device__ __forceinline__ void vn_unit(const Args &A, int k, long unit) {
 #pragma unroll
     for (int t = 0; t < DV; ++t)
         if (t < dv) load_row<R>(A.w.v + row(C.vn_ref[t0 + t], bb, A.batch, G) + L.x0, vv[t]);
-    // u_m = norm(p times every incoming message but m, ascending); pre holds p times
-    // messages 0 .. m-1, and after the last edge it is the a posteriori product.
-    int pre[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) pre[r] = p[r];
-#pragma unroll
-    for (int m = 0; m < DV; ++m) {
-        if (m < dv) {
-            int z[R], u[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) z[r] = pre[r];
-#pragma unroll
-            for (int t = 0; t < DV; ++t)
-                if (t < dv && t > m) {
-#pragma unroll
-                    for (int r = 0; r < R; ++r) z[r] = qmul(z[r], vv[t][r]);
-                }
-            normalise<S>(z, p, u);
-            if (act) store_row<R>(A.w.u + row(C.vn_ref[t0 + m], L.b, A.batch, G) + L.x0, u);
-#pragma unroll
-            for (int r = 0; r < R; ++r) pre[r] = qmul(pre[r], vv[m][r]);
-        }
-    }
-    const int best = seg_argmax<S>(pre, L.x0);
+    auto store_u = [&](int m, const int (&u)[R]) {
+        if (act) store_row<R>(A.w.u + row(C.vn_ref[t0 + m], L.b, A.batch, G) + L.x0, u);
+    };
+    const int best = vn_core<S, R, DV>(dv, L.x0, p, vv, store_u);
     if (act && L.j == 0) {
         ((uint8_t *)A.io.hard)[(size_t)L.b * C.n + L.node] = (uint8_t)best;
         if (L.node == 0) A.w.it[L.b] = (int16_t)k;
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// LDS-resident variant for short codes with degrees up to 4: one workgroup decodes cw
+// codewords with every vector in LDS, all iterations in one launch.  LDS layout (bytes):
+// p [n][cw][g], u [E][cw][g], v [E][cw][g] (int32), four int flags, the last active
+// iteration [cw] (int16), unsatisfied flags [3][cw] (two iteration slots and the final
+// test), decisions [n][cw].
+struct LdsLayout {
+    size_t p, u, v, any, its, unsat, hard, total;
+};
+
+__host__ __device__ inline LdsLayout lds_layout(const DevCode &C, int cw) {
+    LdsLayout Y;
+    const size_t vec = (size_t)cw * C.g * 4;
+    Y.p = 0;
+    Y.u = Y.p + (size_t)C.n * vec;
+    Y.v = Y.u + (size_t)C.E * vec;
+    Y.any = Y.v + (size_t)C.E * vec;
+    Y.its = Y.any + 16;
+    Y.unsat = Y.its + (size_t)cw * 2;
+    Y.hard = Y.unsat + (size_t)cw * 3;
+    Y.total = (Y.hard + (size_t)C.n * cw + 15) & ~(size_t)15;
+    return Y;
+}
+
+// Syndrome of the decisions in LDS, thread per (check, local codeword): marks unsat[lc]
+// and *any.
+__device__ __forceinline__ void lds_syndrome(const DevCode &C, const uint8_t *hard, int cw, int cnt, uint8_t *unsat,
+                                             int *any) {
+    for (int t = threadIdx.x; t < C.m * cnt; t += blockDim.x) {
+        const int r = t / cnt, lc = t - r * cnt;
+        int sy = 0;
+        for (int e = C.row_ptr[r]; e < C.row_ptr[r + 1]; ++e) sy ^= C.gfmul[C.h[e] * C.g + hard[C.col_idx[e] * cw + lc]];
+        if (sy) {
+            unsat[lc] = 1;
+            *any = 1;
+        }
+    }
+}
+
+template <int G>
+__device__ __forceinline__ void lds_decode(const Args &A, int cw, unsigned char *lds) {
+    constexpr int D = 4, S = lanes_for<G, D>(), R = Geo<G, S>::R, CPW = Geo<G, S>::CPW;
+    const DevCode &C = A.C;
+    const LdsLayout Y = lds_layout(C, cw);
+    int *Pl = (int *)(lds + Y.p), *Ul = (int *)(lds + Y.u), *Vl = (int *)(lds + Y.v);
+    int *any = (int *)(lds + Y.any);
+    int16_t *its = (int16_t *)(lds + Y.its);
+    uint8_t *unsat = lds + Y.unsat;
+    uint8_t *hard = lds + Y.hard;
+    const int base = blockIdx.x * cw;
+    const int cnt = min(cw, A.batch - base);
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int waves = nthr >> 6, wave = wave_id();
+    const int lane = tid & 63, j = lane % S, x0 = j * R;
+    const int groups = (cnt + CPW - 1) / CPW;
+    auto lrow = [&](int *arr, int node, int lc) { return arr + ((size_t)node * cw + lc) * G; };
+    for (int t = tid; t < 3 * cw; t += nthr) unsat[t] = 0;
+    for (int t = tid; t < cw; t += nthr) its[t] = 0;
+    if (tid < 4) any[tid] = 0;
+    const Signs sg = signs_of<S>(j);
+    // channel vectors, u = p and v = 0 on every edge, decisions of iteration 0
+    for (int unit = wave; unit < C.n * groups; unit += waves) {
+        const int node = unit / groups, lc = (unit - node * groups) * CPW + lane / S;
+        const bool real = lc < cnt;
+        const int lr = real ? lc : cnt - 1;
+        const int16_t *src = (const int16_t *)A.io.llr + ((size_t)(base + lr) * C.n + node) * G + x0;
+        int w[R], fb[R], p[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            w[r] = C.spa_w[min(max((int)src[r], 0), kSpaWeights - 1)];
+            fb[r] = (1 << kQ) / G;
+        }
+        normalise<S>(w, fb, p);
+        const int best = seg_argmax<S>(p, x0);
+        if (real) {
+            store_row<R>(lrow(Pl, node, lc) + x0, p);
+            const int zero[R] = {};
+            for (int t = C.vn_ptr[node]; t < C.vn_ptr[node + 1]; ++t) {
+                store_row<R>(lrow(Ul, C.vn_ref[t], lc) + x0, p);
+                store_row<R>(lrow(Vl, C.vn_ref[t], lc) + x0, zero);
+            }
+            if (j == 0) hard[node * cw + lc] = (uint8_t)best;
+        }
+    }
+    __syncthreads();
+    for (int k = 1; k <= A.max_iters; ++k) {
+        const int slot = k & 1;
+        if (A.early_stop) {
+            lds_syndrome(C, hard, cw, cnt, unsat + slot * cw, any + slot);
+            __syncthreads();
+            if (any[slot] == 0) break;  // every codeword satisfied: nothing changes any more
+            // the other slot was last read before the previous iteration's final barrier
+            for (int t = tid; t < cw; t += nthr) unsat[(slot ^ 1) * cw + t] = 0;
+            if (tid == 0) any[slot ^ 1] = 0;
+        }
+        const uint8_t *us = unsat + slot * cw;
+        for (int unit = wave; unit < C.m * groups; unit += waves) {
+            const int node = unit / groups, lc = (unit - node * groups) * CPW + lane / S;
+            const bool act = lc < cnt && (!A.early_stop || us[lc]);
+            if (__ballot(act) == 0) continue;
+            const int lr = lc < cnt ? lc : cnt - 1;
+            const int e0 = C.row_ptr[node];
+            auto load_u = [&](int jj, const MulRow<G, R> &ix, int (&U)[R]) {
+                const int *r0 = lrow(Ul, e0 + jj, lr);
+#pragma unroll
+                for (int r = 0; r < R; ++r) U[r] = r0[ix[r]];
+            };
+            auto store_v = [&](int n, const MulRow<G, R> &ix, const int (&v)[R]) {
+                if (act) {
+                    int *r0 = lrow(Vl, e0 + n, lc);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) r0[ix[r]] = v[r];
+                }
+            };
+            cn_core<G, S, D>(C, e0, C.row_ptr[node + 1] - e0, x0, sg, load_u, store_v);
+        }
+        __syncthreads();
+        for (int unit = wave; unit < C.n * groups; unit += waves) {
+            const int node = unit / groups, lc = (unit - node * groups) * CPW + lane / S;
+            const bool act = lc < cnt && (!A.early_stop || us[lc]);
+            if (__ballot(act) == 0) continue;
+            const int lr = lc < cnt ? lc : cnt - 1;
+            const int t0 = C.vn_ptr[node];
+            const int dv = C.vn_ptr[node + 1] - t0;
+            int p[R], vv[D][R];
+            load_row<R>(lrow(Pl, node, lr) + x0, p);
+#pragma unroll
+            for (int t = 0; t < D; ++t)
+                if (t < dv) load_row<R>(lrow(Vl, C.vn_ref[t0 + t], lr) + x0, vv[t]);
+            auto store_u = [&](int m, const int (&u)[R]) {
+                if (act) store_row<R>(lrow(Ul, C.vn_ref[t0 + m], lc) + x0, u);
+            };
+            const int best = vn_core<S, R, D>(dv, x0, p, vv, store_u);
+            if (act && j == 0) {
+                hard[node * cw + lc] = (uint8_t)best;
+                if (node == 0) its[lc] = (int16_t)k;
+            }
+        }
+        __syncthreads();
+    }
+    lds_syndrome(C, hard, cw, cnt, unsat + 2 * cw, any + 2);
+    __syncthreads();
+    for (int t = tid; t < cnt; t += nthr) {
+        A.io.ok[base + t] = unsat[2 * cw + t] ? 0 : 1;
+        A.io.iters[base + t] = its[t];
+    }
+    uint8_t *hout = (uint8_t *)A.io.hard;
+    for (int t = tid; t < C.n * cnt; t += nthr) {
+        const int node = t / cnt, lc = t - node * cnt;
+        hout[(size_t)(base + lc) * C.n + node] = hard[node * cw + lc];
+    }
+    if (A.io.dump_a) {
+        const int per_e = cnt * G;
+        for (int t = tid; t < C.E * per_e; t += nthr) {
+            const int e = t / per_e, r = t - e * per_e, lc = r / G, x = r - lc * G;
+            const size_t o = ((size_t)(base + lc) * C.E + e) * G + x;
+            ((int *)A.io.dump_a)[o] = lrow(Ul, e, lc)[x];
+            ((int *)A.io.dump_b)[o] = lrow(Vl, e, lc)[x];
+        }
     }
 }
 

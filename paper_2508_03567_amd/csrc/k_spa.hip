@@ -22,6 +22,11 @@ template <int G, int DC>
 __global__ void __launch_bounds__(256) k_cn(Args A, int k) { dev::spa::cn_unit<G, DC>(A, k, unit_id()); }
 template <int G, int DV>
 __global__ void __launch_bounds__(256) k_vn(Args A, int k) { dev::spa::vn_unit<G, DV>(A, k, unit_id()); }
+template <int G>
+__global__ void __launch_bounds__(1024) k_spa_lds(Args A, int cw) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    dev::spa::lds_decode<G>(A, cw, lds);
+}
 __global__ void __launch_bounds__(256) k_fin(Args A) { dev::spa::fin_thread(A, (long)blockIdx.x * 256 + threadIdx.x); }
 __global__ void __launch_bounds__(256) k_dump(Args A, const int *src, int *dst) {
     dev::spa::dump_thread(A, src, dst, (long)blockIdx.x * 256 + threadIdx.x);
@@ -78,6 +83,14 @@ hipError_t run_degrees(const Args &A, bool small_dc, bool small_dv, hipStream_t 
     return small_dv ? run<G, D, 4>(A, s) : run<G, D, V>(A, s);
 }
 
+template <int G>
+hipError_t run_lds(const Args &A, int cw, int threads, hipStream_t s) {
+    const size_t lds = dev::spa::lds_layout(A.C, cw).total;
+    allow_full_lds((const void *)k_spa_lds<G>);
+    hipLaunchKernelGGL(k_spa_lds<G>, dim3(blocks(A.batch, cw)), dim3(threads), lds, s, A, cw);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 bool spa_supported(const DevCode &C) {
@@ -98,6 +111,50 @@ hipError_t launch_spa(const DevCode &C, int max_iters, int early_stop, int batch
     case 16: return run_degrees<16>(A, small_dc, small_dv, s);
     case 32: return run_degrees<32>(A, small_dc, small_dv, s);
     case 64: return run_degrees<64>(A, small_dc, small_dv, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+size_t spa_lds_bytes(const DevCode &C, int cw) { return dev::spa::lds_layout(C, cw).total; }
+
+bool spa_lds_supported(const DevCode &C) {
+    return spa_supported(C) && C.dc_max <= 4 && C.dv_max <= 4 && spa_lds_bytes(C, 1) <= kSpaLdsMax;
+}
+
+int spa_lds_cpw(const DevCode &C) { return 64 / std::max(4, C.g / 4); }
+
+int spa_lds_fit(const DevCode &C) {
+    int cw = 64;
+    while (cw > 1 && spa_lds_bytes(C, cw) > kSpaLdsMax) --cw;
+    return cw;
+}
+
+int spa_lds_cw(const DevCode &C, int batch) {
+    const int fit = std::min(spa_lds_fit(C), 32), cpw = spa_lds_cpw(C);
+    int cw = fit >= cpw ? fit - fit % cpw : fit;
+    // small batches: at least one workgroup per compute unit rather than full groups
+    cw = std::min(cw, std::max(1, (batch + 255) / 256));
+    return std::max(1, std::min(cw, batch));
+}
+
+hipError_t launch_spa_lds(const DevCode &C, int max_iters, int early_stop, int batch, int cw, int threads,
+                          const DecodeIO &io, hipStream_t s) {
+    if (!spa_lds_supported(C) || cw < 1 || spa_lds_bytes(C, cw) > kSpaLdsMax ||
+        (threads != 256 && threads != 512 && threads != 1024))
+        return hipErrorInvalidValue;
+    if (batch == 0) return hipSuccess;
+    Args A{};
+    A.C = C;
+    A.max_iters = max_iters;
+    A.early_stop = early_stop;
+    A.batch = batch;
+    A.io = io;
+    switch (C.g) {
+    case 4: return run_lds<4>(A, cw, threads, s);
+    case 8: return run_lds<8>(A, cw, threads, s);
+    case 16: return run_lds<16>(A, cw, threads, s);
+    case 32: return run_lds<32>(A, cw, threads, s);
+    case 64: return run_lds<64>(A, cw, threads, s);
     default: return hipErrorInvalidValue;
     }
 }

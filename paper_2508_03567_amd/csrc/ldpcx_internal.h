@@ -141,6 +141,18 @@ size_t spa_work_bytes(const DevCode &C, int max_iters, int batch);
 int spa_cw_per_wave(const DevCode &C);  // codewords per wave of the check-node kernel
 hipError_t launch_spa(const DevCode &C, int max_iters, int early_stop, int batch, void *ws, const DecodeIO &io,
                       hipStream_t s);
+// FFT-SPA with cw codewords per workgroup and every vector in LDS (check and variable
+// degrees <= 4, spa_lds_bytes(C, cw) <= kSpaLdsMax, 256, 512 or 1024 threads); no workspace.
+constexpr size_t kSpaLdsMax = 160 * 1024;
+bool spa_lds_supported(const DevCode &C);
+size_t spa_lds_bytes(const DevCode &C, int cw);
+int spa_lds_cpw(const DevCode &C);  // codewords per wave of its phases
+int spa_lds_fit(const DevCode &C);  // largest cw <= 64 whose vectors fit
+// Default group: the largest multiple of spa_lds_cpw up to 32 codewords that fits (else
+// the largest group that fits), fewer for batches under 256 groups.
+int spa_lds_cw(const DevCode &C, int batch);
+hipError_t launch_spa_lds(const DevCode &C, int max_iters, int early_stop, int batch, int cw, int threads,
+                          const DecodeIO &io, hipStream_t s);
 
 // Min-Max for g = 128, 256: codeword-major rows per edge.
 struct NbwWork {

@@ -135,8 +135,16 @@ Plan default_plan(const ldpcx_code *c, const ldpcx_decode_params *p, int batch) 
     Plan pl;
     const DeviceInfo &di = device_info(c->device);
     if (c->g > 2 && p->rule == LDPCX_RULE_SPA) {
-        pl.family = FAMILY_SPA;
         pl.schedule = LDPCX_SCHED_FLOODING;
+        // Short low-degree codes of which at least half a wave's worth of codewords fits
+        // in LDS: every vector on chip (measured faster there), else the wave kernels
+        if (spa_lds_supported(c->dev) && 2 * spa_lds_fit(c->dev) >= spa_lds_cpw(c->dev)) {
+            pl.family = FAMILY_SPA_LDS;
+            pl.cpw = spa_lds_cw(c->dev, std::max(1, batch));
+            pl.threads = 1024;
+            return pl;
+        }
+        pl.family = FAMILY_SPA;
         pl.cpw = spa_cw_per_wave(c->dev);
         pl.threads = 256;
         return pl;
@@ -238,6 +246,13 @@ ldpcx_status run_plan(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &p
         e = launch_bin_lds(c->dev, bin_rule(p), p->max_iters, p->early_stop, pl.schedule == LDPCX_SCHED_LAYERED, batch,
                            pl.cpw, pl.threads, io, s);
         if (e != hipSuccess) return fail_hip(e, "binary LDS decoder launch");
+        return LDPCX_OK;
+    }
+    if (pl.family == FAMILY_SPA_LDS) {
+        if (!spa_lds_supported(c->dev) || spa_lds_bytes(c->dev, pl.cpw) > kSpaLdsMax)
+            return fail(LDPCX_E_UNSUPPORTED, "FFT-SPA vectors do not fit the LDS of one workgroup");
+        e = launch_spa_lds(c->dev, p->max_iters, p->early_stop, batch, pl.cpw, pl.threads, io, s);
+        if (e != hipSuccess) return fail_hip(e, "LDS-resident FFT-SPA launch");
         return LDPCX_OK;
     }
     if (pl.family == FAMILY_BIN_IL && pl.schedule == LDPCX_SCHED_LAYERED)
@@ -770,11 +785,12 @@ ldpcx_status ldpcx_plan_set(ldpcx_code *c, const ldpcx_decode_params *params, in
     if (!c) return fail(LDPCX_E_INVAL, "code is NULL");
     ldpcx_status st = check_params(c, params);
     if (st != LDPCX_OK) return st;
-    if (family < 0 || family > 5) return fail(LDPCX_E_INVAL, "unknown kernel family");
-    if ((family == FAMILY_SPA) != (params->rule == LDPCX_RULE_SPA))
-        return fail(LDPCX_E_INVAL, "family 4 runs rule SPA, and rule SPA only family 4");
+    if (family < 0 || family > 6) return fail(LDPCX_E_INVAL, "unknown kernel family");
+    const bool spa_family = family == FAMILY_SPA || family == FAMILY_SPA_LDS;
+    if (spa_family != (params->rule == LDPCX_RULE_SPA))
+        return fail(LDPCX_E_INVAL, "families 4 and 6 run rule SPA, and rule SPA only those");
     if (family == FAMILY_BIN_QC && !c->qc_ok) return fail(LDPCX_E_UNSUPPORTED, "code has no quasi-cyclic description");
-    if ((c->g > 2) != (family == FAMILY_NB || family == FAMILY_SPA || family == FAMILY_NB_LDS))
+    if ((c->g > 2) != (family == FAMILY_NB || spa_family || family == FAMILY_NB_LDS))
         return fail(LDPCX_E_INVAL, "family does not match the field size");
     Plan pl;
     pl.family = family;
@@ -825,6 +841,18 @@ ldpcx_status ldpcx_plan_set(ldpcx_code *c, const ldpcx_decode_params *params, in
     if (family == FAMILY_SPA) {
         pl.cpw = spa_cw_per_wave(c->dev);
         pl.threads = 256;
+    }
+    if (family == FAMILY_SPA_LDS) {
+        if (!spa_lds_supported(c->dev))
+            return fail(LDPCX_E_UNSUPPORTED, "family 6 needs check and variable degrees <= 4 and one codeword's "
+                                             "vectors within 160 KB of LDS");
+        if (threads != 256 && threads != 512 && threads != 1024)
+            return fail(LDPCX_E_INVAL, "family 6 takes 256, 512 or 1024 threads");
+        if (cw_per_wg < 1 || cw_per_wg > 64) return fail(LDPCX_E_INVAL, "cw_per_wg out of range");
+        if (spa_lds_bytes(c->dev, cw_per_wg) > kSpaLdsMax)
+            return fail(LDPCX_E_UNSUPPORTED, "the vectors of cw_per_wg codewords do not fit the LDS of one workgroup");
+        pl.cpw = cw_per_wg;
+        pl.threads = threads;
     }
     std::lock_guard<std::mutex> lk(c->mu);
     c->tuned[tune_key(params, std::max(1, batch))] = pl;

@@ -105,7 +105,8 @@ double est_us(const Request &r, int ncw) {
     case FAMILY_BIN_QC: return work / 2.5e6;
     case FAMILY_BIN_LDS: return work / 1.0e6;
     case FAMILY_BIN_IL: return work / 1.1e6;
-    case FAMILY_SPA: return work * ((double)r.code->g / 64.0) / 2.0e4;
+    case FAMILY_SPA:
+    case FAMILY_SPA_LDS: return work * ((double)r.code->g / 64.0) / 2.0e4;
     default: return work * ((double)r.code->g * r.code->g / 4096.0) / 3.0e3;
     }
 }
@@ -189,6 +190,7 @@ struct ldpcx_server {
             const uint64_t id = queue.front();
             Request &r = reqs.at(id);
             const bool own = cfg.mode == LDPCX_SERVE_PER_REQUEST || r.family == FAMILY_BIN_IL || r.family == FAMILY_SPA ||
+                             r.family == FAMILY_SPA_LDS ||
                              ((r.family == FAMILY_NB || r.family == FAMILY_NB_LDS) &&
                               (r.code->g > 64 || r.prm.schedule != LDPCX_SCHED_FLOODING ||
                                pad64(r.batch - r.next_cw) / 64 >= kOwnLaunchGroups));

@@ -17,6 +17,33 @@ std::vector<Plan> candidates(const ldpcx_code *c, const ldpcx_decode_params *p, 
     std::vector<Plan> out;
     const Plan def = default_plan(c, p, batch);
     out.push_back(def);
+    if (c->g > 2 && p->rule == LDPCX_RULE_SPA) {
+        // FFT-SPA: the wave kernels and, for short low-degree codes, the LDS-resident
+        // kernel
+        Plan pl = def;
+        pl.family = FAMILY_SPA;
+        pl.cpw = spa_cw_per_wave(c->dev);
+        pl.threads = 256;
+        out.push_back(pl);
+        if (spa_lds_supported(c->dev)) {
+            // groups: the default one, the largest that fits, and 8, 16 and 32 codewords
+            const int fit = std::min(spa_lds_fit(c->dev), std::max(1, batch));
+            std::vector<int> cws{spa_lds_cw(c->dev, std::max(1, batch))};
+            for (int cw : {fit, 8, 16, 32})
+                if (cw <= fit && std::find(cws.begin(), cws.end(), cw) == cws.end()) cws.push_back(cw);
+            for (int cw : cws) {
+                for (int thr : {256, 512, 1024}) {
+                    Plan q;
+                    q.family = FAMILY_SPA_LDS;
+                    q.schedule = LDPCX_SCHED_FLOODING;
+                    q.cpw = cw;
+                    q.threads = thr;
+                    out.push_back(q);
+                }
+            }
+        }
+        return out;
+    }
     if (c->g > 2) {
         if (p->rule != LDPCX_RULE_MINMAX || c->g > 64) return out;
         // Min-Max: under AUTO the layered schedule is the other candidate; for codes whose

@@ -561,14 +561,16 @@ def test_minmax_layered_rejections_and_ragged():
     (64, 16, 4, 5, False, 3, 2), (64, 192, 4, 6, True, 5, 2), (16, 20, 5, 7, True, 4, 2), (4, 12, 2, 40, True, 3, 2),
     (64, 16, 6, 9, True, 4, 3), (32, 24, 8, 13, False, 3, 4), (8, 24, 4, 21, True, 4, 6), (64, 16, 4, 6, True, 3, 5), (64, 20, 5, 10, False, 3, 5)])
 def test_spa_matches_oracle(g_size, n, dc, batch, early, iters, dv):
-    """Fixed-point FFT-SPA (Alg. 1): decisions, flags, iteration counts and every u / v' message,
-    for check and variable degrees on both sides of the kernels' register bounds (4)."""
+    """Fixed-point FFT-SPA (Alg. 1) on the wave kernels: decisions, flags, iteration counts and
+    every u / v' message, for check and variable degrees on both sides of the kernels'
+    register bounds (4)."""
     m = n * dv // dc
     code = S.random_regular_nb_code(n, m, dv, dc, g_size, S.PRIM_POLY[g_size], seed=g_size + n + dc)
     cw = S.random_codewords(code, batch, seed=9)
     gam = S.nb_gamma_int16(cw, g_size, 1.5, seed=10)
     prm = dict(rule="spa", schedule="flooding", max_iters=iters, early_stop=early)
     h = L.Code(code)
+    L.plan_set(h, L.params(**prm), batch, "spa_wave")  # the LDS-resident family has its own test
     g = _gpu(h, prm, gam, dump=True)
     ref = O.decode_spa(code, O.params(**prm), gam, dump=True)
     _check_decisions(code, g, ref)
@@ -576,6 +578,88 @@ def test_spa_matches_oracle(g_size, n, dc, batch, early, iters, dv):
     assert (g[4].astype(np.int64) == ref["v"]).all(), "v' messages differ"
     g2 = _gpu(h, prm, gam)
     _check_decisions(code, g2, ref)
+
+
+@pytest.mark.parametrize("g_size,n,dc,batch,early,iters,cw,threads", [
+    (4, 24, 4, 70, True, 6, 64, 256), (8, 24, 4, 33, False, 4, 16, 512), (16, 16, 4, 20, True, 5, 7, 1024),
+    (32, 30, 3, 9, True, 4, 4, 256), (64, 16, 4, 5, False, 3, 2, 512), (64, 16, 4, 11, True, 4, 1, 256),
+    (4, 12, 2, 130, True, 3, 64, 1024), (16, 32, 4, 40, True, 5, 5, 512), (8, 16, 4, 1, True, 3, 32, 256)])
+def test_spa_lds_family_matches_oracle(g_size, n, dc, batch, early, iters, cw, threads):
+    """FFT-SPA with every vector of cw codewords in one workgroup's LDS: decisions, flags,
+    iteration counts and every u / v' message equal the oracle's, for groups smaller
+    and larger than a wave's codewords and a ragged last group."""
+    m = n * 2 // dc
+    code = S.random_regular_nb_code(n, m, 2, dc, g_size, S.PRIM_POLY[g_size], seed=g_size + 3 * n + dc)
+    cwd = S.random_codewords(code, batch, seed=19)
+    gam = S.nb_gamma_int16(cwd, g_size, 1.5, seed=20)
+    d = dict(rule="spa", schedule="flooding", max_iters=iters, early_stop=early)
+    h = L.Code(code)
+    L.plan_set(h, L.params(**d), batch, "spa_lds", cw, threads)
+    info = L.plan_info(h, L.params(**d), batch)
+    assert info["family"] == "spa_lds" and info["cw_per_wg"] == cw and info["threads"] == threads
+    g = _gpu(h, d, gam, dump=True)
+    ref = O.decode_spa(code, O.params(**d), gam, dump=True)
+    _check_decisions(code, g, ref)
+    assert (g[3].astype(np.int64) == ref["u"]).all(), "u messages differ"
+    assert (g[4].astype(np.int64) == ref["v"]).all(), "v' messages differ"
+    g2 = _gpu(h, d, gam)
+    _check_decisions(code, g2, ref)
+
+
+@pytest.mark.parametrize("family,cw,threads", [("spa_wave", 1, 256), ("spa_lds", 16, 512)])
+def test_spa_dump_of_codewords_never_active(family, cw, threads):
+    """Codewords whose channel decisions already satisfy every check never run an
+    iteration under early stopping; their check messages stay 0, as in the oracle, even
+    when the workspace or LDS held other data before."""
+    code = S.random_regular_nb_code(16, 8, 2, 4, 16, S.PRIM_POLY[16], seed=41)
+    h = L.Code(code)
+    d = dict(rule="spa", schedule="flooding", max_iters=4, early_stop=True)
+    L.plan_set(h, L.params(**d), 90, family, cw, threads)
+    noisy = S.nb_gamma_int16(S.random_codewords(code, 90, seed=42), 16, 0.0, seed=43)
+    _gpu(h, d, noisy, dump=True)  # leaves nonzero messages in the memory the next decode gets
+    gam = S.nb_gamma_int16(S.random_codewords(code, 90, seed=44), 16, 6.0, seed=45)
+    g = _gpu(h, d, gam, dump=True)
+    ref = O.decode_spa(code, O.params(**d), gam, dump=True)
+    assert (ref["iters"] == 0).sum() > 10
+    _check_decisions(code, g, ref)
+    assert (g[3].astype(np.int64) == ref["u"]).all() and (g[4].astype(np.int64) == ref["v"]).all()
+
+
+def test_spa_lds_family_limits_and_tuning():
+    d = dict(rule="spa", schedule="flooding", max_iters=3, early_stop=True)
+    big = L.Code(S.random_regular_nb_code(16, 4, 2, 8, 16, S.PRIM_POLY[16], seed=5))  # check degree 8
+    with pytest.raises(L.LdpcxError) as ei:
+        L.plan_set(big, L.params(**d), 32, "spa_lds", 8, 256)
+    assert ei.value.status == L.E_UNSUPPORTED
+    code = S.random_regular_nb_code(64, 32, 2, 4, 64, S.PRIM_POLY[64], seed=6)  # 80 KB per codeword
+    h = L.Code(code)
+    with pytest.raises(L.LdpcxError) as ei:
+        L.plan_set(h, L.params(**d), 32, "spa_lds", 2, 256)
+    assert ei.value.status == L.E_UNSUPPORTED
+    with pytest.raises(L.LdpcxError) as ei:
+        L.plan_set(h, L.params(**d), 32, "spa_lds", 1, 128)
+    assert ei.value.status == L.E_INVAL
+    with pytest.raises(L.LdpcxError) as ei:
+        L.plan_set(h, L.params("minmax", max_iters=3), 32, "spa_lds", 1, 256)
+    assert ei.value.status == L.E_INVAL
+    # the autotuner may pick either FFT-SPA family; the results are the same
+    small = S.random_regular_nb_code(16, 8, 2, 4, 8, S.PRIM_POLY[8], seed=7)
+    hs = L.Code(small)
+    cwd = S.random_codewords(small, 300, seed=8)
+    gam = torch.from_numpy(S.nb_gamma_int16(cwd, 8, 1.5, seed=9)).to(DEV)
+    prm = L.params(**d)
+    ref = L.decode(hs, prm, gam)
+    L.tune(hs, prm, 300)
+    assert L.plan_info(hs, prm, 300)["family"] in ("spa_wave", "spa_lds")
+    got = L.decode(hs, prm, gam)
+    for a, b in zip(got[:3], ref[:3]):
+        assert torch.equal(a, b)
+    # a ragged batch runs the pinned LDS-resident plan as its own launch
+    L.plan_set(hs, prm, 300, "spa_lds", 16, 512)
+    outs = L.decode_ragged([(hs, prm, gam[:100]), (hs, prm, gam[100:])])
+    for o, sl in zip(outs, [slice(0, 100), slice(100, 300)]):
+        for a, b in zip(o, ref[:3]):
+            assert torch.equal(a, b[sl])
 
 
 def test_spa_rejections():
