@@ -18,11 +18,14 @@
 // edge and backward at the first edge are never used by eqs. (11)-(13) and are
 // not computed (3(dc-2) convolutions per check instead of 4dc-6).
 //
-// The check node (cn_core) reads and writes messages through an accessor, so the
-// same code serves three arrangements: the messages in HBM with one launch per
-// phase (flooding: cn_block / vn_block), the layered schedule (layers of checks
+// The check node (cn_core) reads and writes messages through accessors, so the
+// same code serves four arrangements: the messages in HBM with one launch per
+// phase (flooding: cn_block / vn_block); flooding for codes whose variables all have
+// degree 2 with the alphas formed inside the check node from gamma and the other
+// edge's beta, the betas alternating between two arrays and the decisions formed only
+// where they are used (cnf_block / dec_block); the layered schedule (layers of checks
 // sharing no variable, alphas formed per check from the current betas:
-// lay_alpha_block / lay_cn_block), and short codes whose messages of one group of 64
+// lay_alpha_block / lay_cn_block); and short codes whose messages of one group of 64
 // codewords fit in LDS, decoded by one workgroup through every iteration
 // (lds_group).
 #pragma once
@@ -163,9 +166,9 @@ __device__ __forceinline__ bool active(const Args &A, int k, int g, int lane) {
 // beta written through the message accessors; fs: this wave's forward-vector slots in
 // LDS; only lanes with `act` store.
 // mul, hinv: the multiplication table and the inverse coefficients (HBM or LDS copies).
-template <int G, class M>
-__device__ __forceinline__ void cn_core(const DevCode &C, const uint8_t *mul, const uint8_t *hinv, const M &alpha,
-                                        const M &beta, int row, bool act, uint32_t *fs) {
+template <int G, class MA, class MB>
+__device__ __forceinline__ void cn_core(const DevCode &C, const uint8_t *mul, const uint8_t *hinv, const MA &alpha,
+                                        const MB &beta, int row, bool act, uint32_t *fs) {
     constexpr int H = G / 2;
     const int lane = threadIdx.x & 63;
     const int e0 = C.row_ptr[row];
@@ -234,6 +237,114 @@ __device__ __forceinline__ void cn_block(const Args &A, int k, int wpb, int bx, 
     cn_row<G>(A, row, w, by, act, lds);
 }
 
+// Flooding alphas formed inside the check node (eq. (14)) for codes whose variables all
+// have degree 2: the clipped channel vector of the edge's variable plus the previous
+// iteration's beta of the variable's other edge, shifted to minimum 0 and clipped to the
+// message bound, read through the same permutation as an alpha row in HBM.  This
+// replaces the variable node's alpha stores and the check node's alpha loads by loads
+// of gamma and of the other beta.  Two passes over the entries (the minimum, then the
+// values) keep the 32-bit sums out of registers.
+struct FusedAlpha {
+    __amdgpu_buffer_rsrc_t gam, beta;  // [n][x][Bp] channel vectors, [E][x][Bp] previous betas
+    uint32_t Bp2, lane_off;
+    int amax;
+    const int *col_idx, *vn_ptr, *vn_ref;
+
+    __device__ __forceinline__ int ld(__amdgpu_buffer_rsrc_t r, uint32_t soff) const {
+        return (int)(int16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)lane_off, (int)soff, 0);
+    }
+
+    template <int G>
+    __device__ __forceinline__ void load_perm(int e, const uint8_t *mrow, v2s (&A)[G / 2]) const {
+        const uint32_t *mw = (const uint32_t *)mrow;
+        const int v = __builtin_amdgcn_readfirstlane(col_idx[e]);
+        const int q0 = __builtin_amdgcn_readfirstlane(vn_ptr[v]);
+        const int f0 = __builtin_amdgcn_readfirstlane(vn_ref[q0]), f1 = __builtin_amdgcn_readfirstlane(vn_ref[q0 + 1]);
+        const uint32_t gb = __builtin_amdgcn_readfirstlane((uint32_t)v * G * Bp2);
+        const uint32_t fb = __builtin_amdgcn_readfirstlane((uint32_t)(f0 == e ? f1 : f0) * G * Bp2);
+        auto sum_at = [&](int t) {
+            const uint32_t xo = mrow_at(mw, t) * Bp2;
+            return min(ld(gam, gb + xo), amax) + ld(beta, fb + xo);
+        };
+        int mn = sum_at(0);
+#pragma unroll
+        for (int t = 1; t < G; ++t) mn = min(mn, sum_at(t));
+        asm volatile("" ::: "memory");  // the second pass reloads instead of keeping G sums live
+#pragma unroll
+        for (int t = 0; t < G; t += 2) {
+            const uint32_t a0 = (uint32_t)min(sum_at(t) - mn, amax), a1 = (uint32_t)min(sum_at(t + 1) - mn, amax);
+            A[t >> 1] = as_v2s(a0 | (a1 << 16));
+        }
+    }
+};
+
+// Buffer resource over the [n][x][Bp] channel vectors.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t gam_rsrc(const Args &A) {
+    const uint32_t bytes = (uint32_t)A.C.n * (uint32_t)A.C.g * (uint32_t)A.Bp * 2u;
+    return __builtin_amdgcn_make_buffer_rsrc(A.w.gam, (short)0, (int)bytes, 0x00020000);
+}
+
+// A posteriori sums S(x) = gamma'(x) + sum of the variable's betas (eq. (15)) for the
+// lane's codeword, by buffer loads whose scalar offset carries (variable or edge, entry)
+// and whose lane offset is the codeword; returns the arg-min (lowest x on ties) as the
+// minimum of the keys S(x) * 64 + x.
+template <int G>
+__device__ __forceinline__ int app_sums(const Args &A, int v, uint32_t lo, int (&S)[G]) {
+    const DevCode &C = A.C;
+    const uint32_t Bp2 = 2u * (uint32_t)A.Bp;
+    const __amdgpu_buffer_rsrc_t rg = gam_rsrc(A), rb = msg_rsrc(A.w.beta, A);
+    const uint32_t gb = __builtin_amdgcn_readfirstlane((uint32_t)v * G * Bp2);
+#pragma unroll
+    for (int x = 0; x < G; ++x)
+        S[x] = min((int)(int16_t)__builtin_amdgcn_raw_buffer_load_b16(rg, (int)lo, (int)(gb + x * Bp2), 0), A.amax);
+    for (int t = C.vn_ptr[v]; t < C.vn_ptr[v + 1]; ++t) {
+        const uint32_t fb = __builtin_amdgcn_readfirstlane((uint32_t)C.vn_ref[t] * G * Bp2);
+#pragma unroll
+        for (int x = 0; x < G; ++x)
+            S[x] += (int)(int16_t)__builtin_amdgcn_raw_buffer_load_b16(rb, (int)lo, (int)(fb + x * Bp2), 0);
+    }
+    int key = S[0] * 64;
+#pragma unroll
+    for (int x = 1; x < G; ++x) key = min(key, S[x] * 64 + x);
+    return key & 63;
+}
+
+// Decision of iteration k without the alphas (layered schedule, fused flooding): one
+// wave per (variable, group).
+template <int G>
+__device__ __forceinline__ void dec_block(const Args &A, int k, int bx, int by) {
+    const int lane = threadIdx.x & 63;
+    const int v = bx * 4 + wave_id();
+    if (v >= A.C.n) return;
+    const int b = by * 64 + lane;
+    const bool act = active(A, k, by, lane);
+    if (__ballot(act) == 0) return;
+    int S[G];
+    const int best = app_sums<G>(A, v, 2u * (uint32_t)b, S);
+    if (act) {
+        A.w.hard[(long)v * A.Bp + b] = (uint8_t)best;
+        if (v == 0) A.w.it[b] = (int16_t)k;
+    }
+}
+
+// Fused flooding check node of iteration k (alphas from gamma and beta_old, betas to
+// beta_new): wave w of virtual block (bx, by) as in cn_block.
+template <int G>
+__device__ __forceinline__ void cnf_block(const Args &A, int k, int wpb, int bx, int by, uint32_t *lds,
+                                          const int16_t *beta_old, int16_t *beta_new) {
+    const int w = wave_id();
+    if (w >= wpb) return;
+    const int row = bx * wpb + w;
+    if (row >= A.C.m) return;
+    const bool act = active(A, k, by, threadIdx.x & 63);
+    if (__ballot(act) == 0) return;
+    const uint32_t lo = 2u * (uint32_t)(by * 64 + (threadIdx.x & 63));
+    const FusedAlpha alpha{gam_rsrc(A), msg_rsrc(beta_old, A), 2u * (uint32_t)A.Bp, lo, A.amax,
+                           A.C.col_idx, A.C.vn_ptr, A.C.vn_ref};
+    const HbmMsg beta{msg_rsrc(beta_new, A), 2u * (uint32_t)A.Bp, lo};
+    cn_core<G>(A.C, A.C.gfmul, A.C.hinv, alpha, beta, row, act, lds + (size_t)w * A.fslots * (G / 2) * 64);
+}
+
 // Layered schedule: alpha of edge e from eq. (14) with the betas as they stand, i.e. the
 // channel vector of its variable plus the betas of the variable's other edges, shifted
 // to minimum 0 and clipped to the message bound.
@@ -293,55 +404,37 @@ __device__ __forceinline__ void lay_cn_block(const Args &A, int k, int layer, in
 }
 
 // Variable-node update (eqs. (14)-(15)) and decision: one wave per (variable, group).
-// kAlpha = false: the decision only (layered schedule, whose alphas are formed per check).
-template <int G, bool kAlpha = true>
+template <int G>
 __device__ __forceinline__ void vn_block(const Args &A, int k, int bx, int by) {
     const DevCode &C = A.C;
-    const long Bp = A.Bp;
     const int lane = threadIdx.x & 63;
     const int v = bx * 4 + wave_id();
     if (v >= C.n) return;
-    const int g = by;
-    const int b = g * 64 + lane;
-    const uint64_t *slot = A.w.unsat + (size_t)k * A.Gn;
-    const bool act = b < A.batch && (!A.early_stop || ((slot[g] >> lane) & 1ull));
+    const int b = by * 64 + lane;
+    const bool act = active(A, k, by, lane);
     if (__ballot(act) == 0) return;
+    const uint32_t lo = 2u * (uint32_t)b, Bp2 = 2u * (uint32_t)A.Bp;
     int S[G];
-    const int16_t *gp = A.w.gam + (long)v * G * Bp + b;
-#pragma unroll
-    for (int x = 0; x < G; ++x) S[x] = min((int)gp[(long)x * Bp], A.amax);
-    const int t0 = C.vn_ptr[v], t1 = C.vn_ptr[v + 1];
-    for (int t = t0; t < t1; ++t) {
-        const int16_t *bp = A.w.beta + (long)C.vn_ref[t] * G * Bp + b;
-#pragma unroll
-        for (int x = 0; x < G; ++x) S[x] += bp[(long)x * Bp];
-    }
-    int best = 0, bv = S[0];
-#pragma unroll
-    for (int x = 1; x < G; ++x)
-        if (S[x] < bv) {
-            bv = S[x];
-            best = x;
-        }
+    const int best = app_sums<G>(A, v, lo, S);
     if (act) {
-        A.w.hard[(long)v * Bp + b] = (uint8_t)best;
+        A.w.hard[(long)v * A.Bp + b] = (uint8_t)best;
         if (v == 0) A.w.it[b] = (int16_t)k;
     }
-    if (!kAlpha) return;
-    for (int t = t0; t < t1; ++t) {
-        const int e = C.vn_ref[t];
-        const int16_t *bp = A.w.beta + (long)e * G * Bp + b;
+    const __amdgpu_buffer_rsrc_t rb = msg_rsrc(A.w.beta, A), ra = msg_rsrc(A.w.alpha, A);
+    for (int t = C.vn_ptr[v]; t < C.vn_ptr[v + 1]; ++t) {
+        const uint32_t eb = __builtin_amdgcn_readfirstlane((uint32_t)C.vn_ref[t] * G * Bp2);
         int a[G];
         int mn = 0x7fffffff;
 #pragma unroll
         for (int x = 0; x < G; ++x) {
-            a[x] = S[x] - bp[(long)x * Bp];
+            a[x] = S[x] - (int)(int16_t)__builtin_amdgcn_raw_buffer_load_b16(rb, (int)lo, (int)(eb + x * Bp2), 0);
             mn = min(mn, a[x]);
         }
         if (act) {
-            int16_t *ap = A.w.alpha + (long)e * G * Bp + b;
 #pragma unroll
-            for (int x = 0; x < G; ++x) ap[(long)x * Bp] = (int16_t)min(a[x] - mn, A.amax);
+            for (int x = 0; x < G; ++x)
+                __builtin_amdgcn_raw_buffer_store_b16((unsigned short)min(a[x] - mn, A.amax), ra, (int)lo,
+                                                      (int)(eb + x * Bp2), 0);
         }
     }
 }

@@ -35,6 +35,11 @@ __global__ void __launch_bounds__(256) k_cn(Args A, int k, int wpb) {
 template <int G>
 __global__ void __launch_bounds__(256) k_vn(Args A, int k) { dev::nb::vn_block<G>(A, k, blk_node(A.Gn), blk_group(A.Gn)); }
 template <int G>
+__global__ void __launch_bounds__(256) k_cnf(Args A, int k, int wpb, const int16_t *beta_old, int16_t *beta_new) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    dev::nb::cnf_block<G>(A, k, wpb, blk_node(A.Gn), blk_group(A.Gn), lds, beta_old, beta_new);
+}
+template <int G>
 __global__ void __launch_bounds__(256) k_lal(Args A, int k, int layer) {
     dev::nb::lay_alpha_block<G>(A, k, layer, blk_node(A.Gn), blk_group(A.Gn));
 }
@@ -44,9 +49,7 @@ __global__ void __launch_bounds__(256) k_lcn(Args A, int k, int layer, int wpb) 
     dev::nb::lay_cn_block<G>(A, k, layer, wpb, blk_node(A.Gn), blk_group(A.Gn), lds);
 }
 template <int G>
-__global__ void __launch_bounds__(256) k_dec(Args A, int k) {
-    dev::nb::vn_block<G, false>(A, k, blk_node(A.Gn), blk_group(A.Gn));
-}
+__global__ void __launch_bounds__(256) k_dec(Args A, int k) { dev::nb::dec_block<G>(A, k, blk_node(A.Gn), blk_group(A.Gn)); }
 __global__ void __launch_bounds__(256) k_fin(Args A) { dev::nb::fin_block(A, blockIdx.x); }
 // One group of 64 codewords per workgroup, messages in LDS.
 template <int G, bool GL>
@@ -89,6 +92,8 @@ hipError_t run(const Args &A, bool layered, hipStream_t s) {
     const dim3 gvn = lin(dev::nb::grid_vn_x(A), A.Gn);
     const dim3 glay = lin((A.C.nb_lmax + wpb - 1) / wpb, A.Gn);
     const dim3 glal = lin((A.C.nb_emax + 3) / 4, A.Gn);
+    // every variable of degree 2 (and no debug dump): flooding fused into the check node
+    const bool fused = !A.io.dump_a && A.C.dv_max == 2 && A.C.E == 2 * A.C.n;
     for (int k = 1; k <= A.max_iters; ++k) {
         if (A.early_stop) hipLaunchKernelGGL(k_syn, gsy, blk, 0, s, A, k);
         if (layered) {
@@ -99,7 +104,20 @@ hipError_t run(const Args &A, bool layered, hipStream_t s) {
                 hipLaunchKernelGGL(k_lcn<G>, glay, dim3(64 * wpb), smem, s, A, k, l, wpb);
             }
             hipLaunchKernelGGL(k_dec<G>, gvn, blk, 0, s, A, k);
+        } else if (fused) {
+            // Flooding with the alphas formed inside the check node: the betas alternate
+            // between two arrays (the alpha array is free for it), and the decisions are
+            // formed only where they are used (every iteration under early stopping,
+            // else after the last one).
+            int16_t *bo = (k & 1) ? A.w.beta : A.w.alpha, *bn = (k & 1) ? A.w.alpha : A.w.beta;
+            hipLaunchKernelGGL(k_cnf<G>, gcn, dim3(64 * wpb), smem, s, A, k, wpb, bo, bn);
+            if (A.early_stop || k == A.max_iters) {
+                Args D = A;
+                D.w.beta = bn;
+                hipLaunchKernelGGL(k_dec<G>, gvn, blk, 0, s, D, k);
+            }
         } else {
+            // the debug dump keeps the two-phase sequence, whose final alphas it reports
             hipLaunchKernelGGL(k_cn<G>, gcn, dim3(64 * wpb), smem, s, A, k, wpb);
             hipLaunchKernelGGL(k_vn<G>, gvn, blk, 0, s, A, k);
         }

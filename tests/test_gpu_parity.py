@@ -188,6 +188,28 @@ def test_minmax_field_sizes(g_size, family):
     _check_decisions(code, g, ref)
     assert (g[3].astype(np.int32) == ref["alpha"]).all()
     assert (g[4].astype(np.int32) == ref["beta"]).all()
+    # without the dump the interleaved family forms the alphas inside the check node
+    _check_decisions(code, _gpu(h, d, gam), ref)
+    d_fixed = dict(d, early_stop=False)
+    _check_decisions(code, _gpu(h, d_fixed, gam), _ref(code, d_fixed, gam))
+
+
+@pytest.mark.parametrize("early", [True, False])
+@pytest.mark.parametrize("g_size", [8, 64])
+def test_minmax_interleaved_variable_degrees_above_2(g_size, early):
+    """Codes with variables of degree 3 keep the two-phase flooding sequence (alphas from
+    the variable node) with and without the debug dump."""
+    code = S.random_regular_nb_code(24, 12, 3, 6, g_size, S.PRIM_POLY[g_size], seed=50 + g_size)
+    cw = S.random_codewords(code, 90, seed=51)
+    gam = S.nb_gamma_int16(cw, g_size, 1.5, seed=52)
+    d = dict(rule="minmax", schedule="flooding", max_iters=5, early_stop=early)
+    h = L.Code(code)
+    L.plan_set(h, L.params(**d), 90, "minmax_interleaved", 64, 256)
+    ref = _ref(code, d, gam, dump=True)
+    g = _gpu(h, d, gam, dump=True)
+    _check_decisions(code, g, ref)
+    assert (g[3].astype(np.int32) == ref["alpha"]).all() and (g[4].astype(np.int32) == ref["beta"]).all()
+    _check_decisions(code, _gpu(h, d, gam), ref)
 
 
 @pytest.mark.parametrize("dc", [2, 3, 5, 8])
