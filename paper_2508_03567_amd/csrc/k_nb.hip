@@ -92,8 +92,10 @@ hipError_t run(const Args &A, bool layered, hipStream_t s) {
     const dim3 gvn = lin(dev::nb::grid_vn_x(A), A.Gn);
     const dim3 glay = lin((A.C.nb_lmax + wpb - 1) / wpb, A.Gn);
     const dim3 glal = lin((A.C.nb_emax + 3) / 4, A.Gn);
-    // every variable of degree 2 (and no debug dump): flooding fused into the check node
-    const bool fused = !A.io.dump_a && A.C.dv_max == 2 && A.C.E == 2 * A.C.n;
+    // Every variable of degree 2 (and no debug dump): flooding fused into the check node,
+    // when its launch alone has 16 waves per compute unit (the fused check node is the
+    // heavier one; short codes at small batches run faster as two wider launches).
+    const bool fused = !A.io.dump_a && A.C.dv_max == 2 && A.C.E == 2 * A.C.n && (long)A.C.m * A.Gn >= 4096;
     for (int k = 1; k <= A.max_iters; ++k) {
         if (A.early_stop) hipLaunchKernelGGL(k_syn, gsy, blk, 0, s, A, k);
         if (layered) {
