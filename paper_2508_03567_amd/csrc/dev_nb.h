@@ -242,8 +242,12 @@ __device__ __forceinline__ void cn_block(const Args &A, int k, int wpb, int bx, 
 // iteration's beta of the variable's other edge, shifted to minimum 0 and clipped to the
 // message bound, read through the same permutation as an alpha row in HBM.  This
 // replaces the variable node's alpha stores and the check node's alpha loads by loads
-// of gamma and of the other beta.  Two passes over the entries (the minimum, then the
-// values) keep the 32-bit sums out of registers.
+// of gamma and of the other beta.  The sums S are kept as unsigned 16-bit pairs while
+// the minimum is found; betas lie in [0, 32767], so with channel costs in [0, 32767]
+// every S fits and the alphas follow with two packed operations per pair.  A wave with
+// a sum outside [0, 65535] (negative costs) reloads and forms them in 32 bits.
+typedef unsigned short v2u __attribute__((ext_vector_type(2)));
+
 struct FusedAlpha {
     __amdgpu_buffer_rsrc_t gam, beta;  // [n][x][Bp] channel vectors, [E][x][Bp] previous betas
     uint32_t Bp2, lane_off;
@@ -266,12 +270,29 @@ struct FusedAlpha {
             const uint32_t xo = mrow_at(mw, t) * Bp2;
             return min(ld(gam, gb + xo), amax) + ld(beta, fb + xo);
         };
-        int mn = sum_at(0);
-#pragma unroll
-        for (int t = 1; t < G; ++t) mn = min(mn, sum_at(t));
-        asm volatile("" ::: "memory");  // the second pass reloads instead of keeping G sums live
+        int mn = 0x7fffffff;
+        uint32_t wide = 0;  // bits above 16 of any sum (negative sums set them all)
 #pragma unroll
         for (int t = 0; t < G; t += 2) {
+            const int s0 = sum_at(t), s1 = sum_at(t + 1);
+            mn = min(mn, min(s0, s1));
+            wide |= ((uint32_t)s0 | (uint32_t)s1) >> 16;
+            A[t >> 1] = as_v2s(((uint32_t)s0 & 0xFFFFu) | ((uint32_t)s1 << 16));
+        }
+        if (__ballot(wide != 0) == 0) {
+            const v2u m = (v2u){(unsigned short)mn, (unsigned short)mn}, cap = (v2u){(unsigned short)amax, (unsigned short)amax};
+#pragma unroll
+            for (int p = 0; p < G / 2; ++p) {
+                const v2u d = __builtin_bit_cast(v2u, A[p]) - m;  // S - min, no wrap: S >= min
+                A[p] = __builtin_bit_cast(v2s, __builtin_elementwise_min(d, cap));
+            }
+            return;
+        }
+        // Reload pair by pair (the barriers keep the compiler from holding the G 32-bit
+        // sums or hoisting the reloads, so this rare path costs the common one no registers).
+#pragma unroll
+        for (int t = 0; t < G; t += 2) {
+            asm volatile("" ::: "memory");
             const uint32_t a0 = (uint32_t)min(sum_at(t) - mn, amax), a1 = (uint32_t)min(sum_at(t + 1) - mn, amax);
             A[t >> 1] = as_v2s(a0 | (a1 << 16));
         }

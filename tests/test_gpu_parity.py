@@ -313,6 +313,27 @@ def test_full_size_sampled(cfg, sample):
     _check_decisions(w.code, g2, _ref(w.code, d2, llr[idx]), idx)
 
 
+@pytest.mark.parametrize("early", [False, True])
+def test_minmax_fused_flooding_matches_two_phase_and_oracle(early):
+    """Flooding with the alphas formed inside the check node (every variable of degree 2, a
+    check-node launch that fills the device: 96 checks x 44 groups) gives the decisions of
+    the two-phase sequence (the debug-dump path) for every codeword and the oracle's on a
+    sample, also with channel costs below 0 (every seventh codeword), whose sums leave the
+    16-bit range and take the 32-bit path."""
+    w = S.workload(3, batch=2816)
+    cw, gam = S.make_inputs(w)
+    gam = gam.copy()
+    gam[::7] -= 3000
+    d = _prm(w, early_stop=early, max_iters=6)
+    h = _handle(w.code)
+    g = _gpu(h, d, gam)
+    two_phase = _gpu(h, d, gam, dump=True)
+    for a, b in zip(g[:3], two_phase[:3]):
+        assert (a == b).all()
+    idx = np.unique(np.concatenate([np.arange(0, 2816, 97), np.arange(0, 2816, 7)[:10], [2815]]))
+    _check_decisions(w.code, g, _ref(w.code, d, gam[idx]), idx)
+
+
 @pytest.mark.parametrize("cfg,schedule", [(0, "flooding"), (0, "layered"), (1, "layered"), (1, "flooding")])
 @pytest.mark.parametrize("cw_per_wg", [2, 4, 6])
 @pytest.mark.parametrize("early", [True, False])
