@@ -414,6 +414,79 @@ __device__ __forceinline__ void cn_unit(const Args &A, int k, long unit) {
     cn_core<G, S, DC>(C, e0, dc, L.x0, signs_of<S>(L.j), load_u, store_v);
 }
 
+// Flooding for codes whose variables all have degree 2, fused into the check node: the
+// check forms each incoming u = norm(p times the other edge's v of the previous
+// iteration) itself (eqs. (10)-(11) with one factor), so the variable-node phase and
+// its u stores disappear; v alternates between the v and u arrays (v_old -> v_new).
+// With v = 0 before the first iteration the product is 0 and norm falls back to p,
+// which is u before the first iteration.
+template <int G, int DC>
+__device__ __forceinline__ void cnf_unit(const Args &A, int k, long unit, const int *v_old, int *v_new) {
+    constexpr int S = lanes_for<G, DC>(), R = Geo<G, S>::R;
+    const DevCode &C = A.C;
+    const Lane L = lane_of<G, S>(A, unit);
+    if (L.node >= C.m) return;
+    const bool act = active(A, k, L.b);
+    if (__ballot(act) == 0) return;
+    const int e0 = C.row_ptr[L.node];
+    const int dc = C.row_ptr[L.node + 1] - e0;
+    const int bb = L.b < A.batch ? L.b : A.batch - 1;
+    __shared__ __align__(16) int stage[4][64 * R];
+    int *srow = stage[threadIdx.x >> 6] + ((threadIdx.x & 63) / S) * G;
+    auto load_u = [&](int j, const MulRow<G, R> &ix, int (&U)[R]) {
+        const int e = e0 + j;
+        const int var = C.col_idx[e];
+        const int q0 = C.vn_ptr[var];
+        const int f = C.vn_ref[q0] == e ? C.vn_ref[q0 + 1] : C.vn_ref[q0];
+        int p[R], vo[R], z[R], u[R];
+        load_row<R>(A.w.p + row(var, bb, A.batch, G) + L.x0, p);
+        load_row<R>(v_old + row(f, bb, A.batch, G) + L.x0, vo);
+#pragma unroll
+        for (int r = 0; r < R; ++r) z[r] = qmul(p[r], vo[r]);
+        normalise<S>(z, p, u);
+        store_row<R>(srow + L.x0, u);
+        lds_sync_wave();
+#pragma unroll
+        for (int r = 0; r < R; ++r) U[r] = srow[ix[r]];
+        lds_sync_wave();
+    };
+    auto store_v = [&](int n, const MulRow<G, R> &ix, const int (&v)[R]) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) srow[ix[r]] = v[r];
+        lds_sync_wave();
+        int t[R];
+        load_row<R>(srow + L.x0, t);
+        lds_sync_wave();
+        if (act) store_row<R>(v_new + row(e0 + n, L.b, A.batch, G) + L.x0, t);
+    };
+    cn_core<G, S, DC>(C, e0, dc, L.x0, signs_of<S>(L.j), load_u, store_v);
+}
+
+// Decision of iteration k for codes whose variables all have degree 2 (the a posteriori
+// product p v_0 v_1 in ascending edge order): wave `unit` = (variable, group).
+template <int G>
+__device__ __forceinline__ void dec_unit(const Args &A, int k, long unit, const int *v_cur) {
+    constexpr int S = lanes_for<G, 4>(), R = Geo<G, S>::R;
+    const DevCode &C = A.C;
+    const Lane L = lane_of<G, S>(A, unit);
+    if (L.node >= C.n) return;
+    const bool act = active(A, k, L.b);
+    if (__ballot(act) == 0) return;
+    const int bb = L.b < A.batch ? L.b : A.batch - 1;
+    const int t0 = C.vn_ptr[L.node];
+    int p[R], v0[R], v1[R], app[R];
+    load_row<R>(A.w.p + row(L.node, bb, A.batch, G) + L.x0, p);
+    load_row<R>(v_cur + row(C.vn_ref[t0], bb, A.batch, G) + L.x0, v0);
+    load_row<R>(v_cur + row(C.vn_ref[t0 + 1], bb, A.batch, G) + L.x0, v1);
+#pragma unroll
+    for (int r = 0; r < R; ++r) app[r] = qmul(qmul(p[r], v0[r]), v1[r]);
+    const int best = seg_argmax<S>(app, L.x0);
+    if (act && L.j == 0) {
+        ((uint8_t *)A.io.hard)[(size_t)L.b * C.n + L.node] = (uint8_t)best;
+        if (L.node == 0) A.w.it[L.b] = (int16_t)k;
+    }
+}
+
 // Variable-node phase of iteration k and decision: wave `unit` = (variable, group), for
 // variable degrees up to DV.
 template <int G, int DV>

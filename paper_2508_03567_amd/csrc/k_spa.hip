@@ -22,6 +22,12 @@ template <int G, int DC>
 __global__ void __launch_bounds__(256) k_cn(Args A, int k) { dev::spa::cn_unit<G, DC>(A, k, unit_id()); }
 template <int G, int DV>
 __global__ void __launch_bounds__(256) k_vn(Args A, int k) { dev::spa::vn_unit<G, DV>(A, k, unit_id()); }
+template <int G, int DC>
+__global__ void __launch_bounds__(256) k_cnf(Args A, int k, const int *v_old, int *v_new) {
+    dev::spa::cnf_unit<G, DC>(A, k, unit_id(), v_old, v_new);
+}
+template <int G>
+__global__ void __launch_bounds__(256) k_dec(Args A, int k, const int *v_cur) { dev::spa::dec_unit<G>(A, k, unit_id(), v_cur); }
 template <int G>
 __global__ void __launch_bounds__(1024) k_spa_lds(Args A, int cw) {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -58,10 +64,22 @@ hipError_t run(const Args &A, hipStream_t s) {
     if ((e = fill(dev::FillArgs{(uint32_t *)A.w.it, (size_t)(B + 1) / 2, 0u}, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_init<G>, dim3(blocks(C.n * gi, 4)), blk, 0, s, A);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    // Every variable of degree 2 and no debug dump: flooding fused into the check node,
+    // v alternating between the v and u arrays, decisions only where they are used.
+    const bool fused = !A.io.dump_a && C.dv_max == 2 && C.E == 2 * C.n;
+    constexpr int CD = dev::spa::Geo<G, dev::spa::lanes_for<G, 4>()>::CPW;
+    const long gd = (B + CD - 1) / CD;
     for (int k = 1; k <= A.max_iters; ++k) {
         if (A.early_stop) hipLaunchKernelGGL(k_syn, dim3(blocks(C.m * B, 256)), blk, 0, s, A, k);
-        hipLaunchKernelGGL((k_cn<G, DC>), dim3(blocks(C.m * gc, 4)), blk, 0, s, A, k);
-        hipLaunchKernelGGL((k_vn<G, DV>), dim3(blocks(C.n * gv, 4)), blk, 0, s, A, k);
+        if (fused) {
+            int *vo = (k & 1) ? A.w.v : A.w.u, *vn = (k & 1) ? A.w.u : A.w.v;
+            hipLaunchKernelGGL((k_cnf<G, DC>), dim3(blocks(C.m * gc, 4)), blk, 0, s, A, k, vo, vn);
+            if (A.early_stop || k == A.max_iters)
+                hipLaunchKernelGGL(k_dec<G>, dim3(blocks(C.n * gd, 4)), blk, 0, s, A, k, (const int *)vn);
+        } else {
+            hipLaunchKernelGGL((k_cn<G, DC>), dim3(blocks(C.m * gc, 4)), blk, 0, s, A, k);
+            hipLaunchKernelGGL((k_vn<G, DV>), dim3(blocks(C.n * gv, 4)), blk, 0, s, A, k);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_syn, dim3(blocks(C.m * B, 256)), blk, 0, s, A, 0);
