@@ -125,6 +125,37 @@ def test_graph_replays_match_eager(cfg):
         assert (_np(out[1]) == ref["ok"]).all() and (_np(out[2]) == ref["iters"]).all()
 
 
+@pytest.mark.parametrize("rule,batch", [("minmax", 2816), ("spa", 300)])
+def test_graph_replays_of_fused_flooding_match_eager(rule, batch):
+    """Graph replays of the fused flooding sequences (alphas or u formed inside the check
+    node, message arrays alternating per iteration; Min-Max at 96 checks x 44 groups,
+    FFT-SPA on the wave kernels) give the decisions of the eager two-phase sequence
+    (the debug-dump path) on every replay."""
+    if rule == "minmax":
+        w, d, llr = _mk(3, batch, 41, max_iters=5, early_stop=True)
+        code = _code(3)
+        prm = L.params(**d)
+    else:
+        c = S.random_regular_nb_code(64, 32, 2, 4, 64, S.PRIM_POLY[64], seed=43)
+        code = L.Code(c)
+        llr = S.nb_gamma_int16(S.random_codewords(c, batch, seed=44), 64, 1.5, seed=45)
+        prm = L.params("spa", "flooding", 5, early_stop=True)
+        L.plan_set(code, prm, batch, "spa_wave")
+    x = torch.from_numpy(np.ascontiguousarray(llr)).to(DEV)
+    eager = L.debug_dump(code, prm, x)  # never captured, two phases
+    torch.cuda.synchronize()
+    out = L._outputs(code, x.shape[0], DEV)
+    for rep in range(3):
+        for t in out:
+            t.fill_(0x55 if t.dtype == torch.uint8 else 7)
+        y = torch.randn(1 << 20, device=DEV) * 2.0  # unrelated eager work between replays
+        L.decode(code, prm, x, out=out)
+        torch.cuda.synchronize()
+        assert float(y.abs().sum()) > 0
+        for a, b in zip(out, eager[:3]):
+            assert torch.equal(a, b)
+
+
 def test_ragged_gathers_whole_device_jobs():
     """Long-code, Min-Max (flooding, layered, AUTO, 8-bit bound) and FFT-SPA jobs next to
     short binary jobs: the whole-device jobs are gathered per (code, parameters) into one
