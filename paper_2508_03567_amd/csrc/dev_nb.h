@@ -494,10 +494,11 @@ __device__ __forceinline__ void syn_block(const Args &A, int slot_k, int bx, int
         atomicOr((unsigned long long *)&A.w.unsat[(size_t)slot_k * A.Gn + g], (unsigned long long)bits);
 }
 
-// alpha^(0) = gamma of the edge's variable, beta = 0, decision of iteration 0 (wave per
-// (edge or variable, group)).
+// alpha^(0) = gamma of the edge's variable (unless `alpha` is false: the fused flooding
+// forms its alphas itself), beta = 0, decision of iteration 0 (wave per (edge or
+// variable, group)).
 template <int G>
-__device__ __forceinline__ void init_block(const Args &A, int bx, int by) {
+__device__ __forceinline__ void init_block(const Args &A, int bx, int by, bool alpha = true) {
     const DevCode &C = A.C;
     const long Bp = A.Bp;
     const int lane = threadIdx.x & 63;
@@ -509,7 +510,7 @@ __device__ __forceinline__ void init_block(const Args &A, int bx, int by) {
         int16_t *bp = A.w.beta + (long)e * G * Bp + b;
 #pragma unroll 8
         for (int x = 0; x < G; ++x) {
-            ap[(long)x * Bp] = (int16_t)min((int)gp[(long)x * Bp], A.amax);
+            if (alpha) ap[(long)x * Bp] = (int16_t)min((int)gp[(long)x * Bp], A.amax);
             bp[(long)x * Bp] = 0;
         }
     }

@@ -273,10 +273,11 @@ struct MulRow {
     __device__ __forceinline__ int operator[](int r) const { return (w[r >> 2] >> (8 * (r & 3))) & 0xFF; }
 };
 
-// Channel vectors, u = p and v = 0 on every edge of the variable, decision of
-// iteration 0: wave `unit` = (variable, group).
+// Channel vectors, u = p (unless write_u is false: the fused flooding forms u itself)
+// and v = 0 on every edge of the variable, decision of iteration 0: wave `unit` =
+// (variable, group).
 template <int G, int S>
-__device__ __forceinline__ void init_unit(const Args &A, long unit) {
+__device__ __forceinline__ void init_unit(const Args &A, long unit, bool write_u = true) {
     constexpr int R = Geo<G, S>::R;
     const DevCode &C = A.C;
     const Lane L = lane_of<G, S>(A, unit);
@@ -296,7 +297,7 @@ __device__ __forceinline__ void init_unit(const Args &A, long unit) {
     store_row<R>(A.w.p + row(L.node, L.b, A.batch, G) + L.x0, p);
     const int zero[R] = {};
     for (int t = C.vn_ptr[L.node]; t < C.vn_ptr[L.node + 1]; ++t) {
-        store_row<R>(A.w.u + row(C.vn_ref[t], L.b, A.batch, G) + L.x0, p);
+        if (write_u) store_row<R>(A.w.u + row(C.vn_ref[t], L.b, A.batch, G) + L.x0, p);
         store_row<R>(A.w.v + row(C.vn_ref[t], L.b, A.batch, G) + L.x0, zero);  // v = 0 until a check writes it
     }
     if (L.j == 0) ((uint8_t *)A.io.hard)[(size_t)L.b * C.n + L.node] = (uint8_t)best;

@@ -23,7 +23,9 @@ __device__ __forceinline__ int blk_node(int Gn) { return (int)(blockIdx.x / (uns
 __device__ __forceinline__ int blk_group(int Gn) { return (int)(blockIdx.x % (unsigned)Gn); }
 
 template <int G>
-__global__ void __launch_bounds__(256) k_init(Args A) { dev::nb::init_block<G>(A, blk_node(A.Gn), blk_group(A.Gn)); }
+__global__ void __launch_bounds__(256) k_init(Args A, int alpha) {
+    dev::nb::init_block<G>(A, blk_node(A.Gn), blk_group(A.Gn), alpha != 0);
+}
 __global__ void __launch_bounds__(256) k_syn(Args A, int slot) {
     dev::nb::syn_block(A, slot, blk_node(A.Gn), blk_group(A.Gn));
 }
@@ -80,7 +82,11 @@ hipError_t run(const Args &A, bool layered, hipStream_t s) {
     if (most * A.Gn >= (1L << 31)) return hipErrorInvalidConfiguration;
     if ((e = tr(dev::nb::tr_in(A), s)) != hipSuccess) return e;
     const dim3 blk(256);
-    hipLaunchKernelGGL(k_init<G>, lin(dev::nb::grid_init_x(A), A.Gn), blk, 0, s, A);
+    // Every variable of degree 2 (and no debug dump): flooding fused into the check node,
+    // when its launch alone has 16 waves per compute unit (the fused check node is the
+    // heavier one; short codes at small batches run faster as two wider launches).
+    const bool fused = !layered && !A.io.dump_a && A.C.dv_max == 2 && A.C.E == 2 * A.C.n && (long)A.C.m * A.Gn >= 4096;
+    hipLaunchKernelGGL(k_init<G>, lin(dev::nb::grid_init_x(A), A.Gn), blk, 0, s, A, fused ? 0 : 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = fill(dev::nb::fill_unsat(A), s)) != hipSuccess) return e;
     if ((e = fill(dev::nb::fill_it(A), s)) != hipSuccess) return e;
@@ -92,10 +98,6 @@ hipError_t run(const Args &A, bool layered, hipStream_t s) {
     const dim3 gvn = lin(dev::nb::grid_vn_x(A), A.Gn);
     const dim3 glay = lin((A.C.nb_lmax + wpb - 1) / wpb, A.Gn);
     const dim3 glal = lin((A.C.nb_emax + 3) / 4, A.Gn);
-    // Every variable of degree 2 (and no debug dump): flooding fused into the check node,
-    // when its launch alone has 16 waves per compute unit (the fused check node is the
-    // heavier one; short codes at small batches run faster as two wider launches).
-    const bool fused = !A.io.dump_a && A.C.dv_max == 2 && A.C.E == 2 * A.C.n && (long)A.C.m * A.Gn >= 4096;
     for (int k = 1; k <= A.max_iters; ++k) {
         if (A.early_stop) hipLaunchKernelGGL(k_syn, gsy, blk, 0, s, A, k);
         if (layered) {

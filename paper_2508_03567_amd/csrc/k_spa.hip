@@ -14,7 +14,9 @@ __device__ __forceinline__ long unit_id() { return (long)blockIdx.x * 4 + dev::w
 __global__ void __launch_bounds__(256) k_fill(dev::FillArgs F) { dev::fill_block(F, blockIdx.x); }
 constexpr int kInitLanes = 4;  // lanes per codeword of the channel-vector kernel
 template <int G>
-__global__ void __launch_bounds__(256) k_init(Args A) { dev::spa::init_unit<G, kInitLanes>(A, unit_id()); }
+__global__ void __launch_bounds__(256) k_init(Args A, int write_u) {
+    dev::spa::init_unit<G, kInitLanes>(A, unit_id(), write_u != 0);
+}
 __global__ void __launch_bounds__(256) k_syn(Args A, int slot) {
     dev::spa::syn_thread(A, slot, (long)blockIdx.x * 256 + threadIdx.x);
 }
@@ -62,11 +64,11 @@ hipError_t run(const Args &A, hipStream_t s) {
     const dev::spa::Carve cv = dev::spa::carve(C, A.max_iters, A.batch);
     if ((e = fill(dev::FillArgs{(uint32_t *)A.w.unsat, (cv.it - cv.unsat) / 4, 0u}, s)) != hipSuccess) return e;
     if ((e = fill(dev::FillArgs{(uint32_t *)A.w.it, (size_t)(B + 1) / 2, 0u}, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_init<G>, dim3(blocks(C.n * gi, 4)), blk, 0, s, A);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     // Every variable of degree 2 and no debug dump: flooding fused into the check node,
     // v alternating between the v and u arrays, decisions only where they are used.
     const bool fused = !A.io.dump_a && C.dv_max == 2 && C.E == 2 * C.n;
+    hipLaunchKernelGGL(k_init<G>, dim3(blocks(C.n * gi, 4)), blk, 0, s, A, fused ? 0 : 1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     constexpr int CD = dev::spa::Geo<G, dev::spa::lanes_for<G, 4>()>::CPW;
     const long gd = (B + CD - 1) / CD;
     for (int k = 1; k <= A.max_iters; ++k) {
