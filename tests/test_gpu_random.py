@@ -1,0 +1,91 @@
+"""Seeded random parity cases across decoders, families and parameters.
+
+Each case draws a field, a regular code shape, a batch size, an iteration cap, early
+stopping and a launch plan from a fixed seed, decodes on the GPU and compares decisions,
+syndrome flags and iteration counts with the oracle (every codeword for small batches,
+a sample for the large ones that reach the fused flooding sequences).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2508_03567_amd import ldpcx as L
+from paper_2508_03567_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def _code(rng, g, dv, dc, n_lo, n_hi):
+    for _ in range(50):
+        n = int(rng.integers(n_lo, n_hi + 1))
+        n -= n % dc
+        if n < dc or (n * dv) % dc:
+            continue
+        try:
+            return S.random_regular_nb_code(n, n * dv // dc, dv, dc, g, S.PRIM_POLY[g], seed=int(rng.integers(1 << 30)))
+        except RuntimeError:
+            continue
+    pytest.skip("no code drawn")
+
+
+def _check(code, out, ref, idx=None):
+    hard, ok, it = [o.cpu().numpy() for o in out[:3]]
+    sel = slice(None) if idx is None else idx
+    assert (hard[sel] == ref["hard"]).all()
+    assert (ok[sel] == ref["ok"]).all()
+    assert (it[sel] == ref["iters"]).all()
+
+
+@pytest.mark.parametrize("case", range(16))
+def test_random_small(case):
+    rng = np.random.default_rng(1000 + case)
+    rule = ["minmax", "spa"][case % 2]
+    g = int(rng.choice([4, 8, 16, 32, 64]))
+    dv, dc = [(2, 4), (2, 3), (3, 6), (2, 6)][int(rng.integers(4))]
+    code = _code(rng, g, dv, dc, 12, 40)
+    batch = int(rng.integers(1, 150))
+    iters = int(rng.integers(0, 7))
+    early = bool(rng.integers(2))
+    ebn0 = float(rng.uniform(0.5, 4.0))
+    gam = S.nb_gamma_int16(S.random_codewords(code, batch, seed=case), g, ebn0, seed=case + 1)
+    d = dict(rule=rule, schedule="flooding", max_iters=iters, early_stop=early)
+    h = L.Code(code)
+    fams = ["minmax_interleaved", "minmax_lds"] if rule == "minmax" else ["spa_wave", "spa_lds"]
+    fam = fams[int(rng.integers(2))]
+    try:
+        if fam == "spa_lds":
+            L.plan_set(h, L.params(**d), batch, fam, int(rng.integers(1, 33)), int(rng.choice([256, 512, 1024])))
+        elif fam == "minmax_lds":
+            L.plan_set(h, L.params(**d), batch, fam, 64, int(rng.choice([256, 512, 1024])))
+        else:
+            L.plan_set(h, L.params(**d), batch, fam, 64, 256)
+    except L.LdpcxError as e:
+        assert e.status == L.E_UNSUPPORTED  # a family that cannot hold this code keeps the default plan
+    x = torch.from_numpy(gam).to(DEV)
+    out = L.decode(h, L.params(**d), x)
+    torch.cuda.synchronize()
+    ref = (O.decode_nb if rule == "minmax" else O.decode_spa)(code, O.params(**d), gam)
+    _check(code, out, ref)
+
+
+@pytest.mark.parametrize("rule,g,seed", [("minmax", 16, 1), ("minmax", 64, 2), ("spa", 16, 3), ("spa", 64, 4)])
+def test_random_large_fused(rule, g, seed):
+    """(2,4)-regular codes with 64-96 checks at 4096-4500 codewords: the fused flooding
+    sequences, with early stopping on and off, on a sample of the batch."""
+    rng = np.random.default_rng(2000 + seed)
+    code = _code(rng, g, 2, 4, 128, 192)
+    batch = int(rng.integers(4096, 4500))
+    h = L.Code(code)
+    gam = S.nb_gamma_int16(S.random_codewords(code, batch, seed=seed), g, 1.5, seed=seed + 7)
+    x = torch.from_numpy(gam).to(DEV)
+    idx = np.unique(np.concatenate([rng.choice(batch, 12, replace=False), [0, batch - 1]]))
+    for early in (False, True):
+        d = dict(rule=rule, schedule="flooding", max_iters=4, early_stop=early)
+        if rule == "spa":
+            L.plan_set(h, L.params(**d), batch, "spa_wave")
+        out = L.decode(h, L.params(**d), x)
+        torch.cuda.synchronize()
+        ref = (O.decode_nb if rule == "minmax" else O.decode_spa)(code, O.params(**d), gam[idx])
+        _check(code, out, ref, idx)
