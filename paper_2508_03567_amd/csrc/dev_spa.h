@@ -577,7 +577,12 @@ __device__ __forceinline__ void lds_decode(const Args &A, int cw, unsigned char 
     for (int t = tid; t < cw; t += nthr) its[t] = 0;
     if (tid < 4) any[tid] = 0;
     const Signs sg = signs_of<S>(j);
-    // channel vectors, u = p and v = 0 on every edge, decisions of iteration 0
+    // Every variable of degree 2 and no dump: the check phase forms u itself from p and
+    // the other edge's v, v alternating between the v and u arrays, decisions only where
+    // used (as in the wave kernels' fused flooding).
+    const bool fused = !A.io.dump_a && C.dv_max == 2 && C.E == 2 * C.n;
+    // channel vectors, u = p (two-phase only) and v = 0 on every edge, decisions of
+    // iteration 0
     for (int unit = wave; unit < C.n * groups; unit += waves) {
         const int node = unit / groups, lc = (unit - node * groups) * CPW + lane / S;
         const bool real = lc < cnt;
@@ -595,7 +600,7 @@ __device__ __forceinline__ void lds_decode(const Args &A, int cw, unsigned char 
             store_row<R>(lrow(Pl, node, lc) + x0, p);
             const int zero[R] = {};
             for (int t = C.vn_ptr[node]; t < C.vn_ptr[node + 1]; ++t) {
-                store_row<R>(lrow(Ul, C.vn_ref[t], lc) + x0, p);
+                if (!fused) store_row<R>(lrow(Ul, C.vn_ref[t], lc) + x0, p);
                 store_row<R>(lrow(Vl, C.vn_ref[t], lc) + x0, zero);
             }
             if (j == 0) hard[node * cw + lc] = (uint8_t)best;
@@ -613,6 +618,65 @@ __device__ __forceinline__ void lds_decode(const Args &A, int cw, unsigned char 
             if (tid == 0) any[slot ^ 1] = 0;
         }
         const uint8_t *us = unsat + slot * cw;
+        if (fused) {
+            const int *vo = (k & 1) ? Vl : Ul;
+            int *vn = (k & 1) ? Ul : Vl;
+            for (int unit = wave; unit < C.m * groups; unit += waves) {
+                const int node = unit / groups, lc = (unit - node * groups) * CPW + lane / S;
+                const bool act = lc < cnt && (!A.early_stop || us[lc]);
+                if (__ballot(act) == 0) continue;
+                const int lr = lc < cnt ? lc : cnt - 1;
+                const int e0 = C.row_ptr[node];
+                auto load_u = [&](int jj, const MulRow<G, R> &ix, int (&U)[R]) {
+                    const int e = e0 + jj;
+                    const int var = C.col_idx[e];
+                    const int q0 = C.vn_ptr[var];
+                    const int f = C.vn_ref[q0] == e ? C.vn_ref[q0 + 1] : C.vn_ref[q0];
+                    const int *pr = lrow(Pl, var, lr), *vr = vo + ((size_t)f * cw + lr) * G;
+                    int p[R], z[R], u[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        // the permuted entry x' = h^-1 t of u is formed from p(x') and v(x')
+                        p[r] = pr[ix[r]];
+                        z[r] = qmul(p[r], vr[ix[r]]);
+                    }
+                    normalise<S>(z, p, u);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) U[r] = u[r];
+                };
+                auto store_v = [&](int n, const MulRow<G, R> &ix, const int (&v)[R]) {
+                    if (act) {
+                        int *r0 = vn + ((size_t)(e0 + n) * cw + lc) * G;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) r0[ix[r]] = v[r];
+                    }
+                };
+                cn_core<G, S, D>(C, e0, C.row_ptr[node + 1] - e0, x0, sg, load_u, store_v);
+            }
+            __syncthreads();
+            if (A.early_stop || k == A.max_iters) {
+                for (int unit = wave; unit < C.n * groups; unit += waves) {
+                    const int node = unit / groups, lc = (unit - node * groups) * CPW + lane / S;
+                    const bool act = lc < cnt && (!A.early_stop || us[lc]);
+                    if (__ballot(act) == 0) continue;
+                    const int lr = lc < cnt ? lc : cnt - 1;
+                    const int t0 = C.vn_ptr[node];
+                    int p[R], v0[R], v1[R], app[R];
+                    load_row<R>(lrow(Pl, node, lr) + x0, p);
+                    load_row<R>(vn + ((size_t)C.vn_ref[t0] * cw + lr) * G + x0, v0);
+                    load_row<R>(vn + ((size_t)C.vn_ref[t0 + 1] * cw + lr) * G + x0, v1);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) app[r] = qmul(qmul(p[r], v0[r]), v1[r]);
+                    const int best = seg_argmax<S>(app, x0);
+                    if (act && j == 0) {
+                        hard[node * cw + lc] = (uint8_t)best;
+                        if (node == 0) its[lc] = (int16_t)k;
+                    }
+                }
+                __syncthreads();
+            }
+            continue;
+        }
         for (int unit = wave; unit < C.m * groups; unit += waves) {
             const int node = unit / groups, lc = (unit - node * groups) * CPW + lane / S;
             const bool act = lc < cnt && (!A.early_stop || us[lc]);
