@@ -82,10 +82,8 @@ hipError_t run(const Args &A, bool layered, hipStream_t s) {
     if (most * A.Gn >= (1L << 31)) return hipErrorInvalidConfiguration;
     if ((e = tr(dev::nb::tr_in(A), s)) != hipSuccess) return e;
     const dim3 blk(256);
-    // Every variable of degree 2 (and no debug dump): flooding fused into the check node,
-    // when its launch alone has 16 waves per compute unit (the fused check node is the
-    // heavier one; short codes at small batches run faster as two wider launches).
-    const bool fused = !layered && !A.io.dump_a && A.C.dv_max == 2 && A.C.E == 2 * A.C.n && (long)A.C.m * A.Gn >= 4096;
+    // Every variable of degree 2 (and no debug dump): flooding fused into the check node.
+    const bool fused = !layered && !A.io.dump_a && A.C.dv_max == 2 && A.C.E == 2 * A.C.n;
     hipLaunchKernelGGL(k_init<G>, lin(dev::nb::grid_init_x(A), A.Gn), blk, 0, s, A, fused ? 0 : 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = fill(dev::nb::fill_unsat(A), s)) != hipSuccess) return e;
