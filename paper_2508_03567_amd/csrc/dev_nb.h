@@ -424,6 +424,28 @@ __device__ __forceinline__ void lay_cn_block(const Args &A, int k, int layer, in
     cn_row<G>(A, row, w, by, act, lds);
 }
 
+// Layered schedule for codes whose variables all have degree 2, one launch per layer: the
+// layer's check nodes form their alphas themselves (FusedAlpha on the betas as they
+// stand).  The other edge of an edge's variable belongs to a check of another layer, so
+// the betas read are never those the launch writes.
+template <int G>
+__device__ __forceinline__ void lay_cnf_block(const Args &A, int k, int layer, int wpb, int bx, int by,
+                                              uint32_t *lds) {
+    const DevCode &C = A.C;
+    const int w = wave_id();
+    if (w >= wpb) return;
+    const int i = C.nbl_ptr[layer] + bx * wpb + w;
+    if (i >= C.nbl_ptr[layer + 1]) return;
+    const int row = __builtin_amdgcn_readfirstlane(C.nbl_chk[i]);
+    const bool act = active(A, k, by, threadIdx.x & 63);
+    if (__ballot(act) == 0) return;
+    const uint32_t lo = 2u * (uint32_t)(by * 64 + (threadIdx.x & 63));
+    const __amdgpu_buffer_rsrc_t rb = msg_rsrc(A.w.beta, A);
+    const FusedAlpha alpha{gam_rsrc(A), rb, 2u * (uint32_t)A.Bp, lo, A.amax, C.col_idx, C.vn_ptr, C.vn_ref};
+    const HbmMsg beta{rb, 2u * (uint32_t)A.Bp, lo};
+    cn_core<G>(C, C.gfmul, C.hinv, alpha, beta, row, act, lds + (size_t)w * A.fslots * (G / 2) * 64);
+}
+
 // Variable-node update (eqs. (14)-(15)) and decision: one wave per (variable, group).
 // (Global loads with 64-bit addresses measured a few per cent faster here than buffer
 // loads, unlike the decision-only kernel.)

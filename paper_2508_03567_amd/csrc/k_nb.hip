@@ -51,6 +51,11 @@ __global__ void __launch_bounds__(256) k_lcn(Args A, int k, int layer, int wpb) 
     dev::nb::lay_cn_block<G>(A, k, layer, wpb, blk_node(A.Gn), blk_group(A.Gn), lds);
 }
 template <int G>
+__global__ void __launch_bounds__(256) k_lcnf(Args A, int k, int layer, int wpb) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    dev::nb::lay_cnf_block<G>(A, k, layer, wpb, blk_node(A.Gn), blk_group(A.Gn), lds);
+}
+template <int G>
 __global__ void __launch_bounds__(256) k_dec(Args A, int k) { dev::nb::dec_block<G>(A, k, blk_node(A.Gn), blk_group(A.Gn)); }
 __global__ void __launch_bounds__(256) k_fin(Args A) { dev::nb::fin_block(A, blockIdx.x); }
 // One group of 64 codewords per workgroup, messages in LDS.
@@ -82,9 +87,11 @@ hipError_t run(const Args &A, bool layered, hipStream_t s) {
     if (most * A.Gn >= (1L << 31)) return hipErrorInvalidConfiguration;
     if ((e = tr(dev::nb::tr_in(A), s)) != hipSuccess) return e;
     const dim3 blk(256);
-    // Every variable of degree 2 (and no debug dump): flooding fused into the check node.
-    const bool fused = !layered && !A.io.dump_a && A.C.dv_max == 2 && A.C.E == 2 * A.C.n;
-    hipLaunchKernelGGL(k_init<G>, lin(dev::nb::grid_init_x(A), A.Gn), blk, 0, s, A, fused ? 0 : 1);
+    // Every variable of degree 2 (and no debug dump): the alphas formed inside the check
+    // node, in flooding (fused) and layered (dv2) schedules.
+    const bool dv2 = !A.io.dump_a && A.C.dv_max == 2 && A.C.E == 2 * A.C.n;
+    const bool fused = !layered && dv2;
+    hipLaunchKernelGGL(k_init<G>, lin(dev::nb::grid_init_x(A), A.Gn), blk, 0, s, A, dv2 ? 0 : 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = fill(dev::nb::fill_unsat(A), s)) != hipSuccess) return e;
     if ((e = fill(dev::nb::fill_it(A), s)) != hipSuccess) return e;
@@ -102,8 +109,12 @@ hipError_t run(const Args &A, bool layered, hipStream_t s) {
             // two launches per layer (its alphas, then its check nodes): the checks of a
             // layer share no variable
             for (int l = 0; l < A.C.nb_nl; ++l) {
-                hipLaunchKernelGGL(k_lal<G>, glal, blk, 0, s, A, k, l);
-                hipLaunchKernelGGL(k_lcn<G>, glay, dim3(64 * wpb), smem, s, A, k, l, wpb);
+                if (dv2) {
+                    hipLaunchKernelGGL(k_lcnf<G>, glay, dim3(64 * wpb), smem, s, A, k, l, wpb);
+                } else {
+                    hipLaunchKernelGGL(k_lal<G>, glal, blk, 0, s, A, k, l);
+                    hipLaunchKernelGGL(k_lcn<G>, glay, dim3(64 * wpb), smem, s, A, k, l, wpb);
+                }
             }
             hipLaunchKernelGGL(k_dec<G>, gvn, blk, 0, s, A, k);
         } else if (fused) {
