@@ -1,6 +1,8 @@
-// Launch sequence of the fixed-point FFT-SPA decoder (Alg. 1): one kernel per phase,
-// every wavefront an independent (node, codeword group) unit; the phase bodies are
-// the device functions of dev_spa.h.
+// Launch sequences of the fixed-point FFT-SPA decoder (Alg. 1): the wave kernels (one
+// kernel per phase, or one per iteration where the variable phase is fused into the
+// check phase; every wavefront an independent (node, codeword group) unit) and the
+// LDS-resident kernel (one launch per decode).  The bodies are the device functions of
+// dev_spa.h.
 #include <algorithm>
 
 #include "dev_spa.h"
