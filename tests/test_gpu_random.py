@@ -89,3 +89,22 @@ def test_random_large_fused(rule, g, seed):
         torch.cuda.synchronize()
         ref = (O.decode_nb if rule == "minmax" else O.decode_spa)(code, O.params(**d), gam[idx])
         _check(code, out, ref, idx)
+
+
+@pytest.mark.parametrize("family", ["minmax_interleaved", "minmax_lds", "spa_wave", "spa_lds"])
+@pytest.mark.parametrize("iters", [0, 1])
+@pytest.mark.parametrize("early", [True, False])
+def test_fused_flooding_iteration_caps_0_and_1(family, iters, early):
+    """The fused flooding sequences at the smallest iteration caps: no iteration (the
+    channel decisions) and one (the decision pass right after the first check phase)."""
+    rule = "spa" if family.startswith("spa") else "minmax"
+    code = S.random_regular_nb_code(24, 12, 2, 4, 8, S.PRIM_POLY[8], seed=77)
+    gam = S.nb_gamma_int16(S.random_codewords(code, 45, seed=78), 8, 2.5, seed=79)
+    d = dict(rule=rule, schedule="flooding", max_iters=iters, early_stop=early)
+    h = L.Code(code)
+    cw = {"minmax_interleaved": 64, "minmax_lds": 64, "spa_wave": 1, "spa_lds": 8}[family]
+    L.plan_set(h, L.params(**d), 45, family, cw, 256)
+    out = L.decode(h, L.params(**d), torch.from_numpy(gam).to(DEV))
+    torch.cuda.synchronize()
+    ref = (O.decode_nb if rule == "minmax" else O.decode_spa)(code, O.params(**d), gam)
+    _check(code, out, ref)
