@@ -136,11 +136,9 @@ Plan default_plan(const ldpcx_code *c, const ldpcx_decode_params *p, int batch) 
     const DeviceInfo &di = device_info(c->device);
     if (c->g > 2 && p->rule == LDPCX_RULE_SPA) {
         pl.schedule = LDPCX_SCHED_FLOODING;
-        // Short low-degree codes of which a wave's worth of codewords fits in LDS (half a
-        // wave's worth where some variable degree is not 2, so the wave kernels run two
-        // phases): every vector on chip (measured faster there), else the wave kernels
-        const bool dv2 = c->dev.dv_max == 2 && c->dev.E == 2 * c->dev.n;
-        if (spa_lds_supported(c->dev) && (dv2 ? 1 : 2) * spa_lds_fit(c->dev) >= spa_lds_cpw(c->dev)) {
+        // Short low-degree codes of which at least half a wave's worth of codewords fits
+        // in LDS: every vector on chip (measured faster there), else the wave kernels
+        if (spa_lds_supported(c->dev) && 2 * spa_lds_fit(c->dev) >= spa_lds_cpw(c->dev)) {
             pl.family = FAMILY_SPA_LDS;
             pl.cpw = spa_lds_cw(c->dev, std::max(1, batch));
             pl.threads = 1024;
