@@ -15,6 +15,7 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+from typing import Optional
 
 import numpy as np
 
@@ -61,6 +62,10 @@ def lib():
         L.orc_wht.restype = None
         L.orc_wht.argtypes = [ctypes.c_int, i32p, i32p]
         L.orc_spa_cn.restype = None
+        L.orc_spa_qmul.restype = ctypes.c_int32
+        L.orc_spa_qmul.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.orc_spa_norm.restype = ctypes.c_int
+        L.orc_spa_norm.argtypes = [ctypes.c_int, i32p, i32p]
         L.orc_decode_spa.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -169,7 +174,7 @@ def decode_binary(code, prm: Params, llr: np.ndarray, dump: bool = False, nthrea
         None if dq is None else _p(dq, ctypes.c_int32), None if dr is None else _p(dr, ctypes.c_int32),
         None if dl is None else _p(dl, ctypes.c_int32), ctypes.c_int(_nthreads(nthreads)))
     if rc == -2:
-        raise ValueError("oracle: the fixed-point FFT-SPA covers fields up to GF(64)")
+        raise ValueError("oracle: the fixed-point FFT-SPA covers fields up to GF(256)")
     if rc != 0:
         raise ValueError("oracle: every check must have degree >= 2")
     out = dict(hard=hard, ok=ok, iters=it)
@@ -216,6 +221,19 @@ def spa_weight(c: int) -> int:
     return lib().orc_spa_weight(int(c))
 
 
+def spa_qmul(a: int, b: int) -> int:
+    """Product of two Q24 numbers as the fixed-point FFT-SPA takes it."""
+    return int(lib().orc_spa_qmul(int(a), int(b)))
+
+
+def spa_norm(z) -> Optional[np.ndarray]:
+    """Normalisation of a non-negative vector to a Q24 distribution (None when sum z = 0)."""
+    z = np.ascontiguousarray(z, dtype=np.int32)
+    out = np.empty_like(z)
+    ok = lib().orc_spa_norm(ctypes.c_int(len(z)), _p(z, ctypes.c_int32), _p(out, ctypes.c_int32))
+    return out if ok else None
+
+
 def wht(x) -> np.ndarray:
     """Walsh-Hadamard transform of an integer vector (length g)."""
     x = np.ascontiguousarray(x, dtype=np.int32)
@@ -236,7 +254,7 @@ def spa_cn(g: int, poly: int, h, u) -> np.ndarray:
 
 
 def decode_spa(code, prm: Params, gamma: np.ndarray, dump: bool = False, nthreads=None) -> dict:
-    """gamma int16 [B, n, g], g <= 64 -> dict(hard, ok, iters, and u/v dumps [B, E, g] in Q24)."""
+    """gamma int16 [B, n, g], g <= 256 -> dict(hard, ok, iters, and u/v dumps [B, E, g] in Q24)."""
     gamma = np.ascontiguousarray(gamma, dtype=np.int16)
     B, n, g = gamma.shape
     rp = np.ascontiguousarray(code.row_ptr, dtype=np.int32)
@@ -255,7 +273,7 @@ def decode_spa(code, prm: Params, gamma: np.ndarray, dump: bool = False, nthread
         _p(it, ctypes.c_int16), None if du is None else _p(du, ctypes.c_int32),
         None if dv is None else _p(dv, ctypes.c_int32), ctypes.c_int(_nthreads(nthreads)))
     if rc == -2:
-        raise ValueError("oracle: the fixed-point FFT-SPA covers fields up to GF(64)")
+        raise ValueError("oracle: the fixed-point FFT-SPA covers fields up to GF(256)")
     if rc != 0:
         raise ValueError("oracle: every check must have degree >= 2")
     out = dict(hard=hard, ok=ok, iters=it)

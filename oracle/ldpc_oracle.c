@@ -407,7 +407,7 @@ static void nb_decode_one(const nb_code *C, const orc_params *P, const int16_t *
             /* eq. (14) on every edge */
             for (int e = 0; e < E; e++) nb_alpha(C, gamma, beta, e, amax, ap, alpha + (size_t)e * g);
         }
-        /* eq. (15) */
+        /* decision: the a posteriori step after eq. (15) */
         nb_decide(C, gamma, beta, hard);
         it = k;
     }
@@ -462,9 +462,9 @@ int orc_decode_nb(int g, uint32_t poly, int n, int m, const int32_t *row_ptr, co
 /* ------------------------------------------------ fixed-point FFT-SPA (Alg. 1) */
 /*
  * Alg. 1 in the probability domain with fixed point Q24 (2^24 = probability 1),
- * for fields up to GF(64) (so that the transform sums stay within 32 bits).  The
- * paper runs it in floating point and in 32- and 8-bit fixed point without stating
- * the fixed-point rules; these are the readings used here:
+ * for fields up to GF(256).  The paper runs it in floating point and in 32- and
+ * 8-bit fixed point without stating the fixed-point rules; these are the readings
+ * used here:
  *   - channel: p~(x) = W(gamma(x)) with W(c) = round(2^24 exp(-c / 4)) (gamma is the
  *     symbol cost in units of a quarter LLR, so exp(-gamma/4) is proportional to
  *     p(c_n = x | y_n)), then p = norm(p~);
@@ -473,12 +473,13 @@ int orc_decode_nb(int g, uint32_t poly, int n, int m, const int32_t *row_ptr, co
  *     channel vector p_n (uniform 2^24 / g for the channel itself);
  *   - product of two Q24 numbers: qmul(a, b) = floor((a b + 2^23) / 2^24), applied in
  *     ascending edge order (the first factor taken as is);
- *   - eq. (8): the transform over GF(2^q) is the Walsh-Hadamard transform
+ *   - eq. (3): the transform over GF(2^q) is the Walsh-Hadamard transform
  *     F(f) = sum_t (-1)^popcount(f & t) u(t), exact in integers; the inverse is the same
- *     sum followed by floor division by g and a clamp at 0;
- *   - permutation (eq. 7) u'(t) = u(h^-1 t) and depermutation v'(x) = v(h x), as in
+ *     sum, taken in 64 bits (its magnitude reaches g 2^24, beyond 32 bits from GF(128)
+ *     on), followed by floor division by g and a clamp at 0;
+ *   - permutation (eq. (2)) u'(t) = u(h^-1 t) and depermutation (eq. (4)) v'(x) = v(h x), as in
  *     the Min-Max reading (the distribution of h c_n);
- *   - eqs. (10)-(11): z(x) = qmul-product of p_n(x) and the other incoming v'; the
+ *   - eqs. (5)-(6): z(x) = qmul-product of p_n(x) and the other incoming v'; the
  *     outgoing message is norm(z);
  *   - decision: argmax of p_n(x) times every incoming v' (same product rule), lowest
  *     x on ties; the stop rule and iteration count are those of Alg. 2.
@@ -495,13 +496,13 @@ int orc_spa_weight(int c)
 
 static int64_t floordiv(int64_t x, int64_t d) { return x >= 0 ? x / d : -((-x + d - 1) / d); }
 
-static int32_t spa_qmul(int32_t a, int32_t b)
+int32_t orc_spa_qmul(int32_t a, int32_t b)
 {
     return (int32_t)floordiv((int64_t)a * b + ((int64_t)1 << (SPA_Q - 1)), (int64_t)1 << SPA_Q);
 }
 
 /* norm(z) into out; returns 0 when sum z = 0 (out untouched) */
-static int spa_norm(int g, const int32_t *z, int32_t *out)
+int orc_spa_norm(int g, const int32_t *z, int32_t *out)
 {
     int64_t s = 0;
     for (int x = 0; x < g; x++) s += z[x];
@@ -513,14 +514,23 @@ static int spa_norm(int g, const int32_t *z, int32_t *out)
 
 static int popc(unsigned v) { int c = 0; while (v) { c += v & 1u; v >>= 1; } return c; }
 
-/* out(f) = sum_t (-1)^popcount(f & t) in(t) */
-void orc_wht(int g, const int32_t *in, int32_t *out)
+/* out(f) = sum_t (-1)^popcount(f & t) in(t), in 64 bits */
+static void wht64(int g, const int32_t *in, int64_t *out)
 {
     for (int f = 0; f < g; f++) {
         int64_t s = 0;
         for (int t = 0; t < g; t++) s += (popc((unsigned)(f & t)) & 1) ? -(int64_t)in[t] : in[t];
-        out[f] = (int32_t)s;
+        out[f] = s;
     }
+}
+
+/* The same transform with 32-bit outputs (every caller's sums fit 32 bits). */
+void orc_wht(int g, const int32_t *in, int32_t *out)
+{
+    int64_t *w = (int64_t *)malloc(sizeof(int64_t) * g);
+    wht64(g, in, w);
+    for (int f = 0; f < g; f++) out[f] = (int32_t)w[f];
+    free(w);
 }
 
 /* Check-node processing of Alg. 1 for one check: u: [dc][g] incoming Q24 messages,
@@ -531,34 +541,35 @@ void orc_spa_cn(int g, uint32_t poly, int dc, const uint8_t *h, const int32_t *u
     int32_t *t1 = (int32_t *)malloc(sizeof(int32_t) * g);
     int32_t *acc = (int32_t *)malloc(sizeof(int32_t) * g);
     int32_t *vv = (int32_t *)malloc(sizeof(int32_t) * g);
+    int64_t *inv = (int64_t *)malloc(sizeof(int64_t) * g);
     for (int j = 0; j < dc; j++) {
-        orc_gf_permute(g, poly, h[j], u + (size_t)j * g, t1);   /* eq. (7) */
-        orc_wht(g, t1, U + (size_t)j * g);                      /* forward transform of eq. (8) */
+        orc_gf_permute(g, poly, h[j], u + (size_t)j * g, t1);   /* eq. (2) */
+        orc_wht(g, t1, U + (size_t)j * g);                      /* forward transform of eq. (3) */
     }
     for (int n = 0; n < dc; n++) {
         int first = 1;
         for (int j = 0; j < dc; j++) {
             if (j == n) continue;
             for (int f = 0; f < g; f++)
-                acc[f] = first ? U[(size_t)j * g + f] : spa_qmul(acc[f], U[(size_t)j * g + f]);
+                acc[f] = first ? U[(size_t)j * g + f] : orc_spa_qmul(acc[f], U[(size_t)j * g + f]);
             first = 0;
         }
-        orc_wht(g, acc, t1);                                    /* inverse transform */
+        wht64(g, acc, inv);                                     /* inverse transform */
         for (int t = 0; t < g; t++) {
-            int64_t x = floordiv(t1[t], g);
+            int64_t x = floordiv(inv[t], g);
             vv[t] = x < 0 ? 0 : (int32_t)x;
         }
-        for (int x = 0; x < g; x++)                              /* eq. (9): v'(x) = v(h x) */
+        for (int x = 0; x < g; x++)                              /* eq. (4): v'(x) = v(h x) */
             v[(size_t)n * g + x] = vv[orc_gf_mul(g, poly, h[n], x)];
     }
-    free(U); free(t1); free(acc); free(vv);
+    free(U); free(t1); free(acc); free(vv); free(inv);
 }
 
 static void spa_channel(int g, const int16_t *gam, int32_t *p)
 {
     int32_t *w = (int32_t *)malloc(sizeof(int32_t) * g);
     for (int x = 0; x < g; x++) w[x] = orc_spa_weight(gam[x]);
-    if (!spa_norm(g, w, p))
+    if (!orc_spa_norm(g, w, p))
         for (int x = 0; x < g; x++) p[x] = (1 << SPA_Q) / g;
     free(w);
 }
@@ -593,17 +604,17 @@ static void spa_decode_one(const nb_code *C, const orc_params *P, const int16_t 
                 for (int x = 0; x < g; x++) {
                     int32_t a = pch[(size_t)i * g + x];
                     for (int w = C->vn_ptr[i]; w < C->vn_ptr[i + 1]; w++)
-                        if (w != t) a = spa_qmul(a, v[(size_t)C->vn_edge[w] * g + x]);
+                        if (w != t) a = orc_spa_qmul(a, v[(size_t)C->vn_edge[w] * g + x]);
                     z[x] = a;
                 }
-                if (!spa_norm(g, z, u + (size_t)e * g))
+                if (!orc_spa_norm(g, z, u + (size_t)e * g))
                     for (int x = 0; x < g; x++) u[(size_t)e * g + x] = pch[(size_t)i * g + x];
             }
             /* a posteriori product and decision */
             int best = 0, bv = -1;
             for (int x = 0; x < g; x++) {
                 int32_t a = pch[(size_t)i * g + x];
-                for (int w = C->vn_ptr[i]; w < C->vn_ptr[i + 1]; w++) a = spa_qmul(a, v[(size_t)C->vn_edge[w] * g + x]);
+                for (int w = C->vn_ptr[i]; w < C->vn_ptr[i + 1]; w++) a = orc_spa_qmul(a, v[(size_t)C->vn_edge[w] * g + x]);
                 if (a > bv) { bv = a; best = x; }
             }
             hard[i] = (uint8_t)best;
@@ -617,7 +628,7 @@ static void spa_decode_one(const nb_code *C, const orc_params *P, const int16_t 
     free(pch); free(u); free(v); free(z);
 }
 
-/* gamma: int16 [batch][n][g], g <= 64; hard: uint8 [batch][n]; dumps int32 [batch][E][g]
+/* gamma: int16 [batch][n][g], g <= 256; hard: uint8 [batch][n]; dumps int32 [batch][E][g]
  * (may be NULL): u (variable-to-check) and v' (check-to-variable) messages in Q24. */
 int orc_decode_spa(int g, uint32_t poly, int n, int m, const int32_t *row_ptr, const int32_t *col_idx,
                    const uint8_t *h_val, const orc_params *P, int batch, const int16_t *gamma,
@@ -625,7 +636,7 @@ int orc_decode_spa(int g, uint32_t poly, int n, int m, const int32_t *row_ptr, c
                    int32_t *dump_v, int nthreads)
 {
     int E = row_ptr[m];
-    if (g > 64) return -2;
+    if (g > 256) return -2;
     for (int i = 0; i < m; i++)
         if (row_ptr[i + 1] - row_ptr[i] < 2) return -1;
     int32_t *vn_ptr = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));

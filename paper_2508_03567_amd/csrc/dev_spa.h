@@ -1,11 +1,11 @@
 // Fixed-point FFT-SPA decoder (Alg. 1) for fields up to GF(64), as wave-level device
 // functions.
 //
-// Arithmetic: probabilities in Q24 (2^24 = 1); the transform of eq. (8) over GF(2^q)
+// Arithmetic: probabilities in Q24 (2^24 = 1); the transform of eq. (3) over GF(2^q)
 // is the Walsh-Hadamard transform, exact in 32-bit integers; products of two Q24
 // numbers are floor((a b + 2^23) / 2^24), taken in ascending edge order; the inverse
 // transform is followed by a floor division by g and a clamp at 0; a vector z is
-// normalised (eq. (11)) as floor((z(x) R + 2^21) / 2^22) with R = floor(2^46 / sum z);
+// normalised (eq. (6)) as floor((z(x) R + 2^21) / 2^22) with R = floor(2^46 / sum z);
 // channel vectors come from the symbol costs gamma through the weights
 // W(c) = round(2^24 exp(-c / 4)).
 //
@@ -303,7 +303,7 @@ __device__ __forceinline__ void init_unit(const Args &A, long unit, bool write_u
     if (L.j == 0) ((uint8_t *)A.io.hard)[(size_t)L.b * C.n + L.node] = (uint8_t)best;
 }
 
-// Check-node arithmetic of eqs. (7)-(9) for one lane: load_u(j, ix, U) fills the
+// Check-node arithmetic of eqs. (2)-(4) for one lane: load_u(j, ix, U) fills the
 // permuted inputs u'(t) = u(h^-1 t) of edge j (ix: positions h^-1 x of this lane's
 // entries), store_v(n, ix, v) writes output n at the same positions (v'(h^-1 z) = v(z)).
 // Output n takes the product of every other transformed input in ascending order; pre
@@ -348,7 +348,7 @@ __device__ __forceinline__ void cn_core(const DevCode &C, int e0, int dc, int x0
     }
 }
 
-// Variable-node arithmetic of eqs. (10)-(11) for one lane: vv holds the dv incoming
+// Variable-node arithmetic of eqs. (5)-(6) for one lane: vv holds the dv incoming
 // messages, store_u(m, u) writes u_m = norm(p times every incoming message but m,
 // ascending); pre holds p times messages 0 .. m-1 and ends as the a posteriori product,
 // whose arg-max is returned.
@@ -417,7 +417,7 @@ __device__ __forceinline__ void cn_unit(const Args &A, int k, long unit) {
 
 // Flooding for codes whose variables all have degree 2, fused into the check node: the
 // check forms each incoming u = norm(p times the other edge's v of the previous
-// iteration) itself (eqs. (10)-(11) with one factor), so the variable-node phase and
+// iteration) itself (eqs. (5)-(6) with one factor), so the variable-node phase and
 // its u stores disappear; v alternates between the v and u arrays (v_old -> v_new).
 // With v = 0 before the first iteration the product is 0 and norm falls back to p,
 // which is u before the first iteration.

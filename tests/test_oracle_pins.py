@@ -199,6 +199,34 @@ def test_binary_ms_special_cases():
     assert list(O.binary_cn(q0, prm_ms)) == [-4, 0, 0]
 
 
+# Magnitudes f(m) worked out by hand from the two normalisations the binary decoders
+# use: NMS 0.75 takes the floor of 3m/4 on the magnitude and applies the sign after
+# (so -5 gives -3, not floor(-15/4) = -4), OMS with offset 1 takes max(m - 1, 0).
+_HAND_F = {
+    "nms": {0: 0, 1: 0, 2: 1, 3: 2, 5: 3, 127: 95},
+    "oms": {0: 0, 1: 0, 2: 1, 3: 2, 5: 4, 127: 126},
+}
+
+
+@pytest.mark.parametrize("rule", ["nms", "oms"])
+def test_binary_cn_normalisation_hand_values(rule):
+    """Check-node outputs with one small input m among two of magnitude 127: the
+    edges that see m get sign * f(m), the edge of m gets sign * f(127).  Catches a
+    rounded-up NMS ((3m + 2) >> 2 differs at m = 1, 2, 5) and an OMS without its
+    clamp at 0 (m = 0 would give -1)."""
+    prm = O.params(rule, nms_num=3, nms_shift=2, oms_offset=1)
+    f = _HAND_F[rule]
+    for m, fm in f.items():
+        r = O.binary_cn(np.array([m, 127, -127], dtype=np.int32), prm)
+        assert list(r) == [-f[127], -fm, fm], (rule, m)
+        # a negative input: the others see its sign, the magnitude is normalised first
+        r = O.binary_cn(np.array([-m, 127, 127], dtype=np.int32), prm)
+        assert list(r) == [f[127], -fm, -fm], (rule, -m)
+    # a zero input zeroes every other output under both rules (f(0) = 0)
+    r = O.binary_cn(np.array([0, -4, 6], dtype=np.int32), prm)
+    assert list(r) == [-(3 if rule == "nms" else 3), 0, 0]
+
+
 def test_binary_cn_is_gf2_minmax():
     rng = np.random.default_rng(11)
     for dc in range(2, 9):
@@ -483,10 +511,13 @@ def test_fer_falls_with_snr_layered_oms():
     assert fer[0] >= fer[1] >= fer[2]
 
 
-@pytest.mark.parametrize("cfg,sched", [(0, "flooding"), (0, "layered"), (1, "layered"), (1, "flooding")])
-def test_app_is_channel_plus_check_messages(cfg, sched):
-    """Lambda_n = L_n + sum_m r_mn holds exactly after any number of iterations in
-    both schedules (saturation applies to what the check node sees, not to Lambda)."""
+@pytest.mark.parametrize("cfg", [0, 1])
+def test_layered_app_is_channel_plus_check_messages(cfg):
+    """The layered decoder updates Lambda in place (Lambda <- Lambda - r_old + r_new,
+    row by row); after any number of iterations that running sum must equal the closed
+    form L_n + sum_m r_mn (saturation applies to what the check node sees, not to
+    Lambda).  A dropped or doubled r_old in the in-place update breaks it."""
+    sched = "layered"
     w = S.workload(cfg, batch=16)
     cw, llr = S.make_inputs(w)
     for iters in [1, 3, 25]:
@@ -545,7 +576,7 @@ def _exact_spa_cn(g, poly, h, u):
 @pytest.mark.parametrize("g,dc", [(4, 2), (4, 3), (4, 4), (8, 3), (8, 4), (16, 3)])
 def test_spa_cn_matches_exact_convolution(g, dc):
     """The transform-domain check node equals the probability convolution it replaces
-    (eq. (8)), within the rounding of the Q15 products; exact for degree 2."""
+    (eq. (3)), within the rounding of the Q24 products; exact for degree 2."""
     rng = np.random.default_rng(100 * g + dc)
     poly = S.PRIM_POLY[g]
     for _ in range(4):
@@ -588,3 +619,156 @@ def test_spa_fer_falls_with_snr():
         mm.append(float((m["hard"] != cw).any(axis=1).mean()))
     assert fers[2] < fers[0] and fers[2] <= 0.05
     assert sum(fers) <= sum(mm)
+
+
+def _exact_spa_cn_np(g, poly, h, u):
+    """Vectorised form of the enumeration above for degrees 2 and 3 (large fields)."""
+    gf = S._GFEnc(g, poly)
+    dc = len(h)
+    u = np.asarray(u, dtype=np.float64) / float(1 << 24)
+    v = np.zeros((dc, g))
+    c = np.arange(g)
+    for j in range(dc):
+        others = [k for k in range(dc) if k != j]
+        hjinv = int(gf.inv(h[j]))
+        if len(others) == 1:
+            k = others[0]
+            x = gf.mul(hjinv, gf.mul(h[k], c))
+            np.add.at(v[j], x, u[k])
+        else:
+            k1, k2 = others
+            s = gf.mul(h[k1], c)[:, None] ^ gf.mul(h[k2], c)[None, :]
+            x = gf.mul(hjinv, s)
+            np.add.at(v[j], x.ravel(), (u[k1][:, None] * u[k2][None, :]).ravel())
+    return v * float(1 << 24)
+
+
+@pytest.mark.parametrize("g,dc", [(32, 3), (64, 2), (64, 3), (128, 2), (128, 3), (256, 2), (256, 3)])
+def test_spa_cn_matches_exact_convolution_large_fields(g, dc):
+    """Same pin up to GF(256), where the inverse transform's sums (up to g 2^24) leave
+    32 bits: the check node must still equal the exact convolution within the Q24
+    product rounding (a 32-bit wrap-around would be off by multiples of 2^32 / g)."""
+    rng = np.random.default_rng(7 * g + dc)
+    poly = S.PRIM_POLY[g]
+    for _ in range(3):
+        h = rng.integers(1, g, size=dc)
+        w = rng.random((dc, g)) ** 4
+        w[:, rng.integers(0, g)] += 2.0  # a dominant entry, as in decoding
+        u = np.floor(w / w.sum(axis=1, keepdims=True) * (1 << 24)).astype(np.int64)
+        got = O.spa_cn(g, poly, h, u)
+        want = _exact_spa_cn_np(g, poly, h, u)
+        tol = 0 if dc == 2 else 2 * dc + 2
+        assert np.abs(got - want).max() <= tol + 1e-6
+        assert (got >= 0).all()
+    # confident messages (point masses, as near convergence): every transform entry is
+    # +-2^24 and the inverse sum reaches g 2^24 at the one symbol that satisfies the
+    # check, which must come out as probability one
+    gf = S._GFEnc(g, poly)
+    for _ in range(3):
+        h = rng.integers(1, g, size=dc)
+        c = rng.integers(0, g, size=dc)
+        u = np.zeros((dc, g), dtype=np.int64)
+        u[np.arange(dc), c] = 1 << 24
+        got = O.spa_cn(g, poly, h, u)
+        for j in range(dc):
+            s = 0
+            for k in range(dc):
+                if k != j:
+                    s ^= int(gf.mul(h[k], c[k]))
+            want = np.zeros(g, dtype=np.int64)
+            want[int(gf.mul(gf.inv(h[j]), s))] = 1 << 24
+            assert (got[j] == want).all(), (g, dc, j)
+
+
+def test_spa_qmul_is_the_nearest_integer():
+    """qmul(a, b) is ab / 2^24 rounded to the nearest integer, halves rounded up:
+    -2^23 < 2^24 qmul(a, b) - ab <= 2^23, in exact integer arithmetic.  A truncating
+    product (no + 2^23) is off by one on about half of these pairs."""
+    rng = np.random.default_rng(3)
+    a = rng.integers(-(1 << 24), (1 << 24) + 1, size=4000)
+    b = rng.integers(0, (1 << 24) + 1, size=4000)
+    for x, y in list(zip(a, b)) + [(1 << 23, 1), (3, 1 << 23), (-3, 1 << 23), (1 << 24, 1 << 24), (0, 5)]:
+        d = O.spa_qmul(int(x), int(y)) * (1 << 24) - int(x) * int(y)
+        assert -(1 << 23) < d <= (1 << 23), (x, y)
+    # a half rounds up: 3 * 2^23 / 2^24 = 1.5 -> 2, and -1.5 -> -1
+    assert O.spa_qmul(3, 1 << 23) == 2 and O.spa_qmul(-3, 1 << 23) == -1
+
+
+def test_spa_norm_error_bound():
+    """norm(z)(x) approximates 2^24 z(x) / S, S = sum z.  With the truncated reciprocal
+    R = floor(2^46 / S) and rounding to nearest it lies in (t - 1/2 - z(x) / 2^22,
+    t + 1/2] for the exact t = 2^24 z(x) / S; when S = 2^26 the reciprocal is exact and
+    norm(z)(x) = round(z(x) / 4).  A truncating normalisation (no + 2^21) leaves the
+    lower bound on a large share of the entries."""
+    from fractions import Fraction
+    rng = np.random.default_rng(5)
+    for g in (4, 16, 64, 256):
+        for _ in range(40):
+            z = rng.integers(0, 1 << 19, size=g)
+            z[rng.integers(0, g)] += int(rng.integers(0, 1 << 20))
+            out = O.spa_norm(z)
+            S_ = int(z.sum())
+            for zx, nx in zip(z.tolist(), out.tolist()):
+                t = Fraction(zx << 24, S_)
+                assert t - Fraction(1, 2) - Fraction(zx, 1 << 22) < nx <= t + Fraction(1, 2), (g, zx, nx)
+    # S = 2^26: exact reciprocal, plain rounding of z / 4 (halves up)
+    z = np.array([(1 << 26) - 6 - 5 - 7, 6, 5, 7], dtype=np.int64)
+    assert list(O.spa_norm(z)) == [(1 << 24) - 4, 2, 1, 2]
+    assert O.spa_norm(np.zeros(8, dtype=np.int64)) is None
+
+
+@pytest.mark.parametrize("which", ["gf64_dv2", "gf16_dv3"])
+def test_spa_variable_node_against_exact_products(which):
+    """Eqs. (5)-(6) and the decision after them, checked against exact rational
+    arithmetic: after one iteration every u must lie within the error bound of the
+    exact normalised product of p and the variable's other incoming messages, and the
+    decision must be the exact arg-max of p times every message wherever the exact
+    margin exceeds the rounding.  A dropped factor, the edge's own message in place of
+    another, or a wrong edge index all break it."""
+    if which == "gf64_dv2":
+        w = S.workload(3, batch=3, ebn0_db=1.5)
+        code, (cw, gam) = w.code, S.make_inputs(w)
+    else:
+        code = S.random_regular_nb_code(24, 12, 3, 6, 16, S.PRIM_POLY[16], seed=9)
+        gam = np.random.default_rng(2).integers(0, 40, size=(3, 24, 16)).astype(np.int16)
+        gam -= gam.min(axis=2, keepdims=True)
+    g = code.g
+    r = O.decode_spa(code, O.params("spa", "flooding", 1, False), gam, dump=True)
+    edges_of = [[] for _ in range(code.n)]
+    for e, v in enumerate(code.col_idx):
+        edges_of[v].append(e)
+    checked = total = 0
+    for b in range(gam.shape[0]):
+        for i in range(code.n):
+            p = O.spa_norm(np.array([O.spa_weight(int(c)) for c in gam[b, i]]))
+            es = edges_of[i]
+            dv = len(es)
+            for e in es:
+                num = [int(p[x]) for x in range(g)]
+                for f in es:
+                    if f != e:
+                        num = [num[x] * int(r["v"][b, f, x]) for x in range(g)]
+                k = dv - 1
+                eps = 0.5 * k * 1.001  # rounding of k products, in Q24 units
+                den = 1 << (24 * k)
+                S_e = sum(num) / den
+                for x in range(g):
+                    total += 1
+                    if S_e <= 2 * g * eps:
+                        continue
+                    z = num[x] / den
+                    t = (1 << 24) * z / S_e
+                    tol = 0.5 + (z + eps) / (1 << 22) + (1 << 24) * eps * (1 + g) / (S_e - g * eps) + 1e-6
+                    if tol > (1 << 16):  # a bound too loose to pin anything
+                        continue
+                    assert abs(int(r["u"][b, e, x]) - t) <= tol, (b, i, e, x)
+                    checked += 1
+            # decision: arg-max of p times every incoming message
+            app = [int(p[x]) for x in range(g)]
+            for f in es:
+                app = [app[x] * int(r["v"][b, f, x]) for x in range(g)]
+            order = sorted(range(g), key=lambda x: -app[x])
+            margin = (app[order[0]] - app[order[1]]) / (1 << (24 * dv))
+            if margin > dv * 1.001 + 1:
+                assert r["hard"][b, i] == order[0], (b, i)
+    assert checked > total // 2
