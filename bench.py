@@ -77,14 +77,33 @@ def algorithmic_bytes_per_cw(w) -> float:
     return io + w.max_iters * state
 
 
+# Integer operations of binary min-sum per edge and iteration (one codeword): check node
+# (magnitude, minimum and second minimum, sign parity: 6), outgoing message (select,
+# normalise, sign: 6), variable node (add, subtract, saturate: 4).
+BIN_OPS_PER_EDGE = 16
+
+
 def algorithmic_ops_per_cw(w) -> float:
-    """Integer operations the Min-Max method must do per codeword: per iteration, a max
+    """Integer operations the method must do per codeword.  Min-Max: per iteration, a max
     and a min for each of the 3 (dc - 2) g^2 pairs of every check (forward, backward and
-    middle-beta convolutions) plus about 6 E g for the variable nodes."""
+    middle-beta convolutions) plus about 6 E g for the variable nodes.  Binary min-sum:
+    BIN_OPS_PER_EDGE per edge and iteration."""
     c = w.code
+    if c.g == 2:
+        return float(w.max_iters) * BIN_OPS_PER_EDGE * c.nnz
     dc = np.diff(np.asarray(c.row_ptr))
     cn = float(np.sum(2 * 3 * np.maximum(dc - 2, 0))) * c.g * c.g
     return w.max_iters * (cn + 6.0 * c.nnz * c.g)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main() -> None:
@@ -131,8 +150,23 @@ def main() -> None:
                          "Min-Max, fixed iterations (one JSON line per point)")
     ap.add_argument("--sweep-rule", type=str, default="minmax", choices=["minmax", "spa"],
                     help="--sweep: decoder (spa covers GF(4)..GF(64))")
+    ap.add_argument("--prof-summary", type=str, default=None,
+                    help="summarise rocprofv3 CSV output instead of running: comma-separated output directories "
+                         "(one kernel-trace run, or the --pmc runs of one counter summary)")
+    ap.add_argument("--prof-kernel", type=str, default=None,
+                    help="--prof-summary: substring naming the decoder kernels (default: all kernels but copies)")
+    ap.add_argument("--prof-skip", type=int, default=0,
+                    help="--prof-summary: decodes at the start to leave out (warm-up)")
+    ap.add_argument("--prof-decodes", type=int, default=1, help="--prof-summary: decodes that follow them")
+    ap.add_argument("--prof-family", type=str, default=None,
+                    help="--prof-summary of counters: kernel family whose source hash the summary carries")
+    ap.add_argument("--prof-title", type=str, default="", help="--prof-summary: workload name for the heading")
+    ap.add_argument("--prof-cmd", type=str, default="", help="--prof-summary: command(s) that made the output")
     args = ap.parse_args()
 
+    if args.prof_summary:
+        prof_main(args)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); codewords are "
               "independent, so a multi-GPU run would split the batch with no exchange step.", file=sys.stderr)
@@ -305,20 +339,35 @@ def main() -> None:
         cpu = {"value": round(done_cw * w.info_bits_per_cw / cpu_s / 1e9, 6), "unit": "Gbit/s", "cores": nthreads,
                "kind": "oracle",
                "sample": f"{passes} pass(es) over the first {k} of the {w.batch} codewords, "
-                         f"{w.max_iters} fixed iterations, {cpu_s:.1f}s"}
+                         f"{w.max_iters} fixed iterations, {cpu_s:.1f}s",
+               "cpu_model": cpu_model()}
+        # One core: the same oracle on a sample of about a quarter of that time.
+        k1 = int(min(w.batch, max(1, 0.25 * args.cpu_seconds / max(per_cw * nthreads, 1e-9))))
+        t1 = time.perf_counter()
+        dec(w.code, prm_o, llr_np[:k1], nthreads=1)
+        s1 = time.perf_counter() - t1
+        cpu["one_core"] = {"value": round(k1 * w.info_bits_per_cw / s1 / 1e9, 6), "unit": "Gbit/s",
+                           "sample": f"the first {k1} codewords, {w.max_iters} fixed iterations, {s1:.1f}s"}
 
-    if w.code.g == 2:
+    alg_ops = algorithmic_ops_per_cw(w) * w.batch
+    tops = alg_ops / (kernel_ms * 1e-3) / 1e12
+    if plan["family"] == "bin_interleaved":
+        # message state streams through device memory every iteration: bound by HBM
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "alu_achieved_tops": round(tops, 3),
+                "alu_frac": round(tops / ALU_PEAK_TOPS_I16, 4)}
     else:
-        # Min-Max is bound by packed 16-bit integer VALU work, not by memory
-        alg_ops = algorithmic_ops_per_cw(w) * w.batch
-        tops = alg_ops / (kernel_ms * 1e-3) / 1e12
+        # The on-chip binary families (device memory carries only the I/O) and Min-Max are
+        # bound by packed 16-bit integer VALU work; the modelled state bytes per second
+        # are kept beside it as an effective bandwidth, not a roof this kernel meets.
         roof = {"bound": "alu", "achieved": round(tops, 3), "peak": round(ALU_PEAK_TOPS_I16, 2), "unit": "Tops/s int16",
-                "frac": round(tops / ALU_PEAK_TOPS_I16, 4), "algorithmic_ops_per_launch": int(alg_ops),
-                "hbm_achieved_gbs": round(achieved, 2), "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)}
-    roof.update({"traffic": traffic, "valu_frac": None if valu_frac is None else round(valu_frac, 4),
-                 "kernel_ms": round(kernel_ms, 4), "algorithmic_bytes_per_launch": int(alg_bytes)})
+                "frac": round(tops / ALU_PEAK_TOPS_I16, 4),
+                "hbm_model_gbs": round(achieved, 2), "hbm_model_frac": round(achieved / HBM_PEAK_GBS, 4)}
+    roof.update({"traffic": traffic, "hbm_measured_gbs": None if traffic is None else
+                 round(traffic / (kernel_ms * 1e-3) / 1e9, 2),
+                 "valu_frac": None if valu_frac is None else round(valu_frac, 4),
+                 "kernel_ms": round(kernel_ms, 4), "algorithmic_ops_per_launch": int(alg_ops),
+                 "algorithmic_bytes_per_launch": int(alg_bytes)})
     res = {
         "metric": "decoded info Gbit/s at fixed iters",
         "value": round(value, 4),
@@ -341,6 +390,119 @@ def main() -> None:
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
+
+
+# ------------------------------------------------------------------ rocprofv3 summaries
+def _prof_rows(dirs, suffix):
+    """Rows of every rocprofv3 CSV whose name ends in `suffix` under the directories."""
+    import csv
+    rows = []
+    for d in dirs:
+        for root, _, files in os.walk(d):
+            for f in sorted(files):
+                if f.endswith(suffix):
+                    with open(os.path.join(root, f), newline="") as fh:
+                        rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def _is_copy(name: str) -> bool:
+    return "copyBuffer" in name or "fillBuffer" in name or "FillFunctor" in name or "elementwise" in name
+
+
+def prof_main(args) -> None:
+    """Summaries of rocprofv3 runs of this benchmark for profiles/.
+
+    Kernel trace: per kernel, calls and mean / median / min / max duration over the whole
+    run, then the decoder kernels of the timed decodes only (the first --prof-skip decodes'
+    dispatches left out), summed per decode.  Counters (--pmc runs): the decoder kernels'
+    counters summed over the timed decodes' dispatches and divided by --prof-decodes, with
+    FETCH_SIZE and WRITE_SIZE scaled by what they read for the 256 MiB device copy that
+    --calib-copy runs at the end."""
+    dirs = [d for d in args.prof_summary.split(",") if d]
+    sel = (lambda nm: args.prof_kernel in nm) if args.prof_kernel else (lambda nm: not _is_copy(nm))
+    trace = _prof_rows(dirs, "kernel_trace.csv")
+    ctr = _prof_rows(dirs, "counter_collection.csv")
+    K, W = max(1, args.prof_decodes), max(0, args.prof_skip)
+    if trace and not ctr:
+        by = {}
+        order = []
+        for r in trace:
+            nm = r["Kernel_Name"]
+            dt = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+            if nm not in by:
+                by[nm] = []
+                order.append(nm)
+            by[nm].append((int(r["Start_Timestamp"]), dt))
+        total = sum(dt for v in by.values() for _, dt in v)
+        print(f"# rocprofv3 kernel statistics: {args.prof_title}\n")
+        print(f"Command (output under gpurun_out/):\n\n```\n{args.prof_cmd}\n```\n")
+        print("| kernel | calls | mean ns | median ns | min ns | max ns | % of GPU time |")
+        print("|---|---|---|---|---|---|---|")
+        for nm in sorted(order, key=lambda n: -sum(dt for _, dt in by[n])):
+            d = np.array([dt for _, dt in by[nm]], dtype=np.float64)
+            print(f"| `{nm[:110]}` | {len(d)} | {d.mean():.0f} | {np.median(d):.0f} | {d.min():.0f} | {d.max():.0f} "
+                  f"| {100 * d.sum() / total:.2f} |")
+        dec = sorted((t, dt) for nm in order if sel(nm) for t, dt in by[nm])
+        n_all = len(dec)
+        per = n_all // (W + K) if n_all % (W + K) == 0 else None
+        if per is None:
+            print(f"\n{n_all} decoder dispatches do not split evenly into {W} + {K} decodes.")
+            return
+        timed = np.array([dt for _, dt in dec[W * per:]], dtype=np.float64).reshape(K, per).sum(axis=1)
+        print(f"\nDecoder kernels: {per} dispatch(es) per decode; {W} warm-up decode(s) left out; over the "
+              f"{K} timed decodes the kernel time per decode is mean {timed.mean():.0f} ns, median "
+              f"{np.median(timed):.0f} ns, min {timed.min():.0f} ns, max {timed.max():.0f} ns.")
+        return
+    if not ctr:
+        print("no rocprofv3 CSV output found under " + ", ".join(dirs), file=sys.stderr)
+        sys.exit(1)
+    # counters: dispatch -> {counter: value}
+    disp = {}
+    for r in ctr:
+        key = (r.get("Process_Id", ""), r["Dispatch_Id"])
+        e = disp.setdefault(key, {"name": r["Kernel_Name"], "t": int(r.get("Start_Timestamp", 0) or 0), "c": {}})
+        e["c"][r["Counter_Name"]] = e["c"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    names = sorted({c for e in disp.values() for c in e["c"]})
+    out = {}
+    for cname in names:
+        rows = sorted((e["t"], e) for e in disp.values() if cname in e["c"])
+        dec = [e for _, e in rows if sel(e["name"])]
+        per = len(dec) // (W + K) if len(dec) % (W + K) == 0 else None
+        if not per:
+            print(f"{cname}: {len(dec)} decoder dispatches do not split into {W} + {K} decodes", file=sys.stderr)
+            sys.exit(1)
+        out[cname] = sum(e["c"][cname] for e in dec[W * per:]) / K
+        out[cname + "_dispatches"] = per
+        copies = [e["c"][cname] for _, e in rows if "copyBuffer" in e["name"]]
+        if cname in ("FETCH_SIZE", "WRITE_SIZE") and copies:
+            out[cname + "_scale"] = 262144.0 / max(copies)
+    print(f"# HBM traffic and VALU instruction counters per decode, workload {args.prof_title}")
+    for line in args.prof_cmd.split(";;"):
+        print(f"# run: {line.strip()}")
+    print("# Counters are summed over the decoder kernels of the timed decodes (warm-up left out).")
+    print("# FETCH_SIZE and WRITE_SIZE (KiB) are scaled by 256 MiB over what they read for the 256 MiB")
+    print("# device-to-device copy run at the end of the same command.")
+    if args.prof_family:
+        print(f"family: {args.prof_family}")
+        print(f"source_hash: {source_hash(args.prof_family)}")
+    print(f"decodes: {K}")
+    hbm = 0.0
+    for cname in ("FETCH_SIZE", "WRITE_SIZE"):
+        if cname in out:
+            sc = out.get(cname + "_scale", 1.0)
+            print(f"{cname.lower()}_kib_per_launch_raw: {out[cname]:.1f}")
+            print(f"{cname.lower()}_scale: {sc:.4f}")
+            hbm += out[cname] * sc * 1024
+    if "FETCH_SIZE" in out and "WRITE_SIZE" in out:
+        print(f"hbm_bytes_per_launch: {hbm:.0f}")
+    if "SQ_INSTS_VALU" in out:
+        print(f"valu_wave_instr_per_launch: {out['SQ_INSTS_VALU']:.0f}")
+    if "SQ_WAVES" in out:
+        print(f"waves_per_launch: {out['SQ_WAVES']:.0f}")
+    for cname in names:
+        if cname not in ("FETCH_SIZE", "WRITE_SIZE", "SQ_INSTS_VALU", "SQ_WAVES"):
+            print(f"{cname.lower()}_per_launch: {out[cname]:.0f}")
 
 
 # ------------------------------------------------------------------ GF-size sweep

@@ -55,6 +55,26 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
     int *itc = done + npairs;  // [2 * npairs]
     const v2s mm = splat(R.msg_max), nmm = splat(-R.msg_max);
     const PkNorm NP = pk_norm_params(R);
+    int rule = __builtin_amdgcn_readfirstlane(R.rule);  // uniform: scalar branches below
+    asm volatile("" : "+s"(rule));
+    // -128 in both halves, opaque to the compiler so that a * -128 + c stays one
+    // v_pk_mad_u16 instead of a shift and a subtraction
+    int kn128 = (int)0xFF80FF80u;
+    asm volatile("" : "+s"(kn128));
+    const v2s neg128 = as_v2s((uint32_t)kn128);
+    // f1 = f(m1), f2 = f(m2) for the rule (each branch exact for its rule)
+    auto norm2 = [&](v2s m1, v2s m2, v2s &f1, v2s &f2) {
+        if (rule == LDPCX_RULE_NMS) {
+            f1 = (m1 * NP.num) >> NP.shift;
+            f2 = (m2 * NP.num) >> NP.shift;
+        } else if (rule == LDPCX_RULE_OMS) {
+            f1 = pmax(m1 - NP.off, splat(0));
+            f2 = pmax(m2 - NP.off, splat(0));
+        } else {
+            f1 = m1;
+            f2 = m2;
+        }
+    };
 
     for (int idx = tid; idx < ML * MD; idx += T) {
         const int l = idx / MD, j = idx - l * MD;
@@ -157,6 +177,9 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
                 uint32_t sv[MD];
 #pragma unroll
                 for (int j = 0; j < MD; ++j) {
+                    // The last two edge slots are skipped (uniform branch) where the layer has
+                    // fewer edges; earlier slots beyond the degree run as virtual edges.
+                    if (j >= MD - 2 && j >= dc) continue;
                     // |clamp(q, +-msg_max)| = min(|q|, msg_max); the sign of q is the sign of clamp(q)
                     const v2s q = lv[j] - r[l][j];
                     const uint32_t sg = as_u32(q >> splat(15));
@@ -168,12 +191,16 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
                     av[j] = a;
                     sv[j] = sg;
                 }
-                const v2s f1 = pk_norm(NP, m1), f2 = pk_norm(NP, m2);
-                const v2s df = f1 - f2;
+                v2s f1, f2;
+                norm2(m1, m2, f1, f2);
+                // Magnitude out of edge j: f2 where the edge holds the minimum (a = m1), else f1.
+                // With all magnitudes in [0, 127] and 128 >= f2 - f1, that is
+                // max(f1, f2 + 128 (m1 - a)), exact in 16 bits (the sum lies in [-16256, 16383]).
+                const v2s cs = f2 - m1 * neg128;
 #pragma unroll
                 for (int j = 0; j < MD; ++j) {
-                    const v2s t = pmin(av[j] - m1, splat(1));  // 0 where this edge holds the minimum
-                    const v2s mag = f2 + t * df;
+                    if (j >= MD - 2 && j >= dc) continue;
+                    const v2s mag = pmax(f1, av[j] * neg128 + cs);
                     const uint32_t sr = stot ^ sv[j];
                     const v2s rn = as_v2s(as_u32(mag) ^ sr) - as_v2s(sr);
                     const v2s rk = ES ? as_v2s(bfi(M, as_u32(rn), as_u32(r[l][j]))) : rn;
@@ -181,7 +208,7 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
                     if (LAYERED) lds_word(lamp, vv[j]) = as_u32(qv[j] + rk);
                 }
                 // virtual edges wrote q + r into their dummy slot: restore it
-                if (LAYERED && dc < MD) lamp[n + i0] = kDummy;
+                if (LAYERED && dc < MD - 2) lamp[n + i0] = kDummy;
               }
                 if (LAYERED) __syncthreads();
             }
