@@ -168,6 +168,23 @@ ldpcx_status ldpcx_debug_dump(const ldpcx_code *code, const ldpcx_decode_params 
                               int32_t batch, const void *llr, void *hard, uint8_t *syndrome_ok,
                               int16_t *iters, void *msg_a, void *msg_b, void *msg_c, void *stream);
 
+/* Allocation-free variant of ldpcx_decode, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, layouts and results as ldpcx_decode (bit for bit), on the plan
+ * ldpcx_decode would use.  The call allocates nothing: no hipMalloc, no stream-ordered
+ * allocation, no graph capture.  Decoders that need a workspace take it from one static
+ * device array of LDPCX_NOALLOC_SCRATCH_BYTES per GPU, held from the first call on that
+ * GPU until the process ends; the batch then runs as consecutive chunks on `stream`
+ * whose workspaces fit the array.  Every call on one GPU shares that GPU's array, so calls
+ * that overlap on one GPU (other streams or threads, without ordering between them)
+ * race and give wrong results: the caller serialises them.  Errors as ldpcx_decode, plus
+ * LDPCX_E_UNSUPPORTED when the workspace of the smallest chunk the decoder allows (one
+ * group of 256 codewords for long binary codes, one codeword otherwise) exceeds the array. */
+#define LDPCX_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+ldpcx_status ldpcx_decode_noalloc(const ldpcx_code *code, const ldpcx_decode_params *params, int32_t batch,
+                                  const void *llr, void *hard, uint8_t *syndrome_ok, int16_t *iters,
+                                  int32_t *schedule_used, void *stream);
+
 /* One job of a ragged batch: `batch` codewords of `code` with their own parameters and
  * buffers (same layouts as ldpcx_decode). */
 typedef struct {

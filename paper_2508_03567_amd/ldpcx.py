@@ -69,6 +69,9 @@ _SIGS = {
                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                      ctypes.c_void_p],
     "ldpcx_debug_dump": [ctypes.c_void_p, ctypes.POINTER(DecodeParams), ctypes.c_int32] + [ctypes.c_void_p] * 8,
+    "ldpcx_decode_noalloc": [ctypes.c_void_p, ctypes.POINTER(DecodeParams), ctypes.c_int32, ctypes.c_void_p,
+                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                             ctypes.c_void_p],
     "ldpcx_decode_ragged": [ctypes.POINTER(Job), ctypes.c_int32, ctypes.c_void_p],
     "ldpcx_tune": [ctypes.c_void_p, ctypes.POINTER(DecodeParams), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                    ctypes.POINTER(ctypes.c_float), ctypes.c_void_p],
@@ -146,6 +149,14 @@ def ldpcx_decode(code: int, prm: DecodeParams, batch: int, llr: int, hard: int, 
     used = ctypes.c_int32(-1)
     _check(lib().ldpcx_decode(code, ctypes.byref(prm), batch, llr, hard, syndrome_ok, iters, ctypes.byref(used),
                               stream))
+    return used.value
+
+
+def ldpcx_decode_noalloc(code: int, prm: DecodeParams, batch: int, llr: int, hard: int, syndrome_ok: int,
+                         iters: int, stream: int = 0) -> int:
+    used = ctypes.c_int32(-1)
+    _check(lib().ldpcx_decode_noalloc(code, ctypes.byref(prm), batch, llr, hard, syndrome_ok, iters,
+                                      ctypes.byref(used), stream))
     return used.value
 
 
@@ -285,6 +296,16 @@ def decode(code: Code, prm: DecodeParams, llr, stream=None, out=None):
     hard, ok, it = out if out is not None else _outputs(code, batch, llr.device)
     used = ldpcx_decode(code.handle, prm, batch, llr.data_ptr(), hard.data_ptr(), ok.data_ptr(), it.data_ptr(),
                         _stream_ptr(stream))
+    return hard, ok, it, SCHED_NAME.get(used, used)
+
+
+def decode_noalloc(code: Code, prm: DecodeParams, llr, stream=None, out=None):
+    """As decode(), through the allocation-free entry point (caller-provided outputs via `out`)."""
+    _check_llr(code, llr)
+    batch = int(llr.shape[0])
+    hard, ok, it = out if out is not None else _outputs(code, batch, llr.device)
+    used = ldpcx_decode_noalloc(code.handle, prm, batch, llr.data_ptr(), hard.data_ptr(), ok.data_ptr(),
+                                it.data_ptr(), _stream_ptr(stream))
     return hard, ok, it, SCHED_NAME.get(used, used)
 
 
