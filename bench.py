@@ -341,13 +341,17 @@ def main() -> None:
                "sample": f"{passes} pass(es) over the first {k} of the {w.batch} codewords, "
                          f"{w.max_iters} fixed iterations, {cpu_s:.1f}s",
                "cpu_model": cpu_model()}
-        # One core: the same oracle on a sample of about a quarter of that time.
+        # One core: the same oracle, passes over a sample until about a quarter of that time.
         k1 = int(min(w.batch, max(1, 0.25 * args.cpu_seconds / max(per_cw * nthreads, 1e-9))))
-        t1 = time.perf_counter()
-        dec(w.code, prm_o, llr_np[:k1], nthreads=1)
-        s1 = time.perf_counter() - t1
-        cpu["one_core"] = {"value": round(k1 * w.info_bits_per_cw / s1 / 1e9, 6), "unit": "Gbit/s",
-                           "sample": f"the first {k1} codewords, {w.max_iters} fixed iterations, {s1:.1f}s"}
+        s1, p1 = 0.0, 0
+        while s1 < 0.25 * args.cpu_seconds and p1 < 100000:
+            t1 = time.perf_counter()
+            dec(w.code, prm_o, llr_np[:k1], nthreads=1)
+            s1 += time.perf_counter() - t1
+            p1 += 1
+        cpu["one_core"] = {"value": round(p1 * k1 * w.info_bits_per_cw / s1 / 1e9, 6), "unit": "Gbit/s",
+                           "sample": f"{p1} pass(es) over the first {k1} codewords, {w.max_iters} fixed iterations, "
+                                     f"{s1:.1f}s"}
 
     alg_ops = algorithmic_ops_per_cw(w) * w.batch
     tops = alg_ops / (kernel_ms * 1e-3) / 1e12

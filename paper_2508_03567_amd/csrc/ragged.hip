@@ -8,9 +8,13 @@
 //   - quasi-cyclic jobs: one item per 2 * npairs codewords (packed decoder);
 //   - other binary codes whose state fits on chip: one item per cpw codewords
 //     (LDS-resident decoder).
-// The host estimates the cost of every item, sorts them longest first and assigns
-// them greedily to the least-loaded workgroup of a grid sized to the resident
-// capacity of the device (LPT schedule); each workgroup then runs its own list.
+// The host estimates the cost of every item and sorts them longest first; a grid
+// sized to the resident capacity of the device then takes items from that list
+// through one device counter: each workgroup claims the next item with one atomic
+// add, runs it, and claims again until the list is exhausted.  A workgroup whose
+// item stops early (every codeword's syndrome satisfied) therefore moves on at once,
+// so the load stays balanced under early termination without any estimate of it,
+// and no workgroup ever waits for another.
 //
 // Jobs whose iterations need the whole device (long binary codes in the interleaved
 // layout, Min-Max and FFT-SPA over GF(g > 2)) would leave one workgroup to sweep
@@ -22,7 +26,6 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
-#include <queue>
 #include <vector>
 
 #include "dev_bin_lds.h"
@@ -76,13 +79,20 @@ __device__ __forceinline__ void run_item(const JobDesc &J, const Item &it, uint3
     }
 }
 
-// Workgroup w runs items [wg_ptr[w], wg_ptr[w + 1]) in order.
+// Every workgroup claims items from the shared counter (zero at launch) until the
+// list is exhausted.  Claims are the only inter-workgroup interaction: an atomic add
+// that never waits, so the launch completes whatever the residency of its workgroups.
 __global__ void __launch_bounds__(kThreads) k_ragged(const JobDesc *__restrict__ jobs,
-                                                     const Item *__restrict__ items,
-                                                     const int *__restrict__ wg_ptr) {
+                                                     const Item *__restrict__ items, int nitems,
+                                                     int *__restrict__ next) {
     extern __shared__ __align__(16) uint32_t lds[];
-    const int i0 = wg_ptr[blockIdx.x], i1 = wg_ptr[blockIdx.x + 1];
-    for (int i = i0; i < i1; ++i) {
+    __shared__ int claim;
+    for (;;) {
+        if (threadIdx.x == 0) claim = atomicAdd(next, 1);
+        __syncthreads();
+        const int i = claim;
+        __syncthreads();  // every thread has read the claim before thread 0 overwrites it
+        if (i >= nitems) break;
         const Item it = items[i];
         run_item(jobs[it.job], it, lds);
         __syncthreads();
@@ -280,47 +290,30 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
         if (e != hipSuccess || per_cu < 1) return cleanup(), fail(LDPCX_E_UNSUPPORTED, "persistent kernel does not fit");
         const int grid = (int)std::min<long>((long)per_cu * device_info(device).cus, (long)items.size());
 
-        // LPT: longest item first, each to the least-loaded workgroup.
+        // Longest item first: the claims then follow that order (greedy list scheduling).
         std::vector<int> order(items.size());
         for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-        std::vector<std::vector<int>> lists(grid);
-        {
-            typedef std::pair<double, int> Load;
-            std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
-            for (int w = 0; w < grid; ++w) heap.push(Load(0.0, w));
-            for (int i : order) {
-                Load l = heap.top();
-                heap.pop();
-                lists[l.second].push_back(i);
-                heap.push(Load(l.first + cost[i], l.second));
-            }
-        }
         std::vector<Item> flat;
-        std::vector<int> wg_ptr(grid + 1, 0);
         flat.reserve(items.size());
-        for (int w = 0; w < grid; ++w) {
-            for (int i : lists[w]) flat.push_back(items[i]);
-            wg_ptr[w + 1] = (int)flat.size();
-        }
+        for (int i : order) flat.push_back(items[i]);
 
-        // One device table: jobs, items, workgroup ranges.
+        // One device table: jobs, items, the claim counter (uploaded as zero).
         const size_t o_items = align_up(sizeof(JobDesc) * njobs, 256);
         const size_t o_ptr = align_up(o_items + sizeof(Item) * flat.size(), 256);
-        const size_t total = align_up(o_ptr + sizeof(int) * wg_ptr.size(), 256);
+        const size_t total = align_up(o_ptr + sizeof(int), 256);
         char *dbuf = nullptr;
         if (hipMallocAsync((void **)&dbuf, total, s) != hipSuccess) return cleanup(), fail(LDPCX_E_NOMEM, "item table");
         workspaces.push_back(dbuf);
         std::vector<char> host(total, 0);
         std::memcpy(host.data(), J.data(), sizeof(JobDesc) * njobs);
         std::memcpy(host.data() + o_items, flat.data(), sizeof(Item) * flat.size());
-        std::memcpy(host.data() + o_ptr, wg_ptr.data(), sizeof(int) * wg_ptr.size());
         ldpcx_status st = upload_async(dbuf, host.data(), total, device, s);
         if (st != LDPCX_OK) return cleanup(), st;
         const JobDesc *djobs = (const JobDesc *)dbuf;
         const Item *ditems = (const Item *)(dbuf + o_items);
-        const int *dptr = (const int *)(dbuf + o_ptr);
-        hipLaunchKernelGGL(k_ragged, dim3(grid), dim3(kThreads), lds, s, djobs, ditems, dptr);
+        int *dnext = (int *)(dbuf + o_ptr);
+        hipLaunchKernelGGL(k_ragged, dim3(grid), dim3(kThreads), lds, s, djobs, ditems, (int)flat.size(), dnext);
         e = hipGetLastError();
         cleanup();
         if (e != hipSuccess) {

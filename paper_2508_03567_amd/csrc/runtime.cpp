@@ -712,6 +712,8 @@ ldpcx_status ldpcx_code_create(const ldpcx_code_desc *d, ldpcx_code **out) {
         D.nbl_ptr = (const int *)(b + o_lp);
         D.nbl_chk = (const int *)(b + o_lc);
         c->qc.edges = (const int2 *)(b + o_qc);
+        c->hash = code_hash(d);
+        tune_cache_load(c);
         if (g > 2 && !nb_supported(g)) {
             // Valid code, but no compiled Min-Max kernel for this field size.
             c->nb_unsupported = true;

@@ -60,6 +60,7 @@ struct ldpcx_code {
     ldpcx::DevCode dev{};
     std::mutex mu;
     std::map<uint64_t, ldpcx::Plan> tuned;
+    uint64_t hash = 0;  // of the code description (persisted tuning results are keyed by it)
     std::mutex graph_mu;
     std::vector<ldpcx::GraphEntry> graphs;
     uint64_t graph_clock = 0;
@@ -94,5 +95,10 @@ void release_graph(GraphEntry &g);
 // blocking the host: the data goes through a pinned staging buffer that is reused once
 // the copy has completed.
 ldpcx_status upload_async(void *dst, const void *src, size_t bytes, int device, hipStream_t s);
+// Persisted autotuning (file named by LDPCX_TUNE_CACHE; nothing happens when it is unset):
+// load the entries of this code and device into c->tuned, and merge one tuned plan in.
+void tune_cache_load(ldpcx_code *c);
+void tune_cache_store(const ldpcx_code *c, uint64_t key, const Plan &pl, float us);
+uint64_t code_hash(const ldpcx_code_desc *d);
 
 }  // namespace ldpcx

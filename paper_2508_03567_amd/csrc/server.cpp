@@ -12,11 +12,23 @@
 // Completed launches are retired by polling their events: outputs are copied to
 // the requests' host buffers and their budget is released.
 //
+// Every chunk is planned at its own size when it is admitted (the autotuner's choice
+// can differ between batch classes); its budget charge counts that plan's workspace
+// and its launch runs that exact plan.
+//
+// Failure handling: a launch whose staging, enqueue or device work fails finishes the
+// requests of its chunks with that status (LDPCX_E_DEVICE for a device fault) and
+// releases their budget; every other request is unaffected and the scheduler keeps
+// serving.  For tests, LDPCX_FAULT_INJECT=launch:N (read at server creation) makes the
+// server's N-th launch report LDPCX_E_DEVICE without touching the device.
+//
 // Locking: `mu` guards the request table, the queue and the counters.  `io_mu`
 // is held while a launch reads request inputs from host memory and by cancel, so
 // that a cancelled request's host buffers are never touched after cancel
 // returns.  Order: io_mu before mu.
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <condition_variable>
 #include <deque>
@@ -63,6 +75,7 @@ struct Request {
 struct Chunk {
     uint64_t id = 0;
     int cw0 = 0, ncw = 0;
+    Plan plan;                        // the plan this chunk runs (planned at its size)
     size_t charge = 0;                // budget bytes
     size_t o_llr = 0, o_hard = 0;     // offsets in the launch's device buffer
     size_t o_ok = 0, o_it = 0;
@@ -73,6 +86,7 @@ struct Slot {
     hipStream_t s = nullptr;
     hipEvent_t ev = nullptr;
     bool busy = false;
+    uint64_t launch_no = 0;  // 1-based launch count of the server
     std::vector<Chunk> chunks;
     size_t charge = 0;
     size_t in_bytes = 0, out_off = 0, out_bytes = 0, dev_bytes = 0;
@@ -86,14 +100,13 @@ size_t io_bytes(const Request &r, int ncw) {
            align_up((size_t)ncw * 2, 256);
 }
 
-// Device bytes one chunk of `ncw` codewords holds while in flight.
+// Device bytes one chunk of `ncw` codewords holds while in flight, on the plan it runs
+// at that size.
 size_t chunk_bytes(const Request &r, int ncw) {
-    size_t b = io_bytes(r, ncw);
-    if (r.family == FAMILY_BIN_IL) b += bin_il_work_bytes(r.code->dev, r.prm.max_iters, ncw, 0);
-    else if (r.family == FAMILY_NB || r.family == FAMILY_NB_LDS) b += nb_work_bytes(r.code->dev, r.prm.max_iters, ncw);
-    else if (r.family == FAMILY_SPA) b += spa_work_bytes(r.code->dev, r.prm.max_iters, ncw);
+    const Plan pl = plan_for(r.code, &r.prm, std::max(1, ncw));
+    size_t b = io_bytes(r, ncw) + work_bytes(r.code, &r.prm, pl, ncw);
     // a chunk of a whole-device family inside a ragged batch is decoded from a gathered copy
-    if (r.family != FAMILY_BIN_QC && r.family != FAMILY_BIN_LDS) b += io_bytes(r, ncw);
+    if (pl.family != FAMILY_BIN_QC && pl.family != FAMILY_BIN_LDS) b += io_bytes(r, ncw);
     return b;
 }
 
@@ -156,6 +169,7 @@ struct ldpcx_server {
     std::vector<Slot> slots;
     size_t in_use = 0, peak = 0;
     uint64_t completed = 0, codewords = 0, launches = 0;
+    uint64_t fault_launch = 0;  // LDPCX_FAULT_INJECT=launch:N, 0 = off
     std::thread th;
 
     double now_us() const { return std::chrono::duration<double, std::micro>(Clock::now() - t0).count(); }
@@ -217,6 +231,7 @@ struct ldpcx_server {
             c.id = id;
             c.cw0 = r.next_cw;
             c.ncw = n;
+            c.plan = plan_for(r.code, &r.prm, n);
             c.charge = chunk_bytes(r, n);
             c.own_launch = own;
             take.push_back(c);
@@ -236,6 +251,12 @@ struct ldpcx_server {
     // Stage inputs and enqueue the launch of slot `sl` (mu not held).
     void launch(Slot &sl) {
         sl.st = LDPCX_OK;
+        if (fault_launch && sl.launch_no == fault_launch) {
+            // injected failure: nothing reaches the device, the event completes at once
+            sl.st = fail(LDPCX_E_DEVICE, "injected launch fault");
+            if (hipEventRecord(sl.ev, sl.s) != hipSuccess) (void)hipGetLastError();
+            return;
+        }
         // Device layout: all inputs, then all hard decisions, flags and counts, each
         // chunk 256-byte aligned; the pinned buffers mirror the input and output parts.
         size_t off = 0;
@@ -304,9 +325,8 @@ struct ldpcx_server {
                     jobs.push_back(j);
                     continue;
                 }
-                const Plan pl = plan_for(r.code, &r.prm, c.ncw);
                 const DecodeIO io{j.llr, j.hard, j.syndrome_ok, j.iters, nullptr, nullptr, nullptr};
-                const ldpcx_status st = run_plan(r.code, &r.prm, pl, c.ncw, io, sl.s, false);
+                const ldpcx_status st = run_plan(r.code, &r.prm, c.plan, c.ncw, io, sl.s, false);
                 if (st != LDPCX_OK) {
                     sl.st = st;
                     break;
@@ -384,7 +404,7 @@ struct ldpcx_server {
                 for (const Chunk &c : sl.chunks) sl.charge += c.charge;
                 in_use += sl.charge;
                 peak = std::max(peak, in_use);
-                ++launches;
+                sl.launch_no = ++launches;
                 lk.unlock();
                 launch(sl);
                 lk.lock();
@@ -419,6 +439,11 @@ ldpcx_status ldpcx_server_create(const ldpcx_server_config *cfg, ldpcx_server **
         if (S->cfg.mode == LDPCX_SERVE_PER_REQUEST) S->cfg.max_inflight = 1;
         S->device = dev;
         S->t0 = Clock::now();
+        {
+            const char *fi = getenv("LDPCX_FAULT_INJECT");
+            unsigned long long nfi = 0;
+            if (fi && sscanf(fi, "launch:%llu", &nfi) == 1) S->fault_launch = nfi;
+        }
         S->slots.resize(S->cfg.max_inflight);
         for (Slot &sl : S->slots) {
             e = hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking);

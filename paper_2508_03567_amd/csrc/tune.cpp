@@ -4,12 +4,164 @@
 // the LDS-resident binary decoder) and, only when the caller asked for the AUTO
 // schedule, the schedule itself (flooding versus layered): the two schedules
 // are different algorithms, so a fixed schedule is never changed.
+//
+// Tuned plans can persist across processes: when the environment variable
+// LDPCX_TUNE_CACHE names a file, every ldpcx_tune result is merged into it and
+// ldpcx_code_create loads the entries of its code (by a hash of the description) and
+// device (architecture and compute-unit count).  The file is JSON, one entry object
+// per line, rewritten through a temporary file and a rename.
 #include <algorithm>
+#include <cctype>
+#include <cinttypes>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
 #include <vector>
 
 #include "runtime.h"
 
 using namespace ldpcx;
+
+namespace ldpcx {
+
+uint64_t code_hash(const ldpcx_code_desc *d) {
+    uint64_t h = 1469598103934665603ULL;  // FNV-1a
+    auto mix = [&](const void *p, size_t n) {
+        const unsigned char *b = (const unsigned char *)p;
+        for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ULL;
+    };
+    const int32_t hdr[5] = {d->g, (int32_t)d->prim_poly, d->n, d->m, d->z};
+    mix(hdr, sizeof hdr);
+    const int E = d->row_ptr[d->m];
+    mix(d->row_ptr, sizeof(int32_t) * (size_t)(d->m + 1));
+    mix(d->col_idx, sizeof(int32_t) * (size_t)E);
+    if (d->g > 2 && d->h_val) mix(d->h_val, (size_t)E);
+    return h;
+}
+
+namespace {
+
+std::mutex g_cache_mu;
+
+const char *cache_path() {
+    const char *p = getenv("LDPCX_TUNE_CACHE");
+    return (p && p[0]) ? p : nullptr;
+}
+
+std::string device_tag(int dev) {
+    hipDeviceProp_t prop;
+    char buf[160];
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return "unknown";
+    }
+    snprintf(buf, sizeof buf, "%s/%d", prop.gcnArchName, prop.multiProcessorCount);
+    for (char *q = buf; *q; ++q)
+        if (*q == '"' || *q == '\\') *q = '_';
+    return buf;
+}
+
+struct Entry {
+    uint64_t code, key;
+    std::string device;
+    Plan pl;
+    float us;
+};
+
+// Value of "name" inside one JSON object's text (strings without their quotes), or "".
+std::string json_field(const std::string &obj, const char *name) {
+    const std::string key = std::string("\"") + name + "\"";
+    size_t p = obj.find(key);
+    if (p == std::string::npos) return "";
+    p = obj.find(':', p + key.size());
+    if (p == std::string::npos) return "";
+    ++p;
+    while (p < obj.size() && isspace((unsigned char)obj[p])) ++p;
+    if (p < obj.size() && obj[p] == '"') {
+        const size_t q = obj.find('"', p + 1);
+        return q == std::string::npos ? "" : obj.substr(p + 1, q - p - 1);
+    }
+    size_t q = p;
+    while (q < obj.size() && obj[q] != ',' && obj[q] != '}' && !isspace((unsigned char)obj[q])) ++q;
+    return obj.substr(p, q - p);
+}
+
+// Entries of the cache file: every {...} object with all fields (others are dropped).
+std::vector<Entry> read_entries(const char *path) {
+    std::vector<Entry> out;
+    FILE *f = fopen(path, "r");
+    if (!f) return out;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+    fclose(f);
+    for (size_t p = text.find('{'); p != std::string::npos; p = text.find('{', p + 1)) {
+        const size_t q = text.find('}', p);
+        if (q == std::string::npos) break;
+        const std::string obj = text.substr(p, q - p + 1);
+        const char *names[8] = {"code", "device", "key", "family", "schedule", "cw_per_wg", "threads", "us"};
+        std::string v[8];
+        bool all = true;
+        for (int i = 0; i < 8 && all; ++i) all = !(v[i] = json_field(obj, names[i])).empty();
+        if (!all) continue;
+        Entry e;
+        e.code = strtoull(v[0].c_str(), nullptr, 16);
+        e.device = v[1];
+        e.key = strtoull(v[2].c_str(), nullptr, 16);
+        e.pl.family = atoi(v[3].c_str());
+        e.pl.schedule = atoi(v[4].c_str());
+        e.pl.cpw = atoi(v[5].c_str());
+        e.pl.threads = atoi(v[6].c_str());
+        e.us = (float)atof(v[7].c_str());
+        out.push_back(e);
+        p = q;
+    }
+    return out;
+}
+
+}  // namespace
+
+void tune_cache_load(ldpcx_code *c) {
+    const char *path = cache_path();
+    if (!path) return;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    const std::string dev = device_tag(c->device);
+    std::lock_guard<std::mutex> lc(c->mu);
+    for (const Entry &e : read_entries(path))
+        if (e.code == c->hash && e.device == dev && e.pl.family >= 0 && e.pl.family <= FAMILY_SPA_LDS)
+            c->tuned[e.key] = e.pl;
+}
+
+void tune_cache_store(const ldpcx_code *c, uint64_t key, const Plan &pl, float us) {
+    const char *path = cache_path();
+    if (!path) return;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    const std::string dev = device_tag(c->device);
+    std::vector<Entry> all = read_entries(path);
+    all.erase(std::remove_if(all.begin(), all.end(),
+                             [&](const Entry &e) { return e.code == c->hash && e.device == dev && e.key == key; }),
+              all.end());
+    all.push_back(Entry{c->hash, key, dev, pl, us});
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return;  // best effort: an unwritable cache only costs a re-tune
+    fprintf(f, "[\n");
+    for (size_t i = 0; i < all.size(); ++i) {
+        const Entry &e = all[i];
+        fprintf(f,
+                " {\"code\": \"%016" PRIx64 "\", \"device\": \"%s\", \"key\": \"%016" PRIx64
+                "\", \"family\": %d, \"schedule\": %d, \"cw_per_wg\": %d, \"threads\": %d, \"us\": %.1f}%s\n",
+                e.code, e.device.c_str(), e.key, e.pl.family, e.pl.schedule, e.pl.cpw, e.pl.threads, e.us,
+                i + 1 < all.size() ? "," : "");
+    }
+    fprintf(f, "]\n");
+    const bool ok = fclose(f) == 0;
+    if (ok) (void)std::rename(tmp.c_str(), path);
+}
+
+}  // namespace ldpcx
 
 namespace {
 
@@ -182,6 +334,7 @@ extern "C" ldpcx_status ldpcx_tune(const ldpcx_code *code, const ldpcx_decode_pa
             std::lock_guard<std::mutex> lk(c->mu);
             c->tuned[tune_key(params, batch)] = bestp;
         }
+        tune_cache_store(c, tune_key(params, batch), bestp, best);
         if (chosen_schedule) *chosen_schedule = bestp.schedule;
         if (best_us) *best_us = best;
         g_err.clear();

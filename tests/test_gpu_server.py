@@ -141,3 +141,50 @@ def test_layered_minmax_requests():
     for (cfg, prm, llr), (hard, ok, it, _) in zip(reqs, outs):
         h2, ok2, it2 = _alone(cfg, prm, llr)
         assert (hard == h2).all() and (ok == ok2).all() and (it == it2).all()
+
+
+@pytest.mark.parametrize("mode,fail_at", [("per_request", 3), ("continuous", 2)])
+def test_failed_launch_fails_only_its_requests(mode, fail_at, monkeypatch):
+    """LDPCX_FAULT_INJECT=launch:N makes the server's N-th launch report a device error
+    without touching the device: exactly the requests of that launch fail with
+    LDPCX_E_DEVICE, and every request before and after it still completes with what a
+    plain decode of it alone gives (the server keeps serving)."""
+    monkeypatch.setenv("LDPCX_FAULT_INJECT", f"launch:{fail_at}")
+    reqs = [r for r in _requests(10, seed=21, max_size=60) if r[0] != 2][:6]
+    results = []
+    with L.Server(hbm_budget=256 << 20, max_inflight=2, mode=mode) as srv:
+        for cfg, prm, llr in reqs:  # one request in flight at a time: launch k decodes request k
+            t = srv.submit(_code(cfg), prm, llr)
+            try:
+                results.append(srv.wait(t, timeout_ms=120000))
+            except L.LdpcxError as ex:
+                results.append(ex.status)
+        st = srv.stats()
+    for k, ((cfg, prm, llr), res) in enumerate(zip(reqs, results), start=1):
+        if k == fail_at:
+            assert res == L.E_DEVICE, f"request {k} should have failed"
+            continue
+        hard, ok, it, _ = res
+        h2, ok2, it2 = _alone(cfg, prm, llr)
+        assert (hard == h2).all() and (ok == ok2).all() and (it == it2).all()
+    assert st["completed"] == len(reqs) - 1
+    assert st["launches"] == len(reqs)
+
+
+def test_chunks_run_the_plan_of_their_size():
+    """A request whose chunks fall in different batch classes runs each chunk on the plan
+    of its own size (here pinned differently per class), charges that plan's memory and
+    still gives what a plain decode gives."""
+    w1, pool1 = _pool(1, 512)
+    h = L.Code(w1.code)
+    prm = _prm(w1, 6)
+    L.plan_set(h, prm, 512, "bin_qc_packed", 2)      # the class of the whole request
+    L.plan_set(h, prm, 64, "bin_lds", 2, 256)         # the class of its 64-codeword chunks
+    llr = np.ascontiguousarray(pool1[:300])
+    with L.Server(hbm_budget=256 << 20, max_inflight=2, max_launch_cw=64) as srv:
+        hard, ok, it, _ = srv.wait(srv.submit(h, prm, llr), timeout_ms=120000)
+        assert srv.stats()["launches"] >= 5
+    ref = L.decode(h, prm, torch.from_numpy(llr).to(DEV))
+    torch.cuda.synchronize()
+    assert (hard == ref[0].cpu().numpy()).all() and (ok == ref[1].cpu().numpy()).all()
+    assert (it == ref[2].cpu().numpy()).all()
