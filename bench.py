@@ -36,6 +36,9 @@ FAMILY_SOURCES = {
     "bin_interleaved": ["k_bin_il.hip", "dev_bin_il.h", "dev_common.h"],
     "minmax_interleaved": ["k_nb.hip", "dev_nb.h", "dev_common.h"],
     "minmax_lds": ["k_nb.hip", "dev_nb.h", "dev_common.h"],
+    "minmax_cw": ["k_nb1.hip", "dev_nb1.h", "dev_common.h"],
+    "spa_wave": ["k_spa.hip", "dev_spa.h", "dev_common.h"],
+    "spa_lds": ["k_spa.hip", "dev_spa.h", "dev_common.h"],
 }
 
 
@@ -447,6 +450,8 @@ def prof_main(args) -> None:
             d = np.array([dt for _, dt in by[nm]], dtype=np.float64)
             print(f"| `{nm[:110]}` | {len(d)} | {d.mean():.0f} | {np.median(d):.0f} | {d.min():.0f} | {d.max():.0f} "
                   f"| {100 * d.sum() / total:.2f} |")
+        if not args.prof_kernel:
+            return
         dec = sorted((t, dt) for nm in order if sel(nm) for t, dt in by[nm])
         n_all = len(dec)
         per = n_all // (W + K) if n_all % (W + K) == 0 else None

@@ -197,17 +197,25 @@ typedef struct {
     int16_t *iters;
 } ldpcx_job;
 
-/* Decode a ragged batch of jobs over different codes and sizes on `stream`.  Jobs of
- * the workgroup-local families (quasi-cyclic packed and LDS-resident binary decoders)
- * run as items of ONE persistent kernel launch, with per-codeword early termination
- * inside; every job is cut into items that share nothing, so no workgroup waits for
- * another.  Jobs whose iterations need the whole device (binary codes in the
- * interleaved layout, Min-Max and FFT-SPA over GF(g > 2)) are gathered per (code,
- * parameters, resolved schedule) into one batch each and decoded by that batch's own
- * launch sequence on the same stream, after the persistent kernel.  Results are
- * identical to calling ldpcx_decode on each job; AUTO schedules are resolved per job
- * as in ldpcx_decode.  The library allocates stream-ordered scratch for the item
- * tables and the gathered batches and frees it on the stream. */
+/* Decode a ragged batch of jobs over different codes and sizes on `stream` (the
+ * multicodeword mapping of sec. 4: independent decoders).  Jobs whose state fits one
+ * workgroup run as items of the persistent kernel, with per-codeword early termination
+ * inside: quasi-cyclic binary codes (2 x npairs codewords per item), other binary codes
+ * held in LDS (cpw codewords per item), Min-Max over GF(4)..GF(64) whose messages of one
+ * codeword fit a workgroup's LDS and that have at least 32 checks (one codeword per
+ * item, every message in LDS) and FFT-SPA codes of the LDS-resident family (one group of
+ * codewords per item).  Workgroups claim items longest first from a device counter
+ * (one atomic add per item, never a wait for another workgroup), so the load stays
+ * balanced when codewords stop early.  The kernel runs as up to three launches on the
+ * stream, one per kind of item (binary; GF(g) of check degree <= 4; Min-Max of larger
+ * check degree), each with the occupancy its own registers and LDS allow.  Jobs whose
+ * state does not fit a workgroup (binary codes in the interleaved layout, GF(128) and
+ * GF(256), larger codewords, FFT-SPA wave kernels) are gathered per (code, parameters,
+ * resolved schedule) into one batch each and decoded by that batch's own launch
+ * sequence on the same stream, after the persistent kernel.  Results are identical to
+ * calling ldpcx_decode on each job; AUTO schedules are resolved per job as in
+ * ldpcx_decode.  The library allocates stream-ordered scratch for the item tables and
+ * the gathered batches and frees it on the stream. */
 ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs, void *stream);
 
 /* Autotune the launch configuration of (code, params, batch) by timing the candidate
@@ -227,7 +235,10 @@ ldpcx_status ldpcx_tune(const ldpcx_code *code, const ldpcx_decode_params *param
  * codes whose alpha and beta for 64 codewords fit 160 KB; 256, 512 or 1024 threads),
  * 6 = FFT-SPA with cw_per_wg codewords per workgroup and every vector in LDS, all
  * iterations in one launch (check and variable degrees <= 4, the vectors of cw_per_wg
- * codewords within 160 KB; 256, 512 or 1024 threads),
+ * codewords within 160 KB; 256, 512 or 1024 threads), 7 = Min-Max with one codeword per
+ * workgroup, every message in LDS and the lanes over the field entries, all iterations
+ * in one launch (GF(4)..GF(64), the messages of one codeword within 160 KB; 256, 512 or
+ * 1024 threads, at most 256 used for check degrees above 4; both schedules),
  * 3 = packed two-codewords-per-lane binary for quasi-cyclic codes, available
  * when every layer of z rows consists of z x z circulant blocks, at most 16 layers and
  * 8 blocks per layer), codewords per workgroup (family 1: codewords per launch
@@ -242,8 +253,8 @@ ldpcx_status ldpcx_plan_info(const ldpcx_code *code, const ldpcx_decode_params *
  * pairs' rows at most 512 threads) and by family 1 (slice size, rounded up to a multiple
  * of 128 and capped by the batch and the 31-bit offset limit).  The pinned plan must be able to
  * run the requested schedule (LDPCX_E_UNSUPPORTED otherwise; families 1, 4 and 6 are
- * flooding only, families 2 and 5 run the layered schedule up to GF(64)); family 5
- * takes threads = 256, 512 or 1024, family 6 cw_per_wg in [1, 64] and threads = 256,
+ * flooding only, families 2, 5 and 7 run the layered schedule up to GF(64)); families 5
+ * and 7 take threads = 256, 512 or 1024, family 6 cw_per_wg in [1, 64] and threads = 256,
  * 512 or 1024.  Results never depend on the plan. */
 ldpcx_status ldpcx_plan_set(ldpcx_code *code, const ldpcx_decode_params *params, int32_t batch,
                             int32_t family, int32_t cw_per_wg, int32_t threads);

@@ -556,8 +556,10 @@ __device__ __forceinline__ void lds_syndrome(const DevCode &C, const uint8_t *ha
     }
 }
 
+// Codewords [blk cw, blk cw + cw) by the calling workgroup (blk: the kernel's block
+// index, or an item index of the ragged kernel).
 template <int G>
-__device__ __forceinline__ void lds_decode(const Args &A, int cw, unsigned char *lds) {
+__device__ __forceinline__ void lds_decode(const Args &A, int cw, unsigned char *lds, int blk) {
     constexpr int D = 4, S = lanes_for<G, D>(), R = Geo<G, S>::R, CPW = Geo<G, S>::CPW;
     const DevCode &C = A.C;
     const LdsLayout Y = lds_layout(C, cw);
@@ -566,7 +568,7 @@ __device__ __forceinline__ void lds_decode(const Args &A, int cw, unsigned char 
     int16_t *its = (int16_t *)(lds + Y.its);
     uint8_t *unsat = lds + Y.unsat;
     uint8_t *hard = lds + Y.hard;
-    const int base = blockIdx.x * cw;
+    const int base = blk * cw;
     const int cnt = min(cw, A.batch - base);
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int waves = nthr >> 6, wave = wave_id();

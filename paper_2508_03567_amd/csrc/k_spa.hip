@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(256) k_dec(Args A, int k, const int *v_cur) { 
 template <int G>
 __global__ void __launch_bounds__(1024) k_spa_lds(Args A, int cw) {
     extern __shared__ __align__(16) unsigned char lds[];
-    dev::spa::lds_decode<G>(A, cw, lds);
+    dev::spa::lds_decode<G>(A, cw, lds, blockIdx.x);
 }
 __global__ void __launch_bounds__(256) k_fin(Args A) { dev::spa::fin_thread(A, (long)blockIdx.x * 256 + threadIdx.x); }
 __global__ void __launch_bounds__(256) k_dump(Args A, const int *src, int *dst) {

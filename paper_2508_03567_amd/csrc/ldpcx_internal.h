@@ -174,6 +174,13 @@ hipError_t launch_nb_lds(const DevCode &C, int max_iters, int early_stop, int la
 // the layered schedule over the layers of DevCode (g <= 64).
 hipError_t launch_nb(const DevCode &C, int max_iters, int early_stop, int layered, int batch, int amax, void *ws,
                      const DecodeIO &io, hipStream_t s);
+// Min-Max with one codeword per workgroup and all its messages in LDS (g <= 64, check
+// degree <= 16, nb1_lds_bytes(C) <= 160 KB; 256, 512 or 1024 threads, at most 256 used
+// for check degrees above 4); no workspace, both schedules.
+size_t nb1_lds_bytes(const DevCode &C);
+bool nb1_supported(const DevCode &C);
+hipError_t launch_nb1(const DevCode &C, int max_iters, int early_stop, int layered, int batch, int amax, int threads,
+                      const DecodeIO &io, hipStream_t s);
 // Field sizes with a compiled Min-Max kernel (4..64 interleaved, 128 and 256 wide).
 bool nb_supported(int g);
 // The wide (g >= 128) decoder: workspace bytes and launch sequence.

@@ -78,7 +78,8 @@ extern "C" ldpcx_status ldpcx_decode_noalloc(const ldpcx_code *code, const ldpcx
         if (schedule_used) *schedule_used = pl.schedule;
         const DecodeIO io{llr, hard, syndrome_ok, iters, nullptr, nullptr, nullptr};
         // Families whose state stays on chip need no workspace: the plain launch allocates nothing.
-        if (pl.family == FAMILY_BIN_QC || pl.family == FAMILY_BIN_LDS || pl.family == FAMILY_SPA_LDS)
+        if (pl.family == FAMILY_BIN_QC || pl.family == FAMILY_BIN_LDS || pl.family == FAMILY_SPA_LDS ||
+            pl.family == FAMILY_NB1)
             return run_plan(c, params, pl, batch, io, s, false);
         void *ws = nullptr;
         if ((st = scratch_of(c->device, &ws)) != LDPCX_OK) return st;

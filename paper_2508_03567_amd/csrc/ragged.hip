@@ -1,13 +1,22 @@
 // Ragged batches: one call decodes a batch of jobs over different codes, sizes and
 // decoder families.
 //
-// Jobs of the workgroup-local families run as items of ONE persistent kernel launch.
-// Every such job is cut into items that share nothing with other items, so no
-// workgroup ever waits for another and the launch cannot deadlock whatever the
-// residency of its workgroups:
+// Jobs of the workgroup-local families run as items of one persistent kernel.  Every
+// such job is cut into items that share nothing with other items, so no workgroup
+// ever waits for another and the launch cannot deadlock whatever the residency of its
+// workgroups:
 //   - quasi-cyclic jobs: one item per 2 * npairs codewords (packed decoder);
 //   - other binary codes whose state fits on chip: one item per cpw codewords
-//     (LDS-resident decoder).
+//     (LDS-resident decoder);
+//   - Min-Max over GF(4)..GF(64) whose messages of one codeword fit a workgroup's LDS:
+//     one item per codeword (lanes over field entries, every message in LDS);
+//   - FFT-SPA codes of the LDS-resident family: one item per group of codewords.
+// Items run as up to three launches of the persistent kernel, one after the other on
+// the stream, each an instance compiled for one kind of item: binary items (256
+// threads), GF(g) items of check degree <= 4 (1024 threads: one codeword's checks spread
+// over 16 waves) and Min-Max items of larger check degree (256 threads, for their larger
+// register arrays).  A kernel's register and LDS allocation is the maximum over what it
+// may run, so each kind keeps the occupancy its own footprint allows.
 // The host estimates the cost of every item and sorts them longest first; a grid
 // sized to the resident capacity of the device then takes items from that list
 // through one device counter: each workgroup claims the next item with one atomic
@@ -16,13 +25,14 @@
 // so the load stays balanced under early termination without any estimate of it,
 // and no workgroup ever waits for another.
 //
-// Jobs whose iterations need the whole device (long binary codes in the interleaved
-// layout, Min-Max and FFT-SPA over GF(g > 2)) would leave one workgroup to sweep
-// every check and variable of a group of codewords, each iteration, alone.  They are
-// gathered instead per (code, parameters, resolved schedule) into one batch and run
-// as that batch's own launch sequence on the same stream, after the persistent
-// kernel; codewords are decoded independently, so every job still gets exactly what
-// a decode of it alone gives.
+// Jobs whose state does not fit a workgroup (long binary codes in the interleaved
+// layout, Min-Max over GF(128) and GF(256) or with larger codewords, FFT-SPA outside its
+// LDS-resident family) would leave one workgroup to sweep every check and variable
+// of a group of codewords in device memory, each iteration, alone.  They are gathered
+// instead per (code, parameters, resolved schedule) into one batch and run as that
+// batch's own launch sequence on the same stream, after the persistent kernel;
+// codewords are decoded independently, so every job still gets exactly what a decode
+// of it alone gives.
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -30,20 +40,22 @@
 
 #include "dev_bin_lds.h"
 #include "dev_bin_qc.h"
+#include "dev_nb1.h"
+#include "dev_spa.h"
 #include "runtime.h"
 
 namespace ldpcx {
 
 namespace {
 
-enum ItemType { I_QC = 0, I_LDS = 1 };
+enum ItemType { I_QC = 0, I_LDS = 1, I_NB1 = 2, I_SPA = 3 };
 
 struct JobDesc {
     int family, layered, npairs, cpw, ml, md;
     QcDesc qc;
     DevCode C;
     BinRule R;
-    int max_iters, early_stop, batch;
+    int max_iters, early_stop, batch, amax;
     DecodeIO io;
 };
 
@@ -51,8 +63,10 @@ struct Item {
     int type, job, blk, pad;
 };
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;  // binary items (their decoders use at most 256 threads)
 constexpr size_t kStaticLds = 256;  // upper bound of the kernel's static LDS
+enum Kind { K_BIN = 0, K_GF4 = 1, K_GF16 = 2 };
+__host__ __device__ constexpr int kind_threads(int k) { return k == K_GF4 ? 1024 : 256; }
 
 template <bool LAYERED>
 __device__ __forceinline__ void run_qc(const JobDesc &J, int blk, uint32_t *lds) {
@@ -66,8 +80,45 @@ __device__ __forceinline__ void run_qc(const JobDesc &J, int blk, uint32_t *lds)
 #undef LDPCX_QC_RUN
 }
 
+template <int DC>
+__device__ __forceinline__ void run_nb1(const JobDesc &J, int b, uint32_t *lds) {
+    const dev::nb1::Job N{J.C, J.max_iters, J.early_stop, J.layered, J.amax, J.batch, J.io};
+    unsigned char *l = (unsigned char *)lds;
+    switch (J.C.g) {
+    case 4: dev::nb1::decode_cw<4, DC>(N, b, l); break;
+    case 8: dev::nb1::decode_cw<8, DC>(N, b, l); break;
+    case 16: dev::nb1::decode_cw<16, DC>(N, b, l); break;
+    case 32: dev::nb1::decode_cw<32, DC>(N, b, l); break;
+    default: dev::nb1::decode_cw<64, DC>(N, b, l); break;
+    }
+}
+
+__device__ __forceinline__ void run_spa(const JobDesc &J, int blk, uint32_t *lds) {
+    dev::spa::Args A;
+    A.C = J.C;
+    A.max_iters = J.max_iters;
+    A.early_stop = J.early_stop;
+    A.batch = J.batch;
+    A.w = SpaWork{};
+    A.io = J.io;
+    unsigned char *l = (unsigned char *)lds;
+    switch (J.C.g) {
+    case 4: dev::spa::lds_decode<4>(A, J.cpw, l, blk); break;
+    case 8: dev::spa::lds_decode<8>(A, J.cpw, l, blk); break;
+    case 16: dev::spa::lds_decode<16>(A, J.cpw, l, blk); break;
+    case 32: dev::spa::lds_decode<32>(A, J.cpw, l, blk); break;
+    default: dev::spa::lds_decode<64>(A, J.cpw, l, blk); break;
+    }
+}
+
+template <int K>
 __device__ __forceinline__ void run_item(const JobDesc &J, const Item &it, uint32_t *lds) {
-    if (it.type == I_QC) {
+    if (K == K_GF4) {
+        if (it.type == I_NB1) run_nb1<4>(J, it.blk, lds);
+        else run_spa(J, it.blk, lds);
+    } else if (K == K_GF16) {
+        run_nb1<kNbDcMax>(J, it.blk, lds);
+    } else if (it.type == I_QC) {
         if (J.layered) run_qc<true>(J, it.blk, lds);
         else run_qc<false>(J, it.blk, lds);
     } else if (J.layered) {
@@ -82,7 +133,8 @@ __device__ __forceinline__ void run_item(const JobDesc &J, const Item &it, uint3
 // Every workgroup claims items from the shared counter (zero at launch) until the
 // list is exhausted.  Claims are the only inter-workgroup interaction: an atomic add
 // that never waits, so the launch completes whatever the residency of its workgroups.
-__global__ void __launch_bounds__(kThreads) k_ragged(const JobDesc *__restrict__ jobs,
+template <int K>
+__global__ void __launch_bounds__(kind_threads(K)) k_ragged(const JobDesc *__restrict__ jobs,
                                                      const Item *__restrict__ items, int nitems,
                                                      int *__restrict__ next) {
     extern __shared__ __align__(16) uint32_t lds[];
@@ -94,15 +146,17 @@ __global__ void __launch_bounds__(kThreads) k_ragged(const JobDesc *__restrict__
         __syncthreads();  // every thread has read the claim before thread 0 overwrites it
         if (i >= nitems) break;
         const Item it = items[i];
-        run_item(jobs[it.job], it, lds);
+        run_item<K>(jobs[it.job], it, lds);
         __syncthreads();
     }
 }
 
-// Relative cost of one item (arbitrary units, only compared with each other).
+// Relative cost of one item (arbitrary units, only compared within a launch).
 double item_cost(const JobDesc &J, const DevCode &C) {
     const double it = std::max(1, J.max_iters), E = C.E;
     if (J.family == FAMILY_BIN_QC) return it * E * 2.0 / std::max(1, J.qc.Z);
+    if (J.family == FAMILY_NB1) return it * E * (double)C.g * C.g;
+    if (J.family == FAMILY_SPA_LDS) return it * E * J.cpw * (double)C.g;
     return it * E * J.cpw / kThreads;
 }
 
@@ -193,13 +247,13 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
         std::vector<JobDesc> J(njobs);
         std::vector<Item> items;
         std::vector<double> cost;
+        std::vector<size_t> need;  // LDS bytes of each item
         std::vector<void *> workspaces;
         std::vector<WideJob> wide;
         auto cleanup = [&]() {
             for (void *w : workspaces) (void)hipFreeAsync(w, s);
         };
         int device = -1;
-        size_t lds = 0;
         for (int j = 0; j < njobs; ++j) {
             const ldpcx_job &jb = jobs[j];
             if (!jb.code) return cleanup(), fail(LDPCX_E_INVAL, "job without code");
@@ -227,13 +281,32 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
             D.max_iters = p.max_iters;
             D.early_stop = p.early_stop;
             D.batch = jb.batch;
+            D.amax = nb_amax(&p);
             D.io = DecodeIO{jb.llr, jb.hard, jb.syndrome_ok, jb.iters, nullptr, nullptr, nullptr};
             D.layered = pl.schedule == LDPCX_SCHED_LAYERED;
-            auto add = [&](int type, long count) {
+            auto add = [&](int type, long count, size_t bytes) {
                 for (long i = 0; i < count; ++i) items.push_back(Item{type, j, (int)i, 0});
                 const double cst = item_cost(D, D.C);
                 cost.insert(cost.end(), (size_t)count, cst);
+                need.insert(need.end(), (size_t)count, bytes);
             };
+            if (c->g > 2) {
+                // Min-Max: one codeword per item when its messages fit a workgroup and the
+                // code has enough checks to occupy the workgroup's lanes
+                if (p.rule == LDPCX_RULE_MINMAX && nb1_supported(D.C) && D.C.m >= 32 &&
+                    nb1_lds_bytes(D.C) <= cap) {
+                    D.family = FAMILY_NB1;
+                    add(I_NB1, jb.batch, nb1_lds_bytes(D.C));
+                    continue;
+                }
+                // FFT-SPA of the LDS-resident family: one item per group of codewords
+                if (p.rule == LDPCX_RULE_SPA && pl.family == FAMILY_SPA_LDS && spa_lds_bytes(D.C, pl.cpw) <= cap) {
+                    D.family = FAMILY_SPA_LDS;
+                    D.cpw = pl.cpw;
+                    add(I_SPA, (jb.batch + pl.cpw - 1) / pl.cpw, spa_lds_bytes(D.C, pl.cpw));
+                    continue;
+                }
+            }
             // Workgroup-local items run in workgroups of kThreads threads.
             if (pl.family == FAMILY_BIN_QC && c->qc.Z > kThreads) pl.family = FAMILY_BIN_LDS;
             if (pl.family == FAMILY_BIN_QC) {
@@ -250,8 +323,7 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
                     D.npairs = np;
                     D.ml = ml;
                     D.md = md;
-                    lds = std::max(lds, dev::qc_smem_bytes(ml, md, D.C, c->qc.Z, D.layered, np));
-                    add(I_QC, ((jb.batch + 1) / 2 + np - 1) / np);
+                    add(I_QC, ((jb.batch + 1) / 2 + np - 1) / np, dev::qc_smem_bytes(ml, md, D.C, c->qc.Z, D.layered, np));
                     continue;
                 }
             }
@@ -263,8 +335,7 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
                 while (cpw > 1 && bin_lds_smem_bytes(D.C, D.layered, cpw) > cap) --cpw;
                 D.family = FAMILY_BIN_LDS;
                 D.cpw = cpw;
-                lds = std::max(lds, bin_lds_smem_bytes(D.C, D.layered, cpw));
-                add(I_LDS, (jb.batch + cpw - 1) / cpw);
+                add(I_LDS, (jb.batch + cpw - 1) / cpw, bin_lds_smem_bytes(D.C, D.layered, cpw));
                 continue;
             }
             // The whole-device families: decoded after the persistent kernel, with the
@@ -274,53 +345,73 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
             wide.push_back(wj);
         }
         if (items.empty()) return cleanup(), run_wide(jobs, wide, s);
-        if (lds > (size_t)device_info(device).lds_per_block - kStaticLds)
-            return cleanup(), fail(LDPCX_E_UNSUPPORTED, "job mix needs more LDS than one workgroup has");
 
-        // Errors of the calls above were checked where they happened; clear the sticky
-        // last-error state so that the launch check below reports the launch only.
-        (void)hipGetLastError();
-        const void *kern = (const void *)k_ragged;
-        if (lds > 64 * 1024) {
-            hipError_t ea = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (ea != hipSuccess) return cleanup(), fail_hip(ea, "persistent kernel LDS attribute");
-        }
-        int per_cu = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, lds);
-        if (e != hipSuccess || per_cu < 1) return cleanup(), fail(LDPCX_E_UNSUPPORTED, "persistent kernel does not fit");
-        const int grid = (int)std::min<long>((long)per_cu * device_info(device).cus, (long)items.size());
-
-        // Longest item first: the claims then follow that order (greedy list scheduling).
+        // Three launch classes by item kind; within each, longest item first (the claims
+        // then follow that order: greedy list scheduling).
         std::vector<int> order(items.size());
         for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-        std::vector<Item> flat;
-        flat.reserve(items.size());
-        for (int i : order) flat.push_back(items[i]);
+        std::vector<Item> cls[3];
+        size_t lds[3] = {0, 0, 0};
+        for (int i : order) {
+            const Item &it = items[i];
+            const int k = it.type == I_SPA ? K_GF4
+                          : it.type == I_NB1 ? (J[it.job].C.dc_max <= 4 ? K_GF4 : K_GF16)
+                                             : K_BIN;
+            cls[k].push_back(it);
+            lds[k] = std::max(lds[k], need[i]);
+        }
 
-        // One device table: jobs, items, the claim counter (uploaded as zero).
-        const size_t o_items = align_up(sizeof(JobDesc) * njobs, 256);
-        const size_t o_ptr = align_up(o_items + sizeof(Item) * flat.size(), 256);
-        const size_t total = align_up(o_ptr + sizeof(int), 256);
+        // One device table: jobs, the item lists, their claim counters (uploaded as zero).
+        size_t o_it[3];
+        size_t o = align_up(sizeof(JobDesc) * njobs, 256);
+        for (int k = 0; k < 3; ++k) {
+            o_it[k] = o;
+            o = align_up(o + sizeof(Item) * cls[k].size(), 256);
+        }
+        const size_t o_ctr = o;
+        const size_t total = align_up(o_ctr + 3 * sizeof(int), 256);
         char *dbuf = nullptr;
         if (hipMallocAsync((void **)&dbuf, total, s) != hipSuccess) return cleanup(), fail(LDPCX_E_NOMEM, "item table");
         workspaces.push_back(dbuf);
         std::vector<char> host(total, 0);
         std::memcpy(host.data(), J.data(), sizeof(JobDesc) * njobs);
-        std::memcpy(host.data() + o_items, flat.data(), sizeof(Item) * flat.size());
+        for (int k = 0; k < 3; ++k)
+            if (!cls[k].empty()) std::memcpy(host.data() + o_it[k], cls[k].data(), sizeof(Item) * cls[k].size());
         ldpcx_status st = upload_async(dbuf, host.data(), total, device, s);
         if (st != LDPCX_OK) return cleanup(), st;
         const JobDesc *djobs = (const JobDesc *)dbuf;
-        const Item *ditems = (const Item *)(dbuf + o_items);
-        int *dnext = (int *)(dbuf + o_ptr);
-        hipLaunchKernelGGL(k_ragged, dim3(grid), dim3(kThreads), lds, s, djobs, ditems, (int)flat.size(), dnext);
-        e = hipGetLastError();
-        cleanup();
-        if (e != hipSuccess) {
-            char msg[160];
-            snprintf(msg, sizeof msg, "persistent kernel launch (grid %d, %zu bytes of LDS)", grid, lds);
-            return fail_hip(e, msg);
+
+        // Errors of the calls above were checked where they happened; clear the sticky
+        // last-error state so that the launch checks below report the launches only.
+        (void)hipGetLastError();
+        const void *kerns[3] = {(const void *)k_ragged<K_BIN>, (const void *)k_ragged<K_GF4>,
+                                (const void *)k_ragged<K_GF16>};
+        for (int k = 0; k < 3; ++k) {
+            if (cls[k].empty()) continue;
+            const void *kern = kerns[k];
+            allow_full_lds(kern);
+            int per_cu = 0;
+            const int thr = kind_threads(k);
+            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, thr, lds[k]);
+            if (e != hipSuccess || per_cu < 1)
+                return cleanup(), fail(LDPCX_E_UNSUPPORTED, "persistent kernel does not fit");
+            const int grid = (int)std::min<long>((long)per_cu * device_info(device).cus, (long)cls[k].size());
+            const Item *ditems = (const Item *)(dbuf + o_it[k]);
+            int *dnext = (int *)(dbuf + o_ctr) + k;
+            const int ni = (int)cls[k].size();
+            if (k == K_GF4) hipLaunchKernelGGL(k_ragged<K_GF4>, dim3(grid), dim3(thr), lds[k], s, djobs, ditems, ni, dnext);
+            else if (k == K_GF16) hipLaunchKernelGGL(k_ragged<K_GF16>, dim3(grid), dim3(thr), lds[k], s, djobs, ditems, ni, dnext);
+            else hipLaunchKernelGGL(k_ragged<K_BIN>, dim3(grid), dim3(thr), lds[k], s, djobs, ditems, ni, dnext);
+            e = hipGetLastError();
+            if (e != hipSuccess) {
+                cleanup();
+                char msg[160];
+                snprintf(msg, sizeof msg, "persistent kernel launch (grid %d, %zu bytes of LDS)", grid, lds[k]);
+                return fail_hip(e, msg);
+            }
         }
+        cleanup();
         return run_wide(jobs, wide, s);
     } catch (const std::exception &ex) {
         return fail(LDPCX_E_NOMEM, ex.what());

@@ -255,6 +255,14 @@ ldpcx_status run_plan(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &p
         if (e != hipSuccess) return fail_hip(e, "LDS-resident FFT-SPA launch");
         return LDPCX_OK;
     }
+    if (pl.family == FAMILY_NB1) {
+        if (!nb1_supported(c->dev) || p->rule != LDPCX_RULE_MINMAX)
+            return fail(LDPCX_E_UNSUPPORTED, "the messages of one codeword do not fit the LDS of one workgroup");
+        e = launch_nb1(c->dev, p->max_iters, p->early_stop, pl.schedule == LDPCX_SCHED_LAYERED, batch, nb_amax(p),
+                       pl.threads, io, s);
+        if (e != hipSuccess) return fail_hip(e, "one-codeword-per-workgroup Min-Max launch");
+        return LDPCX_OK;
+    }
     if (pl.family == FAMILY_BIN_IL && pl.schedule == LDPCX_SCHED_LAYERED)
         return fail(LDPCX_E_UNSUPPORTED, "the interleaved binary decoder implements the flooding schedule only");
     if (allow_graph && !io.dump_a && graphs_enabled()) {
@@ -787,19 +795,19 @@ ldpcx_status ldpcx_plan_set(ldpcx_code *c, const ldpcx_decode_params *params, in
     if (!c) return fail(LDPCX_E_INVAL, "code is NULL");
     ldpcx_status st = check_params(c, params);
     if (st != LDPCX_OK) return st;
-    if (family < 0 || family > 6) return fail(LDPCX_E_INVAL, "unknown kernel family");
+    if (family < 0 || family > 7) return fail(LDPCX_E_INVAL, "unknown kernel family");
     const bool spa_family = family == FAMILY_SPA || family == FAMILY_SPA_LDS;
     if (spa_family != (params->rule == LDPCX_RULE_SPA))
         return fail(LDPCX_E_INVAL, "families 4 and 6 run rule SPA, and rule SPA only those");
     if (family == FAMILY_BIN_QC && !c->qc_ok) return fail(LDPCX_E_UNSUPPORTED, "code has no quasi-cyclic description");
-    if ((c->g > 2) != (family == FAMILY_NB || spa_family || family == FAMILY_NB_LDS))
+    if ((c->g > 2) != (family == FAMILY_NB || spa_family || family == FAMILY_NB_LDS || family == FAMILY_NB1))
         return fail(LDPCX_E_INVAL, "family does not match the field size");
     Plan pl;
     pl.family = family;
     pl.schedule = params->schedule == LDPCX_SCHED_AUTO ? default_plan(c, params, std::max(1, batch)).schedule
                                                         : params->schedule;
     if (family != FAMILY_BIN_LDS && family != FAMILY_BIN_QC && family != FAMILY_NB && family != FAMILY_NB_LDS &&
-        pl.schedule == LDPCX_SCHED_LAYERED)
+        family != FAMILY_NB1 && pl.schedule == LDPCX_SCHED_LAYERED)
         return fail(LDPCX_E_UNSUPPORTED, "this kernel family runs the flooding schedule only");
     if (family == FAMILY_NB && pl.schedule == LDPCX_SCHED_LAYERED && c->g > 64)
         return fail(LDPCX_E_UNSUPPORTED, "layered Min-Max covers GF(4)..GF(64)");
@@ -838,6 +846,15 @@ ldpcx_status ldpcx_plan_set(ldpcx_code *c, const ldpcx_decode_params *params, in
         if (nb_lds_bytes(c->dev, threads / 64) > (size_t)160 * 1024)
             return fail(LDPCX_E_UNSUPPORTED, "the messages of 64 codewords do not fit the LDS of one workgroup");
         pl.cpw = 64;
+        pl.threads = threads;
+    }
+    if (family == FAMILY_NB1) {
+        if (c->g > 64 || params->rule != LDPCX_RULE_MINMAX || !nb1_supported(c->dev))
+            return fail(LDPCX_E_UNSUPPORTED, "family 7 runs Min-Max over GF(4)..GF(64) for codes whose messages of one "
+                                             "codeword fit 160 KB of LDS");
+        if (threads != 256 && threads != 512 && threads != 1024)
+            return fail(LDPCX_E_INVAL, "family 7 takes 256, 512 or 1024 threads");
+        pl.cpw = 1;
         pl.threads = threads;
     }
     if (family == FAMILY_SPA) {

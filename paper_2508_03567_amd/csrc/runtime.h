@@ -11,7 +11,8 @@
 
 namespace ldpcx {
 
-enum { FAMILY_BIN_LDS = 0, FAMILY_BIN_IL = 1, FAMILY_NB = 2, FAMILY_BIN_QC = 3, FAMILY_SPA = 4, FAMILY_NB_LDS = 5, FAMILY_SPA_LDS = 6 };
+enum { FAMILY_BIN_LDS = 0, FAMILY_BIN_IL = 1, FAMILY_NB = 2, FAMILY_BIN_QC = 3, FAMILY_SPA = 4, FAMILY_NB_LDS = 5, FAMILY_SPA_LDS = 6,
+       FAMILY_NB1 = 7 };
 
 struct Plan {
     int family = FAMILY_BIN_LDS;

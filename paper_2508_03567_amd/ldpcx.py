@@ -23,7 +23,7 @@ SCHED = {"flooding": 0, "layered": 1, "auto": 2}
 SCHED_NAME = {v: k for k, v in SCHED.items()}
 RULE = {"ms": 0, "nms": 1, "oms": 2, "minmax": 3, "spa": 4}
 FAMILY_NAME = {0: "bin_lds", 1: "bin_interleaved", 2: "minmax_interleaved", 3: "bin_qc_packed", 4: "spa_wave",
-               5: "minmax_lds", 6: "spa_lds"}
+               5: "minmax_lds", 6: "spa_lds", 7: "minmax_cw"}
 
 
 class LdpcxError(RuntimeError):
