@@ -237,8 +237,9 @@ ldpcx_status ldpcx_tune(const ldpcx_code *code, const ldpcx_decode_params *param
  * iterations in one launch (check and variable degrees <= 4, the vectors of cw_per_wg
  * codewords within 160 KB; 256, 512 or 1024 threads), 7 = Min-Max with one codeword per
  * workgroup, every message in LDS and the lanes over the field entries, all iterations
- * in one launch (GF(4)..GF(64), the messages of one codeword within 160 KB; 256, 512 or
- * 1024 threads, at most 256 used for check degrees above 4; both schedules),
+ * in one launch (GF(4)..GF(64), the messages of one codeword within 160 KB, stored in 8 bits
+ * when nb_msg_max <= 255; a multiple of 64 threads up to 1024, at most 256 used for check
+ * degrees above 4; both schedules),
  * 3 = packed two-codewords-per-lane binary for quasi-cyclic codes, available
  * when every layer of z rows consists of z x z circulant blocks, at most 16 layers and
  * 8 blocks per layer), codewords per workgroup (family 1: codewords per launch
@@ -253,9 +254,10 @@ ldpcx_status ldpcx_plan_info(const ldpcx_code *code, const ldpcx_decode_params *
  * pairs' rows at most 512 threads) and by family 1 (slice size, rounded up to a multiple
  * of 128 and capped by the batch and the 31-bit offset limit).  The pinned plan must be able to
  * run the requested schedule (LDPCX_E_UNSUPPORTED otherwise; families 1, 4 and 6 are
- * flooding only, families 2, 5 and 7 run the layered schedule up to GF(64)); families 5
- * and 7 take threads = 256, 512 or 1024, family 6 cw_per_wg in [1, 64] and threads = 256,
- * 512 or 1024.  Results never depend on the plan. */
+ * flooding only, families 2, 5 and 7 run the layered schedule up to GF(64)); family 5
+ * takes threads = 256, 512 or 1024, family 7 a multiple of 64 up to 1024, family 6
+ * cw_per_wg in [1, 64] and threads = 256, 512 or 1024.  Results never depend on the
+ * plan. */
 ldpcx_status ldpcx_plan_set(ldpcx_code *code, const ldpcx_decode_params *params, int32_t batch,
                             int32_t family, int32_t cw_per_wg, int32_t threads);
 

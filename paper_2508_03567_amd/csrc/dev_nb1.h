@@ -9,6 +9,12 @@
 // persistent ragged kernel.  It fits codes whose messages of one codeword fit 160 KB
 // (the (2,4)-regular GF(64) code of 192 symbols takes 128 KB).
 //
+// Message storage: 16-bit, or 8-bit when the message bound is at most 255 (the 8-bit
+// variant of sec. 5, bound 127): every stored alpha, beta and gamma' then lies in
+// [0, bound], so bytes hold them exactly, the arithmetic stays 16/32-bit and the
+// results are those of the 16-bit storage; the LDS per codeword halves (66 KB for the
+// GF(64) code, so two codewords share a compute unit).
+//
 // Mapping: a message vector of G entries lives on a segment of S = G / R lanes, lane j
 // of the segment holding the R consecutive entries R j .. R j + R - 1 as R / 2 packed
 // int16 pairs (R = 8, or G below 8); a wave holds 64 / S vectors, one per check or
@@ -35,6 +41,9 @@ struct Job {
     DecodeIO io;
 };
 
+// Bytes of one stored message entry for a message bound.
+__host__ __device__ inline int msg_bytes(int amax) { return amax <= 255 ? 1 : 2; }
+
 template <int G>
 struct Geo {
     static constexpr int R = G >= 8 ? 8 : G;  // entries per lane
@@ -47,16 +56,16 @@ struct Layout {
     size_t gam, alpha, beta, mul, hinv, h, hard, flags, total;
 };
 
-__host__ __device__ inline Layout layout(const DevCode &C) {
+__host__ __device__ inline Layout layout(const DevCode &C, int mb) {
     const size_t G = (size_t)C.g;
     Layout L;
     size_t o = 0;
     L.gam = o;
-    o = align_up(o + 2 * (size_t)C.n * G, 16);
+    o = align_up(o + mb * (size_t)C.n * G, 16);
     L.alpha = o;
-    o = align_up(o + 2 * (size_t)C.E * G, 16);
+    o = align_up(o + mb * (size_t)C.E * G, 16);
     L.beta = o;
-    o = align_up(o + 2 * (size_t)C.E * G, 16);
+    o = align_up(o + mb * (size_t)C.E * G, 16);
     L.mul = o;
     o = align_up(o + G * G, 16);
     L.hinv = o;
@@ -156,29 +165,29 @@ __device__ __forceinline__ void perm_pos(const uint8_t *mul, int hinv, int j, ui
     }
 }
 
-template <int G>
-__device__ __forceinline__ void load_perm(const uint16_t *msg, const uint8_t *mul, int hinv, int e, int j,
+template <int G, class M>
+__device__ __forceinline__ void load_perm(const M *msg, const uint8_t *mul, int hinv, int e, int j,
                                           v2s (&out)[Geo<G>::H]) {
     constexpr int R = Geo<G>::R, H = Geo<G>::H;
     uint8_t pos[R];
     perm_pos<G>(mul, hinv, j, pos);
-    const uint16_t *m = msg + (size_t)e * G;
+    const M *m = msg + (size_t)e * G;
 #pragma unroll
     for (int p = 0; p < H; ++p) out[p] = (v2s){(short)m[pos[2 * p]], (short)m[pos[2 * p + 1]]};
 }
 
 // Write back a permuted vector at the same positions (m(h^-1 t) = m~(t)).
-template <int G>
-__device__ __forceinline__ void store_deperm(uint16_t *msg, const uint8_t *mul, int hinv, int e, int j,
+template <int G, class M>
+__device__ __forceinline__ void store_deperm(M *msg, const uint8_t *mul, int hinv, int e, int j,
                                              const v2s (&v)[Geo<G>::H]) {
     constexpr int R = Geo<G>::R, H = Geo<G>::H;
     uint8_t pos[R];
     perm_pos<G>(mul, hinv, j, pos);
-    uint16_t *m = msg + (size_t)e * G;
+    M *m = msg + (size_t)e * G;
 #pragma unroll
     for (int p = 0; p < H; ++p) {
-        m[pos[2 * p]] = (uint16_t)v[p].x;
-        m[pos[2 * p + 1]] = (uint16_t)v[p].y;
+        m[pos[2 * p]] = (M)v[p].x;
+        m[pos[2 * p + 1]] = (M)v[p].y;
     }
 }
 
@@ -186,15 +195,15 @@ __device__ __forceinline__ void store_deperm(uint16_t *msg, const uint8_t *mul, 
 // F_0 .. F_{dc-2} in registers, the backward vector running down from the last edge,
 // the betas of the middle edges from F_{j-1} and B_{j+1}; F at the last edge and B at
 // the first are never used by the outputs and are not formed.
-template <int G, int DC>
-__device__ __forceinline__ void check(const DevCode &C, const uint16_t *al, uint16_t *bl, const uint8_t *mul,
+template <int G, int DC, class M>
+__device__ __forceinline__ void check(const DevCode &C, const M *al, M *bl, const uint8_t *mul,
                                       const uint8_t *hinvl, int r, int j) {
     constexpr int H = Geo<G>::H;
     const int e0 = C.row_ptr[r], dc = C.row_ptr[r + 1] - e0;
     v2s a[DC][H], F[DC][H], Bv[H], t[H];
 #pragma unroll
     for (int q = 0; q < DC; ++q)
-        if (q < dc) load_perm<G>(al, mul, hinvl[e0 + q], e0 + q, j, a[q]);
+        if (q < dc) load_perm<G, M>(al, mul, hinvl[e0 + q], e0 + q, j, a[q]);
 #pragma unroll
     for (int p = 0; p < H; ++p) F[0][p] = a[0][p];
 #pragma unroll
@@ -204,7 +213,7 @@ __device__ __forceinline__ void check(const DevCode &C, const uint16_t *al, uint
 #pragma unroll
     for (int q = 1; q < DC; ++q)
         if (q == dc - 1) {
-            store_deperm<G>(bl, mul, hinvl[e0 + q], e0 + q, j, F[q - 1]);
+            store_deperm<G, M>(bl, mul, hinvl[e0 + q], e0 + q, j, F[q - 1]);
 #pragma unroll
             for (int p = 0; p < H; ++p) Bv[p] = a[q][p];
         }
@@ -212,27 +221,27 @@ __device__ __forceinline__ void check(const DevCode &C, const uint16_t *al, uint
     for (int q = DC - 2; q >= 1; --q)
         if (q <= dc - 2) {
             conv<G>(F[q - 1], Bv, t);
-            store_deperm<G>(bl, mul, hinvl[e0 + q], e0 + q, j, t);
+            store_deperm<G, M>(bl, mul, hinvl[e0 + q], e0 + q, j, t);
             conv<G>(Bv, a[q], t);
 #pragma unroll
             for (int p = 0; p < H; ++p) Bv[p] = t[p];
         }
-    store_deperm<G>(bl, mul, hinvl[e0], e0, j, Bv);
+    store_deperm<G, M>(bl, mul, hinvl[e0], e0, j, Bv);
 }
 
 // Sum of gamma' and the betas of variable v's edges (all, or all but edge `skip`), for
 // the lane's R entries, in 32 bits.
-template <int G>
-__device__ __forceinline__ void var_sum(const DevCode &C, const uint16_t *gl, const uint16_t *bl, int v, int j,
-                                        int skip, int (&s)[Geo<G>::R]) {
+template <int G, class M>
+__device__ __forceinline__ void var_sum(const DevCode &C, const M *gl, const M *bl, int v, int j, int skip,
+                                        int (&s)[Geo<G>::R]) {
     constexpr int R = Geo<G>::R;
-    const uint16_t *gr = gl + (size_t)v * G + R * j;
+    const M *gr = gl + (size_t)v * G + R * j;
 #pragma unroll
     for (int i = 0; i < R; ++i) s[i] = (int)gr[i];
     for (int t = C.vn_ptr[v]; t < C.vn_ptr[v + 1]; ++t) {
         const int e = C.vn_ref[t];
         if (e == skip) continue;
-        const uint16_t *br = bl + (size_t)e * G + R * j;
+        const M *br = bl + (size_t)e * G + R * j;
 #pragma unroll
         for (int i = 0; i < R; ++i) s[i] += (int)br[i];
     }
@@ -240,28 +249,27 @@ __device__ __forceinline__ void var_sum(const DevCode &C, const uint16_t *gl, co
 
 // alpha of edge e (eq. (14)-(15) of its variable v): gamma' plus the betas of v's other
 // edges, shifted to minimum 0 and clipped to amax.
-template <int G>
-__device__ __forceinline__ void alpha_edge(const DevCode &C, const uint16_t *gl, const uint16_t *bl, uint16_t *al,
-                                           int v, int e, int j, int amax) {
+template <int G, class M>
+__device__ __forceinline__ void alpha_edge(const DevCode &C, const M *gl, const M *bl, M *al, int v, int e, int j,
+                                           int amax) {
     constexpr int R = Geo<G>::R, S = Geo<G>::S;
     int s[R];
-    var_sum<G>(C, gl, bl, v, j, e, s);
+    var_sum<G, M>(C, gl, bl, v, j, e, s);
     int mn = s[0];
 #pragma unroll
     for (int i = 1; i < R; ++i) mn = min(mn, s[i]);
     mn = seg_min<S>(mn);
-    uint16_t *ar = al + (size_t)e * G + R * j;
+    M *ar = al + (size_t)e * G + R * j;
 #pragma unroll
-    for (int i = 0; i < R; ++i) ar[i] = (uint16_t)min(s[i] - mn, amax);
+    for (int i = 0; i < R; ++i) ar[i] = (M)min(s[i] - mn, amax);
 }
 
 // Decision of variable v: the lowest x minimising gamma'(x) + sum of its betas (x).
-template <int G>
-__device__ __forceinline__ void decide(const DevCode &C, const uint16_t *gl, const uint16_t *bl, uint8_t *hl, int v,
-                                       int j) {
+template <int G, class M>
+__device__ __forceinline__ void decide(const DevCode &C, const M *gl, const M *bl, uint8_t *hl, int v, int j) {
     constexpr int R = Geo<G>::R, S = Geo<G>::S;
     int s[R];
-    var_sum<G>(C, gl, bl, v, j, -1, s);
+    var_sum<G, M>(C, gl, bl, v, j, -1, s);
     int key = s[0] * G + R * j;
 #pragma unroll
     for (int i = 1; i < R; ++i) key = min(key, s[i] * G + R * j + i);
@@ -286,14 +294,15 @@ __device__ __forceinline__ bool syndrome_ok(const DevCode &C, const uint8_t *mul
     return ok;
 }
 
-// The whole decode of codeword b by the calling workgroup (any multiple of 64 threads).
-// Ends with a barrier, so the caller may reuse the LDS right after.
-template <int G, int DC>
+// The whole decode of codeword b by the calling workgroup (any multiple of 64 threads),
+// messages stored as M (uint16_t, or uint8_t when the bound is at most 255).  Ends with
+// a barrier, so the caller may reuse the LDS right after.
+template <int G, int DC, class M>
 __device__ __forceinline__ void decode_cw(const Job &J, int b, unsigned char *lds) {
     constexpr int S = Geo<G>::S, VPW = Geo<G>::VPW;
     const DevCode &C = J.C;
-    const Layout Y = layout(C);
-    uint16_t *gl = (uint16_t *)(lds + Y.gam), *al = (uint16_t *)(lds + Y.alpha), *bl = (uint16_t *)(lds + Y.beta);
+    const Layout Y = layout(C, (int)sizeof(M));
+    M *gl = (M *)(lds + Y.gam), *al = (M *)(lds + Y.alpha), *bl = (M *)(lds + Y.beta);
     uint8_t *mul = lds + Y.mul, *hinvl = lds + Y.hinv, *hl_h = lds + Y.h, *hard = lds + Y.hard;
     int *flags = (int *)(lds + Y.flags);
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -303,7 +312,7 @@ __device__ __forceinline__ void decode_cw(const Job &J, int b, unsigned char *ld
 
     // stage: clipped channel vectors, tables, alpha^(0) = gamma', beta = 0
     const int16_t *src = (const int16_t *)J.io.llr + (size_t)b * C.n * G;
-    for (int i = tid; i < C.n * G; i += nthr) gl[i] = (uint16_t)min((int)src[i], amax);
+    for (int i = tid; i < C.n * G; i += nthr) gl[i] = (M)min((int)src[i], amax);
     for (int i = tid; i < G * G; i += nthr) mul[i] = C.gfmul[i];
     for (int i = tid; i < C.E; i += nthr) {
         hinvl[i] = C.hinv[i];
@@ -318,7 +327,7 @@ __device__ __forceinline__ void decode_cw(const Job &J, int b, unsigned char *ld
     }
     __syncthreads();
     // decision of iteration 0: the lowest x minimising gamma'
-    for (int v = myseg; v < C.n; v += segs) decide<G>(C, gl, bl, hard, v, j);
+    for (int v = myseg; v < C.n; v += segs) decide<G, M>(C, gl, bl, hard, v, j);
     __syncthreads();
 
     int it = 0, slot = 0;
@@ -330,28 +339,28 @@ __device__ __forceinline__ void decode_cw(const Job &J, int b, unsigned char *ld
         }
         const bool need_dec = J.early_stop || k == J.max_iters;
         if (!J.layered) {
-            for (int r = myseg; r < C.m; r += segs) check<G, DC>(C, al, bl, mul, hinvl, r, j);
+            for (int r = myseg; r < C.m; r += segs) check<G, DC, M>(C, al, bl, mul, hinvl, r, j);
             __syncthreads();
             for (int t = myseg; t < C.E; t += segs) {
                 const int e = C.vn_edge[t];
-                alpha_edge<G>(C, gl, bl, al, C.col_idx[e], e, j, amax);
+                alpha_edge<G, M>(C, gl, bl, al, C.col_idx[e], e, j, amax);
             }
             if (need_dec)
-                for (int v = myseg; v < C.n; v += segs) decide<G>(C, gl, bl, hard, v, j);
+                for (int v = myseg; v < C.n; v += segs) decide<G, M>(C, gl, bl, hard, v, j);
             __syncthreads();
         } else {
             for (int l = 0; l < C.nb_nl; ++l) {
                 for (int i = C.nbl_eptr[l] + myseg; i < C.nbl_eptr[l + 1]; i += segs) {
                     const int e = C.nbl_edge[i];
-                    alpha_edge<G>(C, gl, bl, al, C.col_idx[e], e, j, amax);
+                    alpha_edge<G, M>(C, gl, bl, al, C.col_idx[e], e, j, amax);
                 }
                 __syncthreads();
                 for (int i = C.nbl_ptr[l] + myseg; i < C.nbl_ptr[l + 1]; i += segs)
-                    check<G, DC>(C, al, bl, mul, hinvl, C.nbl_chk[i], j);
+                    check<G, DC, M>(C, al, bl, mul, hinvl, C.nbl_chk[i], j);
                 __syncthreads();
             }
             if (need_dec) {
-                for (int v = myseg; v < C.n; v += segs) decide<G>(C, gl, bl, hard, v, j);
+                for (int v = myseg; v < C.n; v += segs) decide<G, M>(C, gl, bl, hard, v, j);
                 __syncthreads();
             }
         }

@@ -175,10 +175,11 @@ hipError_t launch_nb_lds(const DevCode &C, int max_iters, int early_stop, int la
 hipError_t launch_nb(const DevCode &C, int max_iters, int early_stop, int layered, int batch, int amax, void *ws,
                      const DecodeIO &io, hipStream_t s);
 // Min-Max with one codeword per workgroup and all its messages in LDS (g <= 64, check
-// degree <= 16, nb1_lds_bytes(C) <= 160 KB; 256, 512 or 1024 threads, at most 256 used
-// for check degrees above 4); no workspace, both schedules.
-size_t nb1_lds_bytes(const DevCode &C);
-bool nb1_supported(const DevCode &C);
+// degree <= 16, nb1_lds_bytes(C, amax) <= 160 KB; a multiple of 64 threads up to 1024, at
+// most 256 used for check degrees above 4); no workspace, both schedules.  Messages are stored in
+// 8 bits when the bound amax is at most 255, else in 16 bits.
+size_t nb1_lds_bytes(const DevCode &C, int amax);
+bool nb1_supported(const DevCode &C, int amax);
 hipError_t launch_nb1(const DevCode &C, int max_iters, int early_stop, int layered, int batch, int amax, int threads,
                       const DecodeIO &io, hipStream_t s);
 // Field sizes with a compiled Min-Max kernel (4..64 interleaved, 128 and 256 wide).

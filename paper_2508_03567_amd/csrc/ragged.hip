@@ -80,17 +80,23 @@ __device__ __forceinline__ void run_qc(const JobDesc &J, int blk, uint32_t *lds)
 #undef LDPCX_QC_RUN
 }
 
-template <int DC>
-__device__ __forceinline__ void run_nb1(const JobDesc &J, int b, uint32_t *lds) {
+template <int DC, class M>
+__device__ __forceinline__ void run_nb1_m(const JobDesc &J, int b, uint32_t *lds) {
     const dev::nb1::Job N{J.C, J.max_iters, J.early_stop, J.layered, J.amax, J.batch, J.io};
     unsigned char *l = (unsigned char *)lds;
     switch (J.C.g) {
-    case 4: dev::nb1::decode_cw<4, DC>(N, b, l); break;
-    case 8: dev::nb1::decode_cw<8, DC>(N, b, l); break;
-    case 16: dev::nb1::decode_cw<16, DC>(N, b, l); break;
-    case 32: dev::nb1::decode_cw<32, DC>(N, b, l); break;
-    default: dev::nb1::decode_cw<64, DC>(N, b, l); break;
+    case 4: dev::nb1::decode_cw<4, DC, M>(N, b, l); break;
+    case 8: dev::nb1::decode_cw<8, DC, M>(N, b, l); break;
+    case 16: dev::nb1::decode_cw<16, DC, M>(N, b, l); break;
+    case 32: dev::nb1::decode_cw<32, DC, M>(N, b, l); break;
+    default: dev::nb1::decode_cw<64, DC, M>(N, b, l); break;
     }
+}
+
+template <int DC>
+__device__ __forceinline__ void run_nb1(const JobDesc &J, int b, uint32_t *lds) {
+    if (dev::nb1::msg_bytes(J.amax) == 1) run_nb1_m<DC, uint8_t>(J, b, lds);
+    else run_nb1_m<DC, uint16_t>(J, b, lds);
 }
 
 __device__ __forceinline__ void run_spa(const JobDesc &J, int blk, uint32_t *lds) {
@@ -293,10 +299,10 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
             if (c->g > 2) {
                 // Min-Max: one codeword per item when its messages fit a workgroup and the
                 // code has enough checks to occupy the workgroup's lanes
-                if (p.rule == LDPCX_RULE_MINMAX && nb1_supported(D.C) && D.C.m >= 32 &&
-                    nb1_lds_bytes(D.C) <= cap) {
+                if (p.rule == LDPCX_RULE_MINMAX && nb1_supported(D.C, D.amax) && D.C.m >= 32 &&
+                    nb1_lds_bytes(D.C, D.amax) <= cap) {
                     D.family = FAMILY_NB1;
-                    add(I_NB1, jb.batch, nb1_lds_bytes(D.C));
+                    add(I_NB1, jb.batch, nb1_lds_bytes(D.C, D.amax));
                     continue;
                 }
                 // FFT-SPA of the LDS-resident family: one item per group of codewords

@@ -256,7 +256,7 @@ ldpcx_status run_plan(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &p
         return LDPCX_OK;
     }
     if (pl.family == FAMILY_NB1) {
-        if (!nb1_supported(c->dev) || p->rule != LDPCX_RULE_MINMAX)
+        if (!nb1_supported(c->dev, nb_amax(p)) || p->rule != LDPCX_RULE_MINMAX)
             return fail(LDPCX_E_UNSUPPORTED, "the messages of one codeword do not fit the LDS of one workgroup");
         e = launch_nb1(c->dev, p->max_iters, p->early_stop, pl.schedule == LDPCX_SCHED_LAYERED, batch, nb_amax(p),
                        pl.threads, io, s);
@@ -849,11 +849,11 @@ ldpcx_status ldpcx_plan_set(ldpcx_code *c, const ldpcx_decode_params *params, in
         pl.threads = threads;
     }
     if (family == FAMILY_NB1) {
-        if (c->g > 64 || params->rule != LDPCX_RULE_MINMAX || !nb1_supported(c->dev))
+        if (c->g > 64 || params->rule != LDPCX_RULE_MINMAX || !nb1_supported(c->dev, nb_amax(params)))
             return fail(LDPCX_E_UNSUPPORTED, "family 7 runs Min-Max over GF(4)..GF(64) for codes whose messages of one "
                                              "codeword fit 160 KB of LDS");
-        if (threads != 256 && threads != 512 && threads != 1024)
-            return fail(LDPCX_E_INVAL, "family 7 takes 256, 512 or 1024 threads");
+        if (threads < 64 || threads > 1024 || threads % 64)
+            return fail(LDPCX_E_INVAL, "family 7 takes a multiple of 64 threads up to 1024");
         pl.cpw = 1;
         pl.threads = threads;
     }

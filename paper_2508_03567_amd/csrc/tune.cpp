@@ -215,8 +215,8 @@ std::vector<Plan> candidates(const ldpcx_code *c, const ldpcx_decode_params *p, 
                 q.threads = thr;
                 out.push_back(q);
             }
-            if (nb1_supported(c->dev))
-                for (int thr : {256, 512, 1024}) {
+            if (nb1_supported(c->dev, nb_amax(p)))
+                for (int thr : {256, 512, 768, 1024}) {
                     if (c->dev.dc_max > 4 && thr > 256) break;
                     Plan q = pl;
                     q.family = FAMILY_NB1;

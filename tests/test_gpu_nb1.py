@@ -44,11 +44,13 @@ def _check(code, got, d, gam, dump=True):
 @pytest.mark.parametrize("iters", [0, 1, 2, 5])
 @pytest.mark.parametrize("sched", ["flooding", "layered"])
 @pytest.mark.parametrize("early", [True, False])
-def test_gf64_workload_every_message(iters, sched, early):
-    """The GF(64) (2,4)-regular n = 192 code of the Min-Max workload, 1.5 dB."""
+@pytest.mark.parametrize("bound", [0, 127])
+def test_gf64_workload_every_message(iters, sched, early, bound):
+    """The GF(64) (2,4)-regular n = 192 code of the Min-Max workload, 1.5 dB; bound 127
+    runs the 8-bit message storage."""
     w = S.workload(3, batch=37, ebn0_db=1.5)
     _, gam = S.make_inputs(w)
-    d = dict(rule="minmax", schedule=sched, max_iters=iters, early_stop=early)
+    d = dict(rule="minmax", schedule=sched, max_iters=iters, early_stop=early, nb_msg_max=bound)
     _check(w.code, _run(w.code, gam, d, 256), d, gam)
 
 
@@ -57,7 +59,8 @@ def test_gf64_workload_every_message(iters, sched, early):
     (16, 96, 3, 6, 21, "flooding", 1024, 0), (32, 64, 2, 4, 19, "flooding", 512, 127),
     (64, 64, 3, 6, 9, "layered", 256, 0), (16, 128, 2, 8, 17, "flooding", 256, 50),
     (8, 32, 2, 16, 11, "flooding", 256, 0), (64, 32, 2, 16, 7, "layered", 512, 0), (64, 40, 2, 5, 13, "flooding", 1024, 0),
-    (4, 96, 2, 3, 50, "layered", 1024, 127), (32, 96, 2, 6, 16, "layered", 256, 0)])
+    (4, 96, 2, 3, 50, "layered", 1024, 127), (32, 96, 2, 6, 16, "layered", 256, 0),
+    (64, 192, 2, 4, 10, "flooding", 768, 127), (16, 64, 2, 4, 12, "layered", 320, 0)])
 def test_fields_degrees_bounds(g_size, n, dv, dc, batch, sched, threads, bound):
     m = n * dv // dc
     code = S.random_regular_nb_code(n, m, dv, dc, g_size, S.PRIM_POLY[g_size], seed=7 * g_size + n + dc)
@@ -90,5 +93,5 @@ def test_limits():
     assert ei.value.status == L.E_UNSUPPORTED
     small = L.Code(S.workload(3).code)
     with pytest.raises(L.LdpcxError) as ei:
-        L.plan_set(small, L.params("minmax", max_iters=2), 8, "minmax_cw", 1, 384)
+        L.plan_set(small, L.params("minmax", max_iters=2), 8, "minmax_cw", 1, 320 + 1)
     assert ei.value.status == L.E_INVAL

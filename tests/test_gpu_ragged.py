@@ -172,3 +172,37 @@ def test_ragged_gathers_whole_device_jobs():
     for (h, prm, x), (hard, ok, it) in zip(items, outs):
         ref = L.decode(h, prm, x)
         assert torch.equal(hard, ref[0]) and torch.equal(ok, ref[1]) and torch.equal(it, ref[2])
+
+
+def test_ragged_gf_items_of_every_kind():
+    """GF(g) jobs that become items of the persistent kernel, next to binary jobs:
+    FFT-SPA on a short code of its LDS-resident family (groups of codewords per item),
+    Min-Max with check degree 8 (the large-degree instance), Min-Max over GF(4) with
+    degree 4, and a Min-Max code with too few checks to become items (gathered).  Every
+    job equals a plain decode of it alone and the oracle."""
+    spa_code = S.random_regular_nb_code(32, 16, 2, 4, 16, S.PRIM_POLY[16], seed=91)
+    big_dc = S.random_regular_nb_code(128, 32, 2, 8, 8, S.PRIM_POLY[8], seed=92)
+    gf4 = S.random_regular_nb_code(96, 48, 2, 4, 4, S.PRIM_POLY[4], seed=93)
+    tiny = S.random_regular_nb_code(16, 8, 2, 4, 8, S.PRIM_POLY[8], seed=94)
+    specs = [(spa_code, "spa", "flooding", 45), (big_dc, "minmax", "flooding", 21), (gf4, "minmax", "layered", 70),
+             (tiny, "minmax", "flooding", 9), (big_dc, "minmax", "layered", 5), (spa_code, "spa", "flooding", 3)]
+    items, refs = [], []
+    for i, (code, rule, sched, batch) in enumerate(specs):
+        cw = S.random_codewords(code, batch, seed=500 + i)
+        gam = S.nb_gamma_int16(cw, code.g, 1.5, seed=600 + i)
+        d = dict(rule=rule, schedule=sched, max_iters=6, early_stop=bool(i % 2 == 0))
+        h = L.Code(code)
+        if rule == "spa":
+            assert L.plan_info(h, L.params(**d), batch)["family"] == "spa_lds"
+        items.append((h, L.params(**d), torch.from_numpy(np.ascontiguousarray(gam)).to(DEV)))
+        refs.append((code, d, gam))
+    w0, d0, llr0 = _mk(0, 60, 650)
+    items.append((_code(0), L.params(**d0), torch.from_numpy(np.ascontiguousarray(llr0)).to(DEV)))
+    outs = L.decode_ragged(items)
+    torch.cuda.synchronize()
+    for (h, prm, x), (hard, ok, it) in zip(items, outs):
+        ref = L.decode(h, prm, x)
+        assert torch.equal(hard, ref[0]) and torch.equal(ok, ref[1]) and torch.equal(it, ref[2])
+    for (code, d, gam), (hard, ok, it) in zip(refs, outs):
+        o = (O.decode_spa if d["rule"] == "spa" else O.decode_nb)(code, O.params(**d), gam)
+        assert (_np(hard) == o["hard"]).all() and (_np(ok) == o["ok"]).all() and (_np(it) == o["iters"]).all()
