@@ -152,7 +152,8 @@ def main() -> None:
                     help="GF-size sweep instead: (2,4)-regular codes of 16/32/64 symbols over GF(4)..GF(256), "
                          "Min-Max, fixed iterations (one JSON line per point)")
     ap.add_argument("--sweep-rule", type=str, default="minmax", choices=["minmax", "spa"],
-                    help="--sweep: decoder (spa covers GF(4)..GF(64))")
+                    help="--sweep: decoder")
+    ap.add_argument("--sweep-fields", type=str, default=None, help="--sweep: comma-separated field sizes (default all)")
     ap.add_argument("--prof-summary", type=str, default=None,
                     help="summarise rocprofv3 CSV output instead of running: comma-separated output directories "
                          "(one kernel-trace run, or the --pmc runs of one counter summary)")
@@ -531,7 +532,7 @@ def sweep_main(args) -> None:
     rule = args.sweep_rule
     for n in SWEEP_N:
         for g in SWEEP_G:
-            if rule == "spa" and g > 64:
+            if args.sweep_fields and g not in [int(x) for x in args.sweep_fields.split(",")]:
                 continue
             batch = args.batch or 8192
             code = S.random_regular_nb_code(n, n // 2, 2, 4, g, S.PRIM_POLY[g], seed=100 + n + g, name=f"n{n}_gf{g}")

@@ -105,11 +105,13 @@ typedef struct {
  * sec. 5, whose channel vectors are clipped to the same range: gamma'(x) =
  * min(gamma(x), nb_msg_max) is used wherever gamma appears); decision = lowest x
  * minimising gamma'_n(x) + sum_m beta_mn(x).  nb_msg_max is ignored for binary codes.
- * FFT-SPA arithmetic (Alg. 1, rule SPA, GF(4)..GF(64), flooding, check and variable
- * degrees <= 16; gamma is the same symbol-cost input): probabilities in Q24 (2^24 = 1),
+ * FFT-SPA arithmetic (Alg. 1, rule SPA, flooding; GF(4)..GF(64) with check and variable
+ * degrees <= 16, GF(128) and GF(256) with degrees <= 4; gamma is the same symbol-cost
+ * input): probabilities in Q24 (2^24 = 1),
  * channel p = norm(W(gamma)) with W(c) = round(2^24 exp(-c/4)); eq. (3) with the
  * Walsh-Hadamard transform exact in integers, products qmul(a, b) = floor((a b + 2^23)
- * / 2^24) in ascending edge order, inverse = transform then floor(. / g) clamped at 0;
+ * / 2^24) in ascending edge order, inverse = transform (its sums in 64 bits) then
+ * floor(. / g) clamped at 0;
  * eqs. (5)-(6) with norm(z)(x) = floor((z(x) R + 2^21) / 2^22), R = floor(2^46 /
  * sum z) (p_n when sum z = 0); decision = lowest x maximising p_n(x) times every
  * incoming message; permutation and stop rule as for Min-Max. */

@@ -1,8 +1,9 @@
-// Fixed-point FFT-SPA decoder (Alg. 1) for fields up to GF(64), as wave-level device
-// functions.
+// Fixed-point FFT-SPA decoder (Alg. 1) for fields up to GF(256), as wave-level device
+// functions (GF(128) and GF(256) for check and variable degrees up to 4).
 //
 // Arithmetic: probabilities in Q24 (2^24 = 1); the transform of eq. (3) over GF(2^q)
-// is the Walsh-Hadamard transform, exact in 32-bit integers; products of two Q24
+// is the Walsh-Hadamard transform, exact in 32-bit integers (the inverse in 64 bits
+// above GF(64), where its sums reach g 2^24); products of two Q24
 // numbers are floor((a b + 2^23) / 2^24), taken in ascending edge order; the inverse
 // transform is followed by a floor division by g and a clamp at 0; a vector z is
 // normalised (eq. (6)) as floor((z(x) R + 2^21) / 2^22) with R = floor(2^46 / sum z);
@@ -49,7 +50,7 @@ struct Args {
 // entries per lane for degrees up to 4, fewer above.
 template <int G, int D>
 constexpr int lanes_for() {
-    return D <= 4 ? (G / 4 > 4 ? G / 4 : 4) : (G < 16 ? G : 16);
+    return D <= 4 ? (G / 4 > 16 ? 16 : (G / 4 > 4 ? G / 4 : 4)) : (G < 16 ? G : 16);
 }
 
 // Entries per lane, codewords per wave, log2(g).
@@ -58,17 +59,17 @@ struct Geo {
     static_assert(S == 4 || S == 8 || S == 16, "segments of 4, 8 or 16 lanes");
     static constexpr int R = G / S;
     static constexpr int CPW = 64 / S;
-    static constexpr int P = G == 64 ? 6 : G == 32 ? 5 : G == 16 ? 4 : G == 8 ? 3 : 2;
+    static constexpr int P = G == 256 ? 8 : G == 128 ? 7 : G == 64 ? 6 : G == 32 ? 5 : G == 16 ? 4 : G == 8 ? 3 : 2;
 };
 
 __device__ __forceinline__ int qmul(int a, int b) {
     return (int)(((long long)a * b + (1ll << (kQ - 1))) >> kQ);
 }
 
-// floor(2^46 / s) for 0 < s < 2^31: the double quotient is within one unit of the
+// floor(2^46 / s) for 0 < s < 2^33: the double quotient is within one unit of the
 // exact one (its error is far below 1 for quotients < 2^47), and two integer checks
 // make it exact.
-__device__ __forceinline__ long long recip46(int s) {
+__device__ __forceinline__ long long recip46(long long s) {
     long long q = (long long)(70368744177664.0 / (double)s);
     if (q * s > (1ll << 46)) --q;
     if ((q + 1) * s <= (1ll << 46)) ++q;
@@ -130,6 +131,42 @@ __device__ __forceinline__ Signs signs_of(int j) {
     return s;
 }
 
+// DPP move of a 64-bit value (both halves through the same control).
+template <int CTRL>
+__device__ __forceinline__ long long dpp64(long long v) {
+    const int lo = dpp<CTRL>((int)(uint32_t)v), hi = dpp<CTRL>((int)(v >> 32));
+    return (long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+template <int CTRL, int R>
+__device__ __forceinline__ void lane_stage64(long long (&v)[R], int mask) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = dpp64<CTRL>(v[r]) + (v[r] ^ (long long)mask);
+}
+
+// The same transform in 64 bits (for the inverse above GF(64)); the per-lane constant of
+// the lane stages is the same small integer as in 32 bits.
+template <int S, int R>
+__device__ __forceinline__ void wht64(long long (&v)[R], const Signs &sg) {
+#pragma unroll
+    for (int s = 1; s < R; s <<= 1) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (!(r & s)) {
+                const long long a = v[r], b = v[r | s];
+                v[r] = a + b;
+                v[r | s] = a - b;
+            }
+        }
+    }
+    lane_stage64<kDppXor1>(v, sg.d1);
+    lane_stage64<kDppXor2>(v, sg.d2);
+    if (S >= 8) lane_stage64<kDppMirror8>(v, sg.d7);
+    if (S >= 16) lane_stage64<kDppRor8>(v, sg.d8);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] -= (long long)sg.corr;
+}
+
 // Walsh-Hadamard transform of the segment (relabelled in the lane bits, see above).
 template <int S, int R>
 __device__ __forceinline__ void wht(int (&v)[R], const Signs &sg) {
@@ -158,6 +195,17 @@ __device__ __forceinline__ int seg_sum(int v) {
     return v;
 }
 
+// Segment sum of per-lane values below 2^31 whose total may exceed 32 bits.
+template <int S>
+__device__ __forceinline__ long long seg_sum64(int v) {
+    long long s = v;
+    s += dpp64<kDppXor1>(s);
+    s += dpp64<kDppXor2>(s);
+    if (S >= 8) s += dpp64<kDppMirror8>(s);
+    if (S >= 16) s += dpp64<kDppRor8>(s);
+    return s;
+}
+
 template <int S>
 __device__ __forceinline__ int seg_max(int v) {
     v = max(v, dpp<kDppXor1>(v));
@@ -170,10 +218,14 @@ __device__ __forceinline__ int seg_max(int v) {
 // out = norm(z) for this lane's entries; `fallback` when the segment sum is 0.
 template <int S, int R>
 __device__ __forceinline__ void normalise(const int (&z)[R], const int (&fallback)[R], int (&out)[R]) {
-    int s = 0;
+    int ls = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) s += z[r];
-    s = seg_sum<S>(s);
+    for (int r = 0; r < R; ++r) ls += z[r];
+    // up to GF(64) the segment sum stays below 2^31; above it can reach g 2^24 (channel
+    // vectors with many equal costs) and is taken in 64 bits
+    long long s;
+    if constexpr (S * R > 64) s = seg_sum64<S>(ls);
+    else s = seg_sum<S>(ls);
     if (s <= 0) {
 #pragma unroll
         for (int r = 0; r < R; ++r) out[r] = fallback[r];
@@ -188,6 +240,19 @@ __device__ __forceinline__ void normalise(const int (&z)[R], const int (&fallbac
 // lane's first entry.
 template <int S, int R>
 __device__ __forceinline__ int seg_argmax(const int (&val)[R], int x0) {
+    if constexpr (S * R > 64) {
+        // above GF(64) the symbol no longer fits beside the value in 32 bits: the maximum
+        // first, then the lowest x holding it
+        int m = val[0];
+#pragma unroll
+        for (int r = 1; r < R; ++r) m = max(m, val[r]);
+        m = seg_max<S>(m);
+        int x = S * R;
+#pragma unroll
+        for (int r = R - 1; r >= 0; --r)
+            if (val[r] == m) x = x0 + r;
+        return -seg_max<S>(-x);
+    }
     int key = val[0] * 64 + (63 - x0);
 #pragma unroll
     for (int r = 1; r < R; ++r) key = max(key, val[r] * 64 + (63 - x0 - r));
@@ -336,9 +401,19 @@ __device__ __forceinline__ void cn_core(const DevCode &C, int e0, int dc, int x0
                     for (int r = 0; r < R; ++r) acc[r] = qmul(acc[r], U[j][r]);
                 }
             }
-            wht<S>(acc, sg);
+            if constexpr (G > 64) {
+                // the inverse sums reach g 2^24: 64 bits, then floor(. / g) clamped at 0
+                long long a64[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] = max(acc[r] >> P, 0);  // floor(. / g), clamped at 0
+                for (int r = 0; r < R; ++r) a64[r] = acc[r];
+                wht64<S>(a64, sg);
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[r] = (int)max(a64[r] >> P, 0ll);
+            } else {
+                wht<S>(acc, sg);
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[r] = max(acc[r] >> P, 0);  // floor(. / g), clamped at 0
+            }
             store_v(n, ix[n], acc);
             if (n + 1 < dc) {
 #pragma unroll

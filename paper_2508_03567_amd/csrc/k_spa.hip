@@ -16,10 +16,12 @@ using dev::spa::Args;
 __device__ __forceinline__ long unit_id() { return (long)blockIdx.x * 4 + dev::wave_id(); }
 
 __global__ void __launch_bounds__(256) k_fill(dev::FillArgs F) { dev::fill_block(F, blockIdx.x); }
-constexpr int kInitLanes = 4;  // lanes per codeword of the channel-vector kernel
+// lanes per codeword of the channel-vector kernel (at most 16 entries per lane)
+template <int G>
+constexpr int init_lanes() { return G > 64 ? 16 : 4; }
 template <int G>
 __global__ void __launch_bounds__(256) k_init(Args A, int write_u) {
-    dev::spa::init_unit<G, kInitLanes>(A, unit_id(), write_u != 0);
+    dev::spa::init_unit<G, init_lanes<G>()>(A, unit_id(), write_u != 0);
 }
 __global__ void __launch_bounds__(256) k_syn(Args A, int slot) {
     dev::spa::syn_thread(A, slot, (long)blockIdx.x * 256 + threadIdx.x);
@@ -59,7 +61,7 @@ hipError_t run(const Args &A, hipStream_t s) {
     const DevCode &C = A.C;
     const long B = A.batch;
     // codeword groups of each kernel (its lanes per codeword set the group size)
-    constexpr int CI = dev::spa::Geo<G, kInitLanes>::CPW;
+    constexpr int CI = dev::spa::Geo<G, init_lanes<G>()>::CPW;
     constexpr int CC = dev::spa::Geo<G, dev::spa::lanes_for<G, DC>()>::CPW;
     constexpr int CV = dev::spa::Geo<G, dev::spa::lanes_for<G, DV>()>::CPW;
     const long gi = (B + CI - 1) / CI, gc = (B + CC - 1) / CC, gv = (B + CV - 1) / CV;
@@ -103,8 +105,13 @@ hipError_t run(const Args &A, hipStream_t s) {
 template <int G>
 hipError_t run_degrees(const Args &A, bool small_dc, bool small_dv, hipStream_t s) {
     constexpr int D = kNbDcMax, V = dev::spa::kVnRegs;
-    if (small_dc) return small_dv ? run<G, 4, 4>(A, s) : run<G, 4, V>(A, s);
-    return small_dv ? run<G, D, 4>(A, s) : run<G, D, V>(A, s);
+    if constexpr (G > 64) {  // check and variable degrees up to 4 only (spa_supported)
+        (void)small_dc, (void)small_dv;
+        return run<G, 4, 4>(A, s);
+    } else {
+        if (small_dc) return small_dv ? run<G, 4, 4>(A, s) : run<G, 4, V>(A, s);
+        return small_dv ? run<G, D, 4>(A, s) : run<G, D, V>(A, s);
+    }
 }
 
 template <int G>
@@ -118,10 +125,13 @@ hipError_t run_lds(const Args &A, int cw, int threads, hipStream_t s) {
 }  // namespace
 
 bool spa_supported(const DevCode &C) {
-    return C.g >= 4 && C.g <= 64 && C.dc_max <= kNbDcMax && C.dv_max <= dev::spa::kVnRegs;
+    if (C.g > 64) return (C.g == 128 || C.g == 256) && C.dc_max <= 4 && C.dv_max <= 4;
+    return C.g >= 4 && C.dc_max <= kNbDcMax && C.dv_max <= dev::spa::kVnRegs;
 }
 
-int spa_cw_per_wave(const DevCode &C) { return C.dc_max <= 4 ? 64 / std::max(4, C.g / 4) : 64 / std::min(C.g, 16); }
+int spa_cw_per_wave(const DevCode &C) {
+    return C.dc_max <= 4 ? 64 / std::min(16, std::max(4, C.g / 4)) : 64 / std::min(C.g, 16);
+}
 
 size_t spa_work_bytes(const DevCode &C, int max_iters, int batch) { return dev::spa::carve(C, max_iters, batch).total; }
 
@@ -135,6 +145,8 @@ hipError_t launch_spa(const DevCode &C, int max_iters, int early_stop, int batch
     case 16: return run_degrees<16>(A, small_dc, small_dv, s);
     case 32: return run_degrees<32>(A, small_dc, small_dv, s);
     case 64: return run_degrees<64>(A, small_dc, small_dv, s);
+    case 128: return run_degrees<128>(A, small_dc, small_dv, s);
+    case 256: return run_degrees<256>(A, small_dc, small_dv, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -142,7 +154,7 @@ hipError_t launch_spa(const DevCode &C, int max_iters, int early_stop, int batch
 size_t spa_lds_bytes(const DevCode &C, int cw) { return dev::spa::lds_layout(C, cw).total; }
 
 bool spa_lds_supported(const DevCode &C) {
-    return spa_supported(C) && C.dc_max <= 4 && C.dv_max <= 4 && spa_lds_bytes(C, 1) <= kSpaLdsMax;
+    return spa_supported(C) && C.g <= 64 && C.dc_max <= 4 && C.dv_max <= 4 && spa_lds_bytes(C, 1) <= kSpaLdsMax;
 }
 
 int spa_lds_cpw(const DevCode &C) { return 64 / std::max(4, C.g / 4); }

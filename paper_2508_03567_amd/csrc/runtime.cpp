@@ -108,7 +108,8 @@ ldpcx_status check_params(const ldpcx_code *c, const ldpcx_decode_params *p) {
         if (p->rule != LDPCX_RULE_MINMAX && p->rule != LDPCX_RULE_SPA)
             return fail(LDPCX_E_INVAL, "codes over GF(g > 2) take rule MINMAX or SPA");
         if (p->rule == LDPCX_RULE_SPA && !spa_supported(c->dev))
-            return fail(LDPCX_E_UNSUPPORTED, "the FFT-SPA decoder covers GF(4)..GF(64), check and variable degrees <= 16");
+            return fail(LDPCX_E_UNSUPPORTED, "the FFT-SPA decoder covers GF(4)..GF(64) with check and variable degrees "
+                                             "<= 16, and GF(128), GF(256) with degrees <= 4");
         if (p->nb_msg_max < 0 || p->nb_msg_max > 32767) return fail(LDPCX_E_INVAL, "nb_msg_max must be in [0, 32767]");
         if (p->schedule == LDPCX_SCHED_LAYERED && p->rule == LDPCX_RULE_SPA)
             return fail(LDPCX_E_UNSUPPORTED, "the FFT-SPA decoder runs the flooding schedule only");

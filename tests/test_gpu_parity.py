@@ -706,9 +706,10 @@ def test_spa_lds_family_limits_and_tuning():
 
 
 def test_spa_rejections():
-    code = S.random_regular_nb_code(16, 8, 2, 4, 128, S.PRIM_POLY[128], seed=1)
+    # GF(128) and GF(256) are covered for check and variable degrees up to 4 only
+    code = S.random_regular_nb_code(18, 6, 2, 6, 128, S.PRIM_POLY[128], seed=1)
     h = L.Code(code)
-    gam = torch.zeros((2, 16, 128), dtype=torch.int16, device=DEV)
+    gam = torch.zeros((2, 18, 128), dtype=torch.int16, device=DEV)
     with pytest.raises(L.LdpcxError) as ei:
         L.decode(h, L.params("spa", max_iters=2), gam)
     assert ei.value.status == L.E_UNSUPPORTED
@@ -746,3 +747,38 @@ def test_minmax_batch_sliced_for_31_bit_offsets(sched):
     ref = _ref(code, d, sample)
     assert (hard.cpu().numpy()[idx] == ref["hard"]).all()
     assert (ok.cpu().numpy()[idx] == ref["ok"]).all() and (it.cpu().numpy()[idx] == ref["iters"]).all()
+
+
+@pytest.mark.parametrize("g_size,n,dv,dc,batch,early,iters,ebn0", [
+    (128, 16, 2, 4, 13, True, 4, 1.5), (128, 32, 2, 4, 9, False, 3, 2.0), (256, 16, 2, 4, 7, True, 3, 1.5),
+    (256, 24, 3, 4, 5, False, 2, 1.0), (128, 24, 2, 3, 6, True, 3, 1.0), (256, 16, 2, 4, 6, False, 3, 9.0)])
+def test_spa_large_fields_match_oracle(g_size, n, dv, dc, batch, early, iters, ebn0):
+    """FFT-SPA over GF(128) and GF(256) (check and variable degrees up to 4): decisions,
+    flags, iteration counts and every u / v' message equal the oracle's.  The 9 dB case
+    gives confident messages whose inverse-transform sums reach g 2^24 (beyond 32 bits)."""
+    m = n * dv // dc
+    code = S.random_regular_nb_code(n, m, dv, dc, g_size, S.PRIM_POLY[g_size], seed=g_size + n + 7 * dc)
+    cw = S.random_codewords(code, batch, seed=29)
+    gam = S.nb_gamma_int16(cw, g_size, ebn0, seed=30)
+    prm = dict(rule="spa", schedule="flooding", max_iters=iters, early_stop=early)
+    h = L.Code(code)
+    assert L.plan_info(h, L.params(**prm), batch)["family"] == "spa_wave"
+    g = _gpu(h, prm, gam, dump=True)
+    ref = O.decode_spa(code, O.params(**prm), gam, dump=True)
+    _check_decisions(code, g, ref)
+    assert (g[3].astype(np.int64) == ref["u"]).all(), "u messages differ"
+    assert (g[4].astype(np.int64) == ref["v"]).all(), "v' messages differ"
+    g2 = _gpu(h, prm, gam)  # fused flooding for degree-2 variables (no dump)
+    _check_decisions(code, g2, ref)
+
+
+def test_spa_large_field_tied_channel():
+    """All symbol costs zero over GF(256): the channel weights sum to 256 2^24 = 2^32, and
+    the normalised channel vector must still be the uniform 2^24 / 256 of the oracle."""
+    code = S.random_regular_nb_code(16, 8, 2, 4, 256, S.PRIM_POLY[256], seed=3)
+    gam = np.zeros((3, 16, 256), dtype=np.int16)
+    prm = dict(rule="spa", schedule="flooding", max_iters=2, early_stop=False)
+    g = _gpu(L.Code(code), prm, gam, dump=True)
+    ref = O.decode_spa(code, O.params(**prm), gam, dump=True)
+    _check_decisions(code, g, ref)
+    assert (g[3].astype(np.int64) == ref["u"]).all() and (g[4].astype(np.int64) == ref["v"]).all()
