@@ -241,6 +241,13 @@ ldpcx_status run_wide(const ldpcx_job *jobs, std::vector<WideJob> &wide, hipStre
 
 }  // namespace
 
+bool ragged_nb1_items(const ldpcx_code *c, const ldpcx_decode_params *p) {
+    const int amax = nb_amax(p);
+    const size_t cap = (size_t)device_info(c->device).lds_per_block - kStaticLds;
+    return p->rule == LDPCX_RULE_MINMAX && nb1_supported(c->dev, amax) && c->dev.m >= 32 &&
+           nb1_lds_bytes(c->dev, amax) <= cap;
+}
+
 }  // namespace ldpcx
 
 using namespace ldpcx;
@@ -299,8 +306,7 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
             if (c->g > 2) {
                 // Min-Max: one codeword per item when its messages fit a workgroup and the
                 // code has enough checks to occupy the workgroup's lanes
-                if (p.rule == LDPCX_RULE_MINMAX && nb1_supported(D.C, D.amax) && D.C.m >= 32 &&
-                    nb1_lds_bytes(D.C, D.amax) <= cap) {
+                if (ragged_nb1_items(c, &p)) {
                     D.family = FAMILY_NB1;
                     add(I_NB1, jb.batch, nb1_lds_bytes(D.C, D.amax));
                     continue;

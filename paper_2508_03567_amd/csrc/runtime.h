@@ -77,6 +77,9 @@ ldpcx_status check_params(const ldpcx_code *c, const ldpcx_decode_params *p);
 ldpcx_status check_device(const ldpcx_code *c);
 BinRule bin_rule(const ldpcx_decode_params *p);
 int nb_amax(const ldpcx_decode_params *p);  // Min-Max message bound of the params
+// Whether the ragged decode runs this Min-Max job's codewords as one-codeword items of
+// its persistent kernel (any schedule) rather than as a whole-device decode
+bool ragged_nb1_items(const ldpcx_code *c, const ldpcx_decode_params *p);
 Plan default_plan(const ldpcx_code *c, const ldpcx_decode_params *p, int batch);
 Plan plan_for(ldpcx_code *c, const ldpcx_decode_params *p, int batch);
 uint64_t tune_key(const ldpcx_decode_params *p, int batch);

@@ -5,8 +5,9 @@
 // the device-memory budget allows, splitting a request that only partly fits at
 // a codeword boundary, and launches the admitted chunks together: one pinned
 // staging copy of the inputs, one ragged persistent launch for the codes whose
-// state fits a workgroup (long interleaved-layout codes and large Min-Max chunks
-// get their own launch sequence on the same stream), one copy of the outputs
+// state fits a workgroup, Min-Max codewords included whatever their number and
+// schedule (long interleaved-layout codes, FFT-SPA and Min-Max codes too large for
+// one-codeword items get their own launch sequence on the same stream), one copy of the outputs
 // back, and an event.  Launches on different slots overlap on the device, so a
 // request that arrives while others run starts without waiting for them.
 // Completed launches are retired by polling their events: outputs are copied to
@@ -14,7 +15,8 @@
 //
 // Every chunk is planned at its own size when it is admitted (the autotuner's choice
 // can differ between batch classes); its budget charge counts that plan's workspace
-// and its launch runs that exact plan.
+// and its launch runs that exact plan.  Min-Max codewords that run as one-codeword
+// items need no workspace and are charged their inputs and outputs only.
 //
 // Failure handling: a launch whose staging, enqueue or device work fails finishes the
 // requests of its chunks with that status (LDPCX_E_DEVICE for a device fault) and
@@ -42,8 +44,8 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-// Interleaved-family chunks with at least this many groups of 64 codewords run as
-// their own launch sequence (parallel over checks and codewords), not as per-group
+// Min-Max chunks of the interleaved family (codes too large for one-codeword items)
+// with at least this many groups of 64 codewords run as their own launch sequence (parallel over checks and codewords), not as per-group
 // ragged items (one workgroup per 64 codewords).
 constexpr int kOwnLaunchGroups = 2;
 // A ragged launch stops taking chunks once its estimated device time reaches this,
@@ -64,6 +66,7 @@ struct Request {
     int16_t *it = nullptr;
     size_t in_cw = 0, out_cw = 0;  // bytes per codeword of llr / hard
     int family = FAMILY_BIN_LDS;
+    bool nb_items = false;  // Min-Max codewords that run as one-codeword items of ragged launches
     int next_cw = 0;   // first codeword not yet admitted
     int done_cw = 0;   // codewords whose outputs are in host memory
     int inflight = 0;  // chunks on the device
@@ -103,6 +106,7 @@ size_t io_bytes(const Request &r, int ncw) {
 // Device bytes one chunk of `ncw` codewords holds while in flight, on the plan it runs
 // at that size.
 size_t chunk_bytes(const Request &r, int ncw) {
+    if (r.nb_items) return io_bytes(r, ncw);  // decoded in place, all state in LDS
     const Plan pl = plan_for(r.code, &r.prm, std::max(1, ncw));
     size_t b = io_bytes(r, ncw) + work_bytes(r.code, &r.prm, pl, ncw);
     // a chunk of a whole-device family inside a ragged batch is decoded from a gathered copy
@@ -114,12 +118,13 @@ size_t chunk_bytes(const Request &r, int ncw) {
 // edge updates per microsecond per family, from the kernels' measured throughput.
 double est_us(const Request &r, int ncw) {
     const double work = (double)ncw * std::max(1, r.prm.max_iters) * r.code->dev.E;
-    switch (r.family) {
+    switch (r.nb_items ? FAMILY_NB1 : r.family) {
     case FAMILY_BIN_QC: return work / 2.5e6;
     case FAMILY_BIN_LDS: return work / 1.0e6;
     case FAMILY_BIN_IL: return work / 1.1e6;
     case FAMILY_SPA:
     case FAMILY_SPA_LDS: return work * ((double)r.code->g / 64.0) / 2.0e4;
+    case FAMILY_NB1: return work * ((double)r.code->g * r.code->g / 4096.0) / 3.0e3;
     default: return work * ((double)r.code->g * r.code->g / 4096.0) / 3.0e3;
     }
 }
@@ -205,7 +210,7 @@ struct ldpcx_server {
             Request &r = reqs.at(id);
             const bool own = cfg.mode == LDPCX_SERVE_PER_REQUEST || r.family == FAMILY_BIN_IL || r.family == FAMILY_SPA ||
                              r.family == FAMILY_SPA_LDS ||
-                             ((r.family == FAMILY_NB || r.family == FAMILY_NB_LDS) &&
+                             ((r.family == FAMILY_NB || r.family == FAMILY_NB_LDS) && !r.nb_items &&
                               (r.code->g > 64 || r.prm.schedule != LDPCX_SCHED_FLOODING ||
                                pad64(r.batch - r.next_cw) / 64 >= kOwnLaunchGroups));
             // A launch is either one chunk with its own launch sequence or a ragged batch.
@@ -490,6 +495,9 @@ ldpcx_status ldpcx_server_submit(ldpcx_server *srv, const ldpcx_code *code, cons
         r.in_cw = c->g == 2 ? (size_t)n : (size_t)n * c->g * 2;
         r.out_cw = c->g == 2 ? (size_t)(n + 7) / 8 : (size_t)n;
         r.family = plan_for(c, params, std::max(1, batch)).family;
+        // Min-Max codes whose codewords are items of the persistent kernel (one codeword
+        // per item, any schedule) always join the ragged launches
+        r.nb_items = srv->cfg.mode != LDPCX_SERVE_PER_REQUEST && ragged_nb1_items(c, params);
         if (batch > 0 && chunk_bytes(r, 1) > srv->cfg.hbm_budget)
             return fail(LDPCX_E_BUDGET, "one codeword does not fit the server's memory budget");
         std::lock_guard<std::mutex> lk(srv->mu);

@@ -127,17 +127,25 @@ def test_budget_rejection():
         assert ei.value.status == L.E_BUDGET
 
 
-def test_layered_minmax_requests():
-    """Layered Min-Max requests run as launches of their own next to ragged batches of
-    other requests; each result equals a plain decode of the request alone."""
+@pytest.mark.parametrize("mode,budget", [("continuous", 256 << 20), ("continuous", 4 << 20), ("per_request", 256 << 20)])
+def test_layered_minmax_requests(mode, budget):
+    """Min-Max requests of either schedule and any size join the ragged launches as
+    one-codeword items (split across launches when the budget is small; launches of
+    their own in per-request mode); each result equals a plain decode of the request
+    alone."""
     w3, pool3 = _pool(3, 512)
     w0, pool0 = _pool(0, 512)
     lay = L.params("minmax", "layered", 8, True)
     reqs = [(3, lay, np.ascontiguousarray(pool3[:100])), (0, _prm(w0), np.ascontiguousarray(pool0[:30])),
-            (3, lay, np.ascontiguousarray(pool3[100:103])), (3, _prm(w3, 8), np.ascontiguousarray(pool3[200:240]))]
-    with L.Server(hbm_budget=256 << 20, max_inflight=3) as srv:
+            (3, lay, np.ascontiguousarray(pool3[100:103])), (3, _prm(w3, 8), np.ascontiguousarray(pool3[200:240])),
+            (3, _prm(w3, 6), np.ascontiguousarray(pool3[:512])), (3, lay, np.ascontiguousarray(pool3[:300]))]
+    with L.Server(hbm_budget=budget, max_inflight=3, mode=mode) as srv:
         tickets = [srv.submit(_code(cfg), prm, llr) for cfg, prm, llr in reqs]
         outs = [srv.wait(t, timeout_ms=120000) for t in tickets]
+        st = srv.stats()
+    assert st["peak_bytes"] <= budget
+    if budget < (8 << 20):
+        assert st["launches"] >= 3  # 812 Min-Max codewords of 24 KB input each
     for (cfg, prm, llr), (hard, ok, it, _) in zip(reqs, outs):
         h2, ok2, it2 = _alone(cfg, prm, llr)
         assert (hard == h2).all() and (ok == ok2).all() and (it == it2).all()
