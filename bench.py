@@ -121,6 +121,7 @@ def main() -> None:
                     help="pin the launch plan instead of tuning: family[:cw_per_wg[:threads]], e.g. bin_interleaved:256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-e2e", action="store_true", help="skip the end-to-end (PCIe-inclusive) leg")
+    ap.add_argument("--e2e-chunks", type=int, default=4, help="chunks of the overlapped end-to-end leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle time")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one 256 MiB device-to-device copy (counter calibration)")
@@ -268,20 +269,43 @@ def main() -> None:
         e2e = {"info_gbit_s": round(w.info_bits_per_cw * w.batch / (e2e_ms * 1e-3) / 1e9, 4),
                "ms_per_batch": round(e2e_ms, 4), "steps": e2e_steps,
                "what": "pinned host LLRs -> device, decode, outputs -> pinned host"}
-        # The same in 4 chunks on 2 streams, so one chunk's copies overlap another's decode.
-        chunks = [(c0, min(w.batch, c0 + (w.batch + 3) // 4)) for c0 in range(0, w.batch, (w.batch + 3) // 4)]
-        streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+        # The same in chunks on three streams (inputs in, decode, outputs out), chained by
+        # per-chunk events: the input copies run back to back while earlier chunks decode,
+        # and each chunk's outputs go back while later chunks decode.  A chunk's device
+        # buffers are reused by the next pass only after its decode / output copy of this
+        # pass has finished.  The events are created once and re-recorded every pass (a
+        # new event per record, and more than four chunks, left the host blocked in the
+        # copy calls for milliseconds per pass).
+        nch = max(1, args.e2e_chunks)
+        step_cw = (w.batch + nch - 1) // nch
+        chunks = [(c0, min(w.batch, c0 + step_cw)) for c0 in range(0, w.batch, step_cw)]
+        s_in, s_dec, s_out = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
         outs = [[o[a:b] for o in out] for a, b in chunks]
         hosts = [[ho[a:b] for ho in host_out] for a, b in chunks]
+        ev_in, ev_dec, ev_out = ([torch.cuda.Event() for _ in chunks] for _ in range(3))
+        passes = [0]
 
         def pipelined():
+            later = passes[0] > 0  # the previous pass's decode / output copy of a chunk is pending
             for i, (a, b) in enumerate(chunks):
-                st = streams[i % 2]
-                with torch.cuda.stream(st):
+                if later:
+                    s_in.wait_event(ev_dec[i])
+                with torch.cuda.stream(s_in):
                     llr_dev[a:b].copy_(llr_host[a:b], non_blocking=True)
-                    L.decode(code, prm, llr_dev[a:b], stream=st, out=outs[i])
+                ev_in[i].record(s_in)
+            for i, (a, b) in enumerate(chunks):
+                s_dec.wait_event(ev_in[i])
+                if later:
+                    s_dec.wait_event(ev_out[i])
+                L.decode(code, prm, llr_dev[a:b], stream=s_dec, out=outs[i])
+                ev_dec[i].record(s_dec)
+            for i in range(len(chunks)):
+                s_out.wait_event(ev_dec[i])
+                with torch.cuda.stream(s_out):
                     for ho, o in zip(hosts[i], outs[i]):
                         ho.copy_(o, non_blocking=True)
+                ev_out[i].record(s_out)
+            passes[0] += 1
 
         pipelined()  # warm-up: one graph per chunk
         torch.cuda.synchronize()
@@ -292,7 +316,8 @@ def main() -> None:
         ov_ms = (time.perf_counter() - t2) * 1e3 / e2e_steps
         e2e["overlapped_info_gbit_s"] = round(w.info_bits_per_cw * w.batch / (ov_ms * 1e-3) / 1e9, 4)
         e2e["overlapped_ms_per_batch"] = round(ov_ms, 4)
-        e2e["overlapped_what"] = "4 chunks on 2 streams: copies of one chunk overlap the decode of another"
+        e2e["overlapped_what"] = (f"{len(chunks)} chunks on three streams (inputs in, decode, outputs out): "
+                                  "copies of one chunk overlap the decode of others")
 
     if args.calib_copy:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.int32, device=dev)

@@ -37,6 +37,7 @@
 #include <map>
 #include <thread>
 
+#include "admit.h"
 #include "runtime.h"
 
 namespace ldpcx {
@@ -45,8 +46,9 @@ namespace {
 using Clock = std::chrono::steady_clock;
 
 // Min-Max chunks of the interleaved family (codes too large for one-codeword items)
-// with at least this many groups of 64 codewords run as their own launch sequence (parallel over checks and codewords), not as per-group
-// ragged items (one workgroup per 64 codewords).
+// with at least this many groups of 64 codewords run as their own launch sequence
+// (parallel over checks and codewords), not as per-group ragged items (one workgroup
+// per 64 codewords).
 constexpr int kOwnLaunchGroups = 2;
 // A ragged launch stops taking chunks once its estimated device time reaches this,
 // so that launches stay short and the slots pipeline.
@@ -56,10 +58,9 @@ constexpr double kLaunchTargetUs = 1500.0;
 // requests behind it are not held for its whole decode.
 constexpr double kOwnChunkTargetUs = 4000.0;
 
-struct Request {
+struct Request : admit::Req {
     ldpcx_code *code = nullptr;
     ldpcx_decode_params prm{};
-    int batch = 0;
     const char *llr = nullptr;
     char *hard = nullptr;
     uint8_t *ok = nullptr;
@@ -67,12 +68,16 @@ struct Request {
     size_t in_cw = 0, out_cw = 0;  // bytes per codeword of llr / hard
     int family = FAMILY_BIN_LDS;
     bool nb_items = false;  // Min-Max codewords that run as one-codeword items of ragged launches
-    int next_cw = 0;   // first codeword not yet admitted
     int done_cw = 0;   // codewords whose outputs are in host memory
     int inflight = 0;  // chunks on the device
     bool done = false, released = false;
     ldpcx_status status = LDPCX_OK;
     double t_submit = 0, t_admit = -1, t_done = 0;
+
+    bool own() const override;
+    int unit() const override;
+    size_t bytes(int n) const override;
+    double us(int n) const override;
 };
 
 struct Chunk {
@@ -129,17 +134,17 @@ double est_us(const Request &r, int ncw) {
     }
 }
 
-// Largest n in [0, cap] with chunk_bytes(r, n) <= avail (monotone in n).
-int max_fit(const Request &r, int cap, size_t avail) {
-    if (cap <= 0 || chunk_bytes(r, 1) > avail) return 0;
-    int lo = 1, hi = cap;
-    while (lo < hi) {
-        const int mid = lo + (hi - lo + 1) / 2;
-        if (chunk_bytes(r, mid) <= avail) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
+bool Request::own() const {
+    return family == FAMILY_BIN_IL || family == FAMILY_SPA || family == FAMILY_SPA_LDS ||
+           ((family == FAMILY_NB || family == FAMILY_NB_LDS) && !nb_items &&
+            (code->g > 64 || prm.schedule != LDPCX_SCHED_FLOODING || pad64(batch - next_cw) / 64 >= kOwnLaunchGroups));
 }
+
+int Request::unit() const { return family == FAMILY_BIN_IL ? bin_il_sub_batch(code->dev, batch - next_cw, 0) : 64; }
+
+size_t Request::bytes(int n) const { return chunk_bytes(*this, n); }
+
+double Request::us(int n) const { return est_us(*this, n); }
 
 bool grow_pinned(char *&p, size_t &cap, size_t need) {
     if (need <= cap) return true;
@@ -201,56 +206,30 @@ struct ldpcx_server {
 
     // Take the chunks of the next launch (mu held).
     std::vector<Chunk> form(bool others_in_flight) {
-        std::vector<Chunk> take;
-        size_t charge = 0;
-        int cw_total = 0;
-        double us = 0;
-        while (!queue.empty()) {
-            const uint64_t id = queue.front();
-            Request &r = reqs.at(id);
-            const bool own = cfg.mode == LDPCX_SERVE_PER_REQUEST || r.family == FAMILY_BIN_IL || r.family == FAMILY_SPA ||
-                             r.family == FAMILY_SPA_LDS ||
-                             ((r.family == FAMILY_NB || r.family == FAMILY_NB_LDS) && !r.nb_items &&
-                              (r.code->g > 64 || r.prm.schedule != LDPCX_SCHED_FLOODING ||
-                               pad64(r.batch - r.next_cw) / 64 >= kOwnLaunchGroups));
-            // A launch is either one chunk with its own launch sequence or a ragged batch.
-            if (own && !take.empty()) break;
-            if (!take.empty() && us >= kLaunchTargetUs) break;
-            const int rem = r.batch - r.next_cw;
-            int cap = rem;
-            if (cfg.max_launch_cw > 0) cap = std::min(cap, cfg.max_launch_cw - cw_total);
-            if (own && cfg.mode == LDPCX_SERVE_CONTINUOUS) {
-                const double per_cw = est_us(r, 1024) / 1024.0;
-                int lim = (int)(kOwnChunkTargetUs / std::max(per_cw, 1e-3));
-                const int unit = r.family == FAMILY_BIN_IL ? bin_il_sub_batch(r.code->dev, rem, 0) : 64;
-                lim = std::max(unit, lim / unit * unit);
-                cap = std::min(cap, lim);
-            }
-            if (cap <= 0) break;
-            const size_t avail = cfg.hbm_budget - in_use - charge;
-            const int n = max_fit(r, cap, avail);
-            if (n == 0) break;
-            // Do not split off a small piece while memory is about to be released.
-            if (n < rem && n < 64 && n < cap && (others_in_flight || !take.empty())) break;
+        admit::Config ac;
+        ac.continuous = cfg.mode == LDPCX_SERVE_CONTINUOUS;
+        ac.max_launch_cw = cfg.max_launch_cw;
+        ac.budget = cfg.hbm_budget;
+        ac.launch_target_us = kLaunchTargetUs;
+        ac.own_chunk_target_us = kOwnChunkTargetUs;
+        const std::vector<admit::Take> takes = admit::form(
+            queue, [&](uint64_t id) -> admit::Req & { return reqs.at(id); }, ac, in_use, others_in_flight);
+        std::vector<Chunk> out;
+        out.reserve(takes.size());
+        for (const admit::Take &t : takes) {
+            Request &r = reqs.at(t.id);
             Chunk c;
-            c.id = id;
-            c.cw0 = r.next_cw;
-            c.ncw = n;
-            c.plan = plan_for(r.code, &r.prm, n);
-            c.charge = chunk_bytes(r, n);
-            c.own_launch = own;
-            take.push_back(c);
-            us += est_us(r, n);
-            r.next_cw += n;
+            c.id = t.id;
+            c.cw0 = t.cw0;
+            c.ncw = t.ncw;
+            c.plan = plan_for(r.code, &r.prm, t.ncw);
+            c.charge = t.charge;
+            c.own_launch = t.own;
             r.inflight += 1;
             if (r.t_admit < 0) r.t_admit = now_us();
-            charge += c.charge;
-            cw_total += n;
-            if (r.next_cw < r.batch) break;  // arrival order: nothing passes a partly admitted request
-            queue.pop_front();
-            if (own) break;
+            out.push_back(c);
         }
-        return take;
+        return out;
     }
 
     // Stage inputs and enqueue the launch of slot `sl` (mu not held).
