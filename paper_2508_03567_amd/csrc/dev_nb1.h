@@ -27,6 +27,18 @@
 // The permutation by the edge coefficient (eqs. (7)-(8), (11)-(12)) is folded into the
 // LDS gathers and scatters of each edge's row: entry t of the permuted vector is entry
 // h^-1 t of the stored one.
+//
+// Codes whose variables all have degree 2 (the (2, dc)-regular codes of the GF(q)
+// workloads) can run without stored alphas ("alpha-free"): the alpha of edge e is then
+// gamma' plus the beta of its variable's other edge e', shifted to minimum 0 and
+// clipped (eqs. (14)-(15)), so the check node forms it from gamma' and beta at the
+// permuted positions it would have read.  The LDS per codeword drops by one message
+// array (GF(64), n = 192, 16-bit: 78 KB instead of 125 KB, two codewords per compute
+// unit).  Flooding keeps every check's inputs of iteration k in registers across a
+// barrier before any beta of iteration k is written (each segment holds at most two
+// checks); the layers of the layered schedule share no variable, so a check there
+// reads only betas that no other check of its layer writes.  The results are those of
+// the stored-alpha decoder, message for message.
 #pragma once
 
 #include "dev_common.h"
@@ -53,17 +65,18 @@ struct Geo {
 };
 
 struct Layout {
-    size_t gam, alpha, beta, mul, hinv, h, hard, flags, total;
+    size_t gam, alpha, beta, mul, hinv, h, hard, flags, vt, total;
 };
 
-__host__ __device__ inline Layout layout(const DevCode &C, int mb) {
+// af: alpha-free (no alpha array; a [E] table of (variable, other edge) instead).
+__host__ __device__ inline Layout layout(const DevCode &C, int mb, bool af = false) {
     const size_t G = (size_t)C.g;
     Layout L;
     size_t o = 0;
     L.gam = o;
     o = align_up(o + mb * (size_t)C.n * G, 16);
     L.alpha = o;
-    o = align_up(o + mb * (size_t)C.E * G, 16);
+    if (!af) o = align_up(o + mb * (size_t)C.E * G, 16);
     L.beta = o;
     o = align_up(o + mb * (size_t)C.E * G, 16);
     L.mul = o;
@@ -76,6 +89,8 @@ __host__ __device__ inline Layout layout(const DevCode &C, int mb) {
     o = align_up(o + (size_t)C.n, 16);
     L.flags = o;
     o += 16;
+    L.vt = o;
+    if (af) o = align_up(o + 4 * (size_t)C.E, 16);
     L.total = o;
     return L;
 }
@@ -196,14 +211,10 @@ __device__ __forceinline__ void store_deperm(M *msg, const uint8_t *mul, int hin
 // the betas of the middle edges from F_{j-1} and B_{j+1}; F at the last edge and B at
 // the first are never used by the outputs and are not formed.
 template <int G, int DC, class M>
-__device__ __forceinline__ void check(const DevCode &C, const M *al, M *bl, const uint8_t *mul,
-                                      const uint8_t *hinvl, int r, int j) {
+__device__ __forceinline__ void check_out(const v2s (&a)[DC][Geo<G>::H], M *bl, const uint8_t *mul,
+                                          const uint8_t *hinvl, int e0, int dc, int j) {
     constexpr int H = Geo<G>::H;
-    const int e0 = C.row_ptr[r], dc = C.row_ptr[r + 1] - e0;
-    v2s a[DC][H], F[DC][H], Bv[H], t[H];
-#pragma unroll
-    for (int q = 0; q < DC; ++q)
-        if (q < dc) load_perm<G, M>(al, mul, hinvl[e0 + q], e0 + q, j, a[q]);
+    v2s F[DC][H], Bv[H], t[H];
 #pragma unroll
     for (int p = 0; p < H; ++p) F[0][p] = a[0][p];
 #pragma unroll
@@ -227,6 +238,59 @@ __device__ __forceinline__ void check(const DevCode &C, const M *al, M *bl, cons
             for (int p = 0; p < H; ++p) Bv[p] = t[p];
         }
     store_deperm<G, M>(bl, mul, hinvl[e0], e0, j, Bv);
+}
+
+template <int G, int DC, class M>
+__device__ __forceinline__ void check(const DevCode &C, const M *al, M *bl, const uint8_t *mul,
+                                      const uint8_t *hinvl, int r, int j) {
+    const int e0 = C.row_ptr[r], dc = C.row_ptr[r + 1] - e0;
+    v2s a[DC][Geo<G>::H];
+#pragma unroll
+    for (int q = 0; q < DC; ++q)
+        if (q < dc) load_perm<G, M>(al, mul, hinvl[e0 + q], e0 + q, j, a[q]);
+    check_out<G, DC, M>(a, bl, mul, hinvl, e0, dc, j);
+}
+
+// alpha~ of edge e (variable v, whose other edge is eo) at the lane's permuted positions,
+// formed from the stored gamma' and beta_eo (alpha-free decoding): the minimum over
+// the vector does not depend on the permutation.  first: alpha^(0) = gamma' itself.
+template <int G, class M>
+__device__ __forceinline__ void alpha_fly(const M *gl, const M *bl, const uint8_t *mul, int hinv, int v, int eo,
+                                          int j, int amax, bool first, v2s (&out)[Geo<G>::H]) {
+    constexpr int R = Geo<G>::R, S = Geo<G>::S, H = Geo<G>::H;
+    uint8_t pos[R];
+    perm_pos<G>(mul, hinv, j, pos);
+    const M *gv = gl + (size_t)v * G, *be = bl + (size_t)eo * G;
+    int s[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) s[i] = (int)gv[pos[i]];
+    if (!first) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) s[i] += (int)be[pos[i]];
+        int mn = s[0];
+#pragma unroll
+        for (int i = 1; i < R; ++i) mn = min(mn, s[i]);
+        mn = seg_min<S>(mn);
+#pragma unroll
+        for (int i = 0; i < R; ++i) s[i] = min(s[i] - mn, amax);
+    }
+#pragma unroll
+    for (int p = 0; p < H; ++p) out[p] = (v2s){(short)s[2 * p], (short)s[2 * p + 1]};
+}
+
+// Inputs alpha~ of check r's edges, formed on the fly (alpha-free decoding); vt[e] holds
+// (variable of e) | (other edge of that variable) << 16.
+template <int G, int DC, class M>
+__device__ __forceinline__ void load_fly(const DevCode &C, const M *gl, const M *bl, const uint8_t *mul,
+                                         const uint8_t *hinvl, const uint32_t *vt, int r, int j, int amax, bool first,
+                                         v2s (&a)[DC][Geo<G>::H]) {
+    const int e0 = C.row_ptr[r], dc = C.row_ptr[r + 1] - e0;
+#pragma unroll
+    for (int q = 0; q < DC; ++q)
+        if (q < dc) {
+            const uint32_t w = vt[e0 + q];
+            alpha_fly<G, M>(gl, bl, mul, hinvl[e0 + q], (int)(w & 0xFFFFu), (int)(w >> 16), j, amax, first, a[q]);
+        }
 }
 
 // Sum of gamma' and the betas of variable v's edges (all, or all but edge `skip`), for
@@ -296,15 +360,18 @@ __device__ __forceinline__ bool syndrome_ok(const DevCode &C, const uint8_t *mul
 
 // The whole decode of codeword b by the calling workgroup (any multiple of 64 threads),
 // messages stored as M (uint16_t, or uint8_t when the bound is at most 255).  Ends with
-// a barrier, so the caller may reuse the LDS right after.
-template <int G, int DC, class M>
+// a barrier, so the caller may reuse the LDS right after.  AF: alpha-free decoding
+// (every variable of degree 2; flooding needs at most two checks per segment, and the
+// debug dump is only taken with flooding).
+template <int G, int DC, class M, bool AF = false>
 __device__ __forceinline__ void decode_cw(const Job &J, int b, unsigned char *lds) {
-    constexpr int S = Geo<G>::S, VPW = Geo<G>::VPW;
+    constexpr int S = Geo<G>::S, VPW = Geo<G>::VPW, H = Geo<G>::H, R = Geo<G>::R;
     const DevCode &C = J.C;
-    const Layout Y = layout(C, (int)sizeof(M));
+    const Layout Y = layout(C, (int)sizeof(M), AF);
     M *gl = (M *)(lds + Y.gam), *al = (M *)(lds + Y.alpha), *bl = (M *)(lds + Y.beta);
     uint8_t *mul = lds + Y.mul, *hinvl = lds + Y.hinv, *hl_h = lds + Y.h, *hard = lds + Y.hard;
     int *flags = (int *)(lds + Y.flags);
+    uint32_t *vt = (uint32_t *)(lds + Y.vt);
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63, seg = lane / S, j = lane % S;
     const int segs = (nthr >> 6) * VPW, myseg = wave_id() * VPW + seg;  // segments of the workgroup
@@ -319,10 +386,19 @@ __device__ __forceinline__ void decode_cw(const Job &J, int b, unsigned char *ld
         hl_h[i] = C.h[i];
     }
     if (tid < 4) flags[tid] = 0;
+    if (AF) {
+        for (int v = tid; v < C.n; v += nthr) {
+            const int t = C.vn_ptr[v], e0 = C.vn_ref[t], e1 = C.vn_ref[t + 1];
+            vt[e0] = (uint32_t)v | ((uint32_t)e1 << 16);
+            vt[e1] = (uint32_t)v | ((uint32_t)e0 << 16);
+        }
+    }
     __syncthreads();
     for (int i = tid; i < C.E * G; i += nthr) {
-        const int e = i / G, x = i - e * G;
-        al[i] = gl[(size_t)C.col_idx[e] * G + x];
+        if (!AF) {
+            const int e = i / G, x = i - e * G;
+            al[i] = gl[(size_t)C.col_idx[e] * G + x];
+        }
         bl[i] = 0;
     }
     __syncthreads();
@@ -338,7 +414,36 @@ __device__ __forceinline__ void decode_cw(const Job &J, int b, unsigned char *ld
             if (done) break;
         }
         const bool need_dec = J.early_stop || k == J.max_iters;
-        if (!J.layered) {
+        if (AF && !J.layered) {
+            // every check's inputs of this iteration (from the betas of the last) are in
+            // registers before any beta of this iteration is written
+            v2s a[2][DC][H];
+            const int r0 = myseg, r1 = myseg + segs;
+            if (r0 < C.m) load_fly<G, DC, M>(C, gl, bl, mul, hinvl, vt, r0, j, amax, k == 1, a[0]);
+            if (r1 < C.m) load_fly<G, DC, M>(C, gl, bl, mul, hinvl, vt, r1, j, amax, k == 1, a[1]);
+            __syncthreads();
+            if (r0 < C.m) check_out<G, DC, M>(a[0], bl, mul, hinvl, C.row_ptr[r0], C.row_ptr[r0 + 1] - C.row_ptr[r0], j);
+            if (r1 < C.m) check_out<G, DC, M>(a[1], bl, mul, hinvl, C.row_ptr[r1], C.row_ptr[r1 + 1] - C.row_ptr[r1], j);
+            __syncthreads();
+            if (need_dec) {
+                for (int v = myseg; v < C.n; v += segs) decide<G, M>(C, gl, bl, hard, v, j);
+                __syncthreads();
+            }
+        } else if (AF) {
+            for (int l = 0; l < C.nb_nl; ++l) {
+                for (int i = C.nbl_ptr[l] + myseg; i < C.nbl_ptr[l + 1]; i += segs) {
+                    const int r = C.nbl_chk[i];
+                    v2s a[DC][H];
+                    load_fly<G, DC, M>(C, gl, bl, mul, hinvl, vt, r, j, amax, false, a);
+                    check_out<G, DC, M>(a, bl, mul, hinvl, C.row_ptr[r], C.row_ptr[r + 1] - C.row_ptr[r], j);
+                }
+                __syncthreads();
+            }
+            if (need_dec) {
+                for (int v = myseg; v < C.n; v += segs) decide<G, M>(C, gl, bl, hard, v, j);
+                __syncthreads();
+            }
+        } else if (!J.layered) {
             for (int r = myseg; r < C.m; r += segs) check<G, DC, M>(C, al, bl, mul, hinvl, r, j);
             __syncthreads();
             for (int t = myseg; t < C.E; t += segs) {
@@ -375,9 +480,32 @@ __device__ __forceinline__ void decode_cw(const Job &J, int b, unsigned char *ld
     for (int v = tid; v < C.n; v += nthr) hout[v] = hard[v];
     if (J.io.dump_a) {
         int16_t *da = (int16_t *)J.io.dump_a + (size_t)b * C.E * G, *db = (int16_t *)J.io.dump_b + (size_t)b * C.E * G;
-        for (int i = tid; i < C.E * G; i += nthr) {
-            da[i] = (int16_t)al[i];
-            db[i] = (int16_t)bl[i];
+        if (AF) {
+            // the alphas the flooding decoder would hold now: gamma' plus the other edge's
+            // beta, normalised (gamma' itself before any iteration)
+            for (int e = myseg; e < C.E; e += segs) {
+                const uint32_t w = vt[e];
+                const M *gv = gl + (size_t)(w & 0xFFFFu) * G + R * j, *be = bl + (size_t)(w >> 16) * G + R * j;
+                int s[R];
+#pragma unroll
+                for (int i = 0; i < R; ++i) s[i] = (int)gv[i] + (it > 0 ? (int)be[i] : 0);
+                if (it > 0) {
+                    int mn = s[0];
+#pragma unroll
+                    for (int i = 1; i < R; ++i) mn = min(mn, s[i]);
+                    mn = seg_min<S>(mn);
+#pragma unroll
+                    for (int i = 0; i < R; ++i) s[i] = min(s[i] - mn, amax);
+                }
+#pragma unroll
+                for (int i = 0; i < R; ++i) da[(size_t)e * G + R * j + i] = (int16_t)s[i];
+            }
+            for (int i = tid; i < C.E * G; i += nthr) db[i] = (int16_t)bl[i];
+        } else {
+            for (int i = tid; i < C.E * G; i += nthr) {
+                da[i] = (int16_t)al[i];
+                db[i] = (int16_t)bl[i];
+            }
         }
     }
     __syncthreads();

@@ -180,6 +180,8 @@ hipError_t launch_nb(const DevCode &C, int max_iters, int early_stop, int layere
 // 8 bits when the bound amax is at most 255, else in 16 bits.
 size_t nb1_lds_bytes(const DevCode &C, int amax);
 bool nb1_supported(const DevCode &C, int amax);
+// Whether launch_nb1 decodes alpha-free (no stored alphas) for these arguments.
+bool nb1_alpha_free(const DevCode &C, int layered, bool dump, int threads);
 hipError_t launch_nb1(const DevCode &C, int max_iters, int early_stop, int layered, int batch, int amax, int threads,
                       const DecodeIO &io, hipStream_t s);
 // Field sizes with a compiled Min-Max kernel (4..64 interleaved, 128 and 256 wide).

@@ -31,8 +31,17 @@ def _run(code, gam, d, threads, dump=True):
     return [o.cpu().numpy() for o in out]
 
 
-def _check(code, got, d, gam, dump=True):
-    ref = O.decode_nb(code, O.params(**d), gam, dump=dump)
+_REF = {}
+
+
+def _check(code, got, d, gam, dump=True, key=None):
+    """key: cache the oracle's result under it (same code and inputs)."""
+    if key is not None and key in _REF:
+        ref = _REF[key]
+    else:
+        ref = O.decode_nb(code, O.params(**d), gam, dump=dump)
+        if key is not None:
+            _REF[key] = ref
     assert (got[0] == ref["hard"]).all(), "decisions differ"
     assert (got[1] == ref["ok"]).all(), "syndrome flags differ"
     assert (got[2] == ref["iters"]).all(), "iteration counts differ"
@@ -47,11 +56,29 @@ def _check(code, got, d, gam, dump=True):
 @pytest.mark.parametrize("bound", [0, 127])
 def test_gf64_workload_every_message(iters, sched, early, bound):
     """The GF(64) (2,4)-regular n = 192 code of the Min-Max workload, 1.5 dB; bound 127
-    runs the 8-bit message storage."""
+    runs the 8-bit message storage.  At 256 threads the alphas are stored; at 512 the
+    flooding decoder runs alpha-free (its dump recomputes the alphas from the betas)."""
     w = S.workload(3, batch=37, ebn0_db=1.5)
     _, gam = S.make_inputs(w)
     d = dict(rule="minmax", schedule=sched, max_iters=iters, early_stop=early, nb_msg_max=bound)
     _check(w.code, _run(w.code, gam, d, 256), d, gam)
+    _check(w.code, _run(w.code, gam, d, 512), d, gam)
+
+
+@pytest.mark.parametrize("threads", [384, 512, 768, 1024])
+@pytest.mark.parametrize("sched", ["flooding", "layered"])
+@pytest.mark.parametrize("bound", [0, 127])
+def test_gf64_alpha_free_outputs(threads, sched, bound):
+    """Alpha-free decoding (every variable of degree 2; flooding with at most two checks
+    per segment, layered without dump) at the thread counts that select it for the
+    workload code: decisions, flags and iteration counts of every codeword equal the
+    oracle's, over iteration caps and both early-stop settings."""
+    w = S.workload(3, batch=64, ebn0_db=2.0)
+    _, gam = S.make_inputs(w, seed_offset=3)
+    for iters, early in ((20, True), (7, False), (1, True)):
+        d = dict(rule="minmax", schedule=sched, max_iters=iters, early_stop=early, nb_msg_max=bound)
+        _check(w.code, _run(w.code, gam, d, threads, dump=False), d, gam, dump=False,
+               key=("af", sched, bound, iters, early))
 
 
 @pytest.mark.parametrize("g_size,n,dv,dc,batch,sched,threads,bound", [
