@@ -643,7 +643,7 @@ def precision_main(args) -> None:
             # bound needs (8 bits for 127): the storage half of the precision comparison.
             ms_cw = None
             if eb == 2.0:
-                L.plan_set(h, prm_fixed, w.batch, "minmax_cw", 1, 768)
+                L.plan_set(h, prm_fixed, w.batch, "minmax_cw", 1, 512)
                 L.decode(h, prm_fixed, gam, out=out)
                 torch.cuda.synchronize()
                 ev0.record(stream)

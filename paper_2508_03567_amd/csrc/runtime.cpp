@@ -151,8 +151,17 @@ Plan default_plan(const ldpcx_code *c, const ldpcx_decode_params *p, int batch) 
         return pl;
     }
     if (c->g > 2) {
-        pl.family = FAMILY_NB;
         pl.schedule = p->schedule == LDPCX_SCHED_LAYERED ? LDPCX_SCHED_LAYERED : LDPCX_SCHED_FLOODING;
+        // Codes whose variables all have degree 2 and with at least 32 checks: one codeword
+        // per workgroup, alpha-free at 512 threads (measured fastest on the GF(64) workload)
+        if (p->rule == LDPCX_RULE_MINMAX && c->dev.m >= 32 && nb1_supported(c->dev, nb_amax(p)) &&
+            nb1_alpha_free(c->dev, pl.schedule == LDPCX_SCHED_LAYERED, false, 512)) {
+            pl.family = FAMILY_NB1;
+            pl.cpw = 1;
+            pl.threads = 512;
+            return pl;
+        }
+        pl.family = FAMILY_NB;
         pl.cpw = 64;
         pl.threads = 256;
         // Short codes whose messages of 64 codewords fit in LDS: one workgroup per group,

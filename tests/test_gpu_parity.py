@@ -92,6 +92,26 @@ def test_every_message_matches_oracle(cfg, iters):
         assert (g[4].astype(np.int32) == ref["beta"]).all(), "beta messages differ"
 
 
+@pytest.mark.parametrize("early", [True, False])
+@pytest.mark.parametrize("iters", [1, 6])
+def test_gf64_workload_interleaved_family(early, iters):
+    """The interleaved Min-Max family on the GF(64) workload code (its fused flooding
+    without dump, the two-phase sequence with it): decisions, flags, iteration counts and
+    every message equal the oracle's."""
+    w = S.workload(3, batch=67)
+    cw, llr = S.make_inputs(w, seed_offset=19)
+    d = _prm(w, max_iters=iters, early_stop=early)
+    h = L.Code(w.code)
+    L.plan_set(h, L.params(**d), 67, "minmax_interleaved", 64, 256)
+    assert L.plan_info(h, L.params(**d), 67)["family"] == "minmax_interleaved"
+    ref = _ref(w.code, d, llr, dump=True)
+    _check_decisions(w.code, _gpu(h, d, llr), ref)
+    g = _gpu(h, d, llr, dump=True)
+    _check_decisions(w.code, g, ref)
+    assert (g[3].astype(np.int32) == ref["alpha"]).all(), "alpha messages differ"
+    assert (g[4].astype(np.int32) == ref["beta"]).all(), "beta messages differ"
+
+
 @pytest.mark.parametrize("family,cpw,threads", [("bin_lds", 1, 64), ("bin_lds", 3, 192), ("bin_lds", 5, 320),
                                                 ("bin_interleaved", 64, 256)])
 @pytest.mark.parametrize("rule", ["nms", "oms", "ms"])
