@@ -2,6 +2,8 @@
 // workgroup-level device function (see k_bin_qc.hip for the design).
 #pragma once
 
+#include <type_traits>
+
 #include "dev_common.h"
 
 namespace ldpcx {
@@ -166,49 +168,63 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
               if (act) {
                 int dc = __builtin_amdgcn_readfirstlane(Q.dc[l]);  // uniform by construction
                 asm volatile("" : "+s"(dc));
-                uint32_t vv[MD];
-                v2s lv[MD];
-                row_offs(l, vv);
+                // One straight-line body per layer-degree class, with DD edge slots (slots at
+                // or beyond the degree run as virtual edges).  Each step runs over all the
+                // slots before the next starts, so that the dependent packed operations of
+                // one edge are separated by those of the others (no hazard wait states).
+                auto layer = [&](auto dd_tag) {
+                    constexpr int DD = decltype(dd_tag)::value;
+                    uint32_t vv[MD], sv[MD], sr[MD];
+                    v2s qv[MD], nq[MD], av[MD], mg[MD];
+                    row_offs(l, vv);
 #pragma unroll
-                for (int j = 0; j < MD; ++j) lv[j] = as_v2s(lds_word(lamp, vv[j]));
-                v2s m1 = splat(0x7FFF), m2 = splat(0x7FFF);
-                uint32_t stot = 0;
-                v2s qv[MD], av[MD];
-                uint32_t sv[MD];
-#pragma unroll
-                for (int j = 0; j < MD; ++j) {
-                    // The last two edge slots are skipped (uniform branch) where the layer has
-                    // fewer edges; earlier slots beyond the degree run as virtual edges.
-                    if (j >= MD - 2 && j >= dc) continue;
+                    for (int j = 0; j < DD; ++j) qv[j] = as_v2s(lds_word(lamp, vv[j])) - r[l][j];
                     // |clamp(q, +-msg_max)| = min(|q|, msg_max); the sign of q is the sign of clamp(q)
-                    const v2s q = lv[j] - r[l][j];
-                    const uint32_t sg = as_u32(q >> splat(15));
-                    const v2s a = pmin(pmax(q, -q), mm);
-                    m2 = pmin(m2, pmax(m1, a));
-                    m1 = pmin(m1, a);
-                    stot ^= sg;
-                    qv[j] = q;
-                    av[j] = a;
-                    sv[j] = sg;
-                }
-                v2s f1, f2;
-                norm2(m1, m2, f1, f2);
-                // Magnitude out of edge j: f2 where the edge holds the minimum (a = m1), else f1.
-                // With all magnitudes in [0, 127] and 128 >= f2 - f1, that is
-                // max(f1, f2 + 128 (m1 - a)), exact in 16 bits (the sum lies in [-16256, 16383]).
-                const v2s cs = f2 - m1 * neg128;
 #pragma unroll
-                for (int j = 0; j < MD; ++j) {
-                    if (j >= MD - 2 && j >= dc) continue;
-                    const v2s mag = pmax(f1, av[j] * neg128 + cs);
-                    const uint32_t sr = stot ^ sv[j];
-                    const v2s rn = as_v2s(as_u32(mag) ^ sr) - as_v2s(sr);
-                    const v2s rk = ES ? as_v2s(bfi(M, as_u32(rn), as_u32(r[l][j]))) : rn;
-                    r[l][j] = rk;
-                    if (LAYERED) lds_word(lamp, vv[j]) = as_u32(qv[j] + rk);
-                }
-                // virtual edges wrote q + r into their dummy slot: restore it
-                if (LAYERED && dc < MD - 2) lamp[n + i0] = kDummy;
+                    for (int j = 0; j < DD; ++j) nq[j] = -qv[j];
+#pragma unroll
+                    for (int j = 0; j < DD; ++j) sv[j] = as_u32(qv[j] >> splat(15));
+#pragma unroll
+                    for (int j = 0; j < DD; ++j) av[j] = pmax(qv[j], nq[j]);
+#pragma unroll
+                    for (int j = 0; j < DD; ++j) av[j] = pmin(av[j], mm);
+                    v2s m1 = splat(0x7FFF), m2 = splat(0x7FFF);
+                    uint32_t stot = 0;
+#pragma unroll
+                    for (int j = 0; j < DD; ++j) {
+                        m2 = pmin(m2, pmax(m1, av[j]));
+                        m1 = pmin(m1, av[j]);
+                        stot ^= sv[j];
+                    }
+                    v2s f1, f2;
+                    norm2(m1, m2, f1, f2);
+                    // Magnitude out of edge j: f2 where the edge holds the minimum (a = m1), else
+                    // f1.  With all magnitudes in [0, 127] and 128 >= f2 - f1, that is
+                    // max(f1, f2 + 128 (m1 - a)), exact in 16 bits (the sum lies in [-16256, 16383]).
+                    const v2s cs = f2 - m1 * neg128;
+#pragma unroll
+                    for (int j = 0; j < DD; ++j) mg[j] = av[j] * neg128 + cs;
+#pragma unroll
+                    for (int j = 0; j < DD; ++j) sr[j] = stot ^ sv[j];
+#pragma unroll
+                    for (int j = 0; j < DD; ++j) mg[j] = pmax(f1, mg[j]);
+#pragma unroll
+                    for (int j = 0; j < DD; ++j) mg[j] = as_v2s(as_u32(mg[j]) ^ sr[j]);
+#pragma unroll
+                    for (int j = 0; j < DD; ++j) {
+                        const v2s rn = mg[j] - as_v2s(sr[j]);
+                        r[l][j] = ES ? as_v2s(bfi(M, as_u32(rn), as_u32(r[l][j]))) : rn;
+                    }
+                    if (LAYERED) {
+#pragma unroll
+                        for (int j = 0; j < DD; ++j) lds_word(lamp, vv[j]) = as_u32(qv[j] + r[l][j]);
+                        // virtual edges wrote q + r into their dummy slot: restore it
+                        if (dc < DD) lamp[n + i0] = kDummy;
+                    }
+                };
+                if (dc >= MD) layer(std::integral_constant<int, MD>{});
+                else if (dc == MD - 1) layer(std::integral_constant<int, MD - 1>{});
+                else layer(std::integral_constant<int, MD - 2>{});
               }
                 if (LAYERED) __syncthreads();
             }
