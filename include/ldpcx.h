@@ -208,9 +208,10 @@ typedef struct {
  * item, every message in LDS) and FFT-SPA codes of the LDS-resident family (one group of
  * codewords per item).  Workgroups claim items longest first from a device counter
  * (one atomic add per item, never a wait for another workgroup), so the load stays
- * balanced when codewords stop early.  The kernel runs as up to three launches on the
- * stream, one per kind of item (binary; GF(g) of check degree <= 4; Min-Max of larger
- * check degree), each with the occupancy its own registers and LDS allow.  Jobs whose
+ * balanced when codewords stop early.  The kernel runs as up to five launches on the
+ * stream, one per kind of item (binary; Min-Max of check degree <= 4, with or without
+ * stored alphas; Min-Max of larger check degree; FFT-SPA), each with the occupancy its
+ * own registers and LDS allow.  Jobs whose
  * state does not fit a workgroup (binary codes in the interleaved layout, GF(128) and
  * GF(256), larger codewords, FFT-SPA wave kernels) are gathered per (code, parameters,
  * resolved schedule) into one batch each and decoded by that batch's own launch

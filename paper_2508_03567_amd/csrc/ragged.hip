@@ -11,12 +11,14 @@
 //   - Min-Max over GF(4)..GF(64) whose messages of one codeword fit a workgroup's LDS:
 //     one item per codeword (lanes over field entries, every message in LDS);
 //   - FFT-SPA codes of the LDS-resident family: one item per group of codewords.
-// Items run as up to three launches of the persistent kernel, one after the other on
+// Items run as up to five launches of the persistent kernel, one after the other on
 // the stream, each an instance compiled for one kind of item: binary items (256
-// threads), GF(g) items of check degree <= 4 (1024 threads: one codeword's checks spread
-// over 16 waves) and Min-Max items of larger check degree (256 threads, for their larger
-// register arrays).  A kernel's register and LDS allocation is the maximum over what it
-// may run, so each kind keeps the occupancy its own footprint allows.
+// threads), Min-Max items of check degree <= 4 (1024 threads: one codeword's checks
+// spread over 16 waves), alpha-free Min-Max items over GF(64) (512 threads at 128
+// VGPRs: two codewords per compute unit), Min-Max items of larger check degree (256
+// threads, for their larger register arrays) and FFT-SPA items (1024 threads).  A
+// kernel's register and LDS allocation is the maximum over what it may run, so each
+// kind keeps the occupancy its own footprint allows.
 // The host estimates the cost of every item and sorts them longest first; a grid
 // sized to the resident capacity of the device then takes items from that list
 // through one device counter: each workgroup claims the next item with one atomic
@@ -56,6 +58,7 @@ struct JobDesc {
     DevCode C;
     BinRule R;
     int max_iters, early_stop, batch, amax;
+    int af;  // Min-Max items: alpha-free decoding
     DecodeIO io;
 };
 
@@ -65,8 +68,14 @@ struct Item {
 
 constexpr int kThreads = 256;  // binary items (their decoders use at most 256 threads)
 constexpr size_t kStaticLds = 256;  // upper bound of the kernel's static LDS
-enum Kind { K_BIN = 0, K_GF4 = 1, K_GF16 = 2 };
-__host__ __device__ constexpr int kind_threads(int k) { return k == K_GF4 ? 1024 : 256; }
+enum Kind { K_BIN = 0, K_GF4 = 1, K_GF16 = 2, K_SPA = 3, K_AF = 4 };
+constexpr int kKinds = 5;
+// Min-Max items of check degree up to 4 and FFT-SPA items run in workgroups of 1024
+// threads; alpha-free Min-Max items in workgroups of 512 threads capped at 128 VGPRs,
+// so that two share a compute unit (78 KB of LDS per GF(64) codeword).
+__host__ __device__ constexpr int kind_threads(int k) {
+    return k == K_GF4 || k == K_SPA ? 1024 : k == K_AF ? 512 : 256;
+}
 
 template <bool LAYERED>
 __device__ __forceinline__ void run_qc(const JobDesc &J, int blk, uint32_t *lds) {
@@ -80,23 +89,39 @@ __device__ __forceinline__ void run_qc(const JobDesc &J, int blk, uint32_t *lds)
 #undef LDPCX_QC_RUN
 }
 
-template <int DC, class M>
-__device__ __forceinline__ void run_nb1_m(const JobDesc &J, int b, uint32_t *lds) {
-    const dev::nb1::Job N{J.C, J.max_iters, J.early_stop, J.layered, J.amax, J.batch, J.io};
-    unsigned char *l = (unsigned char *)lds;
-    switch (J.C.g) {
-    case 4: dev::nb1::decode_cw<4, DC, M>(N, b, l); break;
-    case 8: dev::nb1::decode_cw<8, DC, M>(N, b, l); break;
-    case 16: dev::nb1::decode_cw<16, DC, M>(N, b, l); break;
-    case 32: dev::nb1::decode_cw<32, DC, M>(N, b, l); break;
-    default: dev::nb1::decode_cw<64, DC, M>(N, b, l); break;
+// Alpha-free items over GF(64) only: with the other fields' alpha-free decoders in the
+// same kernel instance its registers spill past 128 VGPRs.
+constexpr int kAfMinG = 64;
+
+template <int DC, class M, bool AF>
+__device__ __forceinline__ void run_nb1_g(const dev::nb1::Job &N, int g, int b, unsigned char *l) {
+    switch (g) {
+    case 4:
+        if constexpr (!AF) dev::nb1::decode_cw<4, DC, M, false>(N, b, l);
+        break;
+    case 8:
+        if constexpr (!AF) dev::nb1::decode_cw<8, DC, M, false>(N, b, l);
+        break;
+    case 16:
+        if constexpr (!AF) dev::nb1::decode_cw<16, DC, M, false>(N, b, l);
+        break;
+    case 32:
+        if constexpr (!AF) dev::nb1::decode_cw<32, DC, M, false>(N, b, l);
+        break;
+    default: dev::nb1::decode_cw<64, DC, M, AF>(N, b, l); break;
     }
 }
 
-template <int DC>
+template <int DC, class M, bool AF>
+__device__ __forceinline__ void run_nb1_m(const JobDesc &J, int b, uint32_t *lds) {
+    const dev::nb1::Job N{J.C, J.max_iters, J.early_stop, J.layered, J.amax, J.batch, J.io};
+    run_nb1_g<DC, M, AF>(N, J.C.g, b, (unsigned char *)lds);
+}
+
+template <int DC, bool AF = false>
 __device__ __forceinline__ void run_nb1(const JobDesc &J, int b, uint32_t *lds) {
-    if (dev::nb1::msg_bytes(J.amax) == 1) run_nb1_m<DC, uint8_t>(J, b, lds);
-    else run_nb1_m<DC, uint16_t>(J, b, lds);
+    if (dev::nb1::msg_bytes(J.amax) == 1) run_nb1_m<DC, uint8_t, AF>(J, b, lds);
+    else run_nb1_m<DC, uint16_t, AF>(J, b, lds);
 }
 
 __device__ __forceinline__ void run_spa(const JobDesc &J, int blk, uint32_t *lds) {
@@ -120,8 +145,11 @@ __device__ __forceinline__ void run_spa(const JobDesc &J, int blk, uint32_t *lds
 template <int K>
 __device__ __forceinline__ void run_item(const JobDesc &J, const Item &it, uint32_t *lds) {
     if (K == K_GF4) {
-        if (it.type == I_NB1) run_nb1<4>(J, it.blk, lds);
-        else run_spa(J, it.blk, lds);
+        run_nb1<4>(J, it.blk, lds);
+    } else if (K == K_AF) {
+        run_nb1<4, true>(J, it.blk, lds);
+    } else if (K == K_SPA) {
+        run_spa(J, it.blk, lds);
     } else if (K == K_GF16) {
         run_nb1<kNbDcMax>(J, it.blk, lds);
     } else if (it.type == I_QC) {
@@ -140,11 +168,8 @@ __device__ __forceinline__ void run_item(const JobDesc &J, const Item &it, uint3
 // list is exhausted.  Claims are the only inter-workgroup interaction: an atomic add
 // that never waits, so the launch completes whatever the residency of its workgroups.
 template <int K>
-__global__ void __launch_bounds__(kind_threads(K)) k_ragged(const JobDesc *__restrict__ jobs,
-                                                     const Item *__restrict__ items, int nitems,
-                                                     int *__restrict__ next) {
-    extern __shared__ __align__(16) uint32_t lds[];
-    __shared__ int claim;
+__device__ __forceinline__ void claim_loop(const JobDesc *__restrict__ jobs, const Item *__restrict__ items,
+                                           int nitems, int *__restrict__ next, uint32_t *lds, int &claim) {
     for (;;) {
         if (threadIdx.x == 0) claim = atomicAdd(next, 1);
         __syncthreads();
@@ -155,6 +180,23 @@ __global__ void __launch_bounds__(kind_threads(K)) k_ragged(const JobDesc *__res
         run_item<K>(jobs[it.job], it, lds);
         __syncthreads();
     }
+}
+
+template <int K>
+__global__ void __launch_bounds__(kind_threads(K)) k_ragged(const JobDesc *__restrict__ jobs,
+                                                     const Item *__restrict__ items, int nitems,
+                                                     int *__restrict__ next) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    __shared__ int claim;
+    claim_loop<K>(jobs, items, nitems, next, lds, claim);
+}
+
+// The alpha-free kind: four waves per SIMD (128 VGPRs), two workgroups per compute unit.
+__global__ void __launch_bounds__(kind_threads(K_AF)) __attribute__((amdgpu_waves_per_eu(4)))
+k_ragged_af(const JobDesc *__restrict__ jobs, const Item *__restrict__ items, int nitems, int *__restrict__ next) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    __shared__ int claim;
+    claim_loop<K_AF>(jobs, items, nitems, next, lds, claim);
 }
 
 // Relative cost of one item (arbitrary units, only compared within a launch).
@@ -308,7 +350,8 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
                 // code has enough checks to occupy the workgroup's lanes
                 if (ragged_nb1_items(c, &p)) {
                     D.family = FAMILY_NB1;
-                    add(I_NB1, jb.batch, nb1_lds_bytes(D.C, D.amax));
+                    D.af = D.C.dc_max <= 4 && D.C.g >= kAfMinG && nb1_alpha_free(D.C, D.layered, false, kind_threads(K_AF));
+                    add(I_NB1, jb.batch, dev::nb1::layout(D.C, dev::nb1::msg_bytes(D.amax), D.af != 0).total);
                     continue;
                 }
                 // FFT-SPA of the LDS-resident family: one item per group of codewords
@@ -358,37 +401,39 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
         }
         if (items.empty()) return cleanup(), run_wide(jobs, wide, s);
 
-        // Three launch classes by item kind; within each, longest item first (the claims
+        // One launch class per item kind; within each, longest item first (the claims
         // then follow that order: greedy list scheduling).
         std::vector<int> order(items.size());
         for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-        std::vector<Item> cls[3];
-        size_t lds[3] = {0, 0, 0};
+        std::vector<Item> cls[kKinds];
+        size_t lds[kKinds] = {0, 0, 0, 0, 0};
         for (int i : order) {
             const Item &it = items[i];
-            const int k = it.type == I_SPA ? K_GF4
-                          : it.type == I_NB1 ? (J[it.job].C.dc_max <= 4 ? K_GF4 : K_GF16)
-                                             : K_BIN;
+            const int k = it.type == I_SPA   ? K_SPA
+                          : it.type != I_NB1 ? K_BIN
+                          : J[it.job].af     ? K_AF
+                          : J[it.job].C.dc_max <= 4 ? K_GF4
+                                                    : K_GF16;
             cls[k].push_back(it);
             lds[k] = std::max(lds[k], need[i]);
         }
 
         // One device table: jobs, the item lists, their claim counters (uploaded as zero).
-        size_t o_it[3];
+        size_t o_it[kKinds];
         size_t o = align_up(sizeof(JobDesc) * njobs, 256);
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < kKinds; ++k) {
             o_it[k] = o;
             o = align_up(o + sizeof(Item) * cls[k].size(), 256);
         }
         const size_t o_ctr = o;
-        const size_t total = align_up(o_ctr + 3 * sizeof(int), 256);
+        const size_t total = align_up(o_ctr + kKinds * sizeof(int), 256);
         char *dbuf = nullptr;
         if (hipMallocAsync((void **)&dbuf, total, s) != hipSuccess) return cleanup(), fail(LDPCX_E_NOMEM, "item table");
         workspaces.push_back(dbuf);
         std::vector<char> host(total, 0);
         std::memcpy(host.data(), J.data(), sizeof(JobDesc) * njobs);
-        for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < kKinds; ++k)
             if (!cls[k].empty()) std::memcpy(host.data() + o_it[k], cls[k].data(), sizeof(Item) * cls[k].size());
         ldpcx_status st = upload_async(dbuf, host.data(), total, device, s);
         if (st != LDPCX_OK) return cleanup(), st;
@@ -397,9 +442,10 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
         // Errors of the calls above were checked where they happened; clear the sticky
         // last-error state so that the launch checks below report the launches only.
         (void)hipGetLastError();
-        const void *kerns[3] = {(const void *)k_ragged<K_BIN>, (const void *)k_ragged<K_GF4>,
-                                (const void *)k_ragged<K_GF16>};
-        for (int k = 0; k < 3; ++k) {
+        const void *kerns[kKinds] = {(const void *)k_ragged<K_BIN>, (const void *)k_ragged<K_GF4>,
+                                     (const void *)k_ragged<K_GF16>, (const void *)k_ragged<K_SPA>,
+                                     (const void *)k_ragged_af};
+        for (int k = 0; k < kKinds; ++k) {
             if (cls[k].empty()) continue;
             const void *kern = kerns[k];
             allow_full_lds(kern);
@@ -413,7 +459,9 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
             int *dnext = (int *)(dbuf + o_ctr) + k;
             const int ni = (int)cls[k].size();
             if (k == K_GF4) hipLaunchKernelGGL(k_ragged<K_GF4>, dim3(grid), dim3(thr), lds[k], s, djobs, ditems, ni, dnext);
+            else if (k == K_AF) hipLaunchKernelGGL(k_ragged_af, dim3(grid), dim3(thr), lds[k], s, djobs, ditems, ni, dnext);
             else if (k == K_GF16) hipLaunchKernelGGL(k_ragged<K_GF16>, dim3(grid), dim3(thr), lds[k], s, djobs, ditems, ni, dnext);
+            else if (k == K_SPA) hipLaunchKernelGGL(k_ragged<K_SPA>, dim3(grid), dim3(thr), lds[k], s, djobs, ditems, ni, dnext);
             else hipLaunchKernelGGL(k_ragged<K_BIN>, dim3(grid), dim3(thr), lds[k], s, djobs, ditems, ni, dnext);
             e = hipGetLastError();
             if (e != hipSuccess) {
