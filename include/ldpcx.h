@@ -145,7 +145,9 @@ ldpcx_status ldpcx_code_info(const ldpcx_code *code, int32_t *n, int32_t *m, int
  * sec. 4: every codeword is an independent decoder).
  *   llr          device, g == 2: int8 [batch][n] channel LLRs;
  *                g > 2: int16 [batch][n][g] channel vectors gamma_n(x) = ln(p(eta)/p(x))
- *                quantised (Alg. 2 initialisation), entries in [0, 32767].
+ *                quantised (Alg. 2 initialisation), entries in [0, 32767] with minimum 0
+ *                over x (gamma_n(eta) = 0 at the most likely symbol eta; the decoders of
+ *                codes whose variables all have degree 2 rely on it).
  *   hard         device, g == 2: uint8 [batch][ceil(n/8)], bit j of codeword b is bit
  *                (j % 8) (LSB first) of byte j / 8; padding bits are 0.
  *                g > 2: uint8 [batch][n] decided symbols.

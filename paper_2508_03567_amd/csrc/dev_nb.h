@@ -780,6 +780,37 @@ __device__ __forceinline__ void lds_group(const Args &A, bool layered, int waves
     }
 }
 
+// Debug dump after the fused flooding: the betas of codeword b sit in the array its last
+// iteration wrote (odd iteration counts: the alpha array, which the fused flooding uses
+// as its second beta array), and its alphas are those the two-phase variable node forms
+// from them (eqs. (14)-(15); gamma' itself before any iteration).  Thread per (edge,
+// codeword), written straight to the [batch][E][G] dump.
+template <int G>
+__device__ __forceinline__ void fdump_block(const Args &A, int bx, int by) {
+    const DevCode &C = A.C;
+    const long Bp = A.Bp;
+    const int e = bx * 4 + wave_id();
+    const int b = by * 64 + (threadIdx.x & 63);
+    if (e >= C.E || b >= A.batch) return;
+    const int it = A.w.it[b];
+    const int16_t *src = (it & 1) ? A.w.alpha : A.w.beta;
+    const int v = C.col_idx[e];
+    const int q0 = C.vn_ptr[v];
+    const int f = C.vn_ref[q0] == e ? C.vn_ref[q0 + 1] : C.vn_ref[q0];
+    const int16_t *gp = A.w.gam + (long)v * G * Bp + b;
+    const int16_t *bf = src + (long)f * G * Bp + b, *be = src + (long)e * G * Bp + b;
+    int16_t *da = (int16_t *)A.io.dump_a + ((size_t)b * C.E + e) * G;
+    int16_t *db = (int16_t *)A.io.dump_b + ((size_t)b * C.E + e) * G;
+    int mn = 0x7fffffff;
+    if (it > 0)
+        for (int x = 0; x < G; ++x) mn = min(mn, min((int)gp[(long)x * Bp], A.amax) + bf[(long)x * Bp]);
+    for (int x = 0; x < G; ++x) {
+        const int s = min((int)gp[(long)x * Bp], A.amax);
+        da[x] = (int16_t)(it > 0 ? min(s + bf[(long)x * Bp] - mn, A.amax) : s);
+        db[x] = be[(long)x * Bp];
+    }
+}
+
 __device__ __forceinline__ void fin_block(const Args &A, long bx) {
     const int b = (int)(bx * 256 + threadIdx.x);
     if (b >= A.batch) return;

@@ -563,6 +563,43 @@ __device__ __forceinline__ void dec_unit(const Args &A, int k, long unit, const 
     }
 }
 
+// Debug dump after the fused flooding: the v of codeword b sit in the array its last
+// iteration wrote (odd iteration counts: the u array, the fused flooding's second v
+// array), and each edge's u is the one the two-phase variable node forms from them
+// (eqs. (5)-(6) with the other edge's v; p itself before any iteration, where v = 0).
+// Wave `unit` = (variable, group), written straight to the [batch][E][G] dump.
+template <int G>
+__device__ __forceinline__ void fdump_unit(const Args &A, long unit) {
+    constexpr int S = lanes_for<G, 4>(), R = Geo<G, S>::R;
+    const DevCode &C = A.C;
+    const Lane L = lane_of<G, S>(A, unit);
+    if (L.node >= C.n) return;
+    const int bb = L.b < A.batch ? L.b : A.batch - 1;
+    const int *src = (A.w.it[bb] & 1) ? A.w.u : A.w.v;
+    const int t0 = C.vn_ptr[L.node];
+    const int e0 = C.vn_ref[t0], e1 = C.vn_ref[t0 + 1];
+    int p[R], v0[R], v1[R], z[R], u0[R], u1[R];
+    load_row<R>(A.w.p + row(L.node, bb, A.batch, G) + L.x0, p);
+    load_row<R>(src + row(e0, bb, A.batch, G) + L.x0, v0);
+    load_row<R>(src + row(e1, bb, A.batch, G) + L.x0, v1);
+#pragma unroll
+    for (int r = 0; r < R; ++r) z[r] = qmul(p[r], v1[r]);
+    normalise<S>(z, p, u0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) z[r] = qmul(p[r], v0[r]);
+    normalise<S>(z, p, u1);
+    if (L.b >= A.batch) return;
+    int *da = (int *)A.io.dump_a, *db = (int *)A.io.dump_b;
+    const size_t o0 = ((size_t)L.b * C.E + e0) * G + L.x0, o1 = ((size_t)L.b * C.E + e1) * G + L.x0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        da[o0 + r] = u0[r];
+        da[o1 + r] = u1[r];
+        db[o0 + r] = v0[r];
+        db[o1 + r] = v1[r];
+    }
+}
+
 // Variable-node phase of iteration k and decision: wave `unit` = (variable, group), for
 // variable degrees up to DV.
 template <int G, int DV>

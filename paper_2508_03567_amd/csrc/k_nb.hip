@@ -58,6 +58,8 @@ __global__ void __launch_bounds__(256) k_lcnf(Args A, int k, int layer, int wpb)
 template <int G>
 __global__ void __launch_bounds__(256) k_dec(Args A, int k) { dev::nb::dec_block<G>(A, k, blk_node(A.Gn), blk_group(A.Gn)); }
 __global__ void __launch_bounds__(256) k_fin(Args A) { dev::nb::fin_block(A, blockIdx.x); }
+template <int G>
+__global__ void __launch_bounds__(256) k_fdump(Args A) { dev::nb::fdump_block<G>(A, blk_node(A.Gn), blk_group(A.Gn)); }
 // One group of 64 codewords per workgroup, messages in LDS.
 template <int G, bool GL>
 __global__ void __launch_bounds__(1024) k_nbl(Args A, int layered, int waves) {
@@ -87,10 +89,13 @@ hipError_t run(const Args &A, bool layered, hipStream_t s) {
     if (most * A.Gn >= (1L << 31)) return hipErrorInvalidConfiguration;
     if ((e = tr(dev::nb::tr_in(A), s)) != hipSuccess) return e;
     const dim3 blk(256);
-    // Every variable of degree 2 (and no debug dump): the alphas formed inside the check
-    // node, in flooding (fused) and layered (dv2) schedules.
-    const bool dv2 = !A.io.dump_a && A.C.dv_max == 2 && A.C.E == 2 * A.C.n;
-    const bool fused = !layered && dv2;
+    // Every variable of degree 2: the alphas formed inside the check node, in flooding
+    // (fused, also under the debug dump, which then forms the final alphas once) and
+    // layered schedules (dv2; the dump there keeps the stored alphas, which depend on the
+    // order of the layers).
+    const bool deg2 = A.C.dv_max == 2 && A.C.E == 2 * A.C.n;
+    const bool fused = !layered && deg2;
+    const bool dv2 = fused || (deg2 && !A.io.dump_a);
     hipLaunchKernelGGL(k_init<G>, lin(dev::nb::grid_init_x(A), A.Gn), blk, 0, s, A, dv2 ? 0 : 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = fill(dev::nb::fill_unsat(A), s)) != hipSuccess) return e;
@@ -130,7 +135,6 @@ hipError_t run(const Args &A, bool layered, hipStream_t s) {
                 hipLaunchKernelGGL(k_dec<G>, gvn, blk, 0, s, D, k);
             }
         } else {
-            // the debug dump keeps the two-phase sequence, whose final alphas it reports
             hipLaunchKernelGGL(k_cn<G>, gcn, dim3(64 * wpb), smem, s, A, k, wpb);
             hipLaunchKernelGGL(k_vn<G>, gvn, blk, 0, s, A, k);
         }
@@ -140,7 +144,10 @@ hipError_t run(const Args &A, bool layered, hipStream_t s) {
     hipLaunchKernelGGL(k_fin, dim3((unsigned)dev::nb::grid_fin(A)), blk, 0, s, A);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = tr(dev::nb::tr_out(A), s)) != hipSuccess) return e;
-    if (A.io.dump_a) {
+    if (A.io.dump_a && fused) {
+        hipLaunchKernelGGL(k_fdump<G>, lin((A.C.E + 3) / 4, A.Gn), blk, 0, s, A);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else if (A.io.dump_a) {
         const long rows = (long)A.C.E * G;
         if ((e = tr(dev::TransposeArgs{A.w.alpha, A.io.dump_a, rows, A.batch, A.Bp, rows, rows, 2}, s)) != hipSuccess)
             return e;

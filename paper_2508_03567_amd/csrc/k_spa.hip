@@ -42,6 +42,8 @@ __global__ void __launch_bounds__(1024) k_spa_lds(Args A, int cw) {
     dev::spa::lds_decode<G>(A, cw, lds, blockIdx.x);
 }
 __global__ void __launch_bounds__(256) k_fin(Args A) { dev::spa::fin_thread(A, (long)blockIdx.x * 256 + threadIdx.x); }
+template <int G>
+__global__ void __launch_bounds__(256) k_fdump(Args A) { dev::spa::fdump_unit<G>(A, unit_id()); }
 __global__ void __launch_bounds__(256) k_dump(Args A, const int *src, int *dst) {
     dev::spa::dump_thread(A, src, dst, (long)blockIdx.x * 256 + threadIdx.x);
 }
@@ -70,9 +72,10 @@ hipError_t run(const Args &A, hipStream_t s) {
     const dev::spa::Carve cv = dev::spa::carve(C, A.max_iters, A.batch);
     if ((e = fill(dev::FillArgs{(uint32_t *)A.w.unsat, (cv.it - cv.unsat) / 4, 0u}, s)) != hipSuccess) return e;
     if ((e = fill(dev::FillArgs{(uint32_t *)A.w.it, (size_t)(B + 1) / 2, 0u}, s)) != hipSuccess) return e;
-    // Every variable of degree 2 and no debug dump: flooding fused into the check node,
-    // v alternating between the v and u arrays, decisions only where they are used.
-    const bool fused = !A.io.dump_a && C.dv_max == 2 && C.E == 2 * C.n;
+    // Every variable of degree 2: flooding fused into the check node, v alternating
+    // between the v and u arrays, decisions only where they are used (the debug dump then
+    // forms the final u once).
+    const bool fused = C.dv_max == 2 && C.E == 2 * C.n;
     hipLaunchKernelGGL(k_init<G>, dim3(blocks(C.n * gi, 4)), blk, 0, s, A, fused ? 0 : 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     constexpr int CD = dev::spa::Geo<G, dev::spa::lanes_for<G, 4>()>::CPW;
@@ -93,7 +96,10 @@ hipError_t run(const Args &A, hipStream_t s) {
     hipLaunchKernelGGL(k_syn, dim3(blocks(C.m * B, 256)), blk, 0, s, A, 0);
     hipLaunchKernelGGL(k_fin, dim3(blocks(B, 256)), blk, 0, s, A);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (A.io.dump_a) {
+    if (A.io.dump_a && fused) {
+        hipLaunchKernelGGL(k_fdump<G>, dim3(blocks(C.n * gd, 4)), blk, 0, s, A);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else if (A.io.dump_a) {
         const long total = (long)C.E * B * G;
         hipLaunchKernelGGL(k_dump, dim3(blocks(total, 256)), blk, 0, s, A, (const int *)A.w.u, (int *)A.io.dump_a);
         hipLaunchKernelGGL(k_dump, dim3(blocks(total, 256)), blk, 0, s, A, (const int *)A.w.v, (int *)A.io.dump_b);
