@@ -7,9 +7,11 @@
 //    it is admitted before it is admitted whole (arrival order);
 //  * a launch is either one chunk with a launch sequence of its own or a ragged batch of
 //    chunks, which stops taking chunks once its estimated device time reaches a target;
-//  * in continuous mode a chunk with its own launch is cut to about a target device
-//    time (in whole units of the request's granularity), so that one large request
-//    spreads over several launches;
+//  * in continuous mode every chunk is cut to about a target device time (in whole
+//    units of the request's granularity): a chunk with its own launch to the own-chunk
+//    target, a chunk of a ragged batch to the launch target, so that one large request
+//    spreads over several launches and no launch holds the requests admitted with it for
+//    much longer than the target;
 //  * while other launches are in flight (memory about to be released), a small piece is
 //    not split off a request.
 #pragma once
@@ -86,12 +88,14 @@ std::vector<Take> form(std::deque<uint64_t> &queue, Lookup &&lookup, const Confi
         const int rem = r.batch - r.next_cw;
         int cap = rem;
         if (cfg.max_launch_cw > 0) cap = std::min(cap, cfg.max_launch_cw - cw_total);
-        if (own && cfg.continuous) {
+        if (cfg.continuous) {
             const double per_cw = r.us(1024) / 1024.0;
-            int lim = (int)(cfg.own_chunk_target_us / std::max(per_cw, 1e-3));
-            const int unit = std::max(1, r.unit());
-            lim = std::max(unit, lim / unit * unit);
-            cap = std::min(cap, lim);
+            const double target = own ? cfg.own_chunk_target_us : cfg.launch_target_us;
+            const double lim_d = target / std::max(per_cw, 1e-3);
+            if (lim_d < (double)rem) {  // the target cuts the remainder: whole units, at least one
+                const int unit = std::max(1, r.unit());
+                cap = std::min(cap, std::max(unit, (int)lim_d / unit * unit));
+            }
         }
         if (cap <= 0) break;
         if (in_use + charge > cfg.budget) break;

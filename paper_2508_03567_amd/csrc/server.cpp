@@ -129,7 +129,7 @@ double est_us(const Request &r, int ncw) {
     case FAMILY_BIN_IL: return work / 1.1e6;
     case FAMILY_SPA:
     case FAMILY_SPA_LDS: return work * ((double)r.code->g / 64.0) / 2.0e4;
-    case FAMILY_NB1: return work * ((double)r.code->g * r.code->g / 4096.0) / 3.0e3;
+    case FAMILY_NB1: return work * ((double)r.code->g * r.code->g / 4096.0) / 5.0e3;
     default: return work * ((double)r.code->g * r.code->g / 4096.0) / 3.0e3;
     }
 }

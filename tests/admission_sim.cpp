@@ -169,11 +169,18 @@ int main(int argc, char **argv) {
                 if (k > 0 && us >= cfg.launch_target_us) die("ragged launch grew past its time target");
                 if (k + 1 < take.size() && c.cw0 + c.ncw != r.batch) die("a partly admitted request was passed");
                 if (c.own && take.size() != 1) die("own chunk shares its launch");
-                if (cfg.continuous && c.own) {
-                    // cut to the time target, in whole units (at least one unit)
+                if (cfg.continuous) {
+                    // cut to its time target (own launch or ragged batch), in whole units
                     const double per_cw = r.us(1024) / 1024.0;
-                    const int lim = std::max(r.unit(), (int)(cfg.own_chunk_target_us / per_cw) / r.unit() * r.unit());
-                    if (c.ncw > lim) die("own chunk longer than its time target");
+                    const double target = c.own ? cfg.own_chunk_target_us : cfg.launch_target_us;
+                    const double lim_d = target / per_cw;
+                    if (c.ncw > lim_d && c.ncw > r.unit())
+                        die(c.own ? "own chunk longer than its time target" : "ragged chunk longer than the launch target");
+                    // a request that fits its target whole is not split by the cut
+                    if (lim_d >= (double)(r.batch - c.cw0) && c.ncw < r.batch - c.cw0 &&
+                        r.bytes(r.batch - c.cw0) + in_use + charge <= cfg.budget &&
+                        (cfg.max_launch_cw == 0 || ncw + r.batch - c.cw0 <= cfg.max_launch_cw))
+                        die("a request that fits its time target was split");
                 }
                 // arrival order: every earlier request (not rejected or failed) is fully admitted
                 for (auto it = reqs.begin(); it != reqs.end() && it->first < c.id; ++it) {
