@@ -331,17 +331,30 @@ def debug_dump(code: Code, prm: DecodeParams, llr, stream=None):
     return (hard, ok, it, a, b, c) if code.g == 2 else (hard, ok, it, a, b)
 
 
+class RaggedBatch:
+    """A ragged batch marshalled once: the output tensors and the C job array are built
+    here, and run() hands the same array to ldpcx_decode_ragged again (the inputs are read
+    from the llr tensors' memory at each run)."""
+
+    def __init__(self, items):
+        self.items = list(items)  # keeps the codes and input tensors alive
+        self.outs, jobs = [], []
+        for code, prm, llr in self.items:
+            _check_llr(code, llr)
+            batch = int(llr.shape[0])
+            hard, ok, it = _outputs(code, batch, llr.device)
+            self.outs.append((hard, ok, it))
+            jobs.append(Job(code.handle, prm, batch, llr.data_ptr(), hard.data_ptr(), ok.data_ptr(), it.data_ptr()))
+        self.arr = (Job * len(jobs))(*jobs)
+
+    def run(self, stream=None):
+        _check(lib().ldpcx_decode_ragged(self.arr, len(self.arr), _stream_ptr(stream)))
+        return self.outs
+
+
 def decode_ragged(items, stream=None):
     """items: list of (Code, DecodeParams, llr tensor).  Returns a list of (hard, ok, iters)."""
-    outs, jobs = [], []
-    for code, prm, llr in items:
-        _check_llr(code, llr)
-        batch = int(llr.shape[0])
-        hard, ok, it = _outputs(code, batch, llr.device)
-        outs.append((hard, ok, it))
-        jobs.append(Job(code.handle, prm, batch, llr.data_ptr(), hard.data_ptr(), ok.data_ptr(), it.data_ptr()))
-    ldpcx_decode_ragged(jobs, _stream_ptr(stream))
-    return outs
+    return RaggedBatch(items).run(stream)
 
 
 def tune(code: Code, prm: DecodeParams, batch: int, stream=None):
