@@ -124,7 +124,8 @@ def main() -> None:
                     help="pin the launch plan instead of tuning: family[:cw_per_wg[:threads]], e.g. bin_interleaved:256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-e2e", action="store_true", help="skip the end-to-end (PCIe-inclusive) leg")
-    ap.add_argument("--e2e-chunks", type=int, default=2, help="chunks of the overlapped end-to-end leg")
+    ap.add_argument("--e2e-chunks", type=int, default=0,
+                    help="chunks of the overlapped end-to-end leg (0: 2 from 16384 codewords up, else 1)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle time")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one 256 MiB device-to-device copy (counter calibration)")
@@ -294,7 +295,7 @@ def main() -> None:
         # pass has finished, so consecutive passes overlap too (the rate is that of a
         # continuous stream of batches).  The events are created once and re-recorded
         # every pass.
-        nch = max(1, args.e2e_chunks)
+        nch = args.e2e_chunks if args.e2e_chunks > 0 else (2 if w.batch >= 16384 else 1)
         step_cw = (w.batch + nch - 1) // nch
         chunks = [(c0, min(w.batch, c0 + step_cw)) for c0 in range(0, w.batch, step_cw)]
         s_in, s_dec, s_out = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
