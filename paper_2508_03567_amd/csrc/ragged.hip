@@ -91,37 +91,37 @@ __device__ __forceinline__ void run_qc(const JobDesc &J, int blk, uint32_t *lds)
 
 // Alpha-free items over GF(64) only: with the other fields' alpha-free decoders in the
 // same kernel instance its registers spill past 128 VGPRs.
-constexpr int kAfMinG = 64;
+constexpr int kAfField = 64;
 
-template <int DC, class M, bool AF>
-__device__ __forceinline__ void run_nb1_g(const dev::nb1::Job &N, int g, int b, unsigned char *l) {
-    switch (g) {
-    case 4:
-        if constexpr (!AF) dev::nb1::decode_cw<4, DC, M, false>(N, b, l);
-        break;
-    case 8:
-        if constexpr (!AF) dev::nb1::decode_cw<8, DC, M, false>(N, b, l);
-        break;
-    case 16:
-        if constexpr (!AF) dev::nb1::decode_cw<16, DC, M, false>(N, b, l);
-        break;
-    case 32:
-        if constexpr (!AF) dev::nb1::decode_cw<32, DC, M, false>(N, b, l);
-        break;
-    default: dev::nb1::decode_cw<64, DC, M, AF>(N, b, l); break;
+template <int DC, class M>
+__device__ __forceinline__ void run_nb1_m(const JobDesc &J, int b, uint32_t *lds) {
+    const dev::nb1::Job N{J.C, J.max_iters, J.early_stop, J.layered, J.amax, J.batch, J.io};
+    unsigned char *l = (unsigned char *)lds;
+    switch (J.C.g) {
+    case 4: dev::nb1::decode_cw<4, DC, M>(N, b, l); break;
+    case 8: dev::nb1::decode_cw<8, DC, M>(N, b, l); break;
+    case 16: dev::nb1::decode_cw<16, DC, M>(N, b, l); break;
+    case 32: dev::nb1::decode_cw<32, DC, M>(N, b, l); break;
+    default: dev::nb1::decode_cw<64, DC, M>(N, b, l); break;
     }
 }
 
-template <int DC, class M, bool AF>
-__device__ __forceinline__ void run_nb1_m(const JobDesc &J, int b, uint32_t *lds) {
+// Alpha-free item: the host marks only GF(64) jobs of check degree <= 4 alpha-free.
+template <class M>
+__device__ __forceinline__ void run_nb1_af_m(const JobDesc &J, int b, uint32_t *lds) {
     const dev::nb1::Job N{J.C, J.max_iters, J.early_stop, J.layered, J.amax, J.batch, J.io};
-    run_nb1_g<DC, M, AF>(N, J.C.g, b, (unsigned char *)lds);
+    dev::nb1::decode_cw<kAfField, 4, M, true>(N, b, (unsigned char *)lds);
 }
 
-template <int DC, bool AF = false>
+template <int DC>
 __device__ __forceinline__ void run_nb1(const JobDesc &J, int b, uint32_t *lds) {
-    if (dev::nb1::msg_bytes(J.amax) == 1) run_nb1_m<DC, uint8_t, AF>(J, b, lds);
-    else run_nb1_m<DC, uint16_t, AF>(J, b, lds);
+    if (dev::nb1::msg_bytes(J.amax) == 1) run_nb1_m<DC, uint8_t>(J, b, lds);
+    else run_nb1_m<DC, uint16_t>(J, b, lds);
+}
+
+__device__ __forceinline__ void run_nb1_af(const JobDesc &J, int b, uint32_t *lds) {
+    if (dev::nb1::msg_bytes(J.amax) == 1) run_nb1_af_m<uint8_t>(J, b, lds);
+    else run_nb1_af_m<uint16_t>(J, b, lds);
 }
 
 __device__ __forceinline__ void run_spa(const JobDesc &J, int blk, uint32_t *lds) {
@@ -147,7 +147,7 @@ __device__ __forceinline__ void run_item(const JobDesc &J, const Item &it, uint3
     if (K == K_GF4) {
         run_nb1<4>(J, it.blk, lds);
     } else if (K == K_AF) {
-        run_nb1<4, true>(J, it.blk, lds);
+        run_nb1_af(J, it.blk, lds);
     } else if (K == K_SPA) {
         run_spa(J, it.blk, lds);
     } else if (K == K_GF16) {
@@ -350,7 +350,7 @@ extern "C" ldpcx_status ldpcx_decode_ragged(const ldpcx_job *jobs, int32_t njobs
                 // code has enough checks to occupy the workgroup's lanes
                 if (ragged_nb1_items(c, &p)) {
                     D.family = FAMILY_NB1;
-                    D.af = D.C.dc_max <= 4 && D.C.g >= kAfMinG && nb1_alpha_free(D.C, D.layered, false, kind_threads(K_AF));
+                    D.af = D.C.dc_max <= 4 && D.C.g == kAfField && nb1_alpha_free(D.C, D.layered, false, kind_threads(K_AF));
                     add(I_NB1, jb.batch, dev::nb1::layout(D.C, dev::nb1::msg_bytes(D.amax), D.af != 0).total);
                     continue;
                 }
