@@ -31,7 +31,8 @@ def _pair(h, prm, llr, what):
 
 @pytest.mark.parametrize("cfg,plan,sizes", [
     (2, None, (600, 100)),                      # interleaved binary, n = 64800: 256-codeword slices
-    (3, None, (2600, 300)),                     # interleaved Min-Max, GF(64): two chunks, then one
+    (3, ("minmax_interleaved", 64, 256), (2600, 300)),  # interleaved Min-Max, GF(64): two chunks, then one
+    (3, None, (2600, 300)),                     # default: one codeword per workgroup, alpha-free, no workspace
     (3, ("spa_wave",), (2600, 300)),            # FFT-SPA wave kernels, GF(64)
     (1, None, (300, 70)),                       # QC packed: no workspace at all
 ])
