@@ -335,22 +335,26 @@ def test_full_size_sampled(cfg, sample):
 
 @pytest.mark.parametrize("early", [False, True])
 def test_minmax_fused_flooding_matches_two_phase_and_oracle(early):
-    """Flooding with the alphas formed inside the check node (every variable of degree 2, a
-    check-node launch that fills the device: 96 checks x 44 groups) gives the decisions of
-    the two-phase sequence (the debug-dump path) for every codeword and the oracle's on a
-    sample, also with channel costs below 0 (every seventh codeword), whose sums leave the
-    16-bit range and take the 32-bit path."""
+    """Interleaved-family flooding with the alphas formed inside the check node (every
+    variable of degree 2, a check-node launch that fills the device: 96 checks x 44
+    groups): the decisions equal the oracle's on a sample of 90 codewords, also with
+    channel costs below 0 (every seventh codeword), whose sums leave the 16-bit range and
+    take the 32-bit path; the debug-dump call (the same fused sequence, then the dump
+    kernel) gives the same decisions for every codeword.  The interleaved family is pinned
+    (the default plan of this code is the one-codeword family, which has its own tests)."""
     w = S.workload(3, batch=2816)
     cw, gam = S.make_inputs(w)
     gam = gam.copy()
     gam[::7] -= 3000
     d = _prm(w, early_stop=early, max_iters=6)
-    h = _handle(w.code)
+    h = L.Code(w.code)
+    L.plan_set(h, L.params(**d), 2816, "minmax_interleaved", 64, 256)
+    assert L.plan_info(h, L.params(**d), 2816)["family"] == "minmax_interleaved"
     g = _gpu(h, d, gam)
-    two_phase = _gpu(h, d, gam, dump=True)
-    for a, b in zip(g[:3], two_phase[:3]):
+    dumped = _gpu(h, d, gam, dump=True)
+    for a, b in zip(g[:3], dumped[:3]):
         assert (a == b).all()
-    idx = np.unique(np.concatenate([np.arange(0, 2816, 97), np.arange(0, 2816, 7)[:10], [2815]]))
+    idx = np.unique(np.concatenate([np.arange(0, 2816, 97), np.arange(0, 2816, 7)[:60], [2815]]))
     _check_decisions(w.code, g, _ref(w.code, d, gam[idx]), idx)
 
 
