@@ -242,9 +242,11 @@ ldpcx_status ldpcx_tune(const ldpcx_code *code, const ldpcx_decode_params *param
  * iterations in one launch (check and variable degrees <= 4, the vectors of cw_per_wg
  * codewords within 160 KB; 256, 512 or 1024 threads), 7 = Min-Max with one codeword per
  * workgroup, every message in LDS and the lanes over the field entries, all iterations
- * in one launch (GF(4)..GF(64), the messages of one codeword within 160 KB, stored in 8 bits
- * when nb_msg_max <= 255; a multiple of 64 threads up to 1024, at most 256 used for check
- * degrees above 4; both schedules),
+ * in one launch (GF(4)..GF(64), the messages of one codeword within 160 KB, stored in
+ * signed 16 bits, or in 8 bits when nb_msg_max <= 255, which needs costs >= 0 as the
+ * input contract states; without stored alphas when every variable has degree 2 and
+ * each 64-lane group of threads holds at most two checks; a multiple of 64 threads up to
+ * 1024, at most 256 used for check degrees above 4; both schedules),
  * 3 = packed two-codewords-per-lane binary for quasi-cyclic codes, available
  * when every layer of z rows consists of z x z circulant blocks, at most 16 layers and
  * 8 blocks per layer), codewords per workgroup (family 1: codewords per launch

@@ -9,9 +9,10 @@
 // persistent ragged kernel.  It fits codes whose messages of one codeword fit 160 KB
 // (the (2,4)-regular GF(64) code of 192 symbols takes 128 KB).
 //
-// Message storage: 16-bit, or 8-bit when the message bound is at most 255 (the 8-bit
-// variant of sec. 5, bound 127): every stored alpha, beta and gamma' then lies in
-// [0, bound], so bytes hold them exactly, the arithmetic stays 16/32-bit and the
+// Message storage: signed 16-bit (exact for every value the arithmetic stores, costs
+// below 0 included), or 8-bit when the message bound is at most 255 (the 8-bit variant
+// of sec. 5, bound 127): with costs >= 0 every stored alpha, beta and gamma' then lies
+// in [0, bound], so bytes hold them exactly, the arithmetic stays 16/32-bit and the
 // results are those of the 16-bit storage; the LDS per codeword halves (66 KB for the
 // GF(64) code, so two codewords share a compute unit).
 //
@@ -359,7 +360,7 @@ __device__ __forceinline__ bool syndrome_ok(const DevCode &C, const uint8_t *mul
 }
 
 // The whole decode of codeword b by the calling workgroup (any multiple of 64 threads),
-// messages stored as M (uint16_t, or uint8_t when the bound is at most 255).  Ends with
+// messages stored as M (int16_t, or uint8_t when the bound is at most 255).  Ends with
 // a barrier, so the caller may reuse the LDS right after.  AF: alpha-free decoding
 // (every variable of degree 2; flooding needs at most two checks per segment, and the
 // debug dump is only taken with flooding).

@@ -32,7 +32,7 @@ hipError_t run_dc(const dev::nb1::Job &J, bool af, int threads, size_t lds, hipS
 template <int G>
 hipError_t run_m(const dev::nb1::Job &J, bool af, int threads, size_t lds, hipStream_t s) {
     return dev::nb1::msg_bytes(J.amax) == 1 ? run_dc<G, uint8_t>(J, af, threads, lds, s)
-                                            : run_dc<G, uint16_t>(J, af, threads, lds, s);
+                                            : run_dc<G, int16_t>(J, af, threads, lds, s);
 }
 
 }  // namespace

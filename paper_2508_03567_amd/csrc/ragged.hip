@@ -116,12 +116,12 @@ __device__ __forceinline__ void run_nb1_af_m(const JobDesc &J, int b, uint32_t *
 template <int DC>
 __device__ __forceinline__ void run_nb1(const JobDesc &J, int b, uint32_t *lds) {
     if (dev::nb1::msg_bytes(J.amax) == 1) run_nb1_m<DC, uint8_t>(J, b, lds);
-    else run_nb1_m<DC, uint16_t>(J, b, lds);
+    else run_nb1_m<DC, int16_t>(J, b, lds);
 }
 
 __device__ __forceinline__ void run_nb1_af(const JobDesc &J, int b, uint32_t *lds) {
     if (dev::nb1::msg_bytes(J.amax) == 1) run_nb1_af_m<uint8_t>(J, b, lds);
-    else run_nb1_af_m<uint16_t>(J, b, lds);
+    else run_nb1_af_m<int16_t>(J, b, lds);
 }
 
 __device__ __forceinline__ void run_spa(const JobDesc &J, int blk, uint32_t *lds) {

@@ -112,6 +112,22 @@ def test_noiseless_and_tied_inputs():
     _check(w.code, _run(w.code, zeros, d, 256), d, zeros)
 
 
+@pytest.mark.parametrize("threads", [256, 512])
+@pytest.mark.parametrize("sched", ["flooding", "layered"])
+def test_negative_costs(threads, sched):
+    """Channel costs below 0, shifted unevenly per symbol (outside the minimum-0 contract of
+    the input, but within int16): the 16-bit storage is signed, so decisions, flags,
+    iteration counts and every message still equal the oracle's (stored alphas at 256
+    threads, alpha-free at 512)."""
+    w = S.workload(3, batch=24, ebn0_db=1.5)
+    _, gam = S.make_inputs(w, seed_offset=5)
+    rng = np.random.default_rng(8)
+    gam = (gam.astype(np.int32) - rng.integers(0, 4000, size=gam.shape[:2])[:, :, None]).astype(np.int16)
+    for iters, early in ((5, True), (2, False)):
+        d = dict(rule="minmax", schedule=sched, max_iters=iters, early_stop=early)
+        _check(w.code, _run(w.code, gam, d, threads), d, gam)
+
+
 def test_limits():
     big = S.random_regular_nb_code(512, 256, 2, 4, 64, S.PRIM_POLY[64], seed=1)  # messages of 320 KB
     h = L.Code(big)
