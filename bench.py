@@ -487,7 +487,7 @@ def prof_main(args) -> None:
             by[nm].append((int(r["Start_Timestamp"]), dt))
         total = sum(dt for v in by.values() for _, dt in v)
         print(f"# rocprofv3 kernel statistics: {args.prof_title}\n")
-        print(f"Command (output under gpurun_out/):\n\n```\n{args.prof_cmd}\n```\n")
+        print(f"Command (rocprofv3 writes its CSV files to the -d directory):\n\n```\n{args.prof_cmd}\n```\n")
         print("| kernel | calls | mean ns | median ns | min ns | max ns | % of GPU time |")
         print("|---|---|---|---|---|---|---|")
         for nm in sorted(order, key=lambda n: -sum(dt for _, dt in by[n])):
