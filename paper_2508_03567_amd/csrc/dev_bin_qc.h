@@ -311,6 +311,243 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
     __syncthreads();
 }
 
+// Flooding with the layers in parallel: thread (layer l, pair, row i) owns row i of layer l
+// only, so a workgroup of Z * npairs * nl threads runs every check node of an iteration at
+// once (nl times the waves of qc_item, each with one layer's messages in registers).
+// Z * npairs is a multiple of 64, so a wave holds rows of one layer and the layer degree
+// is uniform in it.  The variable-node update then adds the layers' messages to Lambda
+// one layer after the other, as in qc_item.  Same LDS layout as qc_item's flooding.
+template <int ML, int MD, bool ES>
+__device__ __forceinline__ void qc_item_lp(const QcDesc &Q, const DevCode &C, const BinRule &R, int max_iters,
+                                           int early_stop, int batch, int npairs, const DecodeIO &io, int blk,
+                                           uint32_t *lds) {
+    const int n = C.n, E = C.E, Z = Q.Z, nl = Q.nl;
+    const int ld = n + Z;
+    const uint32_t Z4 = 4 * Z;
+    const int tid = threadIdx.x, T = blockDim.x;
+    const int per = Z * npairs;                       // threads of one layer
+    const int lt = tid / per, rem = tid - lt * per;   // this thread's layer
+    const bool act = lt < nl;
+    const int p = act ? rem / Z : 0, i0 = act ? rem - p * Z : 0;
+    const int cw0 = blk * npairs * 2;
+    if (cw0 >= batch) return;
+    int2 *sdesc = (int2 *)lds;
+    uint16_t *offs = (uint16_t *)(lds + 2 * ML * MD);
+    uint32_t *lam = lds + 2 * ML * MD + 4 * ML * Z;
+    uint32_t *Lch = lam + (size_t)npairs * ld;
+    int *unsat = (int *)(lam + (size_t)2 * npairs * ld);
+    int *done = unsat + npairs;
+    int *itc = done + npairs;
+    const v2s mm = splat(R.msg_max), nmm = splat(-R.msg_max);
+    const PkNorm NP = pk_norm_params(R);
+    int rule = __builtin_amdgcn_readfirstlane(R.rule);
+    asm volatile("" : "+s"(rule));
+    int kn128 = (int)0xFF80FF80u;  // -128 in both halves, opaque (one v_pk_mad_u16 below)
+    asm volatile("" : "+s"(kn128));
+    const v2s neg128 = as_v2s((uint32_t)kn128);
+
+    for (int idx = tid; idx < ML * MD; idx += T) {
+        const int l = idx / MD, j = idx - l * MD;
+        const int2 e = (l < nl && j < Q.dc[l]) ? Q.edges[l * kQcMaxDc + j] : make_int2(n, 0);
+        sdesc[idx] = make_int2(4 * e.x, 4 * e.y);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < ML * Z; idx += T) {
+        const int l = idx / Z, i = idx - l * Z;
+        uint16_t *o = offs + 8 * idx;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) o[j] = j < MD ? (uint16_t)qc_off(sdesc[l * MD + j], 4 * i, Z4) : (uint16_t)0;
+    }
+    const int8_t *llr = (const int8_t *)io.llr;
+    for (int idx = tid; idx < npairs * ld; idx += T) {
+        const int pp = idx / ld, v = idx - pp * ld;
+        const int c0 = cw0 + 2 * pp;
+        short lo = 0x3FFF, hi = 0x3FFF;
+        if (v < n) {
+            lo = c0 < batch ? (short)llr[(size_t)c0 * n + v] : (short)0;
+            hi = c0 + 1 < batch ? (short)llr[(size_t)(c0 + 1) * n + v] : (short)0;
+        }
+        const uint32_t w = as_u32((v2s){lo, hi});
+        lam[idx] = w;
+        Lch[idx] = w;
+    }
+    for (int idx = tid; idx < npairs; idx += T) {
+        const int c0 = cw0 + 2 * idx;
+        unsat[idx] = 0;
+        done[idx] = (c0 < batch ? 0 : 1) | (c0 + 1 < batch ? 0 : 2);
+        itc[2 * idx] = itc[2 * idx + 1] = 0;
+    }
+    __syncthreads();
+
+    uint32_t *lamp = lam + (size_t)p * ld;
+    uint32_t vv[MD];
+    int dc = 0;
+    if (act) {
+        const uint4 w = *(const uint4 *)(offs + 8 * (lt * Z + i0));
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int j = 0; j < MD; ++j) vv[j] = (j & 1) ? ws[j >> 1] >> 16 : ws[j >> 1] & 0xFFFFu;
+        dc = Q.dc[lt];
+    }
+    dc = __builtin_amdgcn_readfirstlane(dc);  // uniform: a wave holds rows of one layer
+    asm volatile("" : "+s"(dc));
+    v2s r[MD];
+#pragma unroll
+    for (int j = 0; j < MD; ++j) r[j] = splat(0);
+
+    // parity of this thread's row under the current decisions (2 bits, one per codeword)
+    auto row_parity = [&]() -> int {
+        if (!act) return 0;
+        uint32_t x = 0;
+#pragma unroll
+        for (int j = 0; j < MD; ++j) x ^= lds_word(lamp, vv[j]);
+        return (int)((x >> 15) & 1u) | (int)((x >> 30) & 2u);
+    };
+    // check node of this thread's row: DD edge slots (those at or beyond dc are virtual)
+    uint32_t M = 0xFFFFFFFFu;
+    auto check = [&](auto dd_tag) {
+        constexpr int DD = decltype(dd_tag)::value;
+        uint32_t sv[MD], sr[MD];
+        v2s qv[MD], nq[MD], av[MD], mg[MD];
+#pragma unroll
+        for (int j = 0; j < DD; ++j) qv[j] = as_v2s(lds_word(lamp, vv[j])) - r[j];
+#pragma unroll
+        for (int j = 0; j < DD; ++j) nq[j] = -qv[j];
+#pragma unroll
+        for (int j = 0; j < DD; ++j) sv[j] = as_u32(qv[j] >> splat(15));
+#pragma unroll
+        for (int j = 0; j < DD; ++j) av[j] = pmax(qv[j], nq[j]);
+#pragma unroll
+        for (int j = 0; j < DD; ++j) av[j] = pmin(av[j], mm);
+        v2s m1 = splat(0x7FFF), m2 = splat(0x7FFF);
+        uint32_t stot = 0;
+#pragma unroll
+        for (int j = 0; j < DD; ++j) {
+            m2 = pmin(m2, pmax(m1, av[j]));
+            m1 = pmin(m1, av[j]);
+            stot ^= sv[j];
+        }
+        v2s f1, f2;
+        if (rule == LDPCX_RULE_NMS) {
+            f1 = (m1 * NP.num) >> NP.shift;
+            f2 = (m2 * NP.num) >> NP.shift;
+        } else if (rule == LDPCX_RULE_OMS) {
+            f1 = pmax(m1 - NP.off, splat(0));
+            f2 = pmax(m2 - NP.off, splat(0));
+        } else {
+            f1 = m1;
+            f2 = m2;
+        }
+        // magnitude out of edge j: f2 where a = m1, else f1 (as in qc_item)
+        const v2s cs = f2 - m1 * neg128;
+#pragma unroll
+        for (int j = 0; j < DD; ++j) mg[j] = av[j] * neg128 + cs;
+#pragma unroll
+        for (int j = 0; j < DD; ++j) sr[j] = stot ^ sv[j];
+#pragma unroll
+        for (int j = 0; j < DD; ++j) mg[j] = pmax(f1, mg[j]);
+#pragma unroll
+        for (int j = 0; j < DD; ++j) mg[j] = as_v2s(as_u32(mg[j]) ^ sr[j]);
+#pragma unroll
+        for (int j = 0; j < DD; ++j) {
+            const v2s rn = mg[j] - as_v2s(sr[j]);
+            r[j] = ES ? as_v2s(bfi(M, as_u32(rn), as_u32(r[j]))) : rn;
+        }
+    };
+
+    for (int k = 1; k <= max_iters; ++k) {
+        if (ES && early_stop) {
+            const int any = row_parity();
+            if (any) atomicOr(&unsat[p], any);
+            __syncthreads();
+            if (tid < npairs) {
+                done[tid] |= (~unsat[tid]) & 3;
+                unsat[tid] = 0;
+            }
+            __syncthreads();
+            int all = 1;
+            for (int q = 0; q < npairs; ++q) all &= done[q] == 3;
+            if (all) break;
+            const int d = done[p];
+            M = ((d & 1) ? 0u : 0x0000FFFFu) | ((d & 2) ? 0u : 0xFFFF0000u);
+        }
+        if (act) {
+            if (dc >= MD) check(std::integral_constant<int, MD>{});
+            else if (dc == MD - 1) check(std::integral_constant<int, MD - 1>{});
+            else check(std::integral_constant<int, MD - 2>{});
+        }
+        __syncthreads();  // every check node has read Lambda
+        for (int idx = tid; idx < npairs * ld; idx += T) lam[idx] = Lch[idx];
+        __syncthreads();
+        for (int l = 0; l < nl; ++l) {
+            if (act && lt == l) {
+#pragma unroll
+                for (int j = 0; j < MD; ++j) {
+                    if (j < dc) {
+                        uint32_t &w = lds_word(lamp, vv[j]);
+                        w = as_u32(as_v2s(w) + r[j]);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (tid < 2 * npairs && !((done[tid >> 1] >> (tid & 1)) & 1)) itc[tid] = k;
+    }
+
+    // Syndrome of the final decision.
+    __syncthreads();
+    {
+        const int any = row_parity();
+        if (any) atomicOr(&unsat[p], any);
+    }
+    __syncthreads();
+    const int ncw = min(2 * npairs, batch - cw0);
+    if (tid < ncw) {
+        io.ok[cw0 + tid] = ((unsat[tid >> 1] >> (tid & 1)) & 1) ? 0 : 1;
+        io.iters[cw0 + tid] = (int16_t)itc[tid];
+    }
+    const int nbytes = (n + 7) >> 3;
+    uint8_t *hard = (uint8_t *)io.hard + (size_t)cw0 * nbytes;
+    for (int idx = tid; idx < ncw * nbytes; idx += T) {
+        const int c = idx / nbytes, jb = idx - c * nbytes;
+        const uint32_t *lp = lam + (size_t)(c >> 1) * ld;
+        const int sh = (c & 1) ? 31 : 15;
+        uint32_t byte = 0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int v = 8 * jb + b;
+            if (v < n) byte |= ((lp[v] >> sh) & 1u) << b;
+        }
+        hard[idx] = (uint8_t)byte;
+    }
+    if (io.dump_a) {
+        int8_t *dq = (int8_t *)io.dump_a;
+        int8_t *dr = (int8_t *)io.dump_b;
+        int16_t *dl = (int16_t *)io.dump_c;
+        if (act) {
+            const int e0 = C.row_ptr[lt * Z + i0];
+#pragma unroll
+            for (int j = 0; j < MD; ++j)
+                if (j < dc) {
+                    const v2s lv = as_v2s(lds_word(lamp, vv[j]));
+                    const v2s qc = pmin(pmax(lv - r[j], nmm), mm);
+                    for (int h = 0; h < 2; ++h) {
+                        const int c = cw0 + 2 * p + h;
+                        if (c < batch) {
+                            dr[(size_t)c * E + e0 + j] = (int8_t)r[j][h];
+                            dq[(size_t)c * E + e0 + j] = (int8_t)qc[h];
+                        }
+                    }
+                }
+        }
+        for (int idx = tid; idx < ncw * n; idx += T) {
+            const int c = idx / n, v = idx - c * n;
+            dl[(size_t)(cw0 + c) * n + v] = as_v2s(lam[(size_t)(c >> 1) * ld + v])[c & 1];
+        }
+    }
+    __syncthreads();
+}
+
 // Register arrays are sized by the number of layers (ML) and the largest layer degree (MD).
 #define LDPCX_QC_SHAPES(X) X(4, 6) X(4, 8) X(8, 6) X(8, 8) X(12, 7) X(12, 8) X(16, 6) X(16, 8)
 

@@ -39,6 +39,26 @@ __global__ void __launch_bounds__(512) k_bin_qc(QcDesc Q, DevCode C, BinRule R, 
     qc_item<ML, MD, LAYERED, ES>(Q, C, R, max_iters, early_stop, batch, npairs, io, blockIdx.x, lds);
 }
 
+// Flooding with the layers in parallel (qc_item_lp): Z * npairs * nl threads.
+template <int ML, int MD, bool ES>
+__global__ void __launch_bounds__(1024) k_bin_qc_lp(QcDesc Q, DevCode C, BinRule R, int max_iters, int early_stop,
+                                                    int batch, int npairs, DecodeIO io) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    qc_item_lp<ML, MD, ES>(Q, C, R, max_iters, early_stop, batch, npairs, io, blockIdx.x, lds);
+}
+
+template <int ML, int MD, bool ES>
+hipError_t launch_lp_es(const QcDesc &Q, const DevCode &C, const BinRule &R, int max_iters, int early_stop, int batch,
+                        int npairs, const DecodeIO &io, hipStream_t s) {
+    const size_t smem = qc_smem_bytes(ML, MD, C, Q.Z, false, npairs);
+    const int pairs = (batch + 1) / 2;
+    const int grid = (pairs + npairs - 1) / npairs;
+    allow_full_lds((const void *)k_bin_qc_lp<ML, MD, ES>);
+    hipLaunchKernelGGL((k_bin_qc_lp<ML, MD, ES>), dim3(grid), dim3(Q.Z * npairs * Q.nl), smem, s, Q, C, R, max_iters,
+                       early_stop, batch, npairs, io);
+    return hipGetLastError();
+}
+
 template <int ML, int MD, bool LAYERED, bool ES>
 hipError_t launch_es(const QcDesc &Q, const DevCode &C, const BinRule &R, int max_iters, int early_stop, int batch,
                      int npairs, const DecodeIO &io, hipStream_t s) {
@@ -77,6 +97,24 @@ size_t bin_qc_smem_bytes(const QcDesc &Q, const DevCode &C, int layered, int npa
     qc_shape_of(Q, ml, md);
     if (!ml) return (size_t)-1;
     return qc_smem_bytes(ml, md, C, Q.Z, layered, npairs);
+}
+
+bool bin_qc_lp_ok(const QcDesc &Q, int npairs) {
+    return Q.nl > 1 && Q.nl <= kQcMaxL && (Q.Z * npairs) % 64 == 0 && Q.Z * npairs * Q.nl <= 1024;
+}
+
+hipError_t launch_bin_qc_lp(const QcDesc &Q, const DevCode &C, const BinRule &R, int max_iters, int early_stop,
+                            int batch, int npairs, const DecodeIO &io, hipStream_t s) {
+    if (!bin_qc_lp_ok(Q, npairs)) return hipErrorInvalidConfiguration;
+    int ml, md;
+    qc_shape_of(Q, ml, md);
+#define LDPCX_LAUNCH_LP(L_, D_)                                                                                  \
+    if (ml == L_ && md == D_)                                                                                    \
+        return early_stop ? launch_lp_es<L_, D_, true>(Q, C, R, max_iters, early_stop, batch, npairs, io, s)    \
+                          : launch_lp_es<L_, D_, false>(Q, C, R, max_iters, early_stop, batch, npairs, io, s);
+    LDPCX_QC_SHAPES(LDPCX_LAUNCH_LP)
+#undef LDPCX_LAUNCH_LP
+    return hipErrorInvalidConfiguration;
 }
 
 hipError_t launch_bin_qc(const QcDesc &Q, const DevCode &C, const BinRule &R, int max_iters, int early_stop,

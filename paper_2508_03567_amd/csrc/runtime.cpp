@@ -188,6 +188,18 @@ Plan default_plan(const ldpcx_code *c, const ldpcx_decode_params *p, int batch) 
         while (np > 1 && bin_qc_smem_bytes(c->qc, c->dev, sched == LDPCX_SCHED_LAYERED, np) > (size_t)di.lds_per_block) --np;
         pl.cpw = 2 * np;
         pl.threads = Z * np;
+        // Small flooding batches (fewer than 4 workgroups per compute unit): the layers in
+        // parallel, which shortens each codeword's iteration (measured 1.7x faster on 1000
+        // codewords of the n = 192 code, slower from tens of thousands up)
+        if (sched != LDPCX_SCHED_LAYERED) {
+            int npl = 1;
+            while (npl <= 16 && (Z * npl) % 64) ++npl;
+            if (npl <= 16 && bin_qc_lp_ok(c->qc, npl) && (pairs + npl - 1) / npl < 4 * di.cus &&
+                bin_qc_smem_bytes(c->qc, c->dev, false, npl) <= (size_t)di.lds_per_block) {
+                pl.cpw = 2 * npl;
+                pl.threads = Z * npl * c->qc.nl;
+            }
+        }
         return pl;
     }
     const size_t per_cw = bin_lds_smem_bytes(c->dev, sched == LDPCX_SCHED_LAYERED, 1);
@@ -244,8 +256,11 @@ ldpcx_status run_plan(ldpcx_code *c, const ldpcx_decode_params *p, const Plan &p
         const int np = pl.cpw / 2;
         if (bin_qc_smem_bytes(c->qc, c->dev, pl.schedule == LDPCX_SCHED_LAYERED, np) > (size_t)device_info(c->device).lds_per_block)
             return fail(LDPCX_E_UNSUPPORTED, "pair state does not fit the LDS of one workgroup");
-        e = launch_bin_qc(c->qc, c->dev, bin_rule(p), p->max_iters, p->early_stop, pl.schedule == LDPCX_SCHED_LAYERED,
-                          batch, np, io, s);
+        const bool lp = pl.schedule != LDPCX_SCHED_LAYERED && pl.threads == c->qc.Z * np * c->qc.nl &&
+                        bin_qc_lp_ok(c->qc, np);
+        e = lp ? launch_bin_qc_lp(c->qc, c->dev, bin_rule(p), p->max_iters, p->early_stop, batch, np, io, s)
+               : launch_bin_qc(c->qc, c->dev, bin_rule(p), p->max_iters, p->early_stop,
+                               pl.schedule == LDPCX_SCHED_LAYERED, batch, np, io, s);
         if (e != hipSuccess) return fail_hip(e, "QC decoder launch");
         return LDPCX_OK;
     }
@@ -828,7 +843,10 @@ ldpcx_status ldpcx_plan_set(ldpcx_code *c, const ldpcx_decode_params *params, in
             (size_t)device_info(c->device).lds_per_block)
             return fail(LDPCX_E_UNSUPPORTED, "state of cw_per_wg codewords does not fit the LDS");
         pl.cpw = cw_per_wg;
-        pl.threads = c->qc.Z * cw_per_wg / 2;
+        // Z * npairs * nl threads select the layer-parallel flooding kernel
+        const int np = cw_per_wg / 2;
+        const bool lp = threads == c->qc.Z * np * c->qc.nl && pl.schedule != LDPCX_SCHED_LAYERED && bin_qc_lp_ok(c->qc, np);
+        pl.threads = lp ? threads : c->qc.Z * np;
     }
     if (family == FAMILY_BIN_LDS) {
         if (cw_per_wg < 1 || cw_per_wg > 64) return fail(LDPCX_E_INVAL, "cw_per_wg out of range");

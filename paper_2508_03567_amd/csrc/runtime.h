@@ -76,6 +76,11 @@ const DeviceInfo &device_info(int dev);
 ldpcx_status check_params(const ldpcx_code *c, const ldpcx_decode_params *p);
 ldpcx_status check_device(const ldpcx_code *c);
 BinRule bin_rule(const ldpcx_decode_params *p);
+// QC flooding with the layers in parallel (a workgroup of Z * npairs * nl threads; plans
+// mark it by that thread count): whether a shape allows it, and its launch.
+bool bin_qc_lp_ok(const QcDesc &Q, int npairs);
+hipError_t launch_bin_qc_lp(const QcDesc &Q, const DevCode &C, const BinRule &R, int max_iters, int early_stop,
+                            int batch, int npairs, const DecodeIO &io, hipStream_t s);
 int nb_amax(const ldpcx_decode_params *p);  // Min-Max message bound of the params
 // Whether the ragged decode runs this Min-Max job's codewords as one-codeword items of
 // its persistent kernel (any schedule) rather than as a whole-device decode

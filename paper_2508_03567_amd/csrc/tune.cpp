@@ -248,6 +248,10 @@ std::vector<Plan> candidates(const ldpcx_code *c, const ldpcx_decode_params *p, 
                 pl.cpw = 2 * np;
                 pl.threads = c->qc.Z * np;
                 out.push_back(pl);
+                if (!lay && bin_qc_lp_ok(c->qc, np)) {  // flooding with the layers in parallel
+                    pl.threads = c->qc.Z * np * c->qc.nl;
+                    out.push_back(pl);
+                }
             }
         }
         const size_t per_cw = bin_lds_smem_bytes(c->dev, lay, 1);

@@ -378,6 +378,41 @@ def test_qc_packed_family(cfg, schedule, cw_per_wg, early):
     assert (g[5].astype(np.int32) == ref["lam"]).all()
 
 
+@pytest.mark.parametrize("cfg,cw_per_wg,batch", [(0, 4, 29), (0, 8, 61), (0, 4, 2), (0, 12, 1000)])
+@pytest.mark.parametrize("rule", ["nms", "oms", "ms"])
+@pytest.mark.parametrize("early", [True, False])
+def test_qc_layer_parallel_flooding(cfg, cw_per_wg, batch, rule, early):
+    """Flooding with the layers in parallel (a workgroup of Z * npairs * layers threads,
+    each holding one layer's messages): decisions, flags, iteration counts and every q, r
+    and Lambda equal the oracle's, for every rule, with a ragged last workgroup."""
+    w = S.workload(cfg, batch=batch)
+    cw, llr = S.make_inputs(w, seed_offset=13)
+    d = _prm(w, rule=rule, schedule="flooding", max_iters=7, early_stop=early)
+    code = L.Code(w.code)
+    threads = 32 * (cw_per_wg // 2) * 3  # Z = 32, 3 layers
+    L.plan_set(code, L.params(**d), batch, "bin_qc_packed", cw_per_wg, threads)
+    info = L.plan_info(code, L.params(**d), batch)
+    assert info["family"] == "bin_qc_packed" and info["threads"] == threads
+    g = _gpu(code, d, llr, dump=True)
+    ref = _ref(w.code, d, llr, dump=True)
+    _check_decisions(w.code, g, ref)
+    assert (g[3].astype(np.int32) == ref["q"]).all()
+    assert (g[4].astype(np.int32) == ref["r"]).all()
+    assert (g[5].astype(np.int32) == ref["lam"]).all()
+    g2 = _gpu(code, d, llr)
+    _check_decisions(w.code, g2, ref)
+
+
+def test_qc_layer_parallel_needs_whole_waves_per_layer():
+    """The n = 2304 code (Z = 96, 12 layers) has no pair count with Z * npairs a multiple of
+    64 and at most 1024 threads: a plan asking for it keeps the one-row-per-thread kernel."""
+    w = S.workload(1, batch=8)
+    code = L.Code(w.code)
+    prm = L.params(**_prm(w, schedule="flooding"))
+    L.plan_set(code, prm, 8, "bin_qc_packed", 4, 96 * 2 * 12)
+    assert L.plan_info(code, prm, 8)["threads"] == 192
+
+
 @pytest.mark.parametrize("rule", ["nms", "oms", "ms"])
 def test_qc_packed_rules_and_saturation(rule):
     w = S.workload(1, batch=40)
