@@ -249,7 +249,8 @@ ldpcx_status ldpcx_tune(const ldpcx_code *code, const ldpcx_decode_params *param
  * 1024, at most 256 used for check degrees above 4; both schedules),
  * 3 = packed two-codewords-per-lane binary for quasi-cyclic codes, available
  * when every layer of z rows consists of z x z circulant blocks, at most 16 layers and
- * 8 blocks per layer), codewords per workgroup (family 1: codewords per launch
+ * 8 blocks per layer; threads = z * cw_per_wg / 2 * layers is its flooding kernel with the
+ * layers in parallel), codewords per workgroup (family 1: codewords per launch
  * sequence; larger batches run as consecutive slices), threads per workgroup. */
 ldpcx_status ldpcx_plan_info(const ldpcx_code *code, const ldpcx_decode_params *params,
                              int32_t batch, int32_t *family, int32_t *cw_per_wg,
@@ -258,7 +259,9 @@ ldpcx_status ldpcx_plan_info(const ldpcx_code *code, const ldpcx_decode_params *
 /* Pin the launch configuration used for (code, params, batch class) instead of the
  * default or tuned one.  family as in ldpcx_plan_info; cw_per_wg and threads are used by
  * family 0 (threads a multiple of 64 in [64, 1024]); cw_per_wg by family 3 (even, the
- * pairs' rows at most 512 threads) and by family 1 (slice size, rounded up to a multiple
+ * pairs' rows at most 512 threads; threads = z * cw_per_wg / 2 * layers selects the
+ * flooding kernel with the layers in parallel when z * cw_per_wg / 2 is a multiple of 64
+ * and the product at most 1024, else threads is ignored) and by family 1 (slice size, rounded up to a multiple
  * of 128 and capped by the batch and the 31-bit offset limit).  The pinned plan must be able to
  * run the requested schedule (LDPCX_E_UNSUPPORTED otherwise; families 1, 4 and 6 are
  * flooding only, families 2, 5 and 7 run the layered schedule up to GF(64)); family 5
