@@ -403,6 +403,23 @@ def test_qc_layer_parallel_flooding(cfg, cw_per_wg, batch, rule, early):
     _check_decisions(w.code, g2, ref)
 
 
+@pytest.mark.parametrize("batch", [1, 3, 130])
+def test_qc_layer_parallel_noiseless_and_tiny(batch):
+    """Layer-parallel flooding on noiseless codewords (every codeword stops before its first
+    iteration: 0 iterations, syndrome satisfied, decisions = the codeword) and on one or
+    three noisy codewords (a half-empty pair)."""
+    w = S.workload(0, batch=batch)
+    cw, llr = S.make_inputs(w, noiseless=True)
+    d = _prm(w, schedule="flooding", max_iters=5, early_stop=True)
+    code = L.Code(w.code)
+    L.plan_set(code, L.params(**d), batch, "bin_qc_packed", 4, 32 * 2 * 3)
+    assert L.plan_info(code, L.params(**d), batch)["threads"] == 192
+    hard, ok, it = _gpu(code, d, llr)
+    assert (L.unpack_bits(hard, w.code.n) == cw).all() and (ok == 1).all() and (it == 0).all()
+    _, noisy = S.make_inputs(w, seed_offset=21)
+    _check_decisions(w.code, _gpu(code, d, noisy), _ref(w.code, d, noisy))
+
+
 def test_qc_layer_parallel_needs_whole_waves_per_layer():
     """The n = 2304 code (Z = 96, 12 layers) has no pair count with Z * npairs a multiple of
     64 and at most 1024 threads: a plan asking for it keeps the one-row-per-thread kernel."""
