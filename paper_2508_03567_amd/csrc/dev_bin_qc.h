@@ -31,6 +31,109 @@ __device__ __forceinline__ uint32_t bfi(uint32_t M, uint32_t a, uint32_t b) { re
 // its decision bit is 0 for the parity test.
 constexpr uint32_t kDummy = 0x3FFF3FFFu;
 
+// LDS of a QC workgroup: [ML][MD] layer descriptors; [ML][Z] rows of 8 16-bit byte
+// offsets of the rows' Lambda words (one 16-byte LDS read per row and layer instead of
+// the index arithmetic of every edge); [npairs][ld] packed Lambda; in flooding
+// [npairs][ld] packed channel LLRs; then the pairs' parity flags and done bits and the
+// [2 npairs] iteration counts.
+struct QcLds {
+    int2 *sdesc;
+    uint16_t *offs;
+    uint32_t *lam, *Lch;
+    int *unsat, *done, *itc;
+};
+
+template <int ML, int MD>
+__device__ __forceinline__ QcLds qc_lds(uint32_t *lds, int Z, int npairs, int ld, bool layered) {
+    QcLds S;
+    S.sdesc = (int2 *)lds;
+    S.offs = (uint16_t *)(lds + 2 * ML * MD);
+    S.lam = lds + 2 * ML * MD + 4 * ML * Z;
+    S.Lch = S.lam + (size_t)npairs * ld;
+    S.unsat = (int *)(S.lam + (size_t)(layered ? 1 : 2) * npairs * ld);
+    S.done = S.unsat + npairs;
+    S.itc = S.done + npairs;
+    return S;
+}
+
+// Staging of codewords [cw0, cw0 + 2 npairs): layer descriptors and row offsets, Lambda
+// (and in flooding its channel copy) from the input LLRs with +16383 in the dummy slots
+// of virtual edges, cleared flags (codewords past the batch count as done).  Ends with
+// a barrier.
+template <int ML, int MD>
+__device__ __forceinline__ void qc_stage(const QcLds &S, const QcDesc &Q, const DevCode &C, const DecodeIO &io,
+                                         int batch, int npairs, int cw0, int ld, bool layered) {
+    const int n = C.n, Z = Q.Z, nl = Q.nl;
+    const uint32_t Z4 = 4 * Z;
+    const int tid = threadIdx.x, T = blockDim.x;
+    for (int idx = tid; idx < ML * MD; idx += T) {
+        const int l = idx / MD, j = idx - l * MD;
+        const int2 e = (l < nl && j < Q.dc[l]) ? Q.edges[l * kQcMaxDc + j] : make_int2(n, 0);
+        S.sdesc[idx] = make_int2(4 * e.x, 4 * e.y);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < ML * Z; idx += T) {
+        const int l = idx / Z, i = idx - l * Z;
+        uint16_t *o = S.offs + 8 * idx;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) o[j] = j < MD ? (uint16_t)qc_off(S.sdesc[l * MD + j], 4 * i, Z4) : (uint16_t)0;
+    }
+    const int8_t *llr = (const int8_t *)io.llr;
+    for (int idx = tid; idx < npairs * ld; idx += T) {
+        const int pp = idx / ld, v = idx - pp * ld;
+        const int c0 = cw0 + 2 * pp;
+        short lo = 0x3FFF, hi = 0x3FFF;
+        if (v < n) {
+            lo = c0 < batch ? (short)llr[(size_t)c0 * n + v] : (short)0;
+            hi = c0 + 1 < batch ? (short)llr[(size_t)(c0 + 1) * n + v] : (short)0;
+        }
+        const uint32_t w = as_u32((v2s){lo, hi});
+        S.lam[idx] = w;
+        if (!layered) S.Lch[idx] = w;
+    }
+    for (int idx = tid; idx < npairs; idx += T) {
+        const int c0 = cw0 + 2 * idx;
+        S.unsat[idx] = 0;
+        S.done[idx] = (c0 < batch ? 0 : 1) | (c0 + 1 < batch ? 0 : 2);
+        S.itc[2 * idx] = S.itc[2 * idx + 1] = 0;
+    }
+    __syncthreads();
+}
+
+// Outputs once the final syndrome is in the flags: ok and iteration counts, the packed
+// hard decisions and, with the debug dump, Lambda (the per-edge messages are the
+// caller's).
+__device__ __forceinline__ void qc_outputs(const QcLds &S, const DecodeIO &io, int n, int batch, int npairs, int cw0,
+                                           int ld) {
+    const int tid = threadIdx.x, T = blockDim.x;
+    const int ncw = min(2 * npairs, batch - cw0);
+    if (tid < ncw) {
+        io.ok[cw0 + tid] = ((S.unsat[tid >> 1] >> (tid & 1)) & 1) ? 0 : 1;
+        io.iters[cw0 + tid] = (int16_t)S.itc[tid];
+    }
+    const int nbytes = (n + 7) >> 3;
+    uint8_t *hard = (uint8_t *)io.hard + (size_t)cw0 * nbytes;
+    for (int idx = tid; idx < ncw * nbytes; idx += T) {
+        const int c = idx / nbytes, jb = idx - c * nbytes;
+        const uint32_t *lp = S.lam + (size_t)(c >> 1) * ld;
+        const int sh = (c & 1) ? 31 : 15;
+        uint32_t byte = 0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int v = 8 * jb + b;
+            if (v < n) byte |= ((lp[v] >> sh) & 1u) << b;
+        }
+        hard[idx] = (uint8_t)byte;
+    }
+    if (io.dump_a) {
+        int16_t *dl = (int16_t *)io.dump_c;
+        for (int idx = tid; idx < ncw * n; idx += T) {
+            const int c = idx / n, v = idx - c * n;
+            dl[(size_t)(cw0 + c) * n + v] = as_v2s(S.lam[(size_t)(c >> 1) * ld + v])[c & 1];
+        }
+    }
+}
+
 // Decode codewords [2 npairs blk, 2 npairs (blk + 1)) with the calling workgroup.
 // Threads beyond Z * npairs take part in the barriers only.  Ends with a barrier,
 // so the caller may reuse the LDS right after.  ES = false compiles the early-stop
@@ -46,15 +149,10 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
     const int p = act ? tid / Z : 0, i0 = act ? tid - p * Z : 0;
     const int cw0 = blk * npairs * 2;
     if (cw0 >= batch) return;
-    int2 *sdesc = (int2 *)lds;                     // [ML][MD] layer descriptors
-    // [ML][Z] rows of 8 16-bit byte offsets of the rows' Lambda words (one 16-byte LDS
-    // read per row and layer instead of the index arithmetic of every edge)
-    uint16_t *offs = (uint16_t *)(lds + 2 * ML * MD);
-    uint32_t *lam = lds + 2 * ML * MD + 4 * ML * Z;  // [npairs][ld] packed Lambda
-    uint32_t *Lch = lam + (size_t)npairs * ld;     // [npairs][ld] packed channel LLRs (flooding)
-    int *unsat = (int *)(lam + (size_t)(LAYERED ? 1 : 2) * npairs * ld);
-    int *done = unsat + npairs;
-    int *itc = done + npairs;  // [2 * npairs]
+    const QcLds S = qc_lds<ML, MD>(lds, Z, npairs, ld, LAYERED);
+    uint16_t *offs = S.offs;
+    uint32_t *lam = S.lam, *Lch = S.Lch;
+    int *unsat = S.unsat, *done = S.done, *itc = S.itc;
     const v2s mm = splat(R.msg_max), nmm = splat(-R.msg_max);
     const PkNorm NP = pk_norm_params(R);
     int rule = __builtin_amdgcn_readfirstlane(R.rule);  // uniform: scalar branches below
@@ -78,38 +176,7 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
         }
     };
 
-    for (int idx = tid; idx < ML * MD; idx += T) {
-        const int l = idx / MD, j = idx - l * MD;
-        const int2 e = (l < nl && j < Q.dc[l]) ? Q.edges[l * kQcMaxDc + j] : make_int2(n, 0);
-        sdesc[idx] = make_int2(4 * e.x, 4 * e.y);
-    }
-    __syncthreads();
-    for (int idx = tid; idx < ML * Z; idx += T) {
-        const int l = idx / Z, i = idx - l * Z;
-        uint16_t *o = offs + 8 * idx;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) o[j] = j < MD ? (uint16_t)qc_off(sdesc[l * MD + j], 4 * i, Z4) : (uint16_t)0;
-    }
-    const int8_t *llr = (const int8_t *)io.llr;
-    for (int idx = tid; idx < npairs * ld; idx += T) {
-        const int pp = idx / ld, v = idx - pp * ld;
-        const int c0 = cw0 + 2 * pp;
-        short lo = 0x3FFF, hi = 0x3FFF;
-        if (v < n) {
-            lo = c0 < batch ? (short)llr[(size_t)c0 * n + v] : (short)0;
-            hi = c0 + 1 < batch ? (short)llr[(size_t)(c0 + 1) * n + v] : (short)0;
-        }
-        const uint32_t w = as_u32((v2s){lo, hi});
-        lam[idx] = w;
-        if (!LAYERED) Lch[idx] = w;
-    }
-    for (int idx = tid; idx < npairs; idx += T) {
-        const int c0 = cw0 + 2 * idx;
-        unsat[idx] = 0;
-        done[idx] = (c0 < batch ? 0 : 1) | (c0 + 1 < batch ? 0 : 2);
-        itc[2 * idx] = itc[2 * idx + 1] = 0;
-    }
-    __syncthreads();
+    qc_stage<ML, MD>(S, Q, C, io, batch, npairs, cw0, ld, LAYERED);
 
     v2s r[ML][MD];
 #pragma unroll
@@ -260,29 +327,9 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
         if (any) atomicOr(&unsat[p], any);
     }
     __syncthreads();
-    const int ncw = min(2 * npairs, batch - cw0);
-    if (tid < ncw) {
-        io.ok[cw0 + tid] = ((unsat[tid >> 1] >> (tid & 1)) & 1) ? 0 : 1;
-        io.iters[cw0 + tid] = (int16_t)itc[tid];
-    }
-    const int nbytes = (n + 7) >> 3;
-    uint8_t *hard = (uint8_t *)io.hard + (size_t)cw0 * nbytes;
-    for (int idx = tid; idx < ncw * nbytes; idx += T) {
-        const int c = idx / nbytes, jb = idx - c * nbytes;
-        const uint32_t *lp = lam + (size_t)(c >> 1) * ld;
-        const int sh = (c & 1) ? 31 : 15;
-        uint32_t byte = 0;
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const int v = 8 * jb + b;
-            if (v < n) byte |= ((lp[v] >> sh) & 1u) << b;
-        }
-        hard[idx] = (uint8_t)byte;
-    }
     if (io.dump_a) {
         int8_t *dq = (int8_t *)io.dump_a;
         int8_t *dr = (int8_t *)io.dump_b;
-        int16_t *dl = (int16_t *)io.dump_c;
         const int i = i0;
 #pragma unroll
         for (int l = 0; l < ML; ++l) {
@@ -291,7 +338,7 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
 #pragma unroll
                 for (int j = 0; j < MD; ++j)
                     if (j < Q.dc[l]) {
-                        const v2s lv = as_v2s(lds_word(lamp, qc_off(sdesc[l * MD + j], 4 * i, 4 * Z)));
+                        const v2s lv = as_v2s(lds_word(lamp, qc_off(S.sdesc[l * MD + j], 4 * i, Z4)));
                         const v2s qc = pmin(pmax(lv - r[l][j], nmm), mm);
                         for (int h = 0; h < 2; ++h) {
                             const int c = cw0 + 2 * p + h;
@@ -303,11 +350,8 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
                     }
             }
         }
-        for (int idx = tid; idx < ncw * n; idx += T) {
-            const int c = idx / n, v = idx - c * n;
-            dl[(size_t)(cw0 + c) * n + v] = as_v2s(lam[(size_t)(c >> 1) * ld + v])[c & 1];
-        }
     }
+    qc_outputs(S, io, n, batch, npairs, cw0, ld);
     __syncthreads();
 }
 
@@ -323,7 +367,6 @@ __device__ __forceinline__ void qc_item_lp(const QcDesc &Q, const DevCode &C, co
                                            uint32_t *lds) {
     const int n = C.n, E = C.E, Z = Q.Z, nl = Q.nl;
     const int ld = n + Z;
-    const uint32_t Z4 = 4 * Z;
     const int tid = threadIdx.x, T = blockDim.x;
     const int per = Z * npairs;                       // threads of one layer
     const int lt = tid / per, rem = tid - lt * per;   // this thread's layer
@@ -331,13 +374,10 @@ __device__ __forceinline__ void qc_item_lp(const QcDesc &Q, const DevCode &C, co
     const int p = act ? rem / Z : 0, i0 = act ? rem - p * Z : 0;
     const int cw0 = blk * npairs * 2;
     if (cw0 >= batch) return;
-    int2 *sdesc = (int2 *)lds;
-    uint16_t *offs = (uint16_t *)(lds + 2 * ML * MD);
-    uint32_t *lam = lds + 2 * ML * MD + 4 * ML * Z;
-    uint32_t *Lch = lam + (size_t)npairs * ld;
-    int *unsat = (int *)(lam + (size_t)2 * npairs * ld);
-    int *done = unsat + npairs;
-    int *itc = done + npairs;
+    const QcLds S = qc_lds<ML, MD>(lds, Z, npairs, ld, false);
+    uint16_t *offs = S.offs;
+    uint32_t *lam = S.lam, *Lch = S.Lch;
+    int *unsat = S.unsat, *done = S.done, *itc = S.itc;
     const v2s mm = splat(R.msg_max), nmm = splat(-R.msg_max);
     const PkNorm NP = pk_norm_params(R);
     int rule = __builtin_amdgcn_readfirstlane(R.rule);
@@ -346,38 +386,7 @@ __device__ __forceinline__ void qc_item_lp(const QcDesc &Q, const DevCode &C, co
     asm volatile("" : "+s"(kn128));
     const v2s neg128 = as_v2s((uint32_t)kn128);
 
-    for (int idx = tid; idx < ML * MD; idx += T) {
-        const int l = idx / MD, j = idx - l * MD;
-        const int2 e = (l < nl && j < Q.dc[l]) ? Q.edges[l * kQcMaxDc + j] : make_int2(n, 0);
-        sdesc[idx] = make_int2(4 * e.x, 4 * e.y);
-    }
-    __syncthreads();
-    for (int idx = tid; idx < ML * Z; idx += T) {
-        const int l = idx / Z, i = idx - l * Z;
-        uint16_t *o = offs + 8 * idx;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) o[j] = j < MD ? (uint16_t)qc_off(sdesc[l * MD + j], 4 * i, Z4) : (uint16_t)0;
-    }
-    const int8_t *llr = (const int8_t *)io.llr;
-    for (int idx = tid; idx < npairs * ld; idx += T) {
-        const int pp = idx / ld, v = idx - pp * ld;
-        const int c0 = cw0 + 2 * pp;
-        short lo = 0x3FFF, hi = 0x3FFF;
-        if (v < n) {
-            lo = c0 < batch ? (short)llr[(size_t)c0 * n + v] : (short)0;
-            hi = c0 + 1 < batch ? (short)llr[(size_t)(c0 + 1) * n + v] : (short)0;
-        }
-        const uint32_t w = as_u32((v2s){lo, hi});
-        lam[idx] = w;
-        Lch[idx] = w;
-    }
-    for (int idx = tid; idx < npairs; idx += T) {
-        const int c0 = cw0 + 2 * idx;
-        unsat[idx] = 0;
-        done[idx] = (c0 < batch ? 0 : 1) | (c0 + 1 < batch ? 0 : 2);
-        itc[2 * idx] = itc[2 * idx + 1] = 0;
-    }
-    __syncthreads();
+    qc_stage<ML, MD>(S, Q, C, io, batch, npairs, cw0, ld, false);
 
     uint32_t *lamp = lam + (size_t)p * ld;
     uint32_t vv[MD];
@@ -501,29 +510,9 @@ __device__ __forceinline__ void qc_item_lp(const QcDesc &Q, const DevCode &C, co
         if (any) atomicOr(&unsat[p], any);
     }
     __syncthreads();
-    const int ncw = min(2 * npairs, batch - cw0);
-    if (tid < ncw) {
-        io.ok[cw0 + tid] = ((unsat[tid >> 1] >> (tid & 1)) & 1) ? 0 : 1;
-        io.iters[cw0 + tid] = (int16_t)itc[tid];
-    }
-    const int nbytes = (n + 7) >> 3;
-    uint8_t *hard = (uint8_t *)io.hard + (size_t)cw0 * nbytes;
-    for (int idx = tid; idx < ncw * nbytes; idx += T) {
-        const int c = idx / nbytes, jb = idx - c * nbytes;
-        const uint32_t *lp = lam + (size_t)(c >> 1) * ld;
-        const int sh = (c & 1) ? 31 : 15;
-        uint32_t byte = 0;
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const int v = 8 * jb + b;
-            if (v < n) byte |= ((lp[v] >> sh) & 1u) << b;
-        }
-        hard[idx] = (uint8_t)byte;
-    }
     if (io.dump_a) {
         int8_t *dq = (int8_t *)io.dump_a;
         int8_t *dr = (int8_t *)io.dump_b;
-        int16_t *dl = (int16_t *)io.dump_c;
         if (act) {
             const int e0 = C.row_ptr[lt * Z + i0];
 #pragma unroll
@@ -540,11 +529,8 @@ __device__ __forceinline__ void qc_item_lp(const QcDesc &Q, const DevCode &C, co
                     }
                 }
         }
-        for (int idx = tid; idx < ncw * n; idx += T) {
-            const int c = idx / n, v = idx - c * n;
-            dl[(size_t)(cw0 + c) * n + v] = as_v2s(lam[(size_t)(c >> 1) * ld + v])[c & 1];
-        }
     }
+    qc_outputs(S, io, n, batch, npairs, cw0, ld);
     __syncthreads();
 }
 
