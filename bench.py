@@ -87,6 +87,8 @@ def algorithmic_bytes_per_cw(w) -> float:
 BIN_OPS_PER_EDGE = 16
 E2E_WARMUP = 3        # untimed passes of each end-to-end leg, at least ...
 E2E_WARMUP_S = 0.08   # ... and at least this long
+E2E_SPLIT_BYTES = 16 << 20  # input size from which the overlapped leg runs two chunks (one below:
+                             # a small batch decodes faster than the cross-stream waits cost)
 
 
 def algorithmic_ops_per_cw(w) -> float:
@@ -125,7 +127,7 @@ def main() -> None:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-e2e", action="store_true", help="skip the end-to-end (PCIe-inclusive) leg")
     ap.add_argument("--e2e-chunks", type=int, default=0,
-                    help="chunks of the overlapped end-to-end leg (0: 2 from 16384 codewords up, else 1)")
+                    help="chunks of the overlapped end-to-end leg (0: 2 from 16 MiB of input up, else 1)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU oracle time")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one 256 MiB device-to-device copy (counter calibration)")
@@ -295,7 +297,8 @@ def main() -> None:
         # pass has finished, so consecutive passes overlap too (the rate is that of a
         # continuous stream of batches).  The events are created once and re-recorded
         # every pass.
-        nch = args.e2e_chunks if args.e2e_chunks > 0 else (2 if w.batch >= 16384 else 1)
+        in_bytes = llr_host.numel() * llr_host.element_size()
+        nch = args.e2e_chunks if args.e2e_chunks > 0 else (2 if in_bytes >= E2E_SPLIT_BYTES else 1)
         step_cw = (w.batch + nch - 1) // nch
         chunks = [(c0, min(w.batch, c0 + step_cw)) for c0 in range(0, w.batch, step_cw)]
         s_in, s_dec, s_out = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()

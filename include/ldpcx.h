@@ -92,7 +92,9 @@ typedef struct {
  *               runs), or AUTO (the autotuner picks; ldpcx_decode reports the schedule
  *               used).  The FFT-SPA decoder and GF(128)/GF(256) run FLOODING only.
  *   rule        MS / NMS / OMS for g == 2, MINMAX for g > 2.
- *   nms_num, nms_shift   NMS magnitude f(m) = (nms_num * m) >> nms_shift (0.75 = 3, 2).
+ *   nms_num, nms_shift   NMS magnitude f(m) = (nms_num * m) >> nms_shift (0.75 = 3, 2);
+ *               a factor in [0, 1]: 0 <= nms_num <= 2^nms_shift, nms_shift <= 6
+ *               (LDPCX_E_INVAL otherwise), so that f(m) <= m <= msg_max.
  *   oms_offset  OMS magnitude f(m) = max(m - oms_offset, 0).
  *   msg_max     binary variable-to-check message saturation, 1..127 (default 127).
  * Binary arithmetic: channel LLRs L are int8, positive favours bit 0.  Check-to-

@@ -32,6 +32,7 @@ constexpr int kPairs = 2;                     // packed int16 pairs per lane
 constexpr int kLaneCw = 2 * kPairs;           // codewords per lane
 constexpr int kGroup = 64 * kLaneCw;          // codewords per wavefront
 constexpr int kVnRegs = 8;                    // check messages a variable keeps in registers
+constexpr int kVnPerWave = 2;                 // variables of one variable-node wave
 constexpr uint32_t kRsrcWord3 = 0x00020000u;  // raw (untyped) buffer resource, gfx9 family
 
 struct Args {
@@ -114,6 +115,7 @@ __device__ __forceinline__ bool neg_of(const Pk &S, int h) { return (as_u32(S[h 
 // Virtual grids (blocks of 256 threads, 4 waves) of the phases.
 __host__ __device__ inline long grid_rows_x(const Args &A) { return (A.C.m + 3) / 4; }
 __host__ __device__ inline long grid_vars_x(const Args &A) { return (A.C.n + 3) / 4; }
+__host__ __device__ inline long grid_vn_x(const Args &A) { return (A.C.n + 4 * kVnPerWave - 1) / (4 * kVnPerWave); }
 __host__ __device__ inline long grid_edges_x(const Args &A) { return (A.C.E + 3) / 4; }
 __host__ __device__ inline long grid_syn(const Args &A) {
     return ((long)((A.C.m + 31) / 32) * kLaneCw * A.G + 255) / 256;
@@ -208,7 +210,7 @@ __device__ __forceinline__ void cn_block(const Args &A, int k, int bx, int g) {
 #pragma unroll
     for (int j = 0; j < DC; ++j)
         if (j < dc) raw[j] = ld(rq, vo, (uint32_t)(e0 + j) * Bp + gb);
-    Pk m1, m2, f2, df;
+    Pk m1, m2, f1, cs;
     Pk av[DC];
     uint32_t sv[DC][kPairs], stot[kPairs];
 #pragma unroll
@@ -232,11 +234,18 @@ __device__ __forceinline__ void cn_block(const Args &A, int k, int bx, int g) {
             }
         }
     }
+    // Magnitude out of edge j: f(min2) where the edge holds the minimum (a = min1), else
+    // f(min1).  With magnitudes in [0, 127] and f(min2) - f(min1) <= min2 - min1 <= 127
+    // (normalisation factor at most 1) that is max(f(min1), f(min2) + 128 (min1 - a)),
+    // exact in int16: one multiply-add and one maximum per pair.  -128 is opaque to the
+    // compiler so that the product stays one v_pk_mad_u16.
+    int kn128 = (int)0xFF80FF80u;
+    asm volatile("" : "+s"(kn128));
+    const v2s neg128 = as_v2s((uint32_t)kn128);
 #pragma unroll
     for (int p = 0; p < kPairs; ++p) {
-        const v2s f1 = pk_norm(NP, m1[p]);
-        f2[p] = pk_norm(NP, m2[p]);
-        df[p] = f1 - f2[p];
+        f1[p] = pk_norm(NP, m1[p]);
+        cs[p] = pk_norm(NP, m2[p]) - m1[p] * neg128;
     }
 #pragma unroll
     for (int j = 0; j < DC; ++j) {
@@ -244,8 +253,7 @@ __device__ __forceinline__ void cn_block(const Args &A, int k, int bx, int g) {
             Pk rn;
 #pragma unroll
             for (int p = 0; p < kPairs; ++p) {
-                const v2s t = pmin(av[j][p] - m1[p], splat(1));  // 0 where this edge holds the minimum
-                const v2s mag = f2[p] + t * df[p];
+                const v2s mag = pmax(f1[p], av[j][p] * neg128 + cs[p]);
                 const uint32_t sr = stot[p] ^ sv[j][p];
                 rn[p] = as_v2s(as_u32(mag) ^ sr) - as_v2s(sr);
             }
@@ -257,65 +265,82 @@ __device__ __forceinline__ void cn_block(const Args &A, int k, int bx, int g) {
     }
 }
 
-// Variable-node phase of iteration k: one wave per (variable, group).
+// Variable-node phase of iteration k: one wave per (kVnPerWave consecutive variables,
+// group).  The wave issues the loads of all its variables before it sums any of them:
+// a wave's life is mostly index and message latency, so two variables per wave keep
+// more bytes in flight (three measured slower).  The unpacked messages of the first
+// kVnRegs edges stay in registers for the outgoing messages.
 __device__ __forceinline__ void vn_block(const Args &A, int k, int bx, int g) {
+    constexpr int NV = kVnPerWave;
     const DevCode &C = A.C;
     const int lane = threadIdx.x & 63;
-    const int v = bx * 4 + wave_id();
-    if (v >= C.n) return;
+    const int v0 = (bx * 4 + wave_id()) * NV;
+    if (v0 >= C.n) return;
     const Act act = activity(A, k, g, lane);
     if (!act.any) return;
     const uint32_t vo = lane_off(), gb = (uint32_t)g * kGroup, Bp = (uint32_t)A.Bp;
     const auto rL = rsrc(A.w.L, (uint32_t)C.n * Bp);
     const auto rq = rsrc(A.w.q, (uint32_t)C.E * Bp);
     const auto rr = rsrc(A.w.r, (uint32_t)C.E * Bp);
-    const int t0 = C.vn_ptr[v];
-    const int dv = C.vn_ptr[v + 1] - t0;
-    uint32_t rw[kVnRegs], ev[kVnRegs];
-    const uint32_t lw = ld(rL, vo, (uint32_t)v * Bp + gb);
+    int t0[NV], dv[NV];
+    uint32_t lw[NV], rw[NV][kVnRegs], ev[NV][kVnRegs];
 #pragma unroll
-    for (int t = 0; t < kVnRegs; ++t) {
-        if (t < dv) {
-            ev[t] = (uint32_t)C.vn_edge[t0 + t] * Bp + gb;
-            rw[t] = ld(rr, vo, ev[t]);
+    for (int i = 0; i < NV; ++i) {
+        const bool ok = v0 + i < C.n;
+        t0[i] = ok ? C.vn_ptr[v0 + i] : 0;
+        dv[i] = ok ? C.vn_ptr[v0 + i + 1] - t0[i] : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        if (v0 + i < C.n) lw[i] = ld(rL, vo, (uint32_t)(v0 + i) * Bp + gb);
+#pragma unroll
+        for (int t = 0; t < kVnRegs; ++t) {
+            if (t < dv[i]) {
+                ev[i][t] = (uint32_t)C.vn_edge[t0[i] + t] * Bp + gb;
+                rw[i][t] = ld(rr, vo, ev[i][t]);
+            }
         }
     }
-    Pk S;
-    unpack(lw, S);
+    const v2s mm = splat(A.R.msg_max), nmm = splat(-A.R.msg_max);
 #pragma unroll
-    for (int t = 0; t < kVnRegs; ++t) {
-        if (t < dv) {
+    for (int i = 0; i < NV; ++i) {
+        if (v0 + i >= C.n) break;
+        Pk S, ru[kVnRegs];
+        unpack(lw[i], S);
+#pragma unroll
+        for (int t = 0; t < kVnRegs; ++t) {
+            if (t < dv[i]) {
+                unpack(rw[i][t], ru[t]);
+#pragma unroll
+                for (int p = 0; p < kPairs; ++p) S[p] = S[p] + ru[t][p];
+            }
+        }
+        for (int t = kVnRegs; t < dv[i]; ++t) {
             Pk r;
-            unpack(rw[t], r);
+            unpack(ld(rr, vo, (uint32_t)C.vn_edge[t0[i] + t] * Bp + gb), r);
 #pragma unroll
             for (int p = 0; p < kPairs; ++p) S[p] = S[p] + r[p];
         }
-    }
-    for (int t = kVnRegs; t < dv; ++t) {
-        Pk r;
-        unpack(ld(rr, vo, (uint32_t)C.vn_edge[t0 + t] * Bp + gb), r);
+        auto qword = [&](const Pk &r, uint32_t so) {
+            Pk q;
 #pragma unroll
-        for (int p = 0; p < kPairs; ++p) S[p] = S[p] + r[p];
-    }
-    const v2s mm = splat(A.R.msg_max), nmm = splat(-A.R.msg_max);
-    auto qword = [&](uint32_t r_raw, uint32_t so) {
-        Pk r, q;
-        unpack(r_raw, r);
+            for (int p = 0; p < kPairs; ++p) q[p] = pmin(pmax(S[p] - r[p], nmm), mm);
+            uint32_t w = pack(q);
+            if (!act.all) w = merge(act.m8, w, ld(rq, vo, so));
+            st(w, rq, vo, so);
+        };
 #pragma unroll
-        for (int p = 0; p < kPairs; ++p) q[p] = pmin(pmax(S[p] - r[p], nmm), mm);
-        uint32_t w = pack(q);
-        if (!act.all) w = merge(act.m8, w, ld(rq, vo, so));
-        st(w, rq, vo, so);
-    };
-#pragma unroll
-    for (int t = 0; t < kVnRegs; ++t)
-        if (t < dv) qword(rw[t], ev[t]);
-    for (int t = kVnRegs; t < dv; ++t) {
-        const uint32_t so = (uint32_t)C.vn_edge[t0 + t] * Bp + gb;
-        qword(ld(rr, vo, so), so);
+        for (int t = 0; t < kVnRegs; ++t)
+            if (t < dv[i]) qword(ru[t], ev[i][t]);
+        for (int t = kVnRegs; t < dv[i]; ++t) {
+            const uint32_t so = (uint32_t)C.vn_edge[t0[i] + t] * Bp + gb;
+            Pk r;
+            unpack(ld(rr, vo, so), r);
+            qword(r, so);
+        }
+        store_hb(A, v0 + i, g, S, &act);
     }
-    store_hb(A, v, g, S, &act);
-    if (v == 0) {
+    if (v0 == 0) {
         uint32_t *itp = (uint32_t *)(A.w.it + (size_t)g * kGroup) + kPairs * lane;
         const uint32_t kk = (uint32_t)k | ((uint32_t)k << 16);
 #pragma unroll

@@ -64,11 +64,12 @@ hipError_t run_slice(const DevCode &C, const BinRule &R, int max_iters, int earl
     const dim3 gcn((unsigned)dev::il::grid_rows_x(A), G);
     const dim3 gvn((unsigned)dev::il::grid_vars_x(A), G);
     const dim3 gsyn((unsigned)dev::il::grid_syn(A));
+    const dim3 gvnw((unsigned)dev::il::grid_vn_x(A), G);
     for (int k = 1; k <= max_iters; ++k) {
         if (early_stop) hipLaunchKernelGGL(k_syn, gsyn, blk, 0, s, A, k);
         if (C.dc_max <= 8) hipLaunchKernelGGL(k_cn<8>, gcn, blk, 0, s, A, k);
         else hipLaunchKernelGGL(k_cn<kBinDcMax>, gcn, blk, 0, s, A, k);
-        hipLaunchKernelGGL(k_vn, gvn, blk, 0, s, A, k);
+        hipLaunchKernelGGL(k_vn, gvnw, blk, 0, s, A, k);
         LDPCX_CHECK(hipGetLastError());
     }
     hipLaunchKernelGGL(k_syn, gsyn, blk, 0, s, A, 0);

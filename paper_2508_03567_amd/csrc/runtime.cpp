@@ -98,8 +98,9 @@ ldpcx_status check_params(const ldpcx_code *c, const ldpcx_decode_params *p) {
     if (c->g == 2) {
         if (p->rule < 0 || p->rule > 2) return fail(LDPCX_E_INVAL, "binary codes take rule MS, NMS or OMS");
         if (p->msg_max < 1 || p->msg_max > 127) return fail(LDPCX_E_INVAL, "msg_max must be in [1, 127]");
-        if (p->rule == LDPCX_RULE_NMS && (p->nms_num < 0 || p->nms_num > 64 || p->nms_shift < 0 || p->nms_shift > 15))
-            return fail(LDPCX_E_INVAL, "NMS factor out of range");
+        if (p->rule == LDPCX_RULE_NMS && (p->nms_num < 0 || p->nms_shift < 0 || p->nms_shift > 6 ||
+                                          p->nms_num > (1 << p->nms_shift)))
+            return fail(LDPCX_E_INVAL, "NMS factor must be nms_num / 2^nms_shift in [0, 1], nms_shift <= 6");
         if (p->rule == LDPCX_RULE_OMS && (p->oms_offset < 0 || p->oms_offset > 127))
             return fail(LDPCX_E_INVAL, "OMS offset out of range");
         if (p->schedule == LDPCX_SCHED_LAYERED && !c->layers_ok)

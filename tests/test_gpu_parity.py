@@ -596,6 +596,25 @@ def test_minmax_lds_family_matches_oracle(g_size, n, dc, batch, early, sched, th
     _check_decisions(code, g2, ref)
 
 
+def test_nms_factor_limits():
+    """NMS takes a normalisation factor in [0, 1] (the check-node magnitude selection
+    relies on f(min2) - f(min1) <= min2 - min1); a factor of exactly 1 is plain min-sum."""
+    w = S.workload(0, batch=40)
+    h = L.Code(w.code)
+    _, llr = S.make_inputs(w, seed_offset=31)
+    for num, sh in ((5, 2), (65, 6), (1, 7), (-1, 2), (1, -1)):
+        with pytest.raises(L.LdpcxError) as ei:
+            _gpu(h, _prm(w, rule="nms", nms_num=num, nms_shift=sh), llr)
+        assert ei.value.status == L.E_INVAL
+    for family, sub in (("bin_interleaved", 256), ("bin_qc_packed", 4)):
+        d1 = _prm(w, rule="nms", nms_num=64, nms_shift=6, schedule="flooding", max_iters=6)
+        L.plan_set(h, L.params(**d1), 40, family, sub)
+        g = _gpu(h, d1, llr, dump=True)
+        ref = _ref(w.code, _prm(w, rule="ms", schedule="flooding", max_iters=6), llr, dump=True)
+        _check_decisions(w.code, g, ref)
+        assert (g[4].astype(np.int32) == ref["r"]).all()
+
+
 def test_minmax_lds_family_limits():
     w = S.workload(3)
     h = _handle(w.code)
