@@ -359,8 +359,14 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
 // only, so a workgroup of Z * npairs * nl threads runs every check node of an iteration at
 // once (nl times the waves of qc_item, each with one layer's messages in registers).
 // Z * npairs is a multiple of 64, so a wave holds rows of one layer and the layer degree
-// is uniform in it.  The variable-node update then adds the layers' messages to Lambda
-// one layer after the other, as in qc_item.  Same LDS layout as qc_item's flooding.
+// is uniform in it.  The variable-node update adds each edge's change r_new - r_old to
+// Lambda in place (Lambda_old + sum (r_new - r_old) = L + sum r_new, exactly), every layer
+// at once, with 32-bit LDS atomic adds on the packed pair.  For the carry out of the low
+// half to be right, the low halves of Lambda are kept offset by 2^15 (x ^ 0x8000, always
+// in [0, 65535] since Lambda is exact in int16) while the iterations run: adding the
+// unsigned low half of a delta then carries out exactly when the delta is negative, and
+// the high half of the addend is lowered by that carry.  One barrier after the check
+// nodes and one after the adds per iteration.  LDS layout of qc_item's layered schedule.
 template <int ML, int MD, bool ES>
 __device__ __forceinline__ void qc_item_lp(const QcDesc &Q, const DevCode &C, const BinRule &R, int max_iters,
                                            int early_stop, int batch, int npairs, const DecodeIO &io, int blk,
@@ -374,9 +380,9 @@ __device__ __forceinline__ void qc_item_lp(const QcDesc &Q, const DevCode &C, co
     const int p = act ? rem / Z : 0, i0 = act ? rem - p * Z : 0;
     const int cw0 = blk * npairs * 2;
     if (cw0 >= batch) return;
-    const QcLds S = qc_lds<ML, MD>(lds, Z, npairs, ld, false);
+    const QcLds S = qc_lds<ML, MD>(lds, Z, npairs, ld, true);
     uint16_t *offs = S.offs;
-    uint32_t *lam = S.lam, *Lch = S.Lch;
+    uint32_t *lam = S.lam;
     int *unsat = S.unsat, *done = S.done, *itc = S.itc;
     const v2s mm = splat(R.msg_max), nmm = splat(-R.msg_max);
     const PkNorm NP = pk_norm_params(R);
@@ -385,8 +391,11 @@ __device__ __forceinline__ void qc_item_lp(const QcDesc &Q, const DevCode &C, co
     int kn128 = (int)0xFF80FF80u;  // -128 in both halves, opaque (one v_pk_mad_u16 below)
     asm volatile("" : "+s"(kn128));
     const v2s neg128 = as_v2s((uint32_t)kn128);
+    constexpr uint32_t kBias = 0x8000u;  // offset of Lambda's low halves during the iterations
 
-    qc_stage<ML, MD>(S, Q, C, io, batch, npairs, cw0, ld, false);
+    qc_stage<ML, MD>(S, Q, C, io, batch, npairs, cw0, ld, true);
+    for (int idx = tid; idx < npairs * ld; idx += T) lam[idx] ^= kBias;
+    __syncthreads();
 
     uint32_t *lamp = lam + (size_t)p * ld;
     uint32_t vv[MD];
@@ -400,14 +409,15 @@ __device__ __forceinline__ void qc_item_lp(const QcDesc &Q, const DevCode &C, co
     }
     dc = __builtin_amdgcn_readfirstlane(dc);  // uniform: a wave holds rows of one layer
     asm volatile("" : "+s"(dc));
-    v2s r[MD];
+    v2s r[MD], dr[MD];  // the row's messages and their change in this iteration
 #pragma unroll
-    for (int j = 0; j < MD; ++j) r[j] = splat(0);
+    for (int j = 0; j < MD; ++j) r[j] = dr[j] = splat(0);
 
-    // parity of this thread's row under the current decisions (2 bits, one per codeword)
+    // parity of this thread's row under the current decisions (2 bits, one per codeword);
+    // each of the MD words carries the offset's flipped low sign bit
     auto row_parity = [&]() -> int {
         if (!act) return 0;
-        uint32_t x = 0;
+        uint32_t x = (MD & 1) ? kBias : 0u;
 #pragma unroll
         for (int j = 0; j < MD; ++j) x ^= lds_word(lamp, vv[j]);
         return (int)((x >> 15) & 1u) | (int)((x >> 30) & 2u);
@@ -419,7 +429,7 @@ __device__ __forceinline__ void qc_item_lp(const QcDesc &Q, const DevCode &C, co
         uint32_t sv[MD], sr[MD];
         v2s qv[MD], nq[MD], av[MD], mg[MD];
 #pragma unroll
-        for (int j = 0; j < DD; ++j) qv[j] = as_v2s(lds_word(lamp, vv[j])) - r[j];
+        for (int j = 0; j < DD; ++j) qv[j] = as_v2s(lds_word(lamp, vv[j]) ^ kBias) - r[j];
 #pragma unroll
         for (int j = 0; j < DD; ++j) nq[j] = -qv[j];
 #pragma unroll
@@ -459,8 +469,10 @@ __device__ __forceinline__ void qc_item_lp(const QcDesc &Q, const DevCode &C, co
         for (int j = 0; j < DD; ++j) mg[j] = as_v2s(as_u32(mg[j]) ^ sr[j]);
 #pragma unroll
         for (int j = 0; j < DD; ++j) {
-            const v2s rn = mg[j] - as_v2s(sr[j]);
-            r[j] = ES ? as_v2s(bfi(M, as_u32(rn), as_u32(r[j]))) : rn;
+            v2s rn = mg[j] - as_v2s(sr[j]);
+            if (ES) rn = as_v2s(bfi(M, as_u32(rn), as_u32(r[j])));
+            dr[j] = rn - r[j];
+            r[j] = rn;
         }
     };
 
@@ -486,29 +498,27 @@ __device__ __forceinline__ void qc_item_lp(const QcDesc &Q, const DevCode &C, co
             else check(std::integral_constant<int, MD - 2>{});
         }
         __syncthreads();  // every check node has read Lambda
-        for (int idx = tid; idx < npairs * ld; idx += T) lam[idx] = Lch[idx];
-        __syncthreads();
-        for (int l = 0; l < nl; ++l) {
-            if (act && lt == l) {
+        if (act) {
 #pragma unroll
-                for (int j = 0; j < MD; ++j) {
-                    if (j < dc) {
-                        uint32_t &w = lds_word(lamp, vv[j]);
-                        w = as_u32(as_v2s(w) + r[j]);
-                    }
+            for (int j = 0; j < MD; ++j) {
+                if (j < dc) {
+                    const uint32_t d = as_u32(dr[j]);
+                    atomicAdd(&lds_word(lamp, vv[j]), d - ((d & 0x8000u) << 1));
                 }
             }
-            __syncthreads();
         }
+        __syncthreads();
         if (tid < 2 * npairs && !((done[tid >> 1] >> (tid & 1)) & 1)) itc[tid] = k;
     }
 
-    // Syndrome of the final decision.
+    // Syndrome of the final decision, then Lambda back to plain packed int16.
     __syncthreads();
     {
         const int any = row_parity();
         if (any) atomicOr(&unsat[p], any);
     }
+    __syncthreads();
+    for (int idx = tid; idx < npairs * ld; idx += T) lam[idx] ^= kBias;
     __syncthreads();
     if (io.dump_a) {
         int8_t *dq = (int8_t *)io.dump_a;

@@ -189,13 +189,13 @@ Plan default_plan(const ldpcx_code *c, const ldpcx_decode_params *p, int batch) 
         while (np > 1 && bin_qc_smem_bytes(c->qc, c->dev, sched == LDPCX_SCHED_LAYERED, np) > (size_t)di.lds_per_block) --np;
         pl.cpw = 2 * np;
         pl.threads = Z * np;
-        // Small flooding batches (fewer than 4 workgroups per compute unit): the layers in
-        // parallel, which shortens each codeword's iteration (measured 1.7x faster on 1000
-        // codewords of the n = 192 code, slower from tens of thousands up)
+        // Flooding: the layers in parallel where a layer fills whole waves, which shortens
+        // each codeword's iteration (on the n = 192 code 2.5x faster than one row per
+        // thread at 1000 codewords, and at least as fast from 4096 to 65536)
         if (sched != LDPCX_SCHED_LAYERED) {
             int npl = 1;
             while (npl <= 16 && (Z * npl) % 64) ++npl;
-            if (npl <= 16 && bin_qc_lp_ok(c->qc, npl) && (pairs + npl - 1) / npl < 4 * di.cus &&
+            if (npl <= 16 && bin_qc_lp_ok(c->qc, npl) &&
                 bin_qc_smem_bytes(c->qc, c->dev, false, npl) <= (size_t)di.lds_per_block) {
                 pl.cpw = 2 * npl;
                 pl.threads = Z * npl * c->qc.nl;
