@@ -177,6 +177,17 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
     };
 
     qc_stage<ML, MD>(S, Q, C, io, batch, npairs, cw0, ld, LAYERED);
+    // Flooding adds every layer's messages to Lambda at once with 32-bit LDS atomic adds
+    // on the packed pair; Lambda's low halves (and the channel copy's) are kept offset by
+    // 2^15 meanwhile so that the carry between the halves is exact (as in qc_item_lp).
+    constexpr uint32_t kB = LAYERED ? 0u : 0x8000u;
+    if (!LAYERED) {
+        for (int idx = tid; idx < npairs * ld; idx += T) {
+            lam[idx] ^= kB;
+            Lch[idx] ^= kB;
+        }
+        __syncthreads();
+    }
 
     v2s r[ML][MD];
 #pragma unroll
@@ -203,7 +214,7 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
             if (l < nl) {
                 uint32_t vv[MD];
                 row_offs(l, vv);
-                uint32_t x = 0;
+                uint32_t x = (MD & 1) ? kB : 0u;  // each word's low sign bit is flipped by the offset
 #pragma unroll
                 for (int j = 0; j < MD; ++j) x ^= lds_word(lamp, vv[j]);
                 any |= (int)((x >> 15) & 1u) | (int)((x >> 30) & 2u);
@@ -245,7 +256,7 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
                     v2s qv[MD], nq[MD], av[MD], mg[MD];
                     row_offs(l, vv);
 #pragma unroll
-                    for (int j = 0; j < DD; ++j) qv[j] = as_v2s(lds_word(lamp, vv[j])) - r[l][j];
+                    for (int j = 0; j < DD; ++j) qv[j] = as_v2s(lds_word(lamp, vv[j]) ^ kB) - r[l][j];
                     // |clamp(q, +-msg_max)| = min(|q|, msg_max); the sign of q is the sign of clamp(q)
 #pragma unroll
                     for (int j = 0; j < DD; ++j) nq[j] = -qv[j];
@@ -300,33 +311,39 @@ __device__ __forceinline__ void qc_item(const QcDesc &Q, const DevCode &C, const
             __syncthreads();
             for (int idx = tid; idx < npairs * ld; idx += T) lam[idx] = Lch[idx];
             __syncthreads();
+            if (act) {
 #pragma unroll
-            for (int l = 0; l < ML; ++l) {
-                if (l < nl) {
-                    const int dc = Q.dc[l];
-                    uint32_t vv[MD];
-                    row_offs(l, vv);
+                for (int l = 0; l < ML; ++l) {
+                    if (l < nl) {
+                        const int dc = Q.dc[l];
+                        uint32_t vv[MD];
+                        row_offs(l, vv);
 #pragma unroll
-                    for (int j = 0; j < MD; ++j) {
-                        if (act && j < dc) {
-                            uint32_t &w = lds_word(lamp, vv[j]);
-                            w = as_u32(as_v2s(w) + r[l][j]);
+                        for (int j = 0; j < MD; ++j) {
+                            if (j < dc) {
+                                const uint32_t d = as_u32(r[l][j]);
+                                atomicAdd(&lds_word(lamp, vv[j]), d - ((d & 0x8000u) << 1));
+                            }
                         }
                     }
-                    __syncthreads();
                 }
             }
+            __syncthreads();
         }
         if (tid < 2 * npairs && !((done[tid >> 1] >> (tid & 1)) & 1)) itc[tid] = k;
     }
 
-    // Syndrome of the final decision.
+    // Syndrome of the final decision (then Lambda back to plain packed int16).
     __syncthreads();
     {
         const int any = row_parities();
         if (any) atomicOr(&unsat[p], any);
     }
     __syncthreads();
+    if (!LAYERED) {
+        for (int idx = tid; idx < npairs * ld; idx += T) lam[idx] ^= kB;
+        __syncthreads();
+    }
     if (io.dump_a) {
         int8_t *dq = (int8_t *)io.dump_a;
         int8_t *dr = (int8_t *)io.dump_b;
